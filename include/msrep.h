@@ -1,0 +1,284 @@
+/*
+ * msrep.h -- C ABI of libmsrep, an MI355X (gfx950) implementation of the
+ * equal-nnz partitioned sparse matrix-vector product of Chen et al., "msRep:
+ * A Fast yet Light Sparse Matrix Framework for Multi-GPU Systems" (arXiv
+ * 2209.07552), with the paper's split taken across one GPU's compute units,
+ * workgroups and wavefronts instead of across GPUs.
+ *
+ * General conventions
+ *   - Every pointer named *_d, and every array inside msrep_mat / msrep_part,
+ *     is device memory (HBM of the current HIP device) owned by the caller.
+ *     The library never frees caller memory.  Host pointers are marked.
+ *   - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *     All work is stream-ordered; no call synchronises the device unless its
+ *     comment says so.
+ *   - Calls return an msrep_status; on failure nothing has been launched and
+ *     msrep_last_error() returns a description (thread-local).  No C++
+ *     exception crosses this boundary.
+ *   - Indices are int32; nonzero positions and offsets are int64.  A matrix
+ *     holds fewer than 2^31 nonzeros.
+ *   - Cheap O(1) argument checks always run.  The O(nnz) structure checks
+ *     (monotone pointers, indices in range, row-sorted COO) run only in
+ *     msrep_validate; kernels never read or write outside the arrays the
+ *     descriptors give, whatever the contents, but results on invalid
+ *     structure are unspecified.
+ */
+#ifndef MSREP_H
+#define MSREP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t msrep_status;
+#define MSREP_OK 0
+#define MSREP_ERR_ARG (-1)         /* null pointer, negative size, np <= 0, bad enum */
+#define MSREP_ERR_FORMAT (-2)      /* structure invalid (from msrep_validate)        */
+#define MSREP_ERR_SIZE (-3)        /* nnz >= 2^31, buffer or workspace too small     */
+#define MSREP_ERR_HIP (-4)         /* a HIP runtime call failed                      */
+#define MSREP_ERR_BUDGET (-5)      /* a serving request can never fit the budget     */
+#define MSREP_ERR_BUSY (-6)        /* serving queue full                             */
+#define MSREP_ERR_UNSUPPORTED (-7) /* combination not implemented                    */
+
+/* Text of the last failure on this thread ("" after a success). */
+const char *msrep_last_error(void);
+
+/* ------------------------------------------------------------ matrices */
+/* Storage formats of Sec. 2.1: CSR, CSC (the CSR of the transpose) and COO
+ * sorted by row (the order Sec. 3.2.3 assumes for pCOO). */
+enum { MSREP_CSR = 0, MSREP_CSC = 1, MSREP_COO = 2 };
+
+/* Stored value type.  F64 values use FP64 x and y and FP64 arithmetic.  F32
+ * and BF16 values use FP32 x and y, FP32 products and in-chunk sums, and FP64
+ * for sums carried across chunks and partitions (the boundary merge). */
+enum { MSREP_F64 = 0, MSREP_F32 = 1, MSREP_BF16 = 2 };
+
+typedef struct msrep_mat {
+  int32_t fmt;   /* MSREP_CSR / MSREP_CSC / MSREP_COO                          */
+  int32_t vtype; /* MSREP_F64 / MSREP_F32 / MSREP_BF16                          */
+  int32_t m, n;  /* rows, columns                                               */
+  int64_t nnz;   /* number of stored nonzeros                                   */
+  const int32_t *ptr;  /* CSR row_ptr[m+1] | CSC col_ptr[n+1] | COO: NULL      */
+  const int32_t *idx;  /* CSR col_idx | CSC row_idx | COO row_idx (sorted)     */
+  const int32_t *idx2; /* COO col_idx | otherwise NULL                          */
+  const void *val;     /* nnz values of vtype (BF16: raw 16-bit patterns)       */
+} msrep_mat;
+
+/* Bytes of one stored value of vtype, 0 for an unknown vtype. */
+int32_t msrep_vtype_bytes(int32_t vtype);
+
+/* O(nnz) structure check on the GPU: pointer starts at 0, is non-decreasing
+ * and ends at nnz; indices in range; COO row indices non-decreasing.
+ * Returns MSREP_OK or MSREP_ERR_FORMAT (with the first offence described).
+ * Synchronises the stream. */
+msrep_status msrep_validate(const msrep_mat *A, void *stream);
+
+/* ----------------------------------------------------------- partitions */
+/*
+ * One partition of pCSR / pCSC / pCOO (Sec. 3.2.1-3.2.3): the nonzeros
+ * start_idx .. end_idx (inclusive) of the matrix's storage order.  For CSC
+ * the *_row fields hold columns.
+ *   start_idx = floor(i*nnz/np), end_idx = floor((i+1)*nnz/np) - 1
+ *     (Algorithm 2, partitions numbered from 0, products in 64-bit);
+ *   start_row / end_row = the row containing start_idx / end_idx (largest r
+ *     with ptr[r] <= k);
+ *   start_flag = the first row began in an earlier partition (Algorithm 2);
+ *   end_flag   = the last row continues into a later partition (the paper
+ *     infers this from the next partition; it is stored for the kernels);
+ *   lptr_off   = where this partition's local pointer starts in the lptr
+ *     array: start_row + 2*i (0 for pCOO, which has none).
+ * Local pointer: R = end_row - start_row + 1 rows, R + 1 entries
+ *   lptr[lptr_off + j] = clamp(ptr[start_row + j], start_idx, end_idx + 1)
+ *                        - start_idx,  j = 0..R
+ * (the paper's local row_ptr with both ends made explicit).  An empty
+ * partition (np > nnz) has end_idx = start_idx - 1, start_row = the row of
+ * start_idx (or m if start_idx == nnz), end_row = start_row - 1, both flags 0
+ * and the single entry lptr[lptr_off] = 0.
+ */
+typedef struct msrep_part {
+  int64_t start_idx, end_idx;
+  int32_t start_row, end_row;
+  int32_t start_flag, end_flag;
+  int64_t lptr_off;
+} msrep_part;
+
+/* Entries the lptr array needs for a pCSR (rows = m) or pCSC (rows = n) of np
+ * partitions: rows + 2*np.  -1 if an argument is negative or np <= 0. */
+int64_t msrep_lptr_bound(int32_t rows, int32_t np);
+
+/*
+ * Build np equal-nnz partitions of A on the GPU (Algorithms 2, 4, 6; the
+ * local pointers are computed by a device kernel as in the paper's optimised
+ * variant, Sec. 4.1).  O(np * log(m) + m) work, every partition independent.
+ *   parts_d   : np msrep_part, written.
+ *   lptr_d    : lptr_cap int32, written at each partition's entries (gaps
+ *               between partitions are left untouched); may be NULL with
+ *               lptr_cap 0 for COO.  lptr_cap must be >= msrep_lptr_bound.
+ *   lptr_len_d: optional (device int64), receives one past the last entry.
+ * COO must be sorted by row; row indices are read at 2*np positions only.
+ */
+msrep_status msrep_build_partition(const msrep_mat *A, int32_t np,
+                                   msrep_part *parts_d, int32_t *lptr_d,
+                                   int64_t lptr_cap, int64_t *lptr_len_d,
+                                   void *stream);
+
+/* ---------------------------------------------------------- conversion */
+/* Workspace bytes msrep_convert needs to turn src into format dst_fmt. */
+size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt);
+
+/*
+ * Convert between CSR, CSC and row-sorted COO (Sec. 2.1; CSC(A) = CSR(A^T)).
+ * dst->fmt selects the target; dst->m, n, nnz, vtype must equal src's and its
+ * arrays must be allocated (CSR: ptr m+1, idx nnz; CSC: ptr n+1, idx nnz; COO:
+ * idx nnz, idx2 nnz; val nnz).  Values are moved, never rounded.  Conversions
+ * are stable: entries that tie on the new major index keep their storage
+ * order, so canonical input (sorted minor indices, no duplicates) gives the
+ * unique canonical output.  ws_d: msrep_convert_ws_bytes bytes of device
+ * memory.
+ */
+msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,
+                           size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------- SpMV */
+/* Launch shape.  A zeroed struct (or NULL) selects the defaults. */
+typedef struct msrep_tune {
+  int32_t k_per_lane;   /* nonzeros per lane per chunk: 4 (default) or 8       */
+  int32_t waves_per_wg; /* wavefronts per workgroup, 1..8 (default 4); each    */
+                        /* wavefront owns one partition                        */
+  int32_t rows_per_wave;/* 0: segmented-scan kernel (any row lengths);         */
+                        /* 1..64: row-group kernel, 64/rows_per_wave lanes per */
+                        /* row (CSR only; for short, even rows)                */
+  int32_t nnz_per_wave; /* partition size the autotuner recommends, so that    */
+                        /* np = ceil(nnz / nnz_per_wave); not read by msrep_spmv */
+} msrep_tune;
+
+/* Workspace bytes msrep_spmv needs for np partitions (16*np: two FP64 partial
+ * sums per partition for the boundary merge). */
+size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
+
+/*
+ * y = alpha*A*x + beta*y over the np partitions built by msrep_build_partition
+ * (Algorithms 3, 5, 7).  One wavefront streams each partition's nonzeros;
+ * rows inside a partition are written directly; a row split between
+ * partitions is merged by summing its partial sums in partition order with a
+ * compensated FP64 sum and applying beta once; rows covered by no partition
+ * get beta*y.  CSC scatters into y with atomics (after y <- beta*y), as the
+ * paper's column-based merge sums partial vectors; its summation order is
+ * not deterministic.  CSR and COO results are deterministic for a given np
+ * and tune.
+ *   x_d: n values, y_d: m values (FP64 for F64 matrices, FP32 otherwise).
+ *   beta == 0: y is not read.
+ *   ws_d: msrep_spmv_ws_bytes(A, np) bytes.
+ */
+msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
+                        const int32_t *lptr_d, int32_t np, const void *x_d,
+                        void *y_d, double alpha, double beta,
+                        const msrep_tune *tune, void *ws_d, size_t ws_bytes,
+                        void *stream);
+
+/* Launch shape and partition size the autotuner picks for A by timing the
+ * candidates on the stream (synchronises; uses ws_d of at least
+ * msrep_autotune_ws_bytes(A) bytes for partitions and scratch output). */
+size_t msrep_autotune_ws_bytes(const msrep_mat *A);
+msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void *ws_d,
+                            size_t ws_bytes, msrep_tune *out, void *stream);
+
+/* ------------------------------------------------------------- batched */
+/*
+ * A plan runs y_k = alpha*A_k*x_k + beta*y_k for count matrices in one
+ * persistent launch captured in a hipGraph.  Each matrix is split into its
+ * own equal-nnz partitions (np_k = ceil(nnz_k / tune_k.nnz_per_wave)); all
+ * partitions go into one work list that resident wavefronts drain, followed
+ * by one boundary-merge launch.  The plan keeps the partitions, the work list
+ * and the descriptors in ws_d (caller memory, msrep_plan_ws_bytes bytes),
+ * which must stay allocated until msrep_plan_destroy.  All matrices must
+ * share one value type.  tunes may be NULL (defaults per matrix).
+ */
+typedef struct msrep_plan_s *msrep_plan;
+
+size_t msrep_plan_ws_bytes(int32_t count, const msrep_mat *mats,
+                           const msrep_tune *tunes);
+msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
+                               const msrep_tune *tunes, double alpha,
+                               double beta, void *ws_d, size_t ws_bytes,
+                               void *stream, msrep_plan *out);
+/* x_ptrs / y_ptrs: host arrays of count device pointers (x_k: n_k values, y_k:
+ * m_k values).  Stream-ordered; the pointer arrays are copied before return. */
+msrep_status msrep_spmv_batched(msrep_plan plan, const void *const *x_ptrs,
+                                void *const *y_ptrs, void *stream);
+/* Work items in the plan (partitions over all matrices). */
+int64_t msrep_plan_items(msrep_plan plan);
+msrep_status msrep_plan_destroy(msrep_plan plan);
+
+/* --------------------------------------------------------------- serving */
+/*
+ * Continuous-batching server for the iterative-solver pattern: a request is
+ * a matrix of a host pool plus `steps` SpMVs y_j = A*x_j against fresh x_j.
+ * Matrices are uploaded into the caller's arena when the request is admitted
+ * (admission is by bytes: matrix + partitions + vectors must fit in what the
+ * arena has free) and stay resident while the request runs.  Every tick
+ * executes one step of every active request in one batched launch, so
+ * requests that arrive while others run join the next tick.
+ *   x_j[c] = 2*u - 1 with u the top 53 bits of splitmix64(key) / 2^53,
+ *   key = seed ^ (rid << 40) ^ ((uint64)j << 24) ^ c (rid < 2^24, j < 2^16)
+ *   (SplitMix64: Steele, Lea and Flood 2014), rounded to FP32 for F32 pools.
+ * Latency of a request = its arrival (trace time) to the completion on the
+ * device of its last step.  msrep_serve synchronises and returns when the
+ * whole trace has drained.
+ */
+typedef struct msrep_host_mat {
+  msrep_mat A;   /* CSR; ptr/idx/val are HOST pointers (pinned preferred)     */
+  int32_t np;    /* partitions for this matrix (0: nnz_per_wave of the cfg)   */
+  int32_t _pad;
+} msrep_host_mat;
+
+typedef struct msrep_serve_cfg {
+  void *arena_d;        /* device memory the server allocates from           */
+  size_t budget_bytes;  /* bytes of arena_d it may use                        */
+  int32_t max_slots;    /* most requests active at once (1..4096)            */
+  int32_t nnz_per_wave; /* partition size when a pool matrix has np == 0     */
+  uint64_t seed;        /* x generator seed                                   */
+  double time_scale;    /* trace seconds per wall second (1 = real time)     */
+  int32_t keep_y;       /* 1: copy every request's last y into results       */
+  int32_t _pad;
+} msrep_serve_cfg;
+
+typedef struct msrep_request {
+  int64_t rid;        /* < 2^24                                              */
+  double t_arrive;    /* seconds from the start of the trace                 */
+  int32_t matrix;     /* index into the pool                                 */
+  int32_t steps;      /* SpMVs, 1 .. 65535                                   */
+} msrep_request;
+
+typedef struct msrep_result {
+  double t_arrive, t_admit, t_done; /* seconds on the trace clock            */
+  int32_t status;                   /* MSREP_OK or an error                  */
+  int32_t _pad;
+  void *y_host;      /* keep_y: caller-provided host buffer of m values (set */
+                     /* by the caller before the call, may be NULL)           */
+} msrep_result;
+
+typedef struct msrep_serve_stats {
+  double p50_ms, p99_ms, mean_ms, max_ms; /* latency                          */
+  double req_per_s, spmv_per_s;           /* over the makespan                */
+  double makespan_s;
+  double gflops;                          /* 2*nnz per SpMV over the makespan */
+  int64_t n_done, n_failed, ticks;
+  int64_t peak_bytes;                     /* most arena bytes in use          */
+  int32_t peak_active;                    /* most requests active at once     */
+  int32_t _pad;
+} msrep_serve_stats;
+
+msrep_status msrep_serve(const msrep_serve_cfg *cfg,
+                         const msrep_host_mat *pool, int32_t pool_size,
+                         const msrep_request *trace, int64_t n_req,
+                         msrep_result *results, msrep_serve_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSREP_H */

@@ -1,0 +1,131 @@
+// Internal helpers shared by the libmsrep translation units: status/error
+// plumbing for the C ABI, argument checks, and small CDNA wave64 device
+// utilities.  Nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "msrep.h"
+
+namespace msrep {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
+
+// ------------------------------------------------------------ host side
+std::string &last_error();
+msrep_status fail(msrep_status code, const char *fmt, ...);
+inline msrep_status ok() {
+  last_error().clear();
+  return MSREP_OK;
+}
+
+#define MSREP_HIP(call)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return ::msrep::fail(MSREP_ERR_HIP, "%s failed: %s", #call,         \
+                           hipGetErrorString(e_));                        \
+  } while (0)
+
+#define MSREP_LAUNCHED(what)                                              \
+  do {                                                                    \
+    hipError_t e_ = hipGetLastError();                                    \
+    if (e_ != hipSuccess)                                                 \
+      return ::msrep::fail(MSREP_ERR_HIP, "launch of %s failed: %s", what,\
+                           hipGetErrorString(e_));                        \
+  } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// O(1) descriptor checks shared by every entry point.
+msrep_status check_mat(const msrep_mat *A, const char *who);
+int value_bytes(int32_t vtype);
+// x / y element size for a matrix of this value type.
+inline int vec_bytes(int32_t vtype) { return vtype == MSREP_F64 ? 8 : 4; }
+// Rows of the compressed dimension (CSR: m, CSC: n) and of the result (m).
+inline int32_t major_dim(const msrep_mat *A) { return A->fmt == MSREP_CSC ? A->n : A->m; }
+
+__host__ __device__ constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------- device side
+// Block index remapped so that each XCD (blocks are dealt to the 8 XCDs
+// round-robin by id) receives one contiguous run of logical blocks: its L2
+// then sees a contiguous slice of the matrix and of y.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int q = nblocks / kXcds, r = nblocks % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Keep the compiler from moving LDS accesses of one wavefront across this
+// point; a single wavefront's LDS operations execute in program order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T uniform(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "uniform: 4 or 8 bytes");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+  } else {
+    const int64_t u = __builtin_bit_cast(int64_t, v);
+    const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(u));
+    const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(u >> 32));
+    return __builtin_bit_cast(T, (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+  }
+}
+
+// Value of lane `src` (wave-uniform) broadcast to all lanes.
+__device__ __forceinline__ int read_lane(int v, int src) {
+  return __builtin_amdgcn_readlane(v, src);
+}
+
+// Shift up by d lanes within the wavefront (lanes below d get their own value).
+__device__ __forceinline__ int shfl_up_i(int v, int d) {
+  const int l = lane_id();
+  const int src = l >= d ? l - d : l;
+  return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+__device__ __forceinline__ float shfl_up_f(float v, int d) {
+  return __builtin_bit_cast(float, shfl_up_i(__builtin_bit_cast(int, v), d));
+}
+__device__ __forceinline__ double shfl_up_d(double v, int d) {
+  const int64_t u = __builtin_bit_cast(int64_t, v);
+  const int lo = shfl_up_i(static_cast<int>(u), d);
+  const int hi = shfl_up_i(static_cast<int>(u >> 32), d);
+  return __builtin_bit_cast(double, (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+template <typename A>
+__device__ __forceinline__ A shfl_up(A v, int d);
+template <>
+__device__ __forceinline__ float shfl_up<float>(float v, int d) { return shfl_up_f(v, d); }
+template <>
+__device__ __forceinline__ double shfl_up<double>(double v, int d) { return shfl_up_d(v, d); }
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
+}
+
+// Knuth's TwoSum on the device (the compensated boundary merge).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  const double x = a + b;
+  const double z = x - a;
+  e = (a - (x - z)) + (b - z);
+  s = x;
+}
+
+}  // namespace msrep

@@ -1,0 +1,232 @@
+// msrep_spmv: dispatch of the per-format SpMV kernels and of the boundary
+// merge, plus the shared C-ABI helpers (errors, descriptor checks).
+#include <mutex>
+
+#include "common.hpp"
+#include "spmv_coo.hpp"
+#include "spmv_csc.hpp"
+#include "spmv_csr.hpp"
+
+namespace msrep {
+
+std::string &last_error() {
+  static thread_local std::string e;
+  return e;
+}
+
+msrep_status fail(msrep_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  last_error() = buf;
+  return code;
+}
+
+int value_bytes(int32_t vtype) {
+  switch (vtype) {
+    case MSREP_F64: return 8;
+    case MSREP_F32: return 4;
+    case MSREP_BF16: return 2;
+    default: return 0;
+  }
+}
+
+msrep_status check_mat(const msrep_mat *A, const char *who) {
+  if (!A) return fail(MSREP_ERR_ARG, "%s: matrix descriptor is NULL", who);
+  if (A->fmt < MSREP_CSR || A->fmt > MSREP_COO)
+    return fail(MSREP_ERR_ARG, "%s: unknown format %d", who, A->fmt);
+  if (!value_bytes(A->vtype)) return fail(MSREP_ERR_ARG, "%s: unknown value type %d", who, A->vtype);
+  if (A->m < 0 || A->n < 0 || A->nnz < 0)
+    return fail(MSREP_ERR_ARG, "%s: negative size (m=%d n=%d nnz=%lld)", who, A->m, A->n,
+                static_cast<long long>(A->nnz));
+  if (A->nnz >= (int64_t(1) << 31))
+    return fail(MSREP_ERR_SIZE, "%s: nnz=%lld does not fit int32 indices", who,
+                static_cast<long long>(A->nnz));
+  if (A->nnz > 0 && (A->m == 0 || A->n == 0))
+    return fail(MSREP_ERR_ARG, "%s: nonzeros in a matrix with no rows or columns", who);
+  if (A->fmt != MSREP_COO && !A->ptr) return fail(MSREP_ERR_ARG, "%s: ptr is NULL", who);
+  if (A->nnz > 0 && (!A->idx || !A->val)) return fail(MSREP_ERR_ARG, "%s: idx/val is NULL", who);
+  if (A->fmt == MSREP_COO && A->nnz > 0 && !A->idx2)
+    return fail(MSREP_ERR_ARG, "%s: COO col_idx (idx2) is NULL", who);
+  return MSREP_OK;
+}
+
+namespace {
+
+template <int VT, int K, bool B0>
+msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                        int32_t np, const void *x, void *y, double alpha, double beta, int wpb,
+                        double *carry, hipStream_t s) {
+  using Tr = vt_traits<VT>;
+  const size_t lds = seg_lds_per_wave<VT, K>() * wpb;
+  const int grid = (np + wpb - 1) / wpb;
+  hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
+                     static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
+                     static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
+                     A->m, A->n, alpha, beta, carry);
+  MSREP_LAUNCHED("spmv_csr_seg");
+  return MSREP_OK;
+}
+
+template <int VT, int K, bool B0>
+msrep_status launch_coo(const msrep_mat *A, const msrep_part *parts, int32_t np, const void *x,
+                        void *y, double alpha, double beta, int wpb, double *carry,
+                        hipStream_t s) {
+  using Tr = vt_traits<VT>;
+  const size_t lds = coo_lds_per_wave<VT, K>() * wpb;
+  const int grid = (np + wpb - 1) / wpb;
+  hipLaunchKernelGGL((spmv_coo_seg<VT, K, B0>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
+                     A->idx2, static_cast<const typename Tr::V *>(A->val), A->nnz, parts, np,
+                     static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
+                     A->m, A->n, alpha, beta, carry);
+  MSREP_LAUNCHED("spmv_coo_seg");
+  return MSREP_OK;
+}
+
+template <int VT, int K>
+msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                        int32_t np, const void *x, void *y, double alpha, double beta, int wpb,
+                        void *ws, hipStream_t s) {
+  using Tr = vt_traits<VT>;
+  using T = typename Tr::T;
+  // column-based merge: FP64 scatters into y after y <- beta*y; FP32/BF16
+  // scatter into a zeroed FP64 workspace that finish_y rounds into y once
+  const int g = static_cast<int>((A->m + 255) / 256 < 16384 ? (A->m + 255) / 256 : 16384);
+  const size_t lds = csc_lds_per_wave<K>() * wpb;
+  const int grid = (np + wpb - 1) / wpb;
+  if constexpr (VT == MSREP_F64) {
+    hipLaunchKernelGGL((scale_y<T>), dim3(g), dim3(256), 0, s, static_cast<T *>(y), A->m, beta);
+    MSREP_LAUNCHED("scale_y");
+    hipLaunchKernelGGL((spmv_csc_scatter<VT, K, double>), dim3(grid), dim3(wpb * kWave), lds, s,
+                       A->ptr, A->idx, static_cast<const typename Tr::V *>(A->val), parts, lptr,
+                       np, static_cast<const T *>(x), static_cast<double *>(y), A->m, A->n, alpha);
+    MSREP_LAUNCHED("spmv_csc_scatter");
+  } else {
+    double *acc = static_cast<double *>(ws);
+    hipLaunchKernelGGL(zero_f64, dim3(g), dim3(256), 0, s, acc, static_cast<int64_t>(A->m));
+    MSREP_LAUNCHED("zero_f64");
+    hipLaunchKernelGGL((spmv_csc_scatter<VT, K, double>), dim3(grid), dim3(wpb * kWave), lds, s,
+                       A->ptr, A->idx, static_cast<const typename Tr::V *>(A->val), parts, lptr,
+                       np, static_cast<const T *>(x), acc, A->m, A->n, alpha);
+    MSREP_LAUNCHED("spmv_csc_scatter");
+    hipLaunchKernelGGL((finish_y<T>), dim3(g), dim3(256), 0, s, static_cast<T *>(y), acc, A->m,
+                       alpha, beta);
+    MSREP_LAUNCHED("finish_y");
+  }
+  return MSREP_OK;
+}
+
+template <int VT, int K, bool B0>
+msrep_status dispatch_rows(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                           int32_t np, const void *x, void *y, double alpha, double beta,
+                           int wpb, double *carry, hipStream_t s) {
+  if (A->fmt == MSREP_CSR)
+    return launch_csr<VT, K, B0>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+  return launch_coo<VT, K, B0>(A, parts, np, x, y, alpha, beta, wpb, carry, s);
+}
+
+template <int VT>
+msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                         int32_t np, const void *x, void *y, double alpha, double beta, int K,
+                         int wpb, double *carry, hipStream_t s) {
+  using T = typename vt_traits<VT>::T;
+  const bool b0 = beta == 0.0;
+  msrep_status st;
+  if (A->fmt == MSREP_CSC) {
+    return K == 8 ? launch_csc<VT, 8>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
+                  : launch_csc<VT, 4>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+  }
+  if (K == 8)
+    st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
+            : dispatch_rows<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+  else
+    st = b0 ? dispatch_rows<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
+            : dispatch_rows<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+  if (st) return st;
+  if (np > 1) {
+    const int g = (np + 255) / 256;
+    if (b0)
+      hipLaunchKernelGGL((merge_rows<T, true>), dim3(g), dim3(256), 0, s, parts, np, carry,
+                         static_cast<T *>(y), A->m, alpha, beta);
+    else
+      hipLaunchKernelGGL((merge_rows<T, false>), dim3(g), dim3(256), 0, s, parts, np, carry,
+                         static_cast<T *>(y), A->m, alpha, beta);
+    MSREP_LAUNCHED("merge_rows");
+  }
+  return MSREP_OK;
+}
+
+}  // namespace
+
+msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, const char *who) {
+  *K = 4;
+  *wpb = 4;
+  if (!tune) return MSREP_OK;
+  if (tune->k_per_lane != 0 && tune->k_per_lane != 4 && tune->k_per_lane != 8)
+    return fail(MSREP_ERR_ARG, "%s: k_per_lane must be 4 or 8 (got %d)", who, tune->k_per_lane);
+  if (tune->waves_per_wg < 0 || tune->waves_per_wg > 8)
+    return fail(MSREP_ERR_ARG, "%s: waves_per_wg must be 1..8 (got %d)", who, tune->waves_per_wg);
+  if (tune->rows_per_wave < 0 || tune->rows_per_wave > 64)
+    return fail(MSREP_ERR_ARG, "%s: rows_per_wave must be 0..64", who);
+  if (tune->k_per_lane) *K = tune->k_per_lane;
+  if (tune->waves_per_wg) *wpb = tune->waves_per_wg;
+  return MSREP_OK;
+}
+
+msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                         int32_t np, const void *x, void *y, double alpha, double beta, int K,
+                         int wpb, double *carry, hipStream_t s) {
+  switch (A->vtype) {
+    case MSREP_F64:
+      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, carry, s);
+    case MSREP_F32:
+      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, carry, s);
+    default:
+      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, carry, s);
+  }
+}
+
+}  // namespace msrep
+
+using namespace msrep;
+
+extern "C" const char *msrep_last_error(void) { return last_error().c_str(); }
+
+extern "C" int32_t msrep_vtype_bytes(int32_t vtype) { return value_bytes(vtype); }
+
+extern "C" size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np) {
+  if (!A || np <= 0 || A->m < 0) return 0;
+  size_t need = align_up(16 * static_cast<size_t>(np), 256);
+  if (A->fmt == MSREP_CSC && A->vtype != MSREP_F64) {
+    const size_t acc = align_up(8 * static_cast<size_t>(A->m), 256);
+    need = acc > need ? acc : need;
+  }
+  return need;
+}
+
+extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
+                                   const int32_t *lptr_d, int32_t np, const void *x_d, void *y_d,
+                                   double alpha, double beta, const msrep_tune *tune, void *ws_d,
+                                   size_t ws_bytes, void *stream) {
+  if (msrep_status st = check_mat(A, "msrep_spmv")) return st;
+  if (np <= 0) return fail(MSREP_ERR_ARG, "msrep_spmv: np must be positive (got %d)", np);
+  if (!parts_d) return fail(MSREP_ERR_ARG, "msrep_spmv: parts_d is NULL");
+  if (A->fmt != MSREP_COO && !lptr_d) return fail(MSREP_ERR_ARG, "msrep_spmv: lptr_d is NULL");
+  if (A->m > 0 && !y_d) return fail(MSREP_ERR_ARG, "msrep_spmv: y_d is NULL");
+  if (A->nnz > 0 && !x_d) return fail(MSREP_ERR_ARG, "msrep_spmv: x_d is NULL");
+  int K, wpb;
+  if (msrep_status st = resolve_tune(tune, &K, &wpb, "msrep_spmv")) return st;
+  if (tune && tune->rows_per_wave > 0 && A->fmt != MSREP_CSR)
+    return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: rows_per_wave kernel is CSR only");
+  const size_t need = msrep_spmv_ws_bytes(A, np);
+  if (!ws_d || ws_bytes < need)
+    return fail(MSREP_ERR_SIZE, "msrep_spmv: workspace of %zu bytes needed (got %zu)", need,
+                ws_d ? ws_bytes : size_t(0));
+  if (A->m == 0) return ok();
+  if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb,
+                                    static_cast<double *>(ws_d), as_stream(stream)))
+    return st;
+  return ok();
+}

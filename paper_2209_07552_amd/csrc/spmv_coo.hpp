@@ -1,0 +1,172 @@
+// Wave-per-partition segmented SpMV on row-sorted COO (pCOO, msRep
+// Algorithm 7).  Same chunking as the CSR kernel, but the row of every
+// nonzero is stored, so segment boundaries come straight from comparing
+// neighbouring row indices: no local pointer and no search.  The lane that
+// holds a segment's last nonzero writes the row's y (or its partial sum to
+// the carry buffer for a row split across partitions), and the lane holding
+// a segment's first nonzero writes beta*y for the empty rows between it and
+// the previous segment.
+#pragma once
+
+#include "spmv_csr.hpp"
+
+namespace msrep {
+
+template <int VT, int K>
+constexpr size_t coo_lds_per_wave() {
+  return 16;  // one FP64 slot: the sum carried into the next chunk
+}
+
+template <int VT, int K, bool BETA0>
+__global__ __launch_bounds__(512) void spmv_coo_seg(
+    const int32_t *__restrict__ row_idx, const int32_t *__restrict__ col,
+    const typename vt_traits<VT>::V *__restrict__ val, int64_t nnz,
+    const msrep_part *__restrict__ parts, int32_t np,
+    const typename vt_traits<VT>::T *__restrict__ x, typename vt_traits<VT>::T *__restrict__ y,
+    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
+  using Tr = vt_traits<VT>;
+  using V = typename Tr::V;
+  using T = typename Tr::T;
+  using Acc = typename Tr::A;
+  constexpr int CH = kWave * K;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
+  if (p >= np) return;
+  double *s_carry = reinterpret_cast<double *>(lds_raw + wid * coo_lds_per_wave<VT, K>());
+
+  const msrep_part *pp = parts + p;
+  const int64_t s0 = uniform(pp->start_idx);
+  const int64_t e0 = uniform(pp->end_idx);
+  const int32_t r0 = uniform(pp->start_row);
+  const int32_t rE = uniform(pp->end_row);
+  const int32_t sflag = uniform(pp->start_flag);
+  const int32_t eflag = uniform(pp->end_flag);
+  const int32_t nloc = static_cast<int32_t>(e0 - s0 + 1);
+
+  double carry_v = 0.0;  // partial sum of the row continuing from the last chunk
+  bool carry_on = false;
+  const int32_t lead = static_cast<int32_t>(s0 % K);
+  for (int32_t cb = -lead; cb < nloc; cb += CH) {
+    const int32_t cs = cb > 0 ? cb : 0;
+    const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
+    const int32_t q0 = cb + lane * K;
+    int32_t row[K];
+    Acc prod[K];
+    if (q0 >= 0 && q0 + K <= nloc) {
+      int32_t c[K];
+      V v[K];
+      load_vec<int32_t, K>(row_idx + s0 + q0, row);
+      load_vec<int32_t, K>(col + s0 + q0, c);
+      load_vec<V, K>(val + s0 + q0, v);
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const bool okc = static_cast<uint32_t>(c[t]) < static_cast<uint32_t>(n);
+        const T xv = okc ? x[c[t]] : T(0);
+        prod[t] = Tr::val(v[t]) * static_cast<Acc>(xv);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const int32_t q = q0 + t;
+        prod[t] = Acc(0);
+        row[t] = q < 0 ? r0 : rE;  // masked items join the first / last segment
+        if (q >= 0 && q < nloc) {
+          row[t] = row_idx[s0 + q];
+          const int32_t c = col[s0 + q];
+          if (static_cast<uint32_t>(c) < static_cast<uint32_t>(n))
+            prod[t] = Tr::val(val[s0 + q]) * static_cast<Acc>(x[c]);
+        }
+      }
+    }
+    // previous / next row of every item
+    const int32_t up = shfl_up_i(row[K - 1], 1);
+    // row of the nonzero just before the chunk (partition start: none)
+    const int32_t before = cs > 0 ? row_idx[s0 + cs - 1] : -1;
+    const int32_t prev0 = lane == 0 ? before : up;
+    const int32_t dn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, row[0]);
+    // ---- segmented scan (heads where the row changes inside the chunk)
+    bool head[K];
+    Acc run[K];
+    Acc r = Acc(0);
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int32_t q = q0 + t;
+      const int32_t pr = t == 0 ? prev0 : row[t - 1];
+      head[t] = q > cs && q < ce && row[t] != pr;
+      if (head[t]) {
+        r = Acc(0);
+        any = true;
+      }
+      r += prod[t];
+      run[t] = r;
+    }
+    Acc agg = r;
+    int flg = any ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const Acc va = shfl_up<Acc>(agg, d);
+      const int fa = shfl_up_i(flg, d);
+      if (lane >= d) {
+        if (!flg) agg += va;
+        flg |= fa;
+      }
+    }
+    Acc cin = shfl_up<Acc>(agg, 1);
+    int fin = shfl_up_i(flg, 1);
+    if (lane == 0) {
+      cin = Acc(0);
+      fin = 0;
+    }
+    // continuing into the next chunk?
+    const int32_t after = ce < nloc ? row_idx[s0 + ce] : -1;
+    // items before the lane's first head continue the segment of earlier
+    // lanes (cin); only the chunk's first segment continues the carried row
+    bool seen = false;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int32_t q = q0 + t;
+      seen = seen || head[t];
+      const bool first_seg = !seen && fin == 0;
+      const double tot = static_cast<double>(seen ? run[t] : run[t] + cin) +
+                         ((first_seg && carry_on) ? carry_v : 0.0);
+      if (q < cs || q >= ce) continue;
+      const int32_t rr = row[t];
+      const int32_t pr = t == 0 ? prev0 : row[t - 1];
+      // empty rows between the previous nonzero's row and this one
+      if ((q > 0) && rr > pr + 1) {
+        const int32_t lo = pr + 1 > 0 ? pr + 1 : 0, hi = rr < m ? rr : m;
+        for (int32_t g = lo; g < hi; ++g)
+          y[g] = BETA0 ? T(0) : static_cast<T>(beta * static_cast<double>(y[g]));
+      }
+      const int32_t nx = t + 1 < K ? row[t + 1] : dn;
+      const bool end = q == ce - 1 || rr != nx;
+      if (!end) continue;
+      if (q == ce - 1 && after == rr) {
+        *s_carry = tot;  // open row: carried into the next chunk
+      } else if (rr == r0 && sflag) {
+        carry[2 * static_cast<int64_t>(p)] = tot;
+      } else if (rr == rE && eflag) {
+        carry[2 * static_cast<int64_t>(p) + 1] = tot;
+      } else if (static_cast<uint32_t>(rr) < static_cast<uint32_t>(m)) {
+        store_y<T>(y, rr, tot, alpha, beta, BETA0);
+      }
+    }
+    wave_lds_sync();
+    const int32_t last_row = row_idx[s0 + ce - 1];
+    carry_on = after == last_row && ce < nloc;
+    carry_v = carry_on ? *s_carry : 0.0;
+    wave_lds_sync();
+  }
+  const int32_t gap_lo = nloc > 0 ? rE + 1 : r0;
+  const int32_t gap_hi_raw = p + 1 < np ? uniform(parts[p + 1].start_row) : m;
+  const int32_t gap_hi = gap_hi_raw < m ? gap_hi_raw : m;
+  if (!eflag) scale_rows<T>(y, gap_lo > 0 ? gap_lo : 0, gap_hi, beta, BETA0);
+  if (p == 0) scale_rows<T>(y, 0, r0 < m ? r0 : m, beta, BETA0);
+}
+
+}  // namespace msrep

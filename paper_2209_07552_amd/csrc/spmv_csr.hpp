@@ -1,0 +1,290 @@
+// Wave-per-partition CSR SpMV (pCSR, msRep Algorithm 3) for CDNA wave64.
+//
+// Each wavefront owns one equal-nnz partition and streams its nonzeros in
+// chunks of 64*K (K per lane, thread-contiguous, vector loads aligned to K).
+// For every chunk:
+//   1. products val*x[col] in registers;
+//   2. rows of the chunk come from the partition's local pointer: every row
+//      that starts inside the chunk marks its first position in a per-wave
+//      LDS byte array (head flags);
+//   3. a segmented inclusive scan of the products (sequential over the K
+//      items of a lane, then a 6-step Hillis-Steele scan across lanes) is
+//      stored in LDS, so a row's in-chunk sum is the scan value at its last
+//      position;
+//   4. lanes take rows and write y coalesced; the row still open at the end
+//      of the chunk is carried (in FP64 for FP32 values) into the next chunk.
+// Rows wholly inside the partition are written directly.  The partition's
+// first row when start_flag is set (head) and its last row when end_flag is
+// set (tail) are partial: their sums go to the carry buffer and the boundary
+// merge kernel completes them.  Empty rows between this partition and the
+// next one (and, for the first partition, before it) get beta*y here.
+#pragma once
+
+#include "common.hpp"
+
+namespace msrep {
+
+template <int VT>
+struct vt_traits;
+template <>
+struct vt_traits<MSREP_F64> {
+  using V = double;  // stored value
+  using T = double;  // x, y
+  using A = double;  // in-chunk accumulation
+  __device__ static A val(V v) { return v; }
+};
+template <>
+struct vt_traits<MSREP_F32> {
+  using V = float;
+  using T = float;
+  using A = float;
+  __device__ static A val(V v) { return v; }
+};
+template <>
+struct vt_traits<MSREP_BF16> {
+  using V = uint16_t;
+  using T = float;
+  using A = float;
+  __device__ static A val(V v) { return bf16_to_f32(v); }
+};
+
+// Load K consecutive items starting at an index that is a multiple of K.
+template <typename E, int K>
+__device__ __forceinline__ void load_vec(const E *__restrict__ p, E (&out)[K]) {
+  constexpr int bytes = K * sizeof(E);
+  static_assert(bytes % 4 == 0, "vector of whole dwords");
+  if constexpr (bytes % 16 == 0) {
+    const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+#pragma unroll
+    for (int v = 0; v < bytes / 16; ++v) {
+      const u32x4 w = __builtin_nontemporal_load(q + v);
+      uint32_t *o = reinterpret_cast<uint32_t *>(out) + 4 * v;
+      o[0] = w.x;
+      o[1] = w.y;
+      o[2] = w.z;
+      o[3] = w.w;
+    }
+  } else if constexpr (bytes == 8) {
+    const u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+    uint32_t *o = reinterpret_cast<uint32_t *>(out);
+    o[0] = w.x;
+    o[1] = w.y;
+  } else {
+#pragma unroll
+    for (int t = 0; t < K; ++t) out[t] = p[t];
+  }
+}
+
+// Per-wave LDS footprint of the CSR/COO kernels.
+template <int VT, int K>
+constexpr size_t seg_lds_per_wave() {
+  return align_up(kWave * K * sizeof(typename vt_traits<VT>::A), 16) + align_up(kWave * K, 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_y(T *__restrict__ y, int32_t r, double v, double alpha,
+                                       double beta, bool beta0) {
+  const double out = beta0 ? alpha * v : alpha * v + beta * static_cast<double>(y[r]);
+  y[r] = static_cast<T>(out);
+}
+
+// Rows [lo, hi) get y = beta*y (0 when beta == 0), lanes striding.
+template <typename T>
+__device__ __forceinline__ void scale_rows(T *__restrict__ y, int32_t lo, int32_t hi, double beta,
+                                           bool beta0) {
+  for (int32_t r = lo + lane_id(); r < hi; r += kWave)
+    y[r] = beta0 ? static_cast<T>(0) : static_cast<T>(beta * static_cast<double>(y[r]));
+}
+
+template <int VT, int K, bool BETA0>
+__global__ __launch_bounds__(512) void spmv_csr_seg(
+    const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
+    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
+    const typename vt_traits<VT>::T *__restrict__ x, typename vt_traits<VT>::T *__restrict__ y,
+    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
+  using Tr = vt_traits<VT>;
+  using V = typename Tr::V;
+  using T = typename Tr::T;
+  using Acc = typename Tr::A;
+  constexpr int CH = kWave * K;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
+  if (p >= np) return;  // whole wavefront; the kernel has no block barrier
+
+  unsigned char *my = lds_raw + wid * seg_lds_per_wave<VT, K>();
+  Acc *s_sum = reinterpret_cast<Acc *>(my);
+  unsigned char *s_head = my + align_up(CH * sizeof(Acc), 16);
+
+  const msrep_part *pp = parts + p;
+  const int64_t s0 = uniform(pp->start_idx);
+  const int64_t e0 = uniform(pp->end_idx);
+  const int32_t r0 = uniform(pp->start_row);
+  const int32_t R = uniform(pp->end_row) - r0 + 1;
+  const int32_t sflag = uniform(pp->start_flag);
+  const int32_t eflag = uniform(pp->end_flag);
+  const int32_t *__restrict__ lp = lptr + uniform(pp->lptr_off);
+  const int32_t nloc = static_cast<int32_t>(e0 - s0 + 1);
+
+  double carry_v = 0.0;  // sum so far of the row continuing from earlier chunks
+  bool carry_on = false;
+  int32_t j0 = 0;         // first local row of the current chunk
+  const int32_t lead = static_cast<int32_t>(s0 % K);  // align item groups to K
+  for (int32_t cb = -lead; cb < nloc; cb += CH) {
+    const int32_t cs = cb > 0 ? cb : 0;                 // first valid local position
+    const int32_t ce = cb + CH < nloc ? cb + CH : nloc;  // one past the last
+    // ---- 1. products
+    Acc prod[K];
+    {
+      const int32_t q0 = cb + lane * K;
+      if (q0 >= 0 && q0 + K <= nloc) {
+        int32_t c[K];
+        V v[K];
+        load_vec<int32_t, K>(col + s0 + q0, c);
+        load_vec<V, K>(val + s0 + q0, v);
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const bool okc = static_cast<uint32_t>(c[t]) < static_cast<uint32_t>(n);
+          const T xv = okc ? x[c[t]] : T(0);
+          prod[t] = Tr::val(v[t]) * static_cast<Acc>(xv);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const int32_t q = q0 + t;
+          prod[t] = Acc(0);
+          if (q >= 0 && q < nloc) {
+            const int32_t c = col[s0 + q];
+            if (static_cast<uint32_t>(c) < static_cast<uint32_t>(n))
+              prod[t] = Tr::val(val[s0 + q]) * static_cast<Acc>(x[c]);
+          }
+        }
+      }
+    }
+    // ---- 2. head flags from the local pointer
+#pragma unroll
+    for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
+    wave_lds_sync();
+    int32_t jb = j0, cnt, lp_next;
+    for (;;) {
+      const int32_t j = jb + lane;
+      const int32_t v = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
+      const bool in = j <= R - 1 && v < ce;
+      if (in && j > j0) {
+        const int32_t pos = v - cb;
+        if (pos > 0 && pos < CH) s_head[pos] = 1;
+      }
+      cnt = __popcll(__ballot(in));
+      if (cnt < kWave) {
+        lp_next = read_lane(v, cnt);
+        break;
+      }
+      jb += kWave;
+    }
+    const int32_t j1 = jb + cnt - 1;  // last row starting before ce
+    const bool cont = lp_next > ce;   // row j1 continues into the next chunk
+    wave_lds_sync();
+    // ---- 3. segmented scan
+    uint32_t hb[K / 4];
+#pragma unroll
+    for (int w = 0; w < K / 4; ++w) hb[w] = reinterpret_cast<const uint32_t *>(s_head)[lane * (K / 4) + w];
+    Acc run[K];
+    Acc r = Acc(0);
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const bool h = (hb[t / 4] >> (8 * (t % 4))) & 0xffu;
+      if (h) {
+        r = Acc(0);
+        any = true;
+      }
+      r += prod[t];
+      run[t] = r;
+    }
+    Acc agg = r;
+    int flg = any ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const Acc va = shfl_up<Acc>(agg, d);
+      const int fa = shfl_up_i(flg, d);
+      if (lane >= d) {
+        if (!flg) agg += va;
+        flg |= fa;
+      }
+    }
+    Acc cin = shfl_up<Acc>(agg, 1);
+    if (lane == 0) cin = Acc(0);
+    bool seen = false;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      seen = seen || ((hb[t / 4] >> (8 * (t % 4))) & 0xffu);
+      s_sum[lane * K + t] = seen ? run[t] : run[t] + cin;
+    }
+    wave_lds_sync();
+    // ---- 4. rows j0..j1
+    const double last_tot = static_cast<double>(s_sum[ce - 1 - cb]);
+    for (int32_t jr = j0; jr <= j1; jr += kWave) {
+      const int32_t j = jr + lane;
+      if (j >= 0 && j <= j1) {
+        const int32_t a = lp[j], b = lp[j + 1];
+        const int32_t aa = a > cs ? a : cs, bb = b < ce ? b : ce;
+        double tot = bb > aa ? static_cast<double>(s_sum[bb - 1 - cb]) : 0.0;
+        if (j == j0 && carry_on) tot += carry_v;
+        if (!(j == j1 && cont)) {
+          if (j == 0 && sflag)
+            carry[2 * static_cast<int64_t>(p)] = tot;
+          else if (j == R - 1 && eflag)
+            carry[2 * static_cast<int64_t>(p) + 1] = tot;
+          else if (static_cast<uint32_t>(r0 + j) < static_cast<uint32_t>(m))
+            store_y<T>(y, r0 + j, tot, alpha, beta, BETA0);
+        }
+      }
+    }
+    carry_v = cont ? last_tot + ((j1 == j0 && carry_on) ? carry_v : 0.0) : 0.0;
+    carry_on = cont;
+    j0 = cont ? j1 : j1 + 1;
+    wave_lds_sync();  // s_sum / s_head are rewritten by the next chunk
+  }
+  // ---- empty rows after this partition up to the next one's first row
+  const int32_t gap_lo = r0 + R;  // R == 0 for an empty partition
+  const int32_t gap_hi_raw = p + 1 < np ? uniform(parts[p + 1].start_row) : m;
+  const int32_t gap_hi = gap_hi_raw < m ? gap_hi_raw : m;
+  if (!eflag) scale_rows<T>(y, gap_lo > 0 ? gap_lo : 0, gap_hi, beta, BETA0);
+  if (p == 0) scale_rows<T>(y, 0, r0 < m ? r0 : m, beta, BETA0);
+}
+
+// Boundary merge for row-split formats (CSR, COO): one thread per partition.
+// The partition that holds a split row's first nonzero (end_flag set, not a
+// middle piece) sums its tail partial and the head partials of the following
+// partitions, in partition order, with TwoSum compensation, then applies
+// alpha and beta once (msRep Algorithm 3 lines on merging, Sec. 4.3).
+template <typename T, bool BETA0>
+__global__ __launch_bounds__(256) void merge_rows(const msrep_part *__restrict__ parts, int32_t np,
+                                                  const double *__restrict__ carry,
+                                                  T *__restrict__ y, int32_t m, double alpha,
+                                                  double beta) {
+  const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const msrep_part P = parts[p];
+  if (P.end_idx < P.start_idx || !P.end_flag) return;
+  if (P.start_flag && P.start_row == P.end_row) return;  // a later piece, not the owner
+  const int32_t r = P.end_row;
+  double s = carry[2 * static_cast<int64_t>(p) + 1], c = 0.0;
+  for (int32_t q = p + 1; q < np; ++q) {
+    const msrep_part Q = parts[q];
+    if (Q.end_idx < Q.start_idx) continue;
+    if (!Q.start_flag || Q.start_row != r) break;
+    double e;
+    two_sum(s, carry[2 * static_cast<int64_t>(q)], s, e);
+    c += e;
+    if (!(Q.end_flag && Q.end_row == r)) break;  // Q holds the row's last piece
+  }
+  if (r < 0 || r >= m) return;
+  const double tot = s + c;
+  y[r] = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(y[r]));
+}
+
+}  // namespace msrep

@@ -1,0 +1,82 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function
+include/msrep.h declares, its struct layouts agree with the binding, and the
+O(1) argument checks fail cleanly without touching a GPU."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import paper_2209_07552_amd as pk
+from paper_2209_07552_amd import _abi
+
+
+def _lib():
+    if not os.path.exists(pk.lib_path()):
+        pytest.skip("libmsrep.so not built (python -m paper_2209_07552_amd.build)")
+    return pk.load_library()
+
+
+def test_exports_every_declared_symbol():
+    _lib()
+    names = _abi.header_functions()
+    for must in ("msrep_build_partition", "msrep_convert", "msrep_spmv", "msrep_spmv_batched",
+                 "msrep_serve"):
+        assert must in names
+    missing = [n for n, ok in pk.exported_symbols().items() if not ok]
+    assert not missing, missing
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(_abi._Mat) == 56
+    assert pk.PART_DTYPE.itemsize == 40
+    assert ctypes.sizeof(_abi._Tune) == 16
+
+
+def test_lptr_bound_and_vtype_bytes():
+    L = _lib()
+    assert pk.msrep_lptr_bound(100, 8) == 116
+    assert pk.msrep_lptr_bound(0, 1) == 2
+    assert pk.msrep_lptr_bound(-1, 8) == -1 and pk.msrep_lptr_bound(5, 0) == -1
+    assert [L.msrep_vtype_bytes(v) for v in (0, 1, 2, 9)] == [8, 4, 2, 0]
+
+
+def _desc(**kw):
+    d = dict(fmt=0, vtype=0, m=4, n=4, nnz=4, ptr=0x1000, idx=0x2000, idx2=None, val=0x3000)
+    d.update(kw)
+    return _abi._Mat(d["fmt"], d["vtype"], d["m"], d["n"], d["nnz"], d["ptr"], d["idx"], d["idx2"],
+                     d["val"])
+
+
+@pytest.mark.parametrize("kw,np_,code", [
+    (dict(fmt=7), 4, -1),
+    (dict(vtype=5), 4, -1),
+    (dict(m=-1), 4, -1),
+    (dict(nnz=1 << 31), 4, -3),
+    (dict(ptr=None), 4, -1),
+    (dict(m=0), 4, -1),            # nonzeros but no rows
+    (dict(fmt=2, idx2=None), 4, -1),
+    ({}, 0, -1),                   # np <= 0
+])
+def test_build_partition_argument_errors(kw, np_, code):
+    L = _lib()
+    d = _desc(**kw)
+    st = L.msrep_build_partition(ctypes.byref(d), np_, 0x4000, 0x5000, 1 << 20, None, None)
+    assert st == code
+    assert L.msrep_last_error()  # a message is set
+
+
+def test_spmv_argument_errors():
+    L = _lib()
+    d = _desc()
+    # workspace too small
+    st = L.msrep_spmv(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0, None, 0x8000,
+                      16, None)
+    assert st == -3 and b"workspace" in L.msrep_last_error()
+    t = _abi._Tune(5, 0, 0, 0)
+    st = L.msrep_spmv(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0,
+                      ctypes.byref(t), 0x8000, 1 << 20, None)
+    assert st == -1 and b"k_per_lane" in L.msrep_last_error()
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 8) >= 16 * 8
+    dc = _desc(fmt=1, vtype=1, m=1000)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(dc), 8) >= 8 * 1000

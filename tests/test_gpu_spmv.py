@@ -1,0 +1,225 @@
+"""GPU parity: partition metadata bit-exact against the oracle, SpMV within
+the stated tolerances (FP64 1e-12, FP32 1e-5 of |alpha||A||x| + |beta||y|),
+exact on dyadic inputs and on the stencil times ones, deterministic for the
+row-split formats.  Every call goes through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import load_golden
+from gpu_common import F32_TOL, F64_TOL, assert_close, device_mat, host_formats, oracle_y
+
+torch = pytest.importorskip("torch")
+pk = pytest.importorskip("paper_2209_07552_amd")
+
+pytestmark = pytest.mark.gpu
+
+FMTS = ["csr", "csc", "coo"]
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def _golden_csr():
+    kv, _ = load_golden("example_6x6.txt")
+    m, n = int(kv["m"][0]), int(kv["n"][0])
+    A = synth.Csr(m, n, np.array(kv["row_ptr"], np.int32), np.array(kv["col_idx"], np.int32),
+                  np.array(kv["val"], np.float64), name="golden")
+    return A, np.array(kv["x"], np.float64)
+
+
+def _tiny_set():
+    """Adversarial small matrices: empty, all-empty rows, one dense row, long
+    rows crossing many partitions and chunks, leading/trailing empty rows."""
+    out = [_golden_csr()]
+    rng = np.random.default_rng(5)
+
+    def mk(counts, n, name):
+        counts = np.asarray(counts, np.int64)
+        rows = np.repeat(np.arange(len(counts)), counts)
+        cols = np.concatenate([np.sort(rng.choice(n, c, replace=False)) for c in counts]) \
+            if counts.sum() else np.zeros(0, np.int64)
+        ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        A = synth.Csr(len(counts), n, ptr, cols.astype(np.int32), rng.uniform(-1, 1, len(rows)),
+                      name=name)
+        return A, rng.uniform(-1, 1, n)
+
+    out.append(mk([0, 0, 0], 5, "all-empty"))
+    out.append(mk([7], 9, "one-row"))
+    out.append(mk([0, 0, 3000, 0, 1, 0, 0], 4000, "long-row"))
+    out.append(mk([0] * 50 + [2] * 10 + [0] * 40, 64, "lead-trail-empty"))
+    out.append(mk(rng.integers(0, 40, 300) * (rng.random(300) < 0.5), 200, "ragged"))
+    out.append(mk([5000, 1, 2000, 0, 3], 6000, "two-long"))
+    return out
+
+
+# --------------------------------------------------------------- partitions
+def _part_compare(A, fmt, np_):
+    M, _ = device_mat(A, fmt, pk.F64)
+    P = pk.msrep_build_partition(M, np_)
+    torch.cuda.synchronize()
+    rec, lp = P.host()
+    H = host_formats(A)
+    if fmt == "coo":
+        R = oracle.partition_coo(A.m, H["coo"][0], np_)
+    else:
+        rows = A.m if fmt == "csr" else A.n
+        R = oracle.partition_ptr(rows, H[fmt][0], np_)
+    for f in ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag",
+              "lptr_off"):
+        assert np.array_equal(rec[f], getattr(R, f)), (A.name, fmt, np_, f)
+    if fmt != "coo":
+        for i in range(np_):
+            o = int(R.lptr_off[i])
+            k = int(R.end_row[i] - R.start_row[i] + 2)
+            assert np.array_equal(lp[o:o + k], R.lptr[o:o + k]), (A.name, fmt, np_, i)
+        assert int(P.lptr_len.item()) == R.lptr_len
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_partition_tiny_all_np(fmt):
+    for A, _ in _tiny_set():
+        for np_ in sorted({1, 2, 3, 4, 7, 12, A.nnz + 1, A.nnz + 2, 64}):
+            _part_compare(A, fmt, np_)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_partition_uniform_and_rmat(fmt):
+    A, _ = synth.uniform_csr(4096, 4096, 16, seed=0)
+    for np_ in (8, 7, 3, 256):
+        _part_compare(A, fmt, np_)
+    B, _ = synth.rmat_csr(scale=14, edge_factor=16, seed=0)
+    for np_ in (1, 37, 256, 4096, 100_000):
+        _part_compare(B, fmt, np_)
+
+
+def test_partition_uniform_np8_no_partial_rows():
+    A, _ = synth.uniform_csr(4096, 4096, 16, seed=0)
+    M, _ = device_mat(A, "csr", pk.F64)
+    rec, _ = pk.msrep_build_partition(M, 8).host()
+    assert np.all(rec["start_flag"] == 0) and np.all(rec["end_flag"] == 0)
+    assert np.all(rec["end_idx"] - rec["start_idx"] + 1 == 8192)
+
+
+# --------------------------------------------------------------------- SpMV
+def _run(A, x64, fmt, vt, np_, alpha=1.0, beta=0.0, y_in=None, tune=None, M=None, v64=None):
+    if M is None:
+        M, v64 = device_mat(A, fmt, vt)
+    P = pk.msrep_build_partition(M, np_)
+    vdt = torch.float64 if vt == pk.F64 else torch.float32
+    xs = np.asarray(x64, np.float64 if vt == pk.F64 else np.float32)
+    x = torch.from_numpy(np.ascontiguousarray(xs)).to(_dev())
+    if beta == 0.0:
+        y = torch.full((A.m,), float("nan"), dtype=vdt, device=_dev())  # must not be read
+    else:
+        y = torch.from_numpy(np.asarray(y_in, xs.dtype)).to(_dev())
+    pk.msrep_spmv(M, P, x, y, alpha, beta, tune)
+    torch.cuda.synchronize()
+    x_used = xs.astype(np.float64)
+    yi = None if beta == 0.0 else np.asarray(y_in, xs.dtype).astype(np.float64)
+    ref, scale = oracle_y(A, fmt, v64, x_used, alpha, beta, yi)
+    return y.cpu().numpy().astype(np.float64), ref, scale
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_spmv_tiny_set(fmt, vt):
+    tol = F64_TOL if vt == 0 else F32_TOL
+    rng = np.random.default_rng(1)
+    for A, x in _tiny_set():
+        for np_ in sorted({1, 2, 3, 7, A.nnz + 2, 40}):
+            for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
+                y_in = rng.uniform(-1, 1, A.m)
+                y, ref, s = _run(A, x, fmt, vt, np_, alpha, beta, y_in)
+                assert_close(y, ref, s, tol, "%s %s vt%d np%d a%g b%g" % (A.name, fmt, vt, np_,
+                                                                         alpha, beta))
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("tune", [(4, 4), (8, 4), (4, 1), (8, 8)])
+def test_spmv_uniform_4096(fmt, tune):
+    A, x = synth.uniform_csr(4096, 4096, 16, seed=0)
+    t = pk.Tune(k_per_lane=tune[0], waves_per_wg=tune[1])
+    for np_ in (8, 7, 3, 1024):
+        y, ref, s = _run(A, x, fmt, pk.F64, np_, tune=t)
+        assert_close(y, ref, s, F64_TOL, "uniform %s np%d" % (fmt, np_))
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_spmv_rmat14(fmt, vt):
+    A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=3)
+    tol = F64_TOL if vt == 0 else F32_TOL
+    rng = np.random.default_rng(2)
+    y_in = rng.uniform(-1, 1, A.m)
+    M, v64 = device_mat(A, fmt, vt)
+    for np_ in (1, 37, 256, 2048):
+        for k in (4, 8):
+            y, ref, s = _run(A, x, fmt, vt, np_, 1.25, 0.5, y_in, tune=pk.Tune(k_per_lane=k),
+                             M=M, v64=v64)
+            assert_close(y, ref, s, tol, "rmat14 %s vt%d np%d k%d" % (fmt, vt, np_, k))
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_dyadic_bit_exact_any_np(fmt):
+    """Dyadic values and x make every partial sum exact: the result must be
+    bit-identical to the oracle for every np, which pins the merge."""
+    A, _ = synth.rmat_csr(scale=15, edge_factor=16, seed=4)
+    rng = np.random.default_rng(4)
+    A.val = synth.dyadic(rng, A.nnz)
+    x = synth.dyadic(rng, A.n)
+    M, v64 = device_mat(A, fmt, pk.F64)
+    for np_ in (1, 5, 256, 4096, A.nnz + 7):
+        y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64)
+        assert np.array_equal(y, ref), (fmt, np_)
+
+
+def test_stencil_times_ones_exact():
+    A, _ = synth.stencil7_csr(64)
+    r = np.arange(A.m)
+    g = 64
+    i, j, k = r % g, (r // g) % g, r // (g * g)
+    want = sum(((c == 0).astype(int) + (c == g - 1).astype(int)) for c in (i, j, k)).astype(float)
+    for fmt in FMTS:
+        for vt in (0, 1, 2):
+            y, _, _ = _run(A, np.ones(A.n), fmt, vt, 1000)
+            assert np.array_equal(y, want), (fmt, vt)
+
+
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_deterministic(fmt):
+    A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=5)
+    M, v64 = device_mat(A, fmt, pk.F64)
+    y1, _, _ = _run(A, x, fmt, pk.F64, 777, M=M, v64=v64)
+    y2, _, _ = _run(A, x, fmt, pk.F64, 777, M=M, v64=v64)
+    assert np.array_equal(y1, y2)
+
+
+def test_empty_shapes():
+    for m, n in ((0, 0), (5, 0), (0, 5)):
+        A = synth.Csr(m, n, np.zeros(m + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        for fmt in FMTS:
+            if m == 0:
+                continue
+            y, ref, s = _run(A, np.zeros(n), fmt, pk.F64, 3, 1.0, 3.0, np.arange(m, dtype=float))
+            assert np.array_equal(y, ref)
+
+
+def test_validate():
+    A, _ = synth.rmat_csr(scale=10, edge_factor=8, seed=1)
+    for fmt in FMTS:
+        M, _ = device_mat(A, fmt, pk.F64)
+        pk.msrep_validate(M)
+    bad = A.col.copy()
+    bad[17] = A.n + 3
+    M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=bad, val=A.val)
+    with pytest.raises(pk.MsrepError) as e:
+        pk.msrep_validate(M)
+    assert "position 17" in str(e.value)
+    rows = oracle.csr_to_coo(A.m, A.ptr)
+    rows[5], rows[6] = rows[6] + 1, rows[5]
+    M = pk.Mat(pk.COO, pk.F64, A.m, A.n, idx=rows, idx2=A.col, val=A.val)
+    with pytest.raises(pk.MsrepError):
+        pk.msrep_validate(M)
