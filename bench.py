@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the equal-nnz partitioned SpMV (msRep, arXiv 2209.07552) on
+one MI355X.
+
+Default workload: the power-law FP64 configuration -- an R-MAT scale-20
+matrix (1,048,576 rows and columns, edge factor 16, a/b/c/d =
+.57/.19/.19/.05, duplicates merged; values and x ~ U(-1, 1), seed 0) stored
+as CSR, CSC and COO, each split into equal-nnz partitions over the CUs.  One
+step is y = A*x in each of the three formats (partitions and matrices
+resident in HBM, boundary merges included).  Every SpMV of the timed region
+runs cache-cold: a 512 MiB scrub write between SpMVs evicts the 256 MB
+Infinity Cache, and HIP events on the library's stream bracket each SpMV, so
+the reported throughput is the SpMV time alone.  A warm (back-to-back) figure
+is reported beside it.
+
+Prints one JSON line (rank 0, N = 1).  --gpus N > 1 exits: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SCRUB_BYTES = 512 << 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def host_formats(A):
+    """CSC and row-sorted COO arrays of a CSR matrix (plain numpy input
+    preparation: stable sort by column)."""
+    rows = np.repeat(np.arange(A.m, dtype=np.int32), np.diff(A.ptr))
+    perm = np.argsort(A.col, kind="stable")
+    cptr = np.zeros(A.n + 1, np.int64)
+    np.cumsum(np.bincount(A.col, minlength=A.n), out=cptr[1:])
+    return {"csr": (A.ptr, A.col, A.val),
+            "csc": (cptr.astype(np.int32), rows[perm], A.val[perm]),
+            "coo": (rows, A.col, A.val)}
+
+
+def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
+    """Bytes the method must move for one SpMV (values, indices, pointer, x
+    read once, y written once; y read too when beta != 0)."""
+    b = nnz * (vbytes + 4) + n * xbytes + m * xbytes
+    if fmt == "csr":
+        b += (m + 1) * 4
+    elif fmt == "csc":
+        b += (n + 1) * 4
+    else:
+        b += nnz * 4
+    if not beta0:
+        b += m * xbytes
+    return b
+
+
+def load_traffic(kernel_key):
+    """HBM bytes per launch measured by rocprofv3 counters, if a summary for
+    this kernel and workload is committed and still current."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        try:
+            rec = json.loads(line)
+        except ValueError:
+            continue
+        if rec.get("key") == kernel_key and rec.get("current", False):
+            return rec.get("bytes_per_launch")
+    return None
+
+
+def cpu_baseline(A, x, y_gpu, budget_s):
+    """The FP64 oracle (Dot2 CSR SpMV, one thread) timed on this host over
+    whole SpMVs of the same matrix, repeated for about budget_s seconds; also
+    the GPU result's largest error relative to (|A||x|)_i."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    y, s = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
+    one = time.perf_counter() - t0
+    reps = max(1, int(budget_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
+    per = (time.perf_counter() - t0) / reps if reps else one
+    err = float(np.max(np.abs(y_gpu - y) / np.where(s > 0, s, 1.0)))
+    return {"value": round(2.0 * A.nnz / per / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d full CSR SpMVs of the same matrix (%d nnz), Dot2 FP64, 1 thread"
+                      % (reps + 1, A.nnz)}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20", choices=["rmat20", "stencil256", "uniform4096"])
+    ap.add_argument("--vtype", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--formats", default="csr,csc,coo")
+    ap.add_argument("--nnz-per-wave", type=int, default=0, help="partition size (0: tuned)")
+    ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2209_07552_amd as pk
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    vt = {"f64": pk.F64, "f32": pk.F32, "bf16": pk.BF16}[args.vtype]
+    t0 = time.time()
+    if args.workload == "rmat20":
+        A, x64 = synth.rmat_csr(scale=20, edge_factor=16, seed=0)
+        wl = {"workload": "rmat-scale20-ef16", "rows": A.m, "cols": A.n, "nnz": A.nnz,
+              "abcd": [0.57, 0.19, 0.19, 0.05]}
+    elif args.workload == "stencil256":
+        A, x64 = synth.stencil7_csr(256, seed=0)
+        wl = {"workload": "laplace3d-7pt-256^3", "rows": A.m, "cols": A.n, "nnz": A.nnz}
+    else:
+        A, x64 = synth.uniform_csr(4096, 4096, 16, seed=0)
+        wl = {"workload": "uniform-4096-16perrow", "rows": A.m, "cols": A.n, "nnz": A.nnz}
+    log("generated %s in %.1fs" % (wl["workload"], time.time() - t0))
+    fmts = [f for f in args.formats.split(",") if f]
+    H = host_formats(A)
+    vbytes = pk._abi.VALUE_BYTES[vt]
+    xbytes = 8 if vt == pk.F64 else 4
+
+    def stored(v):
+        if vt == pk.F64:
+            return v
+        v32 = np.asarray(v, np.float32)
+        return v32 if vt == pk.F32 else synth.bf16_bits(v32)
+
+    mats = {}
+    for f in fmts:
+        a, b, v = H[f]
+        if f == "csr":
+            mats[f] = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=a, idx=b, val=stored(v))
+        elif f == "csc":
+            mats[f] = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=stored(v))
+        else:
+            mats[f] = pk.Mat(pk.COO, vt, A.m, A.n, idx=a, idx2=b, val=stored(v))
+    del H
+    xs = x64 if vt == pk.F64 else x64.astype(np.float32)
+    x = torch.from_numpy(xs).to(dev)
+    ydt = torch.float64 if vt == pk.F64 else torch.float32
+    ys = {f: torch.zeros(A.m, dtype=ydt, device=dev) for f in fmts}
+    nnz_per_wave = args.nnz_per_wave or 2048
+    np_ = max(1, -(-A.nnz // nnz_per_wave))
+    tune = pk.Tune(k_per_lane=args.k, waves_per_wg=args.wpb)
+    parts = {}
+    torch.cuda.synchronize()
+    part_ms = {}
+    for f in fmts:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        parts[f] = pk.msrep_build_partition(mats[f], np_)
+        e1.record()
+        torch.cuda.synchronize()
+        part_ms[f] = e0.elapsed_time(e1)
+    scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
+    ws = {f: torch.zeros(1 << 24, dtype=torch.uint8, device=dev) for f in fmts}
+
+    def spmv(f):
+        pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tune, ws=ws[f])
+
+    for _ in range(args.warmup):
+        for f in fmts:
+            spmv(f)
+    torch.cuda.synchronize()
+    # ---- timed region: K steps, each SpMV cold and bracketed by events
+    ev = {f: [] for f in fmts}
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        for f in fmts:
+            scrub.fill_(1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            spmv(f)
+            e1.record()
+            ev[f].append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    cold_ms = {f: float(np.mean([a.elapsed_time(b) for a, b in ev[f]])) for f in fmts}
+    # ---- warm: back-to-back SpMVs of one format
+    warm_ms = {}
+    for f in fmts:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            spmv(f)
+        e1.record()
+        torch.cuda.synchronize()
+        warm_ms[f] = e0.elapsed_time(e1) / args.steps
+    step_ms = sum(cold_ms.values())
+    flops = 2.0 * A.nnz * len(fmts)
+    per_fmt = {}
+    for f in fmts:
+        b = alg_bytes(f, A.m, A.n, A.nnz, vbytes, xbytes)
+        per_fmt[f] = {"ms_cold": round(cold_ms[f], 4), "ms_warm": round(warm_ms[f], 4),
+                      "gflops_cold": round(2.0 * A.nnz / cold_ms[f] / 1e6, 2),
+                      "gbs_cold": round(b / cold_ms[f] / 1e6, 1),
+                      "gbs_warm": round(b / warm_ms[f] / 1e6, 1),
+                      "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4)}
+    dom = max(fmts, key=lambda f: cold_ms[f])
+    kname = {"csr": "spmv_csr_seg", "csc": "spmv_csc_scatter", "coo": "spmv_coo_seg"}[dom]
+    achieved = per_fmt[dom]["alg_bytes"] / (cold_ms[dom] * 1e-3) / 1e9
+    traffic = load_traffic("%s/%s/%s" % (kname, wl["workload"], args.vtype))
+    out = {
+        "metric": "SpMV GFLOP/s (cold HBM; CSR+CSC+COO per step)",
+        "value": round(flops / (step_ms * 1e-3) / 1e9, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.vtype, "data": "synthetic",
+        "config": dict(wl, formats=fmts, np=np_, nnz_per_wave=nnz_per_wave,
+                       value_type=args.vtype),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": kname + "(+merge)"},
+        "per_format": per_fmt,
+        "wall_s_timed_region": round(wall, 3),
+    }
+    if not args.no_cpu:
+        f0 = "csr" if "csr" in fmts else fmts[0]
+        yg = ys[f0].double().cpu().numpy()
+        if vt == pk.F64:
+            cb, err = cpu_baseline(A, x64, yg, args.cpu_budget)
+            out["cpu_baseline"] = cb
+            out["max_scaled_error_vs_oracle"] = err
+        else:
+            cb, err = cpu_baseline(A, x64, yg, args.cpu_budget)
+            out["cpu_baseline"] = cb
+            out["max_scaled_error_vs_fp64_oracle"] = err
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

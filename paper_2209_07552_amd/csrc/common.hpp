@@ -57,6 +57,60 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------- device side
+// Raw buffer resources (CDNA "V#"): loads through them are bounds-checked by
+// the hardware against num_records bytes and return 0 outside, so every lane
+// can issue the same loads with no branch and no out-of-range access.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit data format
+constexpr int kNt = 2;                  // cache policy bit: non-temporal (streamed once)
+
+// base and bytes must be the same on every lane of the wavefront; they are
+// read from the first lane so the descriptor lives in scalar registers.
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+  void *p = reinterpret_cast<void *>((static_cast<uint64_t>(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(
+      p, 0, static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)), kRsrcWord3);
+}
+
+// One element at byte offset `off` (0 when out of range).
+template <typename E, int aux = 0>
+__device__ __forceinline__ E buf_load(rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(E) == 8) {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, aux);
+    return __builtin_bit_cast(E, w);
+  } else if constexpr (sizeof(E) == 4) {
+    return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, aux));
+  } else {
+    static_assert(sizeof(E) == 2, "2, 4 or 8 bytes");
+    return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, aux));
+  }
+}
+
+// K consecutive elements starting at byte offset `off` (16-byte pieces).
+template <typename E, int K, int aux = 0>
+__device__ __forceinline__ void buf_load_vec(rsrc_t r, uint32_t off, E (&out)[K]) {
+  constexpr int bytes = K * sizeof(E);
+  uint32_t *o = reinterpret_cast<uint32_t *>(out);
+  if constexpr (bytes % 16 == 0) {
+#pragma unroll
+    for (int v = 0; v < bytes / 16; ++v) {
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * v, 0, aux);
+      o[4 * v] = w.x;
+      o[4 * v + 1] = w.y;
+      o[4 * v + 2] = w.z;
+      o[4 * v + 3] = w.w;
+    }
+  } else {
+    static_assert(bytes == 8, "8 or a multiple of 16 bytes");
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, aux);
+    o[0] = w.x;
+    o[1] = w.y;
+  }
+}
+
 // Block index remapped so that each XCD (blocks are dealt to the 8 XCDs
 // round-robin by id) receives one contiguous run of logical blocks: its L2
 // then sees a contiguous slice of the matrix and of y.

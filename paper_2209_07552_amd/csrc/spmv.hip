@@ -220,6 +220,12 @@ extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d
   if (msrep_status st = resolve_tune(tune, &K, &wpb, "msrep_spmv")) return st;
   if (tune && tune->rows_per_wave > 0 && A->fmt != MSREP_CSR)
     return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: rows_per_wave kernel is CSR only");
+  // x, y and the local pointers are addressed through 32-bit buffer offsets
+  const uint64_t xb = static_cast<uint64_t>(A->n) * vec_bytes(A->vtype);
+  const uint64_t yb = static_cast<uint64_t>(A->m) * vec_bytes(A->vtype);
+  if (xb >= (uint64_t(1) << 32) || yb >= (uint64_t(1) << 32) ||
+      (static_cast<uint64_t>(major_dim(A)) + 1) * 4 >= (uint64_t(1) << 32))
+    return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: x or y larger than 4 GiB");
   const size_t need = msrep_spmv_ws_bytes(A, np);
   if (!ws_d || ws_bytes < need)
     return fail(MSREP_ERR_SIZE, "msrep_spmv: workspace of %zu bytes needed (got %zu)", need,

@@ -12,6 +12,25 @@
 
 namespace msrep {
 
+// Row indices of a lane's K items (see load_items); items before the
+// partition take its first row and items past its end its last row, so they
+// join the first / last segment with a zero product.
+template <int K>
+__device__ __forceinline__ void load_rows(const int32_t *__restrict__ row_idx, int64_t s0,
+                                          int32_t cb, int32_t nloc, int32_t r0, int32_t rE,
+                                          int32_t (&row)[K]) {
+  constexpr int CH = kWave * K;
+  const int32_t span = nloc - cb < CH ? nloc - cb : CH;
+  const rsrc_t rr = make_rsrc(row_idx + s0 + cb, static_cast<uint32_t>(span > 0 ? span : 0) * 4u);
+  const uint32_t l = static_cast<uint32_t>(lane_id() * K);
+  buf_load_vec<int32_t, K, kNt>(rr, l * 4u, row);
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const int32_t q = cb + static_cast<int32_t>(l) + t;
+    row[t] = q < 0 ? r0 : (q >= nloc ? rE : row[t]);
+  }
+}
+
 template <int VT, int K>
 constexpr size_t coo_lds_per_wave() {
   return 16;  // one FP64 slot: the sum carried into the next chunk
@@ -50,42 +69,36 @@ __global__ __launch_bounds__(512) void spmv_coo_seg(
   double carry_v = 0.0;  // partial sum of the row continuing from the last chunk
   bool carry_on = false;
   const int32_t lead = static_cast<int32_t>(s0 % K);
+  const rsrc_t rx = make_rsrc(x, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(T)));
+  // rows, columns and values of a chunk are loaded one chunk ahead
+  int32_t row_cur[K], c_cur[K];
+  V v_cur[K];
+  load_items<V, K>(col, val, s0, -lead, nloc, c_cur, v_cur);
+  load_rows<K>(row_idx, s0, -lead, nloc, r0, rE, row_cur);
   for (int32_t cb = -lead; cb < nloc; cb += CH) {
     const int32_t cs = cb > 0 ? cb : 0;
     const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
     const int32_t q0 = cb + lane * K;
+    T xv[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      xv[t] = buf_load<T>(rx, static_cast<uint32_t>(c_cur[t]) * static_cast<uint32_t>(sizeof(T)));
+    // rows of the nonzeros just before and just after the chunk
+    const int32_t before = cs > 0 ? row_idx[s0 + cs - 1] : -1;
+    const int32_t after = ce < nloc ? row_idx[s0 + ce] : -1;
+    int32_t row_nxt[K], c_nxt[K];
+    V v_nxt[K];
+    load_items<V, K>(col, val, s0, cb + CH, nloc, c_nxt, v_nxt);
+    load_rows<K>(row_idx, s0, cb + CH, nloc, r0, rE, row_nxt);
     int32_t row[K];
     Acc prod[K];
-    if (q0 >= 0 && q0 + K <= nloc) {
-      int32_t c[K];
-      V v[K];
-      load_vec<int32_t, K>(row_idx + s0 + q0, row);
-      load_vec<int32_t, K>(col + s0 + q0, c);
-      load_vec<V, K>(val + s0 + q0, v);
 #pragma unroll
-      for (int t = 0; t < K; ++t) {
-        const bool okc = static_cast<uint32_t>(c[t]) < static_cast<uint32_t>(n);
-        const T xv = okc ? x[c[t]] : T(0);
-        prod[t] = Tr::val(v[t]) * static_cast<Acc>(xv);
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        const int32_t q = q0 + t;
-        prod[t] = Acc(0);
-        row[t] = q < 0 ? r0 : rE;  // masked items join the first / last segment
-        if (q >= 0 && q < nloc) {
-          row[t] = row_idx[s0 + q];
-          const int32_t c = col[s0 + q];
-          if (static_cast<uint32_t>(c) < static_cast<uint32_t>(n))
-            prod[t] = Tr::val(val[s0 + q]) * static_cast<Acc>(x[c]);
-        }
-      }
+    for (int t = 0; t < K; ++t) {
+      row[t] = row_cur[t];
+      prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv[t]);
     }
     // previous / next row of every item
     const int32_t up = shfl_up_i(row[K - 1], 1);
-    // row of the nonzero just before the chunk (partition start: none)
-    const int32_t before = cs > 0 ? row_idx[s0 + cs - 1] : -1;
     const int32_t prev0 = lane == 0 ? before : up;
     const int32_t dn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, row[0]);
     // ---- segmented scan (heads where the row changes inside the chunk)
@@ -122,8 +135,6 @@ __global__ __launch_bounds__(512) void spmv_coo_seg(
       cin = Acc(0);
       fin = 0;
     }
-    // continuing into the next chunk?
-    const int32_t after = ce < nloc ? row_idx[s0 + ce] : -1;
     // items before the lane's first head continue the segment of earlier
     // lanes (cin); only the chunk's first segment continues the carried row
     bool seen = false;
@@ -160,6 +171,12 @@ __global__ __launch_bounds__(512) void spmv_coo_seg(
     const int32_t last_row = row_idx[s0 + ce - 1];
     carry_on = after == last_row && ce < nloc;
     carry_v = carry_on ? *s_carry : 0.0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      row_cur[t] = row_nxt[t];
+      c_cur[t] = c_nxt[t];
+      v_cur[t] = v_nxt[t];
+    }
     wave_lds_sync();
   }
   const int32_t gap_lo = nloc > 0 ? rE + 1 : r0;

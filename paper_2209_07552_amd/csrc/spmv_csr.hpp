@@ -75,6 +75,45 @@ __device__ __forceinline__ void load_vec(const E *__restrict__ p, E (&out)[K]) {
   }
 }
 
+// The K items of a lane at local positions q0 .. q0+K-1 of the chunk that
+// starts at local position cb of a partition whose first nonzero is s0 and
+// which holds nloc nonzeros.  The buffer resources cover exactly the chunk's
+// positions inside the partition, so items past its end read as 0; items
+// before the partition start (q < 0) are masked to index -1 and value 0.
+template <typename V, int K>
+__device__ __forceinline__ void load_items(const int32_t *__restrict__ idx,
+                                           const V *__restrict__ val, int64_t s0, int32_t cb,
+                                           int32_t nloc, int32_t (&c)[K], V (&v)[K]) {
+  constexpr int CH = kWave * K;
+  const int32_t span = nloc - cb < CH ? nloc - cb : CH;  // positions cb .. cb+span-1 exist
+  const int32_t n_ok = span > 0 ? span : 0;
+  const rsrc_t ri = make_rsrc(idx + s0 + cb, static_cast<uint32_t>(n_ok) * 4u);
+  const uint32_t l = static_cast<uint32_t>(lane_id() * K);
+  buf_load_vec<int32_t, K, kNt>(ri, l * 4u, c);
+  if constexpr (sizeof(V) >= 4) {
+    const rsrc_t rv = make_rsrc(val + s0 + cb, static_cast<uint32_t>(n_ok) * sizeof(V));
+    buf_load_vec<V, K, kNt>(rv, l * static_cast<uint32_t>(sizeof(V)), v);
+  } else {
+    // the hardware bounds check is per dword: cover whole dwords only and
+    // fetch an odd last element with a 16-bit load of its own
+    const rsrc_t rv = make_rsrc(val + s0 + cb, (static_cast<uint32_t>(n_ok) * 2u) & ~3u);
+    buf_load_vec<V, K, kNt>(rv, l * 2u, v);
+    const uint32_t last = static_cast<uint32_t>(n_ok - 1);
+    const rsrc_t rt = make_rsrc(val + s0 + cb + (n_ok > 0 ? n_ok - 1 : 0), (n_ok & 1) ? 2u : 0u);
+    const uint32_t tt = last - l;  // item of this lane that is the odd tail, if < K
+    const V tail = buf_load<V>(rt, tt < static_cast<uint32_t>(K) ? 0u : 4u);
+#pragma unroll
+    for (int t = 0; t < K; ++t) v[t] = (n_ok & 1) && tt == static_cast<uint32_t>(t) ? tail : v[t];
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const int32_t q = cb + static_cast<int32_t>(l) + t;
+    const bool in = q >= 0 && q < nloc;
+    c[t] = in ? c[t] : -1;
+    v[t] = in ? v[t] : V(0);
+  }
+}
+
 // Per-wave LDS footprint of the CSR/COO kernels.
 template <int VT, int K>
 constexpr size_t seg_lds_per_wave() {
@@ -133,59 +172,62 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
   bool carry_on = false;
   int32_t j0 = 0;         // first local row of the current chunk
   const int32_t lead = static_cast<int32_t>(s0 % K);  // align item groups to K
+  // the chunk's column indices and values are loaded one chunk ahead
+  const rsrc_t rx = make_rsrc(x, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(T)));
+  const rsrc_t rl = make_rsrc(lp, static_cast<uint32_t>(R + 1 > 0 ? R + 1 : 0) * 4u);
+  int32_t c_cur[K];
+  V v_cur[K];
+  load_items<V, K>(col, val, s0, -lead, nloc, c_cur, v_cur);
   for (int32_t cb = -lead; cb < nloc; cb += CH) {
     const int32_t cs = cb > 0 ? cb : 0;                 // first valid local position
     const int32_t ce = cb + CH < nloc ? cb + CH : nloc;  // one past the last
-    // ---- 1. products
+    // ---- 1. issue: x gathers, the first batch of local row pointers, and
+    //         the next chunk's indices and values
+    // (index -1 and columns >= n read as 0 through the x resource)
+    T xv[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      xv[t] = buf_load<T>(rx, static_cast<uint32_t>(c_cur[t]) * static_cast<uint32_t>(sizeof(T)));
+    const int32_t lpv0 = buf_load<int32_t>(rl, static_cast<uint32_t>(j0 + lane) * 4u);
+    int32_t c_nxt[K];
+    V v_nxt[K];
+    load_items<V, K>(col, val, s0, cb + CH, nloc, c_nxt, v_nxt);
     Acc prod[K];
-    {
-      const int32_t q0 = cb + lane * K;
-      if (q0 >= 0 && q0 + K <= nloc) {
-        int32_t c[K];
-        V v[K];
-        load_vec<int32_t, K>(col + s0 + q0, c);
-        load_vec<V, K>(val + s0 + q0, v);
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-          const bool okc = static_cast<uint32_t>(c[t]) < static_cast<uint32_t>(n);
-          const T xv = okc ? x[c[t]] : T(0);
-          prod[t] = Tr::val(v[t]) * static_cast<Acc>(xv);
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-          const int32_t q = q0 + t;
-          prod[t] = Acc(0);
-          if (q >= 0 && q < nloc) {
-            const int32_t c = col[s0 + q];
-            if (static_cast<uint32_t>(c) < static_cast<uint32_t>(n))
-              prod[t] = Tr::val(val[s0 + q]) * static_cast<Acc>(x[c]);
-          }
-        }
-      }
-    }
+    for (int t = 0; t < K; ++t) prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv[t]);
     // ---- 2. head flags from the local pointer
 #pragma unroll
     for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
     wave_lds_sync();
+    // first batch: rows j0 .. j0+63 (lpv0); more rows than that start inside
+    // the chunk only with many short or empty rows
     int32_t jb = j0, cnt, lp_next;
-    for (;;) {
-      const int32_t j = jb + lane;
-      const int32_t v = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
-      const bool in = j <= R - 1 && v < ce;
-      if (in && j > j0) {
-        const int32_t pos = v - cb;
-        if (pos > 0 && pos < CH) s_head[pos] = 1;
-      }
+    {
+      const int32_t j = j0 + lane;
+      const bool in = j <= R - 1 && lpv0 < ce;
+      const int32_t pos = lpv0 - cb;
+      if (in && j > j0 && pos > 0 && pos < CH) s_head[pos] = 1;
       cnt = __popcll(__ballot(in));
-      if (cnt < kWave) {
-        lp_next = read_lane(v, cnt);
-        break;
+      lp_next = read_lane(lpv0, cnt & (kWave - 1));
+    }
+    if (cnt == kWave) {
+      for (;;) {
+        jb += kWave;
+        const int32_t j = jb + lane;
+        const int32_t v = buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u);
+        const bool in = j <= R - 1 && v < ce;
+        const int32_t pos = v - cb;
+        if (in && pos > 0 && pos < CH) s_head[pos] = 1;
+        cnt = __popcll(__ballot(in));
+        if (cnt < kWave) {
+          lp_next = read_lane(v, cnt);
+          break;
+        }
       }
-      jb += kWave;
     }
     const int32_t j1 = jb + cnt - 1;  // last row starting before ce
     const bool cont = lp_next > ce;   // row j1 continues into the next chunk
+    const bool one_batch = jb == j0;  // rows j0..j1 are the lanes of lpv0
     wave_lds_sync();
     // ---- 3. segmented scan
     uint32_t hb[K / 4];
@@ -226,26 +268,42 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
     wave_lds_sync();
     // ---- 4. rows j0..j1
     const double last_tot = static_cast<double>(s_sum[ce - 1 - cb]);
-    for (int32_t jr = j0; jr <= j1; jr += kWave) {
-      const int32_t j = jr + lane;
-      if (j >= 0 && j <= j1) {
-        const int32_t a = lp[j], b = lp[j + 1];
-        const int32_t aa = a > cs ? a : cs, bb = b < ce ? b : ce;
-        double tot = bb > aa ? static_cast<double>(s_sum[bb - 1 - cb]) : 0.0;
-        if (j == j0 && carry_on) tot += carry_v;
-        if (!(j == j1 && cont)) {
-          if (j == 0 && sflag)
-            carry[2 * static_cast<int64_t>(p)] = tot;
-          else if (j == R - 1 && eflag)
-            carry[2 * static_cast<int64_t>(p) + 1] = tot;
-          else if (static_cast<uint32_t>(r0 + j) < static_cast<uint32_t>(m))
-            store_y<T>(y, r0 + j, tot, alpha, beta, BETA0);
-        }
+    // next lane's pointer = lp[j + 1] while all rows sit in the first batch
+    const int32_t lpv1 = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, lpv0);
+    // one row per lane: in-chunk sum from the scan, plus the carried sum for
+    // a row that began in an earlier chunk; the row still open at the chunk
+    // end is carried on
+    auto finish_row = [&](int32_t j, int32_t a, int32_t b) {
+      const int32_t aa = a > cs ? a : cs, bb = b < ce ? b : ce;
+      double tot = bb > aa ? static_cast<double>(s_sum[bb - 1 - cb]) : 0.0;
+      if (j == j0 && carry_on) tot += carry_v;
+      if (j == j1 && cont) return;
+      if (j == 0 && sflag)
+        carry[2 * static_cast<int64_t>(p)] = tot;
+      else if (j == R - 1 && eflag)
+        carry[2 * static_cast<int64_t>(p) + 1] = tot;
+      else if (static_cast<uint32_t>(r0 + j) < static_cast<uint32_t>(m))
+        store_y<T>(y, r0 + j, tot, alpha, beta, BETA0);
+    };
+    if (one_batch) {
+      const int32_t j = j0 + lane;
+      if (j <= j1) finish_row(j, lpv0, j == j1 ? lp_next : lpv1);
+    } else {
+      for (int32_t jr = j0; jr <= j1; jr += kWave) {
+        const int32_t j = jr + lane;
+        if (j >= 0 && j <= j1)
+          finish_row(j, buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u),
+                     buf_load<int32_t>(rl, static_cast<uint32_t>(j + 1) * 4u));
       }
     }
     carry_v = cont ? last_tot + ((j1 == j0 && carry_on) ? carry_v : 0.0) : 0.0;
     carry_on = cont;
     j0 = cont ? j1 : j1 + 1;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      c_cur[t] = c_nxt[t];
+      v_cur[t] = v_nxt[t];
+    }
     wave_lds_sync();  // s_sum / s_head are rewritten by the next chunk
   }
   // ---- empty rows after this partition up to the next one's first row
