@@ -278,6 +278,25 @@ msrep_status msrep_serve(const msrep_serve_cfg *cfg,
                          const msrep_request *trace, int64_t n_req,
                          msrep_result *results, msrep_serve_stats *stats);
 
+/* The same scheduler (admission, residency, eviction, continuous batching)
+ * driven by a simulated device on a virtual clock instead of the GPU: an
+ * upload takes bytes / upload_bytes_per_s, a tick takes tick_seconds plus
+ * 2*nnz / flops_per_s for each request in it (values <= 0 keep defaults of
+ * 25 GB/s, 500 GFLOP/s, 20 us).  No HIP call is made; cfg->arena_d may be
+ * NULL and keep_y is ignored.  Results carry virtual times.  For testing the
+ * scheduling logic without a GPU. */
+msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
+                                  const msrep_host_mat *pool, int32_t pool_size,
+                                  const msrep_request *trace, int64_t n_req,
+                                  msrep_result *results,
+                                  msrep_serve_stats *stats,
+                                  double upload_bytes_per_s, double flops_per_s,
+                                  double tick_seconds);
+
+/* Entry c of x_step for request rid (see msrep_serve), on the host. */
+double msrep_serve_x_value(uint64_t seed, int64_t rid, int32_t step,
+                           int64_t c);
+
 #ifdef __cplusplus
 }
 #endif

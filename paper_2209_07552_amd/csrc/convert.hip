@@ -1,11 +1,478 @@
-// msrep_convert (placeholder until the conversion kernels land).
+// msrep_convert: CSR <-> CSC <-> row-sorted COO on the GPU (msRep Sec. 2.1;
+// CSC(A) = CSR(A^T)).  All conversions are stable and deterministic:
+//   * expand:  the major index of every nonzero from a compressed pointer
+//              (mark each non-empty row's first position, inclusive max-scan);
+//   * compress: a pointer from sorted major indices (counting + scan);
+//   * transpose: a stable LSD radix sort of (new major index, position)
+//              pairs, 8-bit digits, ranks formed with wavefront ballots, so
+//              entries that tie keep their storage order;
+//   * gathers move indices and values (2, 4 or 8 bytes) by the permutation.
+#include <algorithm>
+
 #include "common.hpp"
-using namespace msrep;
-extern "C" size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt) {
-  (void)src; (void)dst_fmt; return 0;
+
+namespace msrep {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;  // 4096 elements per block
+constexpr int kRadix = 256;
+
+int64_t tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+// ------------------------------------------------------------ scans
+struct SumOp {
+  template <typename T>
+  __device__ static T id() { return T(0); }
+  template <typename T>
+  __device__ static T op(T a, T b) { return a + b; }
+};
+struct MaxOp {
+  template <typename T>
+  __device__ static T id() { return T(-1); }
+  template <typename T>
+  __device__ static T op(T a, T b) { return a > b ? a : b; }
+};
+
+template <typename T, typename Op>
+__device__ T block_reduce(T v, T *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = 32; d > 0; d >>= 1) v = Op::template op<T>(v, __shfl_xor(v, d));
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T r = Op::template id<T>();
+  for (int i = 0; i < kBlock / 64; ++i) r = Op::template op<T>(r, sh[i]);
+  __syncthreads();
+  return r;
 }
+
+// Exclusive block scan of one value per thread; returns the block total.
+template <typename T, typename Op>
+__device__ T block_exscan(T v, T &excl, T *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T inc = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const T o = __shfl_up(inc, d);
+    if (lane >= d) inc = Op::template op<T>(o, inc);
+  }
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  T before = Op::template id<T>(), total = Op::template id<T>();
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < w) before = Op::template op<T>(before, sh[i]);
+    total = Op::template op<T>(total, sh[i]);
+  }
+  const T up = __shfl_up(inc, 1);
+  excl = Op::template op<T>(before, lane == 0 ? Op::template id<T>() : up);
+  __syncthreads();
+  return total;
+}
+
+template <typename T, typename Op>
+__global__ __launch_bounds__(kBlock) void scan_reduce(const T *__restrict__ in, int64_t n,
+                                                      T *__restrict__ agg) {
+  __shared__ T sh[kBlock / 64];
+  const int64_t base = blockIdx.x * int64_t(kTile) + threadIdx.x * int64_t(kItems);
+  T v = Op::template id<T>();
+#pragma unroll
+  for (int i = 0; i < kItems; ++i)
+    if (base + i < n) v = Op::template op<T>(v, in[base + i]);
+  v = block_reduce<T, Op>(v, sh);
+  if (threadIdx.x == 0) agg[blockIdx.x] = v;
+}
+
+// Exclusive scan of the nb block aggregates in place (one block, looping).
+template <typename T, typename Op>
+__global__ __launch_bounds__(kBlock) void scan_aggs(T *__restrict__ agg, int64_t nb) {
+  __shared__ T sh[kBlock / 64];
+  T carry = Op::template id<T>();
+  for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const T v = i < nb ? agg[i] : Op::template id<T>();
+    T ex;
+    const T tot = block_exscan<T, Op>(v, ex, sh);
+    if (i < nb) agg[i] = Op::template op<T>(carry, ex);
+    carry = Op::template op<T>(carry, tot);
+  }
+}
+
+// out = inclusive (or exclusive) scan of in, given the exclusive block
+// prefixes; in and out may alias.
+template <typename T, typename Op>
+__global__ __launch_bounds__(kBlock) void scan_down(const T *in, T *out, int64_t n,
+                                                    const T *__restrict__ pre, bool inclusive) {
+  __shared__ T sh[kBlock / 64];
+  const int64_t base = blockIdx.x * int64_t(kTile) + threadIdx.x * int64_t(kItems);
+  T v[kItems];
+  T local = Op::template id<T>();
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : Op::template id<T>();
+    local = Op::template op<T>(local, v[i]);
+  }
+  T ex;
+  block_exscan<T, Op>(local, ex, sh);
+  T run = Op::template op<T>(pre[blockIdx.x], ex);
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const T next = Op::template op<T>(run, v[i]);
+    if (base + i < n) out[base + i] = inclusive ? next : run;
+    run = next;
+  }
+}
+
+template <typename T, typename Op>
+msrep_status device_scan(const T *in, T *out, int64_t n, T *agg, bool inclusive, hipStream_t s) {
+  if (n <= 0) return MSREP_OK;
+  const int64_t nb = tiles(n);
+  hipLaunchKernelGGL((scan_reduce<T, Op>), dim3(nb), dim3(kBlock), 0, s, in, n, agg);
+  MSREP_LAUNCHED("scan_reduce");
+  hipLaunchKernelGGL((scan_aggs<T, Op>), dim3(1), dim3(kBlock), 0, s, agg, nb);
+  MSREP_LAUNCHED("scan_aggs");
+  hipLaunchKernelGGL((scan_down<T, Op>), dim3(nb), dim3(kBlock), 0, s, in, out, n, agg, inclusive);
+  MSREP_LAUNCHED("scan_down");
+  return MSREP_OK;
+}
+
+// ------------------------------------------------------ expand/compress
+template <typename T>
+__global__ void fill(T *__restrict__ a, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+
+// major index r at the first position of every non-empty major slice
+__global__ void mark_starts(const int32_t *__restrict__ ptr, int32_t rows, int64_t nnz,
+                            int32_t *__restrict__ out) {
+  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < rows;
+       r += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t a = ptr[r], b = ptr[r + 1];
+    if (a < b && a >= 0 && a < nnz) out[a] = static_cast<int32_t>(r);
+  }
+}
+
+// counts[i + 1] += 1 for every index i (counts has minor + 1 entries)
+__global__ void histogram(const int32_t *__restrict__ idx, int64_t nnz, int32_t minor,
+                          int32_t *__restrict__ counts) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < nnz;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t i = idx[k];
+    if (static_cast<uint32_t>(i) < static_cast<uint32_t>(minor)) atomicAdd(counts + i + 1, 1);
+  }
+}
+
+// ptr of a row-sorted COO: ptr[r] = first position whose row is >= r
+__global__ void rows_to_ptr(const int32_t *__restrict__ row, int64_t nnz, int32_t m,
+                            int32_t *__restrict__ ptr) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k <= nnz;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    int64_t lo = k == 0 ? 0 : static_cast<int64_t>(row[k - 1]) + 1;
+    int64_t hi = k == nnz ? m : static_cast<int64_t>(row[k]);
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > m ? m : hi;
+    for (int64_t r = lo; r <= hi; ++r) ptr[r] = static_cast<int32_t>(k);
+  }
+}
+
+// --------------------------------------------------- LSD radix sort
+__global__ void iota(int32_t *__restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    a[i] = static_cast<int32_t>(i);
+}
+
+// hist[d * nb + b] = number of keys of tile b whose digit is d
+__global__ __launch_bounds__(kBlock) void radix_hist(const uint32_t *__restrict__ keys, int64_t n,
+                                                     int shift, int64_t nb,
+                                                     int32_t *__restrict__ hist) {
+  __shared__ int32_t cnt[kRadix];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * int64_t(kTile);
+  for (int i = 0; i < kItems; ++i) {
+    const int64_t k = base + i * kBlock + threadIdx.x;
+    if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & (kRadix - 1)], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: tile items are taken in storage order (round i holds items
+// i*256 + tid); an item's rank is the number of earlier tile items with its
+// digit, found with ballots inside a wavefront and LDS counts across them.
+__global__ __launch_bounds__(kBlock) void radix_scatter(
+    const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n, int shift,
+    int64_t nb, const int32_t *__restrict__ off, uint32_t *__restrict__ kout,
+    int32_t *__restrict__ vout) {
+  __shared__ int32_t run[kRadix];
+  __shared__ int32_t wcnt[kBlock / 64][kRadix];
+  __shared__ int32_t base_off[kRadix];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  run[tid] = 0;
+  base_off[tid] = off[tid * nb + blockIdx.x];
+  for (int i = 0; i < kBlock / 64; ++i) wcnt[i][tid] = 0;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = blockIdx.x * int64_t(kTile);
+  for (int i = 0; i < kItems; ++i) {
+    const int64_t k = base + i * kBlock + tid;
+    const bool valid = k < n;
+    const uint32_t key = valid ? kin[k] : 0u;
+    const int32_t val = valid ? vin[k] : 0;
+    const int d = static_cast<int>((key >> shift) & (kRadix - 1));
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? bal : ~bal;
+    }
+    const int wrank = __popcll(peers & lt);
+    if (valid && wrank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int32_t r = run[d] + wrank;
+      for (int v = 0; v < w; ++v) r += wcnt[v][d];
+      const int64_t dst = static_cast<int64_t>(base_off[d]) + r;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    int32_t add = 0;
+    for (int v = 0; v < kBlock / 64; ++v) {
+      add += wcnt[v][tid];
+      wcnt[v][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------- gathers
+template <typename E>
+__global__ void gather(const E *__restrict__ src, const int32_t *__restrict__ perm, int64_t n,
+                       E *__restrict__ dst) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[perm[i]];
+}
+
+int grid_for(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return static_cast<int>(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+// ----------------------------------------------------- workspace plan
+struct Ws {
+  int32_t *major;          // nnz: major index of every source entry
+  uint32_t *ka, *kb;       // nnz: radix keys
+  int32_t *va, *vb;        // nnz: radix values (positions)
+  int32_t *hist;           // 256 * tiles(nnz)
+  int32_t *agg;            // tiles(max(nnz, 256*tiles, minor+1)) scan aggregates
+  int64_t *agg64;
+  size_t bytes;
+};
+
+Ws plan_ws(void *base, int64_t nnz, int64_t minor) {
+  Ws w{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o += align_up(b, 256);
+    return base ? static_cast<char *>(base) + at : nullptr;
+  };
+  const int64_t nt = tiles(nnz);
+  const int64_t hist_n = kRadix * nt;
+  const int64_t scan_n = std::max<int64_t>({nnz, hist_n, minor + 1, 1});
+  w.major = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz)));
+  w.ka = reinterpret_cast<uint32_t *>(take(4 * static_cast<size_t>(nnz)));
+  w.kb = reinterpret_cast<uint32_t *>(take(4 * static_cast<size_t>(nnz)));
+  w.va = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz)));
+  w.vb = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz)));
+  w.hist = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(hist_n)));
+  w.agg = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(tiles(scan_n) + 1)));
+  w.agg64 = nullptr;
+  w.bytes = o;
+  return w;
+}
+
+// Major index (row of CSR, column of CSC) of every entry.
+msrep_status expand(const int32_t *ptr, int32_t rows, int64_t nnz, int32_t *out, int32_t *agg,
+                    hipStream_t s) {
+  if (nnz == 0) return MSREP_OK;
+  hipLaunchKernelGGL(fill<int32_t>, dim3(grid_for(nnz)), dim3(256), 0, s, out, nnz, int32_t(-1));
+  MSREP_LAUNCHED("fill");
+  hipLaunchKernelGGL(mark_starts, dim3(grid_for(rows)), dim3(256), 0, s, ptr, rows, nnz, out);
+  MSREP_LAUNCHED("mark_starts");
+  return device_scan<int32_t, MaxOp>(out, out, nnz, agg, true, s);
+}
+
+// Pointer of minor+1 entries from unsorted indices: counts, then a scan.
+msrep_status compress_counts(const int32_t *idx, int64_t nnz, int32_t minor, int32_t *ptr,
+                             int32_t *agg, hipStream_t s) {
+  hipLaunchKernelGGL(fill<int32_t>, dim3(grid_for(minor + 1)), dim3(256), 0, s, ptr,
+                     int64_t(minor) + 1, int32_t(0));
+  MSREP_LAUNCHED("fill");
+  if (nnz > 0) {
+    hipLaunchKernelGGL(histogram, dim3(grid_for(nnz)), dim3(256), 0, s, idx, nnz, minor, ptr);
+    MSREP_LAUNCHED("histogram");
+  }
+  return device_scan<int32_t, SumOp>(ptr, ptr, int64_t(minor) + 1, agg, true, s);
+}
+
+// Stable sort of positions 0..nnz-1 by key (keys < 2^bits); returns the
+// buffer holding the permutation and the sorted keys.
+msrep_status stable_sort(const int32_t *keys, int64_t nnz, int bits, Ws &w, hipStream_t s,
+                         int32_t **perm, uint32_t **sorted) {
+  uint32_t *kin = w.ka, *kout = w.kb;
+  int32_t *vin = w.va, *vout = w.vb;
+  MSREP_HIP(hipMemcpyAsync(kin, keys, 4 * static_cast<size_t>(nnz), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(iota, dim3(grid_for(nnz)), dim3(256), 0, s, vin, nnz);
+  MSREP_LAUNCHED("iota");
+  const int64_t nt = tiles(nnz);
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(radix_hist, dim3(nt), dim3(kBlock), 0, s, kin, nnz, shift, nt, w.hist);
+    MSREP_LAUNCHED("radix_hist");
+    if (msrep_status st = device_scan<int32_t, SumOp>(w.hist, w.hist, kRadix * nt, w.agg, false, s))
+      return st;
+    hipLaunchKernelGGL(radix_scatter, dim3(nt), dim3(kBlock), 0, s, kin, vin, nnz, shift, nt,
+                       w.hist, kout, vout);
+    MSREP_LAUNCHED("radix_scatter");
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  *perm = vin;
+  *sorted = kin;
+  return MSREP_OK;
+}
+
+int key_bits(int64_t range) {
+  int b = 1;
+  while (b < 32 && (int64_t(1) << b) < range) ++b;
+  return b;
+}
+
+msrep_status gather_values(const void *src, const int32_t *perm, int64_t nnz, int32_t vtype,
+                           void *dst, hipStream_t s) {
+  const int g = grid_for(nnz);
+  switch (value_bytes(vtype)) {
+    case 8:
+      hipLaunchKernelGGL(gather<uint64_t>, dim3(g), dim3(256), 0, s,
+                         static_cast<const uint64_t *>(src), perm, nnz, static_cast<uint64_t *>(dst));
+      break;
+    case 4:
+      hipLaunchKernelGGL(gather<uint32_t>, dim3(g), dim3(256), 0, s,
+                         static_cast<const uint32_t *>(src), perm, nnz, static_cast<uint32_t *>(dst));
+      break;
+    default:
+      hipLaunchKernelGGL(gather<uint16_t>, dim3(g), dim3(256), 0, s,
+                         static_cast<const uint16_t *>(src), perm, nnz, static_cast<uint16_t *>(dst));
+  }
+  MSREP_LAUNCHED("gather");
+  return MSREP_OK;
+}
+
+}  // namespace
+}  // namespace msrep
+
+using namespace msrep;
+
+extern "C" size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt) {
+  if (!src || src->nnz < 0 || src->m < 0 || src->n < 0) return 0;
+  (void)dst_fmt;
+  const int64_t minor = std::max(src->m, src->n);
+  return plan_ws(nullptr, src->nnz, minor).bytes;
+}
+
 extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,
                                       size_t ws_bytes, void *stream) {
-  (void)src; (void)dst; (void)ws_d; (void)ws_bytes; (void)stream;
-  return fail(MSREP_ERR_UNSUPPORTED, "msrep_convert: not built yet");
+  if (msrep_status st = check_mat(src, "msrep_convert")) return st;
+  if (!dst) return fail(MSREP_ERR_ARG, "msrep_convert: dst is NULL");
+  if (dst->fmt < MSREP_CSR || dst->fmt > MSREP_COO)
+    return fail(MSREP_ERR_ARG, "msrep_convert: unknown target format %d", dst->fmt);
+  if (dst->m != src->m || dst->n != src->n || dst->nnz != src->nnz || dst->vtype != src->vtype)
+    return fail(MSREP_ERR_ARG, "msrep_convert: dst shape/nnz/vtype differ from src");
+  const int64_t nnz = src->nnz;
+  int32_t *dptr = const_cast<int32_t *>(dst->ptr);
+  int32_t *didx = const_cast<int32_t *>(dst->idx);
+  int32_t *didx2 = const_cast<int32_t *>(dst->idx2);
+  void *dval = const_cast<void *>(dst->val);
+  if (dst->fmt != MSREP_COO && !dptr) return fail(MSREP_ERR_ARG, "msrep_convert: dst ptr is NULL");
+  if (nnz > 0 && (!didx || !dval || (dst->fmt == MSREP_COO && !didx2)))
+    return fail(MSREP_ERR_ARG, "msrep_convert: dst arrays are NULL");
+  const size_t need = msrep_convert_ws_bytes(src, dst->fmt);
+  if (!ws_d || ws_bytes < need)
+    return fail(MSREP_ERR_SIZE, "msrep_convert: workspace of %zu bytes needed (got %zu)", need,
+                ws_d ? ws_bytes : size_t(0));
+  hipStream_t s = as_stream(stream);
+  Ws w = plan_ws(ws_d, nnz, std::max(src->m, src->n));
+  const size_t vb = static_cast<size_t>(value_bytes(src->vtype)) * nnz;
+  const int sf = src->fmt, df = dst->fmt;
+
+  if (sf == df) {  // same format: a copy
+    const int32_t major = major_dim(src);
+    if (sf != MSREP_COO)
+      MSREP_HIP(hipMemcpyAsync(dptr, src->ptr, 4 * (static_cast<size_t>(major) + 1),
+                               hipMemcpyDeviceToDevice, s));
+    if (nnz > 0) {
+      MSREP_HIP(hipMemcpyAsync(didx, src->idx, 4 * nnz, hipMemcpyDeviceToDevice, s));
+      if (sf == MSREP_COO)
+        MSREP_HIP(hipMemcpyAsync(didx2, src->idx2, 4 * nnz, hipMemcpyDeviceToDevice, s));
+      MSREP_HIP(hipMemcpyAsync(dval, src->val, vb, hipMemcpyDeviceToDevice, s));
+    }
+    return ok();
+  }
+  if (sf == MSREP_CSR && df == MSREP_COO) {
+    if (msrep_status st = expand(src->ptr, src->m, nnz, didx, w.agg, s)) return st;
+    if (nnz > 0) {
+      MSREP_HIP(hipMemcpyAsync(didx2, src->idx, 4 * nnz, hipMemcpyDeviceToDevice, s));
+      MSREP_HIP(hipMemcpyAsync(dval, src->val, vb, hipMemcpyDeviceToDevice, s));
+    }
+    return ok();
+  }
+  if (sf == MSREP_COO && df == MSREP_CSR) {
+    hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for(nnz + 1)), dim3(256), 0, s, src->idx, nnz,
+                       src->m, dptr);
+    MSREP_LAUNCHED("rows_to_ptr");
+    if (nnz > 0) {
+      MSREP_HIP(hipMemcpyAsync(didx, src->idx2, 4 * nnz, hipMemcpyDeviceToDevice, s));
+      MSREP_HIP(hipMemcpyAsync(dval, src->val, vb, hipMemcpyDeviceToDevice, s));
+    }
+    return ok();
+  }
+  // the transposing conversions: sort positions by the new major index
+  //   CSR -> CSC: key = column (idx), other index = row (expanded ptr)
+  //   COO -> CSC: key = column (idx2), other = row (idx)
+  //   CSC -> CSR / COO: key = row (idx), other = column (expanded ptr)
+  const int32_t *key = nullptr;
+  const int32_t *other = nullptr;
+  int32_t key_range = 0;
+  if (sf == MSREP_CSR || sf == MSREP_CSC) {
+    if (msrep_status st = expand(src->ptr, major_dim(src), nnz, w.major, w.agg, s)) return st;
+    other = w.major;
+    key = src->idx;
+    key_range = sf == MSREP_CSR ? src->n : src->m;
+  } else {  // COO -> CSC
+    other = src->idx;
+    key = src->idx2;
+    key_range = src->n;
+  }
+  if (df == MSREP_CSC || df == MSREP_CSR) {
+    if (msrep_status st = compress_counts(key, nnz, key_range, dptr, w.agg, s)) return st;
+  }
+  if (nnz == 0) return ok();
+  int32_t *perm = nullptr;
+  uint32_t *sorted = nullptr;
+  if (msrep_status st = stable_sort(key, nnz, key_bits(key_range), w, s, &perm, &sorted)) return st;
+  const int g = grid_for(nnz);
+  if (df == MSREP_COO) {  // CSC -> COO: rows are the sorted keys, columns gathered
+    MSREP_HIP(hipMemcpyAsync(didx, sorted, 4 * nnz, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(gather<int32_t>, dim3(g), dim3(256), 0, s, other, perm, nnz, didx2);
+  } else {
+    hipLaunchKernelGGL(gather<int32_t>, dim3(g), dim3(256), 0, s, other, perm, nnz, didx);
+  }
+  MSREP_LAUNCHED("gather");
+  if (msrep_status st = gather_values(src->val, perm, nnz, src->vtype, dval, s)) return st;
+  return ok();
 }

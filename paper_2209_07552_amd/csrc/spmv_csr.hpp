@@ -135,26 +135,23 @@ __device__ __forceinline__ void scale_rows(T *__restrict__ y, int32_t lo, int32_
     y[r] = beta0 ? static_cast<T>(0) : static_cast<T>(beta * static_cast<double>(y[r]));
 }
 
+// One wavefront processes partition p of a CSR matrix (the routine shared by
+// the single-matrix kernel and the persistent batched kernel).  `carry`
+// points at this matrix's two FP64 slots per partition; `my` at this
+// wavefront's LDS region (seg_lds_per_wave bytes).
 template <int VT, int K, bool BETA0>
-__global__ __launch_bounds__(512) void spmv_csr_seg(
+__device__ __forceinline__ void csr_partition(
     const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
-    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
+    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np, int32_t p,
     const typename vt_traits<VT>::T *__restrict__ x, typename vt_traits<VT>::T *__restrict__ y,
-    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
+    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry,
+    unsigned char *my) {
   using Tr = vt_traits<VT>;
   using V = typename Tr::V;
   using T = typename Tr::T;
   using Acc = typename Tr::A;
   constexpr int CH = kWave * K;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-
   const int lane = lane_id();
-  const int wid = threadIdx.x / kWave;
-  const int wpb = blockDim.x / kWave;
-  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
-  if (p >= np) return;  // whole wavefront; the kernel has no block barrier
-
-  unsigned char *my = lds_raw + wid * seg_lds_per_wave<VT, K>();
   Acc *s_sum = reinterpret_cast<Acc *>(my);
   unsigned char *s_head = my + align_up(CH * sizeof(Acc), 16);
 
@@ -313,6 +310,22 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
   if (!eflag) scale_rows<T>(y, gap_lo > 0 ? gap_lo : 0, gap_hi, beta, BETA0);
   if (p == 0) scale_rows<T>(y, 0, r0 < m ? r0 : m, beta, BETA0);
 }
+
+template <int VT, int K, bool BETA0>
+__global__ __launch_bounds__(512) void spmv_csr_seg(
+    const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
+    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
+    const typename vt_traits<VT>::T *__restrict__ x, typename vt_traits<VT>::T *__restrict__ y,
+    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int wid = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
+  if (p >= np) return;  // whole wavefront; the kernel has no block barrier
+  csr_partition<VT, K, BETA0>(col, val, parts, lptr, np, p, x, y, m, n, alpha, beta, carry,
+                              lds_raw + wid * seg_lds_per_wave<VT, K>());
+}
+
 
 // Boundary merge for row-split formats (CSR, COO): one thread per partition.
 // The partition that holds a split row's first nonzero (end_flag set, not a

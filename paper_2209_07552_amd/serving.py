@@ -1,0 +1,106 @@
+"""Binding of msrep_serve / msrep_serve_simulate (argument marshalling only).
+
+A pool entry is a host CSR matrix (ptr, col, val numpy arrays, FP64 or FP32
+values).  For msrep_serve the arrays are copied once into pinned host memory
+so that uploads into the arena are asynchronous; the arena is one device
+tensor of `budget_bytes`.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _abi
+from ._abi import F32, F64, MsrepError, _check, _HostMat, _Mat, _Request, _Result, _ServeCfg, \
+    _ServeStats, load_library
+
+
+@dataclass
+class ServeResult:
+    t_arrive: float
+    t_admit: float
+    t_done: float
+    status: int
+    y: Optional[np.ndarray] = None
+
+
+def _bind(L):
+    P = ctypes.POINTER
+    f = L.msrep_serve_simulate
+    f.restype = ctypes.c_int32
+    f.argtypes = [P(_ServeCfg), P(_HostMat), ctypes.c_int32, P(_Request), ctypes.c_int64,
+                  P(_Result), P(_ServeStats), ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    g = L.msrep_serve_x_value
+    g.restype = ctypes.c_double
+    g.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64]
+
+
+def x_value(seed, rid, step, c):
+    L = load_library()
+    _bind(L)
+    return float(L.msrep_serve_x_value(seed, rid, step, c))
+
+
+def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 256,
+          nnz_per_wave: int = 1024, vtype: int = F64, seed: int = 0, time_scale: float = 1.0,
+          keep_y: bool = False, simulate: bool = False, sim=(0.0, 0.0, -1.0), nps=None):
+    """Run a request trace.  pool: list of synth.Csr (or objects with m, n,
+    ptr, col, val); trace: list of synth.Request.  Returns (results, stats)."""
+    L = load_library()
+    _bind(L)
+    keep = []
+    hm = (_HostMat * len(pool))()
+    vdt = np.float64 if vtype == F64 else np.float32
+    xdt = vdt
+    torch = None
+    if not simulate:
+        import torch as _t
+        torch = _t
+        if not torch.cuda.is_available():
+            raise MsrepError(-4, "msrep_serve needs a GPU")
+    for k, A in enumerate(pool):
+        ptr = np.ascontiguousarray(A.ptr, np.int32)
+        col = np.ascontiguousarray(A.col, np.int32)
+        val = np.ascontiguousarray(A.val, vdt)
+        if torch is not None:  # pinned host copies
+            arrs = [torch.from_numpy(a).pin_memory() for a in (ptr, col, val)]
+            keep.extend(arrs)
+            pp, cp, vp = (a.data_ptr() for a in arrs)
+        else:
+            keep.extend((ptr, col, val))
+            pp, cp, vp = ptr.ctypes.data, col.ctypes.data, val.ctypes.data
+        hm[k].A = _Mat(0, vtype, A.m, A.n, int(ptr[-1]), pp, cp, None, vp)
+        hm[k].np = 0 if nps is None else int(nps[k])
+    n = len(trace)
+    tr = (_Request * max(n, 1))()
+    for i, r in enumerate(trace):
+        tr[i] = _Request(r.rid, r.t_arrive, r.matrix, r.steps)
+    res = (_Result * max(n, 1))()
+    ybufs = []
+    if keep_y:
+        for i, r in enumerate(trace):
+            y = np.zeros(pool[r.matrix].m, xdt)
+            ybufs.append(y)
+            res[i].y_host = y.ctypes.data
+    arena = None
+    if not simulate:
+        arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
+    cfg = _ServeCfg(None if arena is None else arena.data_ptr(), int(budget_bytes), int(max_slots),
+                    int(nnz_per_wave), int(seed), float(time_scale), int(keep_y), 0)
+    st = _ServeStats()
+    if simulate:
+        rc = L.msrep_serve_simulate(ctypes.byref(cfg), hm, len(pool), tr, n, res,
+                                    ctypes.byref(st), float(sim[0]), float(sim[1]), float(sim[2]))
+    else:
+        rc = L.msrep_serve(ctypes.byref(cfg), hm, len(pool), tr, n, res, ctypes.byref(st))
+    _check(rc, "serve")
+    out: List[ServeResult] = []
+    for i in range(n):
+        out.append(ServeResult(res[i].t_arrive, res[i].t_admit, res[i].t_done, res[i].status,
+                               ybufs[i] if keep_y else None))
+    stats = {f: getattr(st, f) for f, _ in _ServeStats._fields_ if not f.startswith("_")}
+    del keep
+    return out, stats

@@ -224,3 +224,28 @@ def bf16_bits(v32: np.ndarray) -> np.ndarray:
 
 def bf16_to_f64(bits: np.ndarray) -> np.ndarray:
     return (np.asarray(bits, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_SM_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_SM_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(key: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function (Steele, Lea, Flood 2014) of uint64 keys."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(key, np.uint64) + _SM_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _SM_M1
+        z = (z ^ (z >> np.uint64(27))) * _SM_M2
+        return z ^ (z >> np.uint64(31))
+
+
+def serving_x(n: int, seed: int, rid: int, step: int) -> np.ndarray:
+    """Fresh x of step `step` of request `rid` in the serving loop:
+    x[c] = 2u - 1, u = top 53 bits of splitmix64(key) / 2^53,
+    key = seed ^ (rid << 40) ^ (step << 24) ^ c."""
+    c = np.arange(n, dtype=np.uint64)
+    key = (np.uint64(seed) ^ (np.uint64(rid) << np.uint64(40)) ^
+           (np.uint64(step) << np.uint64(24))) ^ c
+    u = (splitmix64(key) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return 2.0 * u - 1.0

@@ -1,0 +1,103 @@
+"""CPU tests of the serving scheduler through msrep_serve_simulate (the same
+admission / residency / continuous-batching code as msrep_serve, driven by a
+virtual device clock)."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pk = pytest.importorskip("paper_2209_07552_amd")
+from paper_2209_07552_amd import serving  # noqa: E402
+
+if not os.path.exists(pk.lib_path()):
+    pytest.skip("libmsrep.so not built", allow_module_level=True)
+
+
+def _pool(count=6, m_hi=20_000):
+    return [A for A, _ in synth.batched_set(count, seed=3, m_lo=500, m_hi=m_hi)]
+
+
+def _bytes(A, np_, xb=8):
+    r = lambda b: (b + 255) // 256 * 256
+    mat = r(4 * (A.m + 1)) + r(4 * A.nnz) + r(xb * A.nnz)
+    req = r(xb * A.n) + r(xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) + r(16 * np_)
+    return mat, req
+
+
+def test_all_complete_with_a_large_budget():
+    pool = _pool()
+    trace = synth.serving_trace(40, rate=2000.0, pool=len(pool), seed=1, k_lo=3, k_hi=12)
+    res, st = serving.serve(pool, trace, budget_bytes=1 << 34, simulate=True)
+    assert all(r.status == 0 for r in res)
+    for r, q in zip(res, trace):
+        assert r.t_arrive == q.t_arrive and r.t_admit >= r.t_arrive and r.t_done > r.t_admit
+    assert st["n_done"] == 40 and st["n_failed"] == 0
+    assert st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    # continuous batching: far fewer ticks than SpMV steps
+    assert st["ticks"] < sum(q.steps for q in trace)
+    assert st["peak_active"] > 1
+
+
+def test_request_that_can_never_fit_fails_alone():
+    pool = _pool()
+    big = max(range(len(pool)), key=lambda k: pool[k].nnz)
+    mat, req = _bytes(pool[big], max(1, -(-pool[big].nnz // 1024)))
+    budget = mat + req - 4096  # too small for the largest matrix only
+    others = [k for k in range(len(pool)) if sum(_bytes(pool[k], max(1, -(-pool[k].nnz // 1024)))) + 512 <= budget]
+    trace = [synth.Request(0, 0.0, big, 5)] + [synth.Request(i + 1, 1e-4 * i, k, 4)
+                                               for i, k in enumerate(others)]
+    res, st = serving.serve(pool, trace, budget_bytes=budget, simulate=True)
+    assert res[0].status == pk._abi.MsrepError(-5, "").status
+    assert all(r.status == 0 for r in res[1:])
+    assert st["peak_bytes"] <= budget
+
+
+def test_budget_bounds_residency_and_queues():
+    pool = _pool()
+    sizes = [sum(_bytes(A, max(1, -(-A.nnz // 1024)))) for A in pool]
+    budget = max(sizes) + 1024  # room for one request of any matrix at a time
+    trace = synth.serving_trace(30, rate=1e6, pool=len(pool), seed=2, k_lo=2, k_hi=6)
+    res, st = serving.serve(pool, trace, budget_bytes=budget, simulate=True)
+    assert all(r.status == 0 for r in res)
+    assert st["peak_bytes"] <= budget
+    # requests on different matrices never overlapped: each waited its turn
+    iv = sorted((r.t_admit, r.t_done, q.matrix) for r, q in zip(res, trace))
+    for (a0, d0, m0), (a1, d1, m1) in zip(iv, iv[1:]):
+        if m0 != m1 and sizes[m0] + sizes[m1] - 0 > budget:
+            assert a1 >= d0 - 1e-12
+
+
+def test_max_slots_one_serialises():
+    pool = _pool()
+    trace = synth.serving_trace(12, rate=1e6, pool=len(pool), seed=4, k_lo=2, k_hi=5)
+    res, st = serving.serve(pool, trace, budget_bytes=1 << 34, max_slots=1, simulate=True)
+    iv = sorted((r.t_admit, r.t_done) for r in res)
+    for (a0, d0), (a1, d1) in zip(iv, iv[1:]):
+        assert a1 >= d0 - 1e-12
+    assert st["peak_active"] == 1
+
+
+def test_simulation_is_deterministic():
+    pool = _pool()
+    trace = synth.serving_trace(25, rate=5000.0, pool=len(pool), seed=5, k_lo=3, k_hi=9)
+    a = serving.serve(pool, trace, budget_bytes=1 << 30, simulate=True)
+    b = serving.serve(pool, trace, budget_bytes=1 << 30, simulate=True)
+    assert [(r.t_admit, r.t_done) for r in a[0]] == [(r.t_admit, r.t_done) for r in b[0]]
+    assert a[1] == b[1]
+
+
+def test_bad_requests_rejected():
+    pool = _pool(2)
+    with pytest.raises(pk.MsrepError):
+        serving.serve(pool, [synth.Request(0, 0.0, 5, 3)], budget_bytes=1 << 30, simulate=True)
+    with pytest.raises(pk.MsrepError):
+        serving.serve(pool, [synth.Request(0, 0.0, 0, 0)], budget_bytes=1 << 30, simulate=True)
+
+
+def test_x_generator_matches_published_definition():
+    xs = [serving.x_value(11, 7, 3, c) for c in range(16)]
+    assert np.array_equal(np.array(xs), synth.serving_x(16, 11, 7, 3))
+    # known SplitMix64 output for key 0 (first output of a generator seeded 0)
+    assert int(synth.splitmix64(np.array([0], np.uint64))[0]) == 0xE220A8397B1DCDAF
