@@ -109,7 +109,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20", choices=["rmat20", "stencil256", "uniform4096"])
+    ap.add_argument("--workload", default="rmat20",
+                    choices=["rmat20", "stencil256", "uniform4096", "batched", "serve"])
+    ap.add_argument("--count", type=int, default=512, help="batched / serving pool size")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
+    ap.add_argument("--rates", default="0.1,0.5,0.9,1.2", help="serving: fractions of capacity")
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--vtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--formats", default="csr,csc,coo")
     ap.add_argument("--nnz-per-wave", type=int, default=0, help="partition size (0: tuned)")
@@ -133,6 +138,10 @@ def main():
         return 1
     dev = torch.device("cuda:0")
     vt = {"f64": pk.F64, "f32": pk.F32, "bf16": pk.BF16}[args.vtype]
+    if args.workload == "batched":
+        return bench_batched(args, vt)
+    if args.workload == "serve":
+        return bench_serve(args, vt)
     t0 = time.time()
     if args.workload == "rmat20":
         A, x64 = synth.rmat_csr(scale=20, edge_factor=16, seed=0)
@@ -259,6 +268,142 @@ def main():
             cb, err = cpu_baseline(A, x64, yg, args.cpu_budget)
             out["cpu_baseline"] = cb
             out["max_scaled_error_vs_fp64_oracle"] = err
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _timed(fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(args, vt):
+    """512 uneven matrices (log-uniform rows in [1e3, 2e5], half uniform 4-64
+    nnz/row, half R-MAT-like) in one persistent hipGraph launch, against the
+    plain path (one msrep_spmv launch per matrix, same partitions)."""
+    import torch
+
+    import paper_2209_07552_amd as pk
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    mats = synth.batched_set(args.count, seed=0)
+    log("generated %d matrices in %.1fs" % (args.count, time.time() - t0))
+    vdt = np.float64 if vt == pk.F64 else np.float32
+    Ms = [pk.Mat(pk.CSR, vt, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val.astype(vdt)) for A, _ in mats]
+    xs = [torch.from_numpy(x.astype(vdt)).to(dev) for _, x in mats]
+    ys = [torch.zeros(A.m, dtype=xs[0].dtype, device=dev) for A, _ in mats]
+    nnz = sum(A.nnz for A, _ in mats)
+    xb = 8 if vt == pk.F64 else 4
+    byts = sum(A.nnz * (pk._abi.VALUE_BYTES[vt] + 4) + (A.m + 1) * 4 + (A.n + A.m) * xb for A, _ in mats)
+    # autotuned partition size per matrix class (uniform / power-law x size)
+    t0 = time.time()
+    classes = {}
+    for k, (A, _) in enumerate(mats):
+        key = (k % 2, int(np.log10(max(A.m, 10))))
+        classes.setdefault(key, k)
+    tuned = {key: pk.msrep_autotune(Ms[k], xs[k]) for key, k in classes.items()}
+    tunes = [pk.Tune(k_per_lane=4, waves_per_wg=4,
+                     nnz_per_wave=tuned[(k % 2, int(np.log10(max(A.m, 10))))].nnz_per_wave)
+             for k, (A, _) in enumerate(mats)]
+    log("autotuned %d classes in %.1fs" % (len(classes), time.time() - t0))
+    plan = pk.msrep_plan_create(Ms, tunes)
+    for _ in range(args.warmup):
+        pk.msrep_spmv_batched(plan, xs, ys)
+    ms_b = _timed(lambda: pk.msrep_spmv_batched(plan, xs, ys), args.steps)
+    # plain path: one launch (plus merge) per matrix
+    parts = [pk.msrep_build_partition(M, max(1, -(-M.nnz // t.nnz_per_wave))) for M, t in zip(Ms, tunes)]
+    ws = torch.zeros(1 << 26, dtype=torch.uint8, device=dev)
+
+    def plain():
+        for M, P, x, y, t in zip(Ms, parts, xs, ys, tunes):
+            pk.msrep_spmv(M, P, x, y, 1.0, 0.0, t, ws=ws)
+    for _ in range(args.warmup):
+        plain()
+    ms_p = _timed(plain, max(1, args.steps // 4))
+    out = {"metric": "batched SpMV/s (%d uneven matrices, one persistent hipGraph launch)" % args.count,
+           "value": round(args.count / (ms_b * 1e-3), 1), "unit": "SpMV/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.vtype,
+           "data": "synthetic",
+           "config": {"workload": "batched-%d" % args.count, "total_nnz": nnz, "items": plan.items()},
+           "gflops": round(2.0 * nnz / (ms_b * 1e-3) / 1e9, 2),
+           "alg_gbs": round(byts / (ms_b * 1e-3) / 1e9, 1),
+           "plain_path": {"ms_per_batch": round(ms_p, 4),
+                          "spmv_per_s": round(args.count / (ms_p * 1e-3), 1)},
+           "speedup_vs_plain": round(ms_p / ms_b, 3)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args, vt):
+    """Poisson request stream over a pool of batched-style matrices; each
+    request = one matrix + 10..100 SpMVs with fresh x; arena budget as given.
+    Rates are fractions of the measured batched capacity.  Beside it, the
+    plain FP64 path: one request at a time, one msrep_spmv launch per SpMV."""
+    import torch
+
+    import paper_2209_07552_amd as pk
+    from paper_2209_07552_amd import serving
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool = [A for A, _ in synth.batched_set(args.count, seed=0)]
+    log("generated pool of %d in %.1fs" % (len(pool), time.time() - t0))
+    mean_steps = 55.0
+    # capacity estimate from a saturated run: SpMVs per second of the mix
+    probe = synth.serving_trace(max(64, args.count // 4), rate=1e9, pool=len(pool), seed=99)
+    _, st = serving.serve(pool, probe, budget_bytes=int(args.budget_gb * (1 << 30)), vtype=vt,
+                          max_slots=256)
+    cap_req = st["spmv_per_s"] / mean_steps
+    log("saturated mix: %.0f SpMV/s -> capacity ~%.1f req/s" % (st["spmv_per_s"], cap_req))
+    points = []
+    for f in [float(v) for v in args.rates.split(",")]:
+        trace = synth.serving_trace(args.requests, rate=max(f * cap_req, 1e-3), pool=len(pool), seed=1)
+        _, st = serving.serve(pool, trace, budget_bytes=int(args.budget_gb * (1 << 30)), vtype=vt,
+                              max_slots=256)
+        points.append({"load": f, "rate_req_s": round(f * cap_req, 2),
+                       "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                       "req_per_s": round(st["req_per_s"], 2),
+                       "spmv_per_s": round(st["spmv_per_s"], 1), "gflops": round(st["gflops"], 2),
+                       "peak_active": st["peak_active"], "ticks": st["ticks"]})
+        log(json.dumps(points[-1]))
+    # plain FP64 path: requests one after another, one launch per SpMV
+    sample = synth.serving_trace(64, rate=1.0, pool=len(pool), seed=1)
+    ws = torch.zeros(1 << 26, dtype=torch.uint8, device=dev)
+    lat = []
+    for q in sample:
+        A = pool[q.matrix]
+        M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val)
+        P = pk.msrep_build_partition(M, max(1, -(-A.nnz // 1024)))
+        x = torch.empty(A.n, dtype=torch.float64, device=dev)
+        y = torch.empty(A.m, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for j in range(q.steps):
+            x.copy_(torch.from_numpy(synth.serving_x(A.n, 0, q.rid, j)), non_blocking=False)
+            pk.msrep_spmv(M, P, x, y, ws=ws)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    best = max(points, key=lambda p: p["req_per_s"])
+    out = {"metric": "served p50/p99 latency and req/s (Poisson, continuous batching)",
+           "value": best["req_per_s"], "unit": "req/s", "n_gpus": 1, "steps": args.requests,
+           "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.vtype, "data": "synthetic",
+           "config": {"workload": "serve-pool%d" % len(pool), "budget_gb": args.budget_gb,
+                      "steps_per_request": "U{10..100}"},
+           "points": points,
+           "plain_fp64_one_request_at_a_time": {
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "req_per_s": round(1e3 / float(np.mean(lat)), 2),
+               "note": "service time only (no queueing); x generated on the host per step"}}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -154,6 +154,9 @@ typedef struct msrep_tune {
                         /* row (CSR only; for short, even rows)                */
   int32_t nnz_per_wave; /* partition size the autotuner recommends, so that    */
                         /* np = ceil(nnz / nnz_per_wave); not read by msrep_spmv */
+  int32_t pipeline;     /* CSR: chunks of indices/values loaded ahead, 1 or 2  */
+                        /* (2 also gathers x one chunk ahead); 0 = default 2   */
+  int32_t _pad;
 } msrep_tune;
 
 /* Workspace bytes msrep_spmv needs for np partitions (16*np: two FP64 partial

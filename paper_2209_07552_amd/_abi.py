@@ -38,7 +38,7 @@ class _Mat(ctypes.Structure):
 
 class _Tune(ctypes.Structure):
     _fields_ = [("k_per_lane", c_i32), ("waves_per_wg", c_i32), ("rows_per_wave", c_i32),
-                ("nnz_per_wave", c_i32)]
+                ("nnz_per_wave", c_i32), ("pipeline", c_i32), ("_pad", c_i32)]
 
 
 class _HostMat(ctypes.Structure):
@@ -252,9 +252,11 @@ class Tune:
     waves_per_wg: int = 0
     rows_per_wave: int = 0
     nnz_per_wave: int = 0
+    pipeline: int = 0
 
     def c(self) -> _Tune:
-        return _Tune(self.k_per_lane, self.waves_per_wg, self.rows_per_wave, self.nnz_per_wave)
+        return _Tune(self.k_per_lane, self.waves_per_wg, self.rows_per_wave, self.nnz_per_wave,
+                     self.pipeline, 0)
 
 
 class Partition:
@@ -346,7 +348,8 @@ def msrep_autotune(A: Mat, x, stream=None) -> Tune:
     out = _Tune()
     _check(L.msrep_autotune(ctypes.byref(d), _ptr(x), _ptr(ws), ws.numel(), ctypes.byref(out),
                             _stream(stream)), "autotune")
-    return Tune(out.k_per_lane, out.waves_per_wg, out.rows_per_wave, out.nnz_per_wave)
+    return Tune(out.k_per_lane, out.waves_per_wg, out.rows_per_wave, out.nnz_per_wave,
+                out.pipeline)
 
 
 class Plan:

@@ -58,14 +58,20 @@ namespace {
 template <int VT, int K, bool B0>
 msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                         int32_t np, const void *x, void *y, double alpha, double beta, int wpb,
-                        double *carry, hipStream_t s) {
+                        int pf, double *carry, hipStream_t s) {
   using Tr = vt_traits<VT>;
   const size_t lds = seg_lds_per_wave<VT, K>() * wpb;
   const int grid = (np + wpb - 1) / wpb;
-  hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
-                     static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
-                     static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
-                     A->m, A->n, alpha, beta, carry);
+  if (pf == 1)
+    hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 1>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
+                       static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
+                       static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
+                       A->m, A->n, alpha, beta, carry);
+  else
+    hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 2>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
+                       static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
+                       static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
+                       A->m, A->n, alpha, beta, carry);
   MSREP_LAUNCHED("spmv_csr_seg");
   return MSREP_OK;
 }
@@ -121,16 +127,16 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
 template <int VT, int K, bool B0>
 msrep_status dispatch_rows(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                            int32_t np, const void *x, void *y, double alpha, double beta,
-                           int wpb, double *carry, hipStream_t s) {
+                           int wpb, int pf, double *carry, hipStream_t s) {
   if (A->fmt == MSREP_CSR)
-    return launch_csr<VT, K, B0>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+    return launch_csr<VT, K, B0>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s);
   return launch_coo<VT, K, B0>(A, parts, np, x, y, alpha, beta, wpb, carry, s);
 }
 
 template <int VT>
 msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
-                         int wpb, double *carry, hipStream_t s) {
+                         int wpb, int pf, double *carry, hipStream_t s) {
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
@@ -139,11 +145,11 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
                   : launch_csc<VT, 4>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
   }
   if (K == 8)
-    st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
-            : dispatch_rows<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+    st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s)
+            : dispatch_rows<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s);
   else
-    st = b0 ? dispatch_rows<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
-            : dispatch_rows<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+    st = b0 ? dispatch_rows<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s)
+            : dispatch_rows<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s);
   if (st) return st;
   if (np > 1) {
     const int g = (np + 255) / 256;
@@ -160,10 +166,14 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
 
 }  // namespace
 
-msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, const char *who) {
+msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, const char *who) {
   *K = 4;
   *wpb = 4;
+  *pf = 2;
   if (!tune) return MSREP_OK;
+  if (tune->pipeline < 0 || tune->pipeline > 2)
+    return fail(MSREP_ERR_ARG, "%s: pipeline must be 0, 1 or 2 (got %d)", who, tune->pipeline);
+  if (tune->pipeline) *pf = tune->pipeline;
   if (tune->k_per_lane != 0 && tune->k_per_lane != 4 && tune->k_per_lane != 8)
     return fail(MSREP_ERR_ARG, "%s: k_per_lane must be 4 or 8 (got %d)", who, tune->k_per_lane);
   if (tune->waves_per_wg < 0 || tune->waves_per_wg > 8)
@@ -177,14 +187,14 @@ msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, const char *
 
 msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
-                         int wpb, double *carry, hipStream_t s) {
+                         int wpb, int pf, double *carry, hipStream_t s) {
   switch (A->vtype) {
     case MSREP_F64:
-      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, carry, s);
+      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, s);
     case MSREP_F32:
-      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, carry, s);
+      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, s);
     default:
-      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, carry, s);
+      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, s);
   }
 }
 
@@ -216,8 +226,8 @@ extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d
   if (A->fmt != MSREP_COO && !lptr_d) return fail(MSREP_ERR_ARG, "msrep_spmv: lptr_d is NULL");
   if (A->m > 0 && !y_d) return fail(MSREP_ERR_ARG, "msrep_spmv: y_d is NULL");
   if (A->nnz > 0 && !x_d) return fail(MSREP_ERR_ARG, "msrep_spmv: x_d is NULL");
-  int K, wpb;
-  if (msrep_status st = resolve_tune(tune, &K, &wpb, "msrep_spmv")) return st;
+  int K, wpb, pf;
+  if (msrep_status st = resolve_tune(tune, &K, &wpb, &pf, "msrep_spmv")) return st;
   if (tune && tune->rows_per_wave > 0 && A->fmt != MSREP_CSR)
     return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: rows_per_wave kernel is CSR only");
   // x, y and the local pointers are addressed through 32-bit buffer offsets
@@ -231,7 +241,7 @@ extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d
     return fail(MSREP_ERR_SIZE, "msrep_spmv: workspace of %zu bytes needed (got %zu)", need,
                 ws_d ? ws_bytes : size_t(0));
   if (A->m == 0) return ok();
-  if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb,
+  if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb, pf,
                                     static_cast<double *>(ws_d), as_stream(stream)))
     return st;
   return ok();

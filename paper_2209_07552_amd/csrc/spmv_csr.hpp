@@ -139,7 +139,7 @@ __device__ __forceinline__ void scale_rows(T *__restrict__ y, int32_t lo, int32_
 // the single-matrix kernel and the persistent batched kernel).  `carry`
 // points at this matrix's two FP64 slots per partition; `my` at this
 // wavefront's LDS region (seg_lds_per_wave bytes).
-template <int VT, int K, bool BETA0>
+template <int VT, int K, bool BETA0, int PF = 1>
 __device__ __forceinline__ void csr_partition(
     const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
     const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np, int32_t p,
@@ -169,29 +169,44 @@ __device__ __forceinline__ void csr_partition(
   bool carry_on = false;
   int32_t j0 = 0;         // first local row of the current chunk
   const int32_t lead = static_cast<int32_t>(s0 % K);  // align item groups to K
-  // the chunk's column indices and values are loaded one chunk ahead
+  // software pipeline: with PF == 1 the chunk's column indices and values are
+  // loaded one chunk ahead; with PF == 2 they are loaded two chunks ahead and
+  // the x gather runs one chunk ahead, so every wavefront keeps its gathers in
+  // flight while it scans.
   const rsrc_t rx = make_rsrc(x, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(T)));
   const rsrc_t rl = make_rsrc(lp, static_cast<uint32_t>(R + 1 > 0 ? R + 1 : 0) * 4u);
-  int32_t c_cur[K];
-  V v_cur[K];
+  auto gather = [&](const int32_t(&c)[K], T(&xv)[K]) {
+    // (index -1 and columns >= n read as 0 through the x resource)
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      xv[t] = buf_load<T>(rx, static_cast<uint32_t>(c[t]) * static_cast<uint32_t>(sizeof(T)));
+  };
+  int32_t c_cur[K], c_nxt[K];
+  V v_cur[K], v_nxt[K];
+  T xv_cur[K], xv_nxt[K];
   load_items<V, K>(col, val, s0, -lead, nloc, c_cur, v_cur);
+  if constexpr (PF == 2) {
+    gather(c_cur, xv_cur);
+    load_items<V, K>(col, val, s0, -lead + CH, nloc, c_nxt, v_nxt);
+  }
   for (int32_t cb = -lead; cb < nloc; cb += CH) {
     const int32_t cs = cb > 0 ? cb : 0;                 // first valid local position
     const int32_t ce = cb + CH < nloc ? cb + CH : nloc;  // one past the last
-    // ---- 1. issue: x gathers, the first batch of local row pointers, and
-    //         the next chunk's indices and values
-    // (index -1 and columns >= n read as 0 through the x resource)
-    T xv[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t)
-      xv[t] = buf_load<T>(rx, static_cast<uint32_t>(c_cur[t]) * static_cast<uint32_t>(sizeof(T)));
+    // ---- 1. issue: the first batch of local row pointers, then the loads of
+    //         later chunks, while this chunk's products are formed
     const int32_t lpv0 = buf_load<int32_t>(rl, static_cast<uint32_t>(j0 + lane) * 4u);
-    int32_t c_nxt[K];
-    V v_nxt[K];
-    load_items<V, K>(col, val, s0, cb + CH, nloc, c_nxt, v_nxt);
+    int32_t c_nn[K];
+    V v_nn[K];
+    if constexpr (PF == 2) {
+      gather(c_nxt, xv_nxt);
+      load_items<V, K>(col, val, s0, cb + 2 * CH, nloc, c_nn, v_nn);
+    } else {
+      gather(c_cur, xv_cur);
+      load_items<V, K>(col, val, s0, cb + CH, nloc, c_nxt, v_nxt);
+    }
     Acc prod[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv[t]);
+    for (int t = 0; t < K; ++t) prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv_cur[t]);
     // ---- 2. head flags from the local pointer
 #pragma unroll
     for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
@@ -300,6 +315,11 @@ __device__ __forceinline__ void csr_partition(
     for (int t = 0; t < K; ++t) {
       c_cur[t] = c_nxt[t];
       v_cur[t] = v_nxt[t];
+      if constexpr (PF == 2) {
+        xv_cur[t] = xv_nxt[t];
+        c_nxt[t] = c_nn[t];
+        v_nxt[t] = v_nn[t];
+      }
     }
     wave_lds_sync();  // s_sum / s_head are rewritten by the next chunk
   }
@@ -311,7 +331,7 @@ __device__ __forceinline__ void csr_partition(
   if (p == 0) scale_rows<T>(y, 0, r0 < m ? r0 : m, beta, BETA0);
 }
 
-template <int VT, int K, bool BETA0>
+template <int VT, int K, bool BETA0, int PF>
 __global__ __launch_bounds__(512) void spmv_csr_seg(
     const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
     const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
@@ -322,8 +342,8 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
   const int wpb = blockDim.x / kWave;
   const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
   if (p >= np) return;  // whole wavefront; the kernel has no block barrier
-  csr_partition<VT, K, BETA0>(col, val, parts, lptr, np, p, x, y, m, n, alpha, beta, carry,
-                              lds_raw + wid * seg_lds_per_wave<VT, K>());
+  csr_partition<VT, K, BETA0, PF>(col, val, parts, lptr, np, p, x, y, m, n, alpha, beta, carry,
+                                  lds_raw + wid * seg_lds_per_wave<VT, K>());
 }
 
 

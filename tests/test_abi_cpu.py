@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
 def test_struct_sizes():
     assert ctypes.sizeof(_abi._Mat) == 56
     assert pk.PART_DTYPE.itemsize == 40
-    assert ctypes.sizeof(_abi._Tune) == 16
+    assert ctypes.sizeof(_abi._Tune) == 24
 
 
 def test_lptr_bound_and_vtype_bytes():
@@ -73,7 +73,7 @@ def test_spmv_argument_errors():
     st = L.msrep_spmv(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0, None, 0x8000,
                       16, None)
     assert st == -3 and b"workspace" in L.msrep_last_error()
-    t = _abi._Tune(5, 0, 0, 0)
+    t = _abi._Tune(5, 0, 0, 0, 0, 0)
     st = L.msrep_spmv(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0,
                       ctypes.byref(t), 0x8000, 1 << 20, None)
     assert st == -1 and b"k_per_lane" in L.msrep_last_error()

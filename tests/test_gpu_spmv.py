@@ -223,3 +223,15 @@ def test_validate():
     M = pk.Mat(pk.COO, pk.F64, A.m, A.n, idx=rows, idx2=A.col, val=A.val)
     with pytest.raises(pk.MsrepError):
         pk.msrep_validate(M)
+
+
+def test_autotune_returns_a_valid_tune_and_correct_results():
+    A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=9)
+    M, v64 = device_mat(A, "csr", pk.F64)
+    xd = torch.from_numpy(x).to(_dev())
+    t = pk.msrep_autotune(M, xd)
+    assert t.k_per_lane in (4, 8) and t.waves_per_wg in (2, 4, 8)
+    assert t.nnz_per_wave in (256, 512, 1024, 2048, 4096)
+    np_ = max(1, -(-A.nnz // t.nnz_per_wave))
+    y, ref, s = _run(A, x, "csr", pk.F64, np_, tune=t, M=M, v64=v64)
+    assert_close(y, ref, s, F64_TOL, "autotuned")
