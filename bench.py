@@ -64,23 +64,109 @@ def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
     return b
 
 
+COPY_CAL_BYTES = 256 << 20  # plain copy used to calibrate the byte counters
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: a stored counter reading is current only while
+    the kernels are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2209_07552_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def load_traffic(kernel_key):
-    """HBM bytes per launch measured by rocprofv3 counters, if a summary for
-    this kernel and workload is committed and still current."""
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (profiles/traffic.txt), or None when there is none or the kernel
+    sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
+    cur = kernel_source_hash()
     for line in open(path):
         line = line.strip()
-        if not line or line.startswith("#"):
+        if not line.startswith("{"):
             continue
         try:
             rec = json.loads(line)
         except ValueError:
             continue
-        if rec.get("key") == kernel_key and rec.get("current", False):
+        if rec.get("key") == kernel_key and rec.get("source_hash") == cur:
             return rec.get("bytes_per_launch")
     return None
+
+
+def _read_counters(d):
+    """{(kernel name, counter): [values per dispatch]} from a rocprofv3
+    --pmc ... --output-format csv directory."""
+    import csv
+    import glob
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            out.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, kernel, key, command):
+    """Turn two counter runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) into
+    HBM bytes per launch of `kernel`, each counter scaled by what it reads for
+    the plain copy of COPY_CAL_BYTES in the same run; append to
+    profiles/traffic.txt."""
+    out = {}
+    for d, ctr in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        c = _read_counters(d)
+        kv = [v for (k, n), vs in c.items() if n == ctr and kernel in k for v in vs]
+        cv = [v for (k, n), vs in c.items() if n == ctr and "copy" in k.lower() for v in vs]
+        if not kv or not cv:
+            raise SystemExit("no %s readings for %s / the copy kernel in %s" % (ctr, kernel, d))
+        scale = COPY_CAL_BYTES / (float(np.median(cv)) * 1024.0)
+        out[ctr] = (float(np.median(kv)), float(np.median(cv)), scale)
+    fetch = out["FETCH_SIZE"][0] * 1024.0 * out["FETCH_SIZE"][2]
+    write = out["WRITE_SIZE"][0] * 1024.0 * out["WRITE_SIZE"][2]
+    rec = {"key": key, "kernel": kernel, "bytes_per_launch": int(fetch + write),
+           "fetch_bytes": int(fetch), "write_bytes": int(write),
+           "fetch_kib_raw": out["FETCH_SIZE"][0], "write_kib_raw": out["WRITE_SIZE"][0],
+           "copy_fetch_kib_raw": out["FETCH_SIZE"][1], "copy_write_kib_raw": out["WRITE_SIZE"][1],
+           "fetch_scale": round(out["FETCH_SIZE"][2], 4), "write_scale": round(out["WRITE_SIZE"][2], 4),
+           "source_hash": kernel_source_hash(), "command": command}
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    lines = []
+    if os.path.exists(path):
+        lines = [l for l in open(path) if not (l.startswith("{") and json.loads(l).get("key") == key)]
+    if not lines:
+        lines = ["# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per\n",
+                 "# dispatch), each scaled by its reading for a plain 256 MiB copy in the same run.\n"]
+    lines.append(json.dumps(rec) + "\n")
+    open(path, "w").writelines(lines)
+    print(json.dumps(rec))
+
+
+def trace_summary(trace_dir, out_name, command):
+    """Kernel-trace statistics (rocprofv3 --kernel-trace --stats, csv) as a
+    short text table under profiles/."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no kernel_stats.csv under %s" % trace_dir)
+    rows = list(csv.DictReader(open(files[0])))
+    lines = ["# rocprofv3 kernel statistics", "# command: " + command, "",
+             "%-72s %8s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_us", "pct")]
+    for r in rows:
+        name = r.get("Name", r.get("KernelName", ""))
+        short = name.split("(")[0][-72:]
+        lines.append("%-72s %8s %12.2f %12.2f %7.2f" % (
+            short, r.get("Calls"), float(r.get("AverageNs", 0)) / 1e3,
+            float(r.get("TotalDurationNs", 0)) / 1e3, float(r.get("Percentage", 0))))
+    path = os.path.join(ROOT, "profiles", out_name)
+    open(path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(A, x, y_gpu, budget_s):
@@ -120,9 +206,21 @@ def main():
     ap.add_argument("--nnz-per-wave", type=int, default=0, help="partition size (0: tuned)")
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--pipeline", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB copy (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "KEY"))
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"))
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, command=args.command)
+        return 0
+    if args.trace_summary:
+        trace_summary(*args.trace_summary, command=args.command)
+        return 0
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
               "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -179,16 +277,20 @@ def main():
     x = torch.from_numpy(xs).to(dev)
     ydt = torch.float64 if vt == pk.F64 else torch.float32
     ys = {f: torch.zeros(A.m, dtype=ydt, device=dev) for f in fmts}
-    nnz_per_wave = args.nnz_per_wave or 2048
-    np_ = max(1, -(-A.nnz // nnz_per_wave))
-    tune = pk.Tune(k_per_lane=args.k, waves_per_wg=args.wpb)
-    parts = {}
-    torch.cuda.synchronize()
-    part_ms = {}
+    # launch shape and partition size per format: the autotuner's choice
+    # unless given on the command line
+    tunes, parts, part_ms = {}, {}, {}
     for f in fmts:
+        if args.nnz_per_wave:
+            tunes[f] = pk.Tune(k_per_lane=args.k, waves_per_wg=args.wpb,
+                               nnz_per_wave=args.nnz_per_wave, pipeline=args.pipeline)
+        else:
+            tunes[f] = pk.msrep_autotune(mats[f], x)
+        np_f = max(1, -(-A.nnz // tunes[f].nnz_per_wave))
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        parts[f] = pk.msrep_build_partition(mats[f], np_)
+        parts[f] = pk.msrep_build_partition(mats[f], np_f)
         e1.record()
         torch.cuda.synchronize()
         part_ms[f] = e0.elapsed_time(e1)
@@ -196,11 +298,17 @@ def main():
     ws = {f: torch.zeros(1 << 24, dtype=torch.uint8, device=dev) for f in fmts}
 
     def spmv(f):
-        pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tune, ws=ws[f])
+        pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tunes[f], ws=ws[f])
 
     for _ in range(args.warmup):
         for f in fmts:
             spmv(f)
+    if args.copy_calibration:
+        src = torch.empty(COPY_CAL_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        scrub.fill_(1)
+        dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
     # ---- timed region: K steps, each SpMV cold and bracketed by events
     ev = {f: [] for f in fmts}
@@ -236,7 +344,12 @@ def main():
                       "gflops_cold": round(2.0 * A.nnz / cold_ms[f] / 1e6, 2),
                       "gbs_cold": round(b / cold_ms[f] / 1e6, 1),
                       "gbs_warm": round(b / warm_ms[f] / 1e6, 1),
-                      "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4)}
+                      "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4),
+                      "np": parts[f].np,
+                      "tune": {"k_per_lane": tunes[f].k_per_lane or 4,
+                               "waves_per_wg": tunes[f].waves_per_wg or 4,
+                               "nnz_per_wave": tunes[f].nnz_per_wave,
+                               "pipeline": tunes[f].pipeline or 2}}
     dom = max(fmts, key=lambda f: cold_ms[f])
     kname = {"csr": "spmv_csr_seg", "csc": "spmv_csc_scatter", "coo": "spmv_coo_seg"}[dom]
     achieved = per_fmt[dom]["alg_bytes"] / (cold_ms[dom] * 1e-3) / 1e9
@@ -249,8 +362,7 @@ def main():
         "ms_per_step": round(step_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.vtype, "data": "synthetic",
-        "config": dict(wl, formats=fmts, np=np_, nnz_per_wave=nnz_per_wave,
-                       value_type=args.vtype),
+        "config": dict(wl, formats=fmts, value_type=args.vtype),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname + "(+merge)"},
