@@ -295,7 +295,8 @@ def main():
         torch.cuda.synchronize()
         part_ms[f] = e0.elapsed_time(e1)
     scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
-    ws = {f: torch.zeros(1 << 24, dtype=torch.uint8, device=dev) for f in fmts}
+    ws = {f: torch.zeros(max(256, pk.msrep_spmv_ws_bytes(mats[f], parts[f].np)), dtype=torch.uint8,
+                         device=dev) for f in fmts}
 
     def spmv(f):
         pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tunes[f], ws=ws[f])

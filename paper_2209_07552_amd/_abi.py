@@ -310,6 +310,11 @@ def _workspace(nbytes, device):
     return buf
 
 
+def msrep_spmv_ws_bytes(A: Mat, np_: int) -> int:
+    """Bytes of device workspace msrep_spmv needs for A split into np_ parts."""
+    return int(load_library().msrep_spmv_ws_bytes(ctypes.byref(A.desc()), int(np_)))
+
+
 def msrep_spmv(A: Mat, P: Partition, x, y, alpha=1.0, beta=0.0, tune: Optional[Tune] = None,
                ws=None, stream=None):
     """y <- alpha*A*x + beta*y (in place on the device tensor y); returns y."""

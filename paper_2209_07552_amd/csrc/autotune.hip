@@ -12,6 +12,7 @@ namespace msrep {
 msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
                          int wpb, int pf, double *carry, hipStream_t s);
+size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t np);
 namespace {
 
 constexpr int kNpw[] = {256, 512, 1024, 2048, 4096};
@@ -37,9 +38,9 @@ TuneWs tune_ws(const msrep_mat *A) {
   };
   w.parts = take(sizeof(msrep_part) * w.np_max);
   w.lptr = take(4 * static_cast<size_t>(msrep_lptr_bound(major_dim(A), w.np_max)));
-  // y, and for CSC with FP32/BF16 the FP64 accumulator shares the carry region
   w.y = take(static_cast<size_t>(vec_bytes(A->vtype)) * A->m);
-  w.carry = take(std::max<size_t>(16 * static_cast<size_t>(w.np_max), 8 * static_cast<size_t>(A->m)));
+  // the SpMV workspace (merge slots, or the CSC buckets) at the largest np
+  w.carry = take(spmv_ws_bytes(A->fmt, A->vtype, A->m, A->nnz, w.np_max));
   w.total = o;
   return w;
 }

@@ -66,21 +66,10 @@ __global__ __launch_bounds__(256) void merge_batched(const BatchMat *__restrict_
   const msrep_part P = M.parts[p];
   if (P.end_idx < P.start_idx || !P.end_flag) return;
   if (P.start_flag && P.start_row == P.end_row) return;
-  const double *c = M.carry;
   const int32_t r = P.end_row;
-  double s = c[2 * static_cast<int64_t>(p) + 1], e = 0.0;
-  for (int32_t q = p + 1; q < M.np; ++q) {
-    const msrep_part Q = M.parts[q];
-    if (Q.end_idx < Q.start_idx) continue;
-    if (!Q.start_flag || Q.start_row != r) break;
-    double t;
-    two_sum(s, c[2 * static_cast<int64_t>(q)], s, t);
-    e += t;
-    if (!(Q.end_flag && Q.end_row == r)) break;
-  }
+  const double tot = split_row_total(M.parts, M.np, M.carry, p, r);
   if (r < 0 || r >= M.m) return;
   T *y = static_cast<T *>(xy[wk.x].y);
-  const double tot = s + e;
   y[r] = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(y[r]));
 }
 

@@ -170,6 +170,61 @@ __device__ __forceinline__ float shfl_up<float>(float v, int d) { return shfl_up
 template <>
 __device__ __forceinline__ double shfl_up<double>(double v, int d) { return shfl_up_d(v, d); }
 
+// ------------------------------------------------- DPP wavefront scans
+// Lane moves through the data-parallel-primitive path (GCN-style DPP kept by
+// CDNA): row_shr:n shifts within rows of 16 lanes, row_bcast:15 / :31 pass a
+// row's last lane to the following rows, wave_shr:1 shifts the whole wave.
+// Lanes with no source receive 0.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL, ROWS>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int64_t u = __builtin_bit_cast(int64_t, v);
+  const int lo = dpp_i<CTRL, ROWS>(static_cast<int>(u));
+  const int hi = dpp_i<CTRL, ROWS>(static_cast<int>(u >> 32));
+  return __builtin_bit_cast(double, (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+template <int CTRL, int ROWS = 0xF, typename A>
+__device__ __forceinline__ A dpp(A v) {
+  if constexpr (sizeof(A) == 8)
+    return dpp_d<CTRL, ROWS>(v);
+  else
+    return dpp_f<CTRL, ROWS>(v);
+}
+
+// One step of a segmented inclusive scan: combine with the (value, flag) a
+// DPP move brings from an earlier lane; a lane whose own segment already
+// started (flag set) keeps its value.
+template <int CTRL, int ROWS, typename A>
+__device__ __forceinline__ void seg_step(A &v, int &f) {
+  const A pv = dpp<CTRL, ROWS>(v);
+  const int pf = dpp_i<CTRL, ROWS>(f);
+  if (!f) v += pv;
+  f |= pf;
+}
+
+// Inclusive segmented scan across the 64 lanes of (value, "a segment starts
+// in or before this lane" flag): within rows of 16 by row shifts, then rows
+// 1 and 3 from rows 0 and 2, then rows 2 and 3 from row 1.
+template <typename A>
+__device__ __forceinline__ void wave_seg_scan(A &v, int &f) {
+  seg_step<kDppRowShr1, 0xF>(v, f);
+  seg_step<kDppRowShr2, 0xF>(v, f);
+  seg_step<kDppRowShr4, 0xF>(v, f);
+  seg_step<kDppRowShr8, 0xF>(v, f);
+  seg_step<kDppRowBcast15, 0xA>(v, f);
+  seg_step<kDppRowBcast31, 0xC>(v, f);
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
 }

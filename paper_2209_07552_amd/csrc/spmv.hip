@@ -97,30 +97,43 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
                         void *ws, hipStream_t s) {
   using Tr = vt_traits<VT>;
   using T = typename Tr::T;
-  // column-based merge: FP64 scatters into y after y <- beta*y; FP32/BF16
-  // scatter into a zeroed FP64 workspace that finish_y rounds into y once
-  const int g = static_cast<int>((A->m + 255) / 256 < 16384 ? (A->m + 255) / 256 : 16384);
-  const size_t lds = csc_lds_per_wave<K>() * wpb;
-  const int grid = (np + wpb - 1) / wpb;
-  if constexpr (VT == MSREP_F64) {
-    hipLaunchKernelGGL((scale_y<T>), dim3(g), dim3(256), 0, s, static_cast<T *>(y), A->m, beta);
-    MSREP_LAUNCHED("scale_y");
-    hipLaunchKernelGGL((spmv_csc_scatter<VT, K, double>), dim3(grid), dim3(wpb * kWave), lds, s,
-                       A->ptr, A->idx, static_cast<const typename Tr::V *>(A->val), parts, lptr,
-                       np, static_cast<const T *>(x), static_cast<double *>(y), A->m, A->n, alpha);
-    MSREP_LAUNCHED("spmv_csc_scatter");
-  } else {
-    double *acc = static_cast<double *>(ws);
-    hipLaunchKernelGGL(zero_f64, dim3(g), dim3(256), 0, s, acc, static_cast<int64_t>(A->m));
-    MSREP_LAUNCHED("zero_f64");
-    hipLaunchKernelGGL((spmv_csc_scatter<VT, K, double>), dim3(grid), dim3(wpb * kWave), lds, s,
-                       A->ptr, A->idx, static_cast<const typename Tr::V *>(A->val), parts, lptr,
-                       np, static_cast<const T *>(x), acc, A->m, A->n, alpha);
-    MSREP_LAUNCHED("spmv_csc_scatter");
-    hipLaunchKernelGGL((finish_y<T>), dim3(g), dim3(256), 0, s, static_cast<T *>(y), acc, A->m,
-                       alpha, beta);
-    MSREP_LAUNCHED("finish_y");
-  }
+  using Acc = typename Tr::A;
+  CscLayout L;
+  if (!csc_layout(A->m, A->nnz, np, sizeof(Acc), L))
+    return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: CSC supports at most %d rows",
+                kCscMaxBuckets << kCscMaxShift);
+  char *b = static_cast<char *>(ws);
+  int32_t *cnt = reinterpret_cast<int32_t *>(b + L.cnt);
+  int32_t *agg = reinterpret_cast<int32_t *>(b + L.agg);
+  int32_t *pbase = reinterpret_cast<int32_t *>(b + L.pbase);
+  int32_t *mbase = reinterpret_cast<int32_t *>(b + L.mbase);
+  Acc *prod = reinterpret_cast<Acc *>(b + L.prod);
+  uint16_t *rlo = reinterpret_cast<uint16_t *>(b + L.rlo);
+  double *part = reinterpret_cast<double *>(b + L.part);
+  const size_t cur_lds = align_up(static_cast<size_t>(L.nb) * 4, 16);
+  hipLaunchKernelGGL(csc_count, dim3(L.P), dim3(kCscScatterWaves * kWave), cur_lds, s, A->idx, A->nnz, parts, np,
+                     L.P, A->m, L.shift, L.nb, cnt);
+  MSREP_LAUNCHED("csc_count");
+  if (msrep_status st = scan::device_scan<int32_t, scan::SumOp>(
+          cnt, cnt, static_cast<int64_t>(L.nb) * L.P + 1, agg, false, s))
+    return st;
+  (void)wpb;  // the scatter always runs one 16-wavefront producer per CU
+  hipLaunchKernelGGL((csc_scatter<VT, K>), dim3(L.P), dim3(kCscScatterWaves * kWave),
+                     cur_lds + csc_lds_per_wave<K>() * kCscScatterWaves, s, A->idx,
+                     static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
+                     static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
+  MSREP_LAUNCHED("csc_scatter");
+  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kCscBlock), 0, s, cnt, L.nb, L.P, pbase, mbase);
+  MSREP_LAUNCHED("csc_plan");
+  hipLaunchKernelGGL((csc_reduce<T, Acc>), dim3(static_cast<uint32_t>(L.max_pieces)),
+                     dim3(kCscBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
+                     L.nb, L.P, L.shift, A->m, A->nnz, L.max_slots, part, static_cast<T *>(y),
+                     alpha, beta);
+  MSREP_LAUNCHED("csc_reduce");
+  hipLaunchKernelGGL((csc_merge<T>), dim3(L.nb, (1 << L.shift) / kCscBlock), dim3(kCscBlock), 0, s,
+                     pbase, mbase, L.shift, A->m, L.max_slots, part, static_cast<T *>(y), alpha,
+                     beta);
+  MSREP_LAUNCHED("csc_merge");
   return MSREP_OK;
 }
 
@@ -140,7 +153,7 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
-  if (A->fmt == MSREP_CSC) {
+  if (A->fmt == MSREP_CSC) {  // carry is the whole workspace here
     return K == 8 ? launch_csc<VT, 8>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
                   : launch_csc<VT, 4>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
   }
@@ -206,14 +219,23 @@ extern "C" const char *msrep_last_error(void) { return last_error().c_str(); }
 
 extern "C" int32_t msrep_vtype_bytes(int32_t vtype) { return value_bytes(vtype); }
 
-extern "C" size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np) {
-  if (!A || np <= 0 || A->m < 0) return 0;
-  size_t need = align_up(16 * static_cast<size_t>(np), 256);
-  if (A->fmt == MSREP_CSC && A->vtype != MSREP_F64) {
-    const size_t acc = align_up(8 * static_cast<size_t>(A->m), 256);
-    need = acc > need ? acc : need;
+namespace msrep {
+
+
+size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t np) {
+  if (fmt == MSREP_CSC) {
+    CscLayout L;
+    const int pb = vtype == MSREP_F64 ? 8 : 4;
+    return csc_layout(m, nnz, np, pb, L) ? L.total : 0;
   }
-  return need;
+  return align_up(16 * static_cast<size_t>(np), 256);
+}
+
+}  // namespace msrep
+
+extern "C" size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np) {
+  if (!A || np <= 0 || A->m < 0 || A->nnz < 0) return 0;
+  return spmv_ws_bytes(A->fmt, A->vtype, A->m, A->nnz, np);
 }
 
 extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
@@ -236,6 +258,12 @@ extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d
   if (xb >= (uint64_t(1) << 32) || yb >= (uint64_t(1) << 32) ||
       (static_cast<uint64_t>(major_dim(A)) + 1) * 4 >= (uint64_t(1) << 32))
     return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: x or y larger than 4 GiB");
+  if (A->fmt == MSREP_CSC) {
+    CscLayout L;
+    if (!csc_layout(A->m, A->nnz, np, 8, L))
+      return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: CSC supports at most %d rows",
+                  kCscMaxBuckets << kCscMaxShift);
+  }
   const size_t need = msrep_spmv_ws_bytes(A, np);
   if (!ws_d || ws_bytes < need)
     return fail(MSREP_ERR_SIZE, "msrep_spmv: workspace of %zu bytes needed (got %zu)", need,

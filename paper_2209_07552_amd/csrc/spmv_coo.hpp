@@ -120,21 +120,9 @@ __global__ __launch_bounds__(512) void spmv_coo_seg(
     }
     Acc agg = r;
     int flg = any ? 1 : 0;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const Acc va = shfl_up<Acc>(agg, d);
-      const int fa = shfl_up_i(flg, d);
-      if (lane >= d) {
-        if (!flg) agg += va;
-        flg |= fa;
-      }
-    }
-    Acc cin = shfl_up<Acc>(agg, 1);
-    int fin = shfl_up_i(flg, 1);
-    if (lane == 0) {
-      cin = Acc(0);
-      fin = 0;
-    }
+    wave_seg_scan<Acc>(agg, flg);
+    const Acc cin = dpp<kDppWaveShr1>(agg);   // exclusive: lane 0 gets 0
+    const int fin = dpp_i<kDppWaveShr1>(flg);
     // items before the lane's first head continue the segment of earlier
     // lanes (cin); only the chunk's first segment continues the carried row
     bool seen = false;

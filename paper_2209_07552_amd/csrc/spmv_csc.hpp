@@ -1,154 +1,383 @@
-// Wave-per-partition CSC scatter SpMV (pCSC, msRep Algorithm 5).  Every
-// nonzero of column j adds val * x[j] to y[row]; the paper merges the
-// partitions' full-length partial vectors by summing them (Sec. 4.3), which on
-// one GPU is an atomic add into y after y <- beta*y.  The column of each
-// nonzero comes from the partition's local column pointer: columns that start
-// inside a chunk store their index at their first position in LDS and a
-// max-scan carries it forward.  FP32/BF16 values accumulate into an FP64
-// workspace that a final pass rounds into y once.
+// Bucketed pCSC SpMV (msRep Algorithm 5; partial vectors summed as in
+// Sec. 4.3) on one GPU.
+//
+// Every pCSC partition contributes a partial vector over all rows, and the
+// paper sums the partitions' full-length partial vectors.  On one GPU, np
+// dense partial vectors would cost np*m*8 bytes, and adding each product
+// straight into y with device atomics is bound by the atomic units (a few
+// tens of G atomics/s, far less on power-law rows that many columns share).
+// Here the partial vectors stay sparse: every product is written once,
+// grouped by row bucket (2^shift consecutive rows), and each bucket is then
+// summed in LDS.
+//   csc_count    one workgroup (a "producer") per contiguous run of
+//                partitions counts its nonzeros per bucket (LDS histogram);
+//   device scan  bucket-major exclusive offsets of every producer's run;
+//   csc_scatter  the producer's wavefronts walk its partitions, form the
+//                products val*x[col] and write them, with the row's low
+//                bits, into the producer's run of each bucket;
+//   csc_plan     each bucket is cut into pieces of at most kCscPiece items;
+//   csc_reduce   one workgroup per piece adds its products into an LDS row
+//                array; a bucket of one piece writes y = alpha*sum + beta*y
+//                directly, a bucket of several stores the arrays;
+//   csc_merge    one thread per row of those buckets adds the pieces' arrays
+//                in piece order.
+// Streaming traffic: about (s_v + 4) + 2*(s_p + 2) + 4 bytes per nonzero
+// (s_p the product size), no global atomics on y.
 #pragma once
 
+#include "scan.hpp"
 #include "spmv_csr.hpp"
 
 namespace msrep {
+
+constexpr int kCscMinShift = 12;              // 4096-row buckets
+constexpr int kCscMaxShift = 13;              // 8192 rows: 64 KB of FP64 sums
+constexpr int32_t kCscMaxBuckets = 8192;      // LDS cursors of one producer
+// One resident producer per CU: the runs being written at once (producers x
+// buckets lines) then fit the L2, which merges the scattered stores into
+// whole lines before they reach HBM.
+constexpr int32_t kCscMaxProducers = 256;
+constexpr int kCscScatterWaves = 16;
+constexpr int64_t kCscMaxCounters = int64_t(1) << 22;
+constexpr int64_t kCscPiece = 32768;          // products summed by one workgroup
+constexpr int kCscBlock = 256;                // count / plan / reduce blocks
+constexpr int kUnroll = 8;                    // loads in flight per thread
+
+// Workspace carve-up of the bucketed CSC path (byte offsets).
+struct CscLayout {
+  int shift = 0;
+  int32_t nb = 0, P = 0;
+  int64_t max_pieces = 0, max_slots = 0;
+  size_t cnt = 0, agg = 0, pbase = 0, mbase = 0, prod = 0, rlo = 0, part = 0, total = 0;
+};
+
+// false when m needs more buckets than one producer's LDS holds
+inline bool csc_layout(int32_t m, int64_t nnz, int32_t np, int prod_bytes, CscLayout &L) {
+  int shift = kCscMinShift;
+  auto buckets = [&](int s) { return (static_cast<int64_t>(m) + (int64_t(1) << s) - 1) >> s; };
+  while (shift < kCscMaxShift && buckets(shift) > kCscMaxBuckets) ++shift;
+  const int64_t nb = std::max<int64_t>(1, buckets(shift));
+  if (nb > kCscMaxBuckets) return false;
+  L.shift = shift;
+  L.nb = static_cast<int32_t>(nb);
+  L.P = static_cast<int32_t>(std::max<int64_t>(
+      1, std::min<int64_t>({static_cast<int64_t>(std::max(np, 1)), kCscMaxProducers,
+                            kCscMaxCounters / nb})));
+  // sum over buckets of max(1, ceil(c/S)) < nb + nnz/S; buckets of several
+  // pieces hold fewer than 2*nnz/S pieces in all
+  L.max_pieces = nb + nnz / kCscPiece + 1;
+  L.max_slots = 2 * (nnz / kCscPiece) + 1;
+  const int64_t ncnt = nb * L.P + 1;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o += align_up(b ? b : 1, 256);
+    return at;
+  };
+  L.cnt = take(4 * static_cast<size_t>(ncnt));
+  L.agg = take(4 * static_cast<size_t>(scan::tiles(ncnt)));
+  L.pbase = take(4 * static_cast<size_t>(nb + 1));
+  L.mbase = take(4 * static_cast<size_t>(nb + 1));
+  L.prod = take(static_cast<size_t>(prod_bytes) * static_cast<size_t>(nnz));
+  L.rlo = take(2 * static_cast<size_t>(nnz));
+  L.part = take(8 * static_cast<size_t>(L.max_slots) << shift);
+  L.total = o;
+  return true;
+}
 
 template <int K>
 constexpr size_t csc_lds_per_wave() {
   return align_up(kWave * K * sizeof(int32_t), 16);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void scale_y(T *__restrict__ y, int32_t m, double beta) {
-  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < m;
-       r += int64_t(gridDim.x) * blockDim.x)
-    y[r] = beta == 0.0 ? T(0) : static_cast<T>(beta * static_cast<double>(y[r]));
+// Partitions [pa, pb) of producer p: an equal share of the np partitions.
+__device__ __forceinline__ void producer_range(int p, int32_t np, int32_t P, int64_t &pa,
+                                               int64_t &pb) {
+  pa = static_cast<int64_t>(p) * np / P;
+  pb = static_cast<int64_t>(p + 1) * np / P;
 }
 
-__global__ __launch_bounds__(256) void zero_f64(double *__restrict__ a, int64_t n) {
-  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < n;
-       r += int64_t(gridDim.x) * blockDim.x)
-    a[r] = 0.0;
-}
-
-// y = beta*y + alpha*acc, rounded once (FP32 results of the CSC path).
-template <typename T>
-__global__ __launch_bounds__(256) void finish_y(T *__restrict__ y, const double *__restrict__ acc,
-                                                int32_t m, double alpha, double beta) {
-  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < m;
-       r += int64_t(gridDim.x) * blockDim.x) {
-    const double b = beta == 0.0 ? 0.0 : beta * static_cast<double>(y[r]);
-    y[r] = static_cast<T>(alpha * acc[r] + b);
+// cnt[t*P + p] = nonzeros of producer p whose row lies in bucket t.
+__global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(const int32_t *__restrict__ row_idx,
+                                                       int64_t nnz,
+                                                       const msrep_part *__restrict__ parts,
+                                                       int32_t np, int32_t P, int32_t m,
+                                                       int shift, int32_t nb,
+                                                       int32_t *__restrict__ cnt) {
+  extern __shared__ int32_t hist[];
+  const int p = blockIdx.x;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  int64_t pa, pb;
+  producer_range(p, np, P, pa, pb);
+  if (pb > pa) {
+    int64_t k0 = parts[pa].start_idx, k1 = parts[pb - 1].end_idx + 1;
+    k0 = k0 < 0 ? 0 : k0;
+    k1 = k1 > nnz ? nnz : k1;
+    const int64_t bd = blockDim.x;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kUnroll * bd) {
+      int32_t rr[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        rr[u] = k + u * bd < k1 ? __builtin_nontemporal_load(row_idx + k + u * bd) : -1;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (static_cast<uint32_t>(rr[u]) < static_cast<uint32_t>(m))
+          atomicAdd(&hist[rr[u] >> shift], 1);
+    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) cnt[static_cast<int64_t>(i) * P + p] = hist[i];
+  if (p == 0 && threadIdx.x == 0) cnt[static_cast<int64_t>(nb) * P] = 0;
 }
 
-// ACC: the array atomically accumulated into (y itself for FP64, else the
-// FP64 workspace).  SCALE: alpha is applied per product (FP64 into y) or in
-// finish_y (workspace).
-template <int VT, int K, typename ACC>
-__global__ __launch_bounds__(512) void spmv_csc_scatter(
-    const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ row_idx,
-    const typename vt_traits<VT>::V *__restrict__ val, const msrep_part *__restrict__ parts,
-    const int32_t *__restrict__ lptr, int32_t np, const typename vt_traits<VT>::T *__restrict__ x,
-    ACC *__restrict__ acc, int32_t m, int32_t n, double alpha) {
+// Products of producer p written into its run of each bucket.  The column of
+// every position comes from the partition's local column pointer: columns
+// that start inside a chunk mark their first position in LDS and a max-scan
+// carries the index forward.  Rows outside [0, m) are skipped here exactly
+// as csc_count skips them; a column outside [0, n) contributes 0.
+template <int VT, int K>
+__global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
+    const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
+    int64_t nnz, const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr,
+    int32_t np, int32_t P, const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n,
+    int shift, int32_t nb, const int32_t *__restrict__ off,
+    typename vt_traits<VT>::A *__restrict__ prod, uint16_t *__restrict__ rlo) {
   using Tr = vt_traits<VT>;
   using V = typename Tr::V;
   using Acc = typename Tr::A;
   constexpr int CH = kWave * K;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  (void)col_ptr;
+  int32_t *cur = reinterpret_cast<int32_t *>(lds_raw);
 
   const int lane = lane_id();
   const int wid = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
-  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
-  if (p >= np) return;
-  int32_t *s_col = reinterpret_cast<int32_t *>(lds_raw + wid * csc_lds_per_wave<K>());
+  const int p = xcd_block(blockIdx.x, gridDim.x);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) cur[i] = off[static_cast<int64_t>(i) * P + p];
+  __syncthreads();
+  int32_t *s_col = reinterpret_cast<int32_t *>(lds_raw + align_up(static_cast<size_t>(nb) * 4, 16) +
+                                               wid * csc_lds_per_wave<K>());
+  const uint32_t mask = (1u << shift) - 1u;
+  int64_t pa, pb;
+  producer_range(p, np, P, pa, pb);
 
-  const msrep_part *pp = parts + p;
-  const int64_t s0 = uniform(pp->start_idx);
-  const int64_t e0 = uniform(pp->end_idx);
-  const int32_t c0 = uniform(pp->start_row);  // first column
-  const int32_t R = uniform(pp->end_row) - c0 + 1;
-  const int32_t *__restrict__ lp = lptr + uniform(pp->lptr_off);
-  const int32_t nloc = static_cast<int32_t>(e0 - s0 + 1);
-  const int32_t lead = static_cast<int32_t>(s0 % K);
-  int32_t j0 = 0;  // local column containing the chunk's first position
-  for (int32_t cb = -lead; cb < nloc; cb += CH) {
-    const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
-    const int32_t q0 = cb + lane * K;
-    int32_t rows[K];
-    V v[K];
-    bool full = q0 >= 0 && q0 + K <= nloc;
-    if (full) {
-      load_vec<int32_t, K>(row_idx + s0 + q0, rows);
-      load_vec<V, K>(val + s0 + q0, v);
-    } else {
+  for (int64_t pi = pa + wid; pi < pb; pi += wpb) {
+    const msrep_part *pp = parts + pi;
+    const int64_t s0 = uniform(pp->start_idx);
+    const int64_t e0 = uniform(pp->end_idx);
+    const int32_t c0 = uniform(pp->start_row);  // first column
+    const int32_t R = uniform(pp->end_row) - c0 + 1;
+    const int32_t *__restrict__ lp = lptr + uniform(pp->lptr_off);
+    const int32_t nloc = static_cast<int32_t>(e0 - s0 + 1);
+    const int32_t lead = static_cast<int32_t>(s0 % K);
+    int32_t j0 = 0;  // local column containing the chunk's first position
+    for (int32_t cb = -lead; cb < nloc; cb += CH) {
+      const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
+      const int32_t q0 = cb + lane * K;
+      int32_t rows[K];
+      V v[K];
+      const bool full = q0 >= 0 && q0 + K <= nloc;
+      if (full) {
+        load_vec<int32_t, K>(row_idx + s0 + q0, rows);
+        load_vec<V, K>(val + s0 + q0, v);
+      } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const int32_t q = q0 + t;
+          rows[t] = -1;
+          v[t] = V(0);
+          if (q >= 0 && q < nloc) {
+            rows[t] = row_idx[s0 + q];
+            v[t] = val[s0 + q];
+          }
+        }
+      }
+      // columns starting inside the chunk mark their first position
+#pragma unroll
+      for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
+      wave_lds_sync();
+      int32_t jb = j0, cnt;
+      for (;;) {
+        const int32_t j = jb + lane;
+        const int32_t a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
+        const bool in = j <= R - 1 && a < ce;
+        if (in && j > j0) {
+          const int32_t pos = a - cb;
+          if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
+        }
+        cnt = __popcll(__ballot(in));
+        if (cnt < kWave) break;
+        jb += kWave;
+      }
+      const int32_t j1 = jb + cnt - 1;
+      wave_lds_sync();
+      int32_t cj[K];
+      int32_t mx = j0;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const int32_t h = s_col[lane * K + t];
+        mx = h > mx ? h : mx;
+        cj[t] = mx;
+      }
+      int32_t agg = mx;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t o = shfl_up_i(agg, d);
+        if (lane >= d) agg = o > agg ? o : agg;
+      }
+      int32_t cin = shfl_up_i(agg, 1);
+      if (lane == 0) cin = j0;
 #pragma unroll
       for (int t = 0; t < K; ++t) {
         const int32_t q = q0 + t;
-        rows[t] = -1;
-        v[t] = V(0);
-        if (q >= 0 && q < nloc) {
-          rows[t] = row_idx[s0 + q];
-          v[t] = val[s0 + q];
+        const int32_t j = cj[t] > cin ? cj[t] : cin;
+        const int32_t c = c0 + j;
+        if (q < 0 || q >= nloc) continue;
+        const int32_t r = rows[t];
+        if (static_cast<uint32_t>(r) >= static_cast<uint32_t>(m)) continue;
+        const Acc pr = static_cast<uint32_t>(c) < static_cast<uint32_t>(n)
+                           ? Tr::val(v[t]) * static_cast<Acc>(x[c])
+                           : Acc(0);
+        const int32_t at = atomicAdd(&cur[static_cast<uint32_t>(r) >> shift], 1);
+        if (static_cast<uint64_t>(at) < static_cast<uint64_t>(nnz)) {
+          prod[at] = pr;
+          rlo[at] = static_cast<uint16_t>(static_cast<uint32_t>(r) & mask);
         }
       }
+      // the column holding the chunk's last position continues, unless it ends
+      const int32_t nxt = (j1 + 1 >= 0 && j1 + 1 <= R) ? lp[j1 + 1] : nloc;
+      j0 = nxt > ce ? j1 : j1 + 1;
+      wave_lds_sync();
     }
-    // columns starting inside the chunk mark their first position
-#pragma unroll
-    for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
-    wave_lds_sync();
-    int32_t jb = j0, cnt;
-    for (;;) {
-      const int32_t j = jb + lane;
-      const int32_t a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
-      const bool in = j <= R - 1 && a < ce;
-      if (in && j > j0) {
-        const int32_t pos = a - cb;
-        if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
-      }
-      cnt = __popcll(__ballot(in));
-      if (cnt < kWave) break;
-      jb += kWave;
-    }
-    const int32_t j1 = jb + cnt - 1;
-    wave_lds_sync();
-    int32_t cj[K];
-    int32_t mx = j0;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const int32_t h = s_col[lane * K + t];
-      mx = h > mx ? h : mx;
-      cj[t] = mx;
-    }
-    int32_t agg = mx;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int32_t o = shfl_up_i(agg, d);
-      if (lane >= d) agg = o > agg ? o : agg;
-    }
-    int32_t cin = shfl_up_i(agg, 1);
-    if (lane == 0) cin = j0;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const int32_t q = q0 + t;
-      const int32_t j = cj[t] > cin ? cj[t] : cin;
-      const int32_t c = c0 + j;
-      if (q < 0 || q >= nloc) continue;
-      if (static_cast<uint32_t>(rows[t]) >= static_cast<uint32_t>(m)) continue;
-      if (static_cast<uint32_t>(c) >= static_cast<uint32_t>(n)) continue;
-      const Acc pr = Tr::val(v[t]) * static_cast<Acc>(x[c]);
-      if constexpr (VT == MSREP_F64) {
-        atomicAdd(acc + rows[t], static_cast<ACC>(alpha * static_cast<double>(pr)));
-      } else {
-        atomicAdd(acc + rows[t], static_cast<ACC>(pr));
-      }
-    }
-    // the column holding the chunk's last position continues, unless it ends
-    const int32_t nxt = (j1 + 1 >= 0 && j1 + 1 <= R) ? lp[j1 + 1] : nloc;
-    j0 = nxt > ce ? j1 : j1 + 1;
-    wave_lds_sync();
   }
+}
+
+// Pieces of every bucket: pbase = exclusive scan of max(1, ceil(c_t/S)),
+// mbase = exclusive scan of the piece counts of buckets with more than one
+// piece (their partial-array slots).  One block of kCscBlock threads.
+__global__ __launch_bounds__(kCscBlock) void csc_plan(const int32_t *__restrict__ off, int32_t nb,
+                                                      int32_t P, int32_t *__restrict__ pbase,
+                                                      int32_t *__restrict__ mbase) {
+  __shared__ int32_t sh[scan::kBlock / 64];
+  int32_t carry_p = 0, carry_m = 0;
+  for (int32_t t0 = 0; t0 < nb; t0 += kCscBlock) {
+    const int32_t t = t0 + threadIdx.x;
+    int32_t np_t = 0, ms_t = 0;
+    if (t < nb) {
+      const int64_t c = static_cast<int64_t>(off[static_cast<int64_t>(t + 1) * P]) -
+                        off[static_cast<int64_t>(t) * P];
+      np_t = c > 0 ? static_cast<int32_t>((c + kCscPiece - 1) / kCscPiece) : 1;
+      ms_t = np_t > 1 ? np_t : 0;
+    }
+    int32_t ex_p, ex_m;
+    const int32_t tot_p = scan::block_exscan<int32_t, scan::SumOp>(np_t, ex_p, sh);
+    const int32_t tot_m = scan::block_exscan<int32_t, scan::SumOp>(ms_t, ex_m, sh);
+    if (t < nb) {
+      pbase[t] = carry_p + ex_p;
+      mbase[t] = carry_m + ex_m;
+    }
+    carry_p += tot_p;
+    carry_m += tot_m;
+  }
+  if (threadIdx.x == 0) {
+    pbase[nb] = carry_p;
+    mbase[nb] = carry_m;
+  }
+}
+
+// One workgroup per piece (grid: an upper bound on the number of pieces).
+// Offsets are clamped to nnz and partial slots to max_slots, so partition
+// metadata that does not match the matrix cannot move an access outside the
+// workspace.
+template <typename T, typename PT>
+__global__ __launch_bounds__(kCscBlock) void csc_reduce(
+    const PT *__restrict__ prod, const uint16_t *__restrict__ rlo, const int32_t *__restrict__ off,
+    const int32_t *__restrict__ pbase, const int32_t *__restrict__ mbase, int32_t nb, int32_t P,
+    int shift, int32_t m, int64_t nnz, int64_t max_slots, double *__restrict__ part,
+    T *__restrict__ y, double alpha, double beta) {
+  extern __shared__ double acc[];
+  const int32_t g = blockIdx.x;
+  if (g >= pbase[nb]) return;
+  int32_t lo = 0, hi = nb - 1;  // the bucket t with pbase[t] <= g < pbase[t+1]
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (pbase[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int32_t t = lo, j = g - pbase[t], npc = pbase[t + 1] - pbase[t];
+  int64_t b0 = off[static_cast<int64_t>(t) * P], b1 = off[static_cast<int64_t>(t + 1) * P];
+  b0 = b0 < 0 ? 0 : (b0 > nnz ? nnz : b0);
+  b1 = b1 < b0 ? b0 : (b1 > nnz ? nnz : b1);
+  const int64_t i0 = b0 + static_cast<int64_t>(j) * kCscPiece;
+  const int64_t i1 = i0 + kCscPiece < b1 ? i0 + kCscPiece : b1;
+  const int32_t span = 1 << shift;
+  const uint32_t mask = static_cast<uint32_t>(span) - 1u;
+  const int32_t r0 = t << shift;
+  const int32_t rows = m - r0 < span ? m - r0 : span;
+  for (int r = threadIdx.x; r < span; r += blockDim.x) acc[r] = 0.0;
+  __syncthreads();
+  // kUnroll loads in flight per thread before their LDS adds
+  const int64_t bd = blockDim.x;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kUnroll * bd) {
+    uint32_t rr[kUnroll];
+    double pv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t k = i + u * bd;
+      rr[u] = k < i1 ? __builtin_nontemporal_load(rlo + k) : 0u;
+      pv[u] = k < i1 ? static_cast<double>(__builtin_nontemporal_load(prod + k)) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (i + u * bd < i1) atomicAdd(&acc[rr[u] & mask], pv[u]);
+  }
+  __syncthreads();
+  auto out = [&](int32_t r, double s) {
+    const double b = beta == 0.0 ? 0.0 : beta * static_cast<double>(y[r0 + r]);
+    y[r0 + r] = static_cast<T>(alpha * s + b);
+  };
+  if (npc == 1) {
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) out(r, acc[r]);
+    return;
+  }
+  if (mbase[t] < 0 || static_cast<int64_t>(mbase[t]) + npc > max_slots) return;
+  double *mine = part + (static_cast<int64_t>(mbase[t] + j) << shift);
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) mine[r] = acc[r];
+}
+
+// Rows of buckets cut into several pieces: the pieces' arrays added in piece
+// order.  Grid (nb, 2^shift / kCscBlock): one thread per row of every bucket;
+// buckets of one piece were finished by csc_reduce.
+template <typename T>
+__global__ __launch_bounds__(kCscBlock) void csc_merge(const int32_t *__restrict__ pbase,
+                                                      const int32_t *__restrict__ mbase,
+                                                      int shift, int32_t m, int64_t max_slots,
+                                                      const double *__restrict__ part,
+                                                      T *__restrict__ y, double alpha,
+                                                      double beta) {
+  const int32_t t = blockIdx.x;
+  const int32_t npc = pbase[t + 1] - pbase[t];
+  if (npc <= 1) return;
+  if (mbase[t] < 0 || static_cast<int64_t>(mbase[t]) + npc > max_slots) return;
+  const int32_t r = blockIdx.y * blockDim.x + threadIdx.x;
+  const int32_t r0 = t << shift;
+  if (r >= (1 << shift) || r0 + r >= m) return;
+  const double *base = part + (static_cast<int64_t>(mbase[t]) << shift) + r;
+  double s = 0.0;
+  int32_t q = 0;
+  for (; q + kUnroll <= npc; q += kUnroll) {
+    double v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = base[static_cast<int64_t>(q + u) << shift];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) s += v[u];
+  }
+  for (; q < npc; ++q) s += base[static_cast<int64_t>(q) << shift];
+  const double b = beta == 0.0 ? 0.0 : beta * static_cast<double>(y[r0 + r]);
+  y[r0 + r] = static_cast<T>(alpha * s + b);
 }
 
 }  // namespace msrep

@@ -114,6 +114,10 @@ __device__ __forceinline__ void load_items(const int32_t *__restrict__ idx,
   }
 }
 
+// Rows covering at most this many positions of a chunk are summed by one
+// lane each; a chunk holding a longer row uses the segmented scan.
+constexpr int kShortRow = 32;
+
 // Per-wave LDS footprint of the CSR/COO kernels.
 template <int VT, int K>
 constexpr size_t seg_lds_per_wave() {
@@ -207,18 +211,13 @@ __device__ __forceinline__ void csr_partition(
     Acc prod[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv_cur[t]);
-    // ---- 2. head flags from the local pointer
-#pragma unroll
-    for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
-    wave_lds_sync();
-    // first batch: rows j0 .. j0+63 (lpv0); more rows than that start inside
-    // the chunk only with many short or empty rows
+    // ---- 2. rows that start inside the chunk: the first batch covers rows
+    //         j0 .. j0+63 (lpv0); more start inside the chunk only with many
+    //         short or empty rows
     int32_t jb = j0, cnt, lp_next;
     {
       const int32_t j = j0 + lane;
       const bool in = j <= R - 1 && lpv0 < ce;
-      const int32_t pos = lpv0 - cb;
-      if (in && j > j0 && pos > 0 && pos < CH) s_head[pos] = 1;
       cnt = __popcll(__ballot(in));
       lp_next = read_lane(lpv0, cnt & (kWave - 1));
     }
@@ -228,8 +227,6 @@ __device__ __forceinline__ void csr_partition(
         const int32_t j = jb + lane;
         const int32_t v = buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u);
         const bool in = j <= R - 1 && v < ce;
-        const int32_t pos = v - cb;
-        if (in && pos > 0 && pos < CH) s_head[pos] = 1;
         cnt = __popcll(__ballot(in));
         if (cnt < kWave) {
           lp_next = read_lane(v, cnt);
@@ -240,54 +237,15 @@ __device__ __forceinline__ void csr_partition(
     const int32_t j1 = jb + cnt - 1;  // last row starting before ce
     const bool cont = lp_next > ce;   // row j1 continues into the next chunk
     const bool one_batch = jb == j0;  // rows j0..j1 are the lanes of lpv0
-    wave_lds_sync();
-    // ---- 3. segmented scan
-    uint32_t hb[K / 4];
-#pragma unroll
-    for (int w = 0; w < K / 4; ++w) hb[w] = reinterpret_cast<const uint32_t *>(s_head)[lane * (K / 4) + w];
-    Acc run[K];
-    Acc r = Acc(0);
-    bool any = false;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const bool h = (hb[t / 4] >> (8 * (t % 4))) & 0xffu;
-      if (h) {
-        r = Acc(0);
-        any = true;
-      }
-      r += prod[t];
-      run[t] = r;
-    }
-    Acc agg = r;
-    int flg = any ? 1 : 0;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const Acc va = shfl_up<Acc>(agg, d);
-      const int fa = shfl_up_i(flg, d);
-      if (lane >= d) {
-        if (!flg) agg += va;
-        flg |= fa;
-      }
-    }
-    Acc cin = shfl_up<Acc>(agg, 1);
-    if (lane == 0) cin = Acc(0);
-    bool seen = false;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      seen = seen || ((hb[t / 4] >> (8 * (t % 4))) & 0xffu);
-      s_sum[lane * K + t] = seen ? run[t] : run[t] + cin;
-    }
-    wave_lds_sync();
-    // ---- 4. rows j0..j1
-    const double last_tot = static_cast<double>(s_sum[ce - 1 - cb]);
     // next lane's pointer = lp[j + 1] while all rows sit in the first batch
     const int32_t lpv1 = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, lpv0);
-    // one row per lane: in-chunk sum from the scan, plus the carried sum for
-    // a row that began in an earlier chunk; the row still open at the chunk
-    // end is carried on
-    auto finish_row = [&](int32_t j, int32_t a, int32_t b) {
-      const int32_t aa = a > cs ? a : cs, bb = b < ce ? b : ce;
-      double tot = bb > aa ? static_cast<double>(s_sum[bb - 1 - cb]) : 0.0;
+    // this lane's row and its positions inside the chunk (first batch)
+    const int32_t jl = j0 + lane;
+    const int32_t aa = lpv0 > cs ? lpv0 : cs;
+    const int32_t bl = jl == j1 ? lp_next : lpv1;
+    const int32_t bb = bl < ce ? bl : ce;
+    // a row is written (or its partial sum carried) once its total is known
+    auto finish_row = [&](int32_t j, double tot) {
       if (j == j0 && carry_on) tot += carry_v;
       if (j == j1 && cont) return;
       if (j == 0 && sflag)
@@ -297,18 +255,88 @@ __device__ __forceinline__ void csr_partition(
       else if (static_cast<uint32_t>(r0 + j) < static_cast<uint32_t>(m))
         store_y<T>(y, r0 + j, tot, alpha, beta, BETA0);
     };
-    if (one_batch) {
-      const int32_t j = j0 + lane;
-      if (j <= j1) finish_row(j, lpv0, j == j1 ? lp_next : lpv1);
+    // ---- 3a. short rows (every row covers at most kShortRow positions of
+    //          the chunk): each lane sums its own row's products from LDS
+    const bool short_rows =
+        one_batch && __ballot(jl <= j1 && bb - aa > kShortRow) == 0ull;
+    double next_carry = 0.0;
+    if (short_rows) {
+#pragma unroll
+      for (int t = 0; t < K; ++t) s_sum[lane * K + t] = prod[t];
+      wave_lds_sync();
+      Acc acc = Acc(0);
+      for (int32_t q = aa; q < bb; ++q) acc += s_sum[q - cb];
+      double tot = static_cast<double>(acc);
+      if (jl <= j1) finish_row(jl, tot);
+      if (cont) {  // the open row's sum so far, from the lane that holds it
+        if (jl == j0 && carry_on) tot += carry_v;
+        const int src = j1 - j0;
+        const int64_t u = __builtin_bit_cast(int64_t, tot);
+        const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), src);
+        const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+        next_carry = __builtin_bit_cast(double, (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+      }
     } else {
+      // ---- 3b. segmented scan: rows starting inside the chunk mark their
+      //          first position; the scan restarts at every mark
+#pragma unroll
+      for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
+      wave_lds_sync();
       for (int32_t jr = j0; jr <= j1; jr += kWave) {
         const int32_t j = jr + lane;
-        if (j >= 0 && j <= j1)
-          finish_row(j, buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u),
-                     buf_load<int32_t>(rl, static_cast<uint32_t>(j + 1) * 4u));
+        const int32_t v = jr == j0 ? lpv0 : buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u);
+        const int32_t pos = v - cb;
+        if (j > j0 && j <= j1 && pos > 0 && pos < CH) s_head[pos] = 1;
+      }
+      wave_lds_sync();
+      uint32_t hb[K / 4];
+#pragma unroll
+      for (int w = 0; w < K / 4; ++w) hb[w] = reinterpret_cast<const uint32_t *>(s_head)[lane * (K / 4) + w];
+      Acc run[K];
+      Acc r = Acc(0);
+      bool any = false;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const bool h = (hb[t / 4] >> (8 * (t % 4))) & 0xffu;
+        if (h) {
+          r = Acc(0);
+          any = true;
+        }
+        r += prod[t];
+        run[t] = r;
+      }
+      Acc agg = r;
+      int flg = any ? 1 : 0;
+      wave_seg_scan<Acc>(agg, flg);
+      const Acc cin = dpp<kDppWaveShr1>(agg);  // exclusive: lane 0 gets 0
+      bool seen = false;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        seen = seen || ((hb[t / 4] >> (8 * (t % 4))) & 0xffu);
+        s_sum[lane * K + t] = seen ? run[t] : run[t] + cin;
+      }
+      wave_lds_sync();
+      // a row's in-chunk sum is the scan value at its last position
+      auto scanned = [&](int32_t a, int32_t b) {
+        const int32_t a2 = a > cs ? a : cs, b2 = b < ce ? b : ce;
+        return b2 > a2 ? static_cast<double>(s_sum[b2 - 1 - cb]) : 0.0;
+      };
+      if (one_batch) {
+        if (jl <= j1) finish_row(jl, scanned(lpv0, bl));
+      } else {
+        for (int32_t jr = j0; jr <= j1; jr += kWave) {
+          const int32_t j = jr + lane;
+          if (j >= 0 && j <= j1)
+            finish_row(j, scanned(buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u),
+                                  buf_load<int32_t>(rl, static_cast<uint32_t>(j + 1) * 4u)));
+        }
+      }
+      if (cont) {
+        const double last_tot = static_cast<double>(s_sum[ce - 1 - cb]);
+        next_carry = last_tot + ((j1 == j0 && carry_on) ? carry_v : 0.0);
       }
     }
-    carry_v = cont ? last_tot + ((j1 == j0 && carry_on) ? carry_v : 0.0) : 0.0;
+    carry_v = next_carry;
     carry_on = cont;
     j0 = cont ? j1 : j1 + 1;
 #pragma unroll
@@ -352,6 +380,47 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
 // middle piece) sums its tail partial and the head partials of the following
 // partitions, in partition order, with TwoSum compensation, then applies
 // alpha and beta once (msRep Algorithm 3 lines on merging, Sec. 4.3).
+// Total of a row split across partitions, owned by partition p (the one
+// holding the row's first piece): p's tail plus the heads of the following
+// partitions that continue row r, added in partition order with TwoSum.  The
+// chain is read eight partitions per round so that a row spanning many
+// partitions costs a few dependent memory rounds, not one per partition.
+__device__ __forceinline__ double split_row_total(const msrep_part *__restrict__ parts, int32_t np,
+                                                  const double *__restrict__ carry, int32_t p,
+                                                  int32_t r) {
+  constexpr int B = 8;
+  double s = carry[2 * static_cast<int64_t>(p) + 1], c = 0.0;
+  bool going = true;
+  for (int32_t q0 = p + 1; going && q0 < np; q0 += B) {
+    msrep_part Q[B];
+    double h[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int32_t q = q0 + b < np ? q0 + b : np - 1;  // in bounds; unused past np
+      Q[b] = parts[q];
+      h[b] = carry[2 * static_cast<int64_t>(q)];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (!going) break;
+      if (q0 + b >= np) {
+        going = false;
+        break;
+      }
+      if (Q[b].end_idx < Q[b].start_idx) continue;  // empty partition
+      if (!Q[b].start_flag || Q[b].start_row != r) {
+        going = false;
+        break;
+      }
+      double e;
+      two_sum(s, h[b], s, e);
+      c += e;
+      if (!(Q[b].end_flag && Q[b].end_row == r)) going = false;  // the row's last piece
+    }
+  }
+  return s + c;
+}
+
 template <typename T, bool BETA0>
 __global__ __launch_bounds__(256) void merge_rows(const msrep_part *__restrict__ parts, int32_t np,
                                                   const double *__restrict__ carry,
@@ -363,18 +432,8 @@ __global__ __launch_bounds__(256) void merge_rows(const msrep_part *__restrict__
   if (P.end_idx < P.start_idx || !P.end_flag) return;
   if (P.start_flag && P.start_row == P.end_row) return;  // a later piece, not the owner
   const int32_t r = P.end_row;
-  double s = carry[2 * static_cast<int64_t>(p) + 1], c = 0.0;
-  for (int32_t q = p + 1; q < np; ++q) {
-    const msrep_part Q = parts[q];
-    if (Q.end_idx < Q.start_idx) continue;
-    if (!Q.start_flag || Q.start_row != r) break;
-    double e;
-    two_sum(s, carry[2 * static_cast<int64_t>(q)], s, e);
-    c += e;
-    if (!(Q.end_flag && Q.end_row == r)) break;  // Q holds the row's last piece
-  }
+  const double tot = split_row_total(parts, np, carry, p, r);
   if (r < 0 || r >= m) return;
-  const double tot = s + c;
   y[r] = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(y[r]));
 }
 

@@ -80,3 +80,20 @@ def test_spmv_argument_errors():
     assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 8) >= 16 * 8
     dc = _desc(fmt=1, vtype=1, m=1000)
     assert L.msrep_spmv_ws_bytes(ctypes.byref(dc), 8) >= 8 * 1000
+
+
+def test_csc_workspace_and_row_limit():
+    """The CSC path keeps one product and a 16-bit row offset per nonzero in
+    its workspace; its row buckets cap m at 2^26 (UNSUPPORTED beyond)."""
+    L = _lib()
+    d = _desc(fmt=1, m=1 << 20, n=1 << 20, nnz=1 << 24)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 16384) >= 10 * (1 << 24)
+    d32 = _desc(fmt=1, vtype=1, m=1 << 20, n=1 << 20, nnz=1 << 24)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(d32), 16384) >= 6 * (1 << 24)
+    big = _desc(fmt=1, m=(1 << 26) + 1, n=4, nnz=4)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(big), 8) == 0
+    st = L.msrep_spmv(ctypes.byref(big), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0, None,
+                      0x8000, 1 << 30, None)
+    assert st == -7 and b"CSC" in L.msrep_last_error()
+    ok = _desc(fmt=1, m=1 << 26, n=4, nnz=4)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(ok), 8) > 0

@@ -235,3 +235,18 @@ def test_autotune_returns_a_valid_tune_and_correct_results():
     np_ = max(1, -(-A.nnz // t.nnz_per_wave))
     y, ref, s = _run(A, x, "csr", pk.F64, np_, tune=t, M=M, v64=v64)
     assert_close(y, ref, s, F64_TOL, "autotuned")
+
+
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_csc_many_buckets_and_pieces(vt):
+    """CSC sums products by row bucket: R-MAT scale 16 puts a third of its
+    nonzeros into the first bucket (several pieces merged in order) and the
+    stencil spreads them over 64 buckets; both with beta != 0."""
+    tol = F64_TOL if vt == 0 else F32_TOL
+    rng = np.random.default_rng(11)
+    for A, x in (synth.rmat_csr(scale=16, edge_factor=16, seed=6), synth.stencil7_csr(64)):
+        M, v64 = device_mat(A, "csc", vt)
+        y_in = rng.uniform(-1, 1, A.m)
+        for np_ in (5, 4096, 100_000):
+            y, ref, s = _run(A, x, "csc", vt, np_, 0.75, -1.5, y_in, M=M, v64=v64)
+            assert_close(y, ref, s, tol, "%s csc vt%d np%d" % (A.name, vt, np_))
