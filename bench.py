@@ -30,6 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Launch shape per workload and format used unless --autotune or explicit
+# --nnz-per-wave/--k/--wpb/--pipeline are given: the tuner's picks on MI355X
+# (Tune fields: nnz_per_wave, k_per_lane, waves_per_wg, pipeline).
+DEFAULT_TUNES = {
+    "rmat20": {"csr": (512, 4, 2, 2), "coo": (512, 4, 8, 2), "csc": (512, 4, 8, 2)},
+}
 SCRUB_BYTES = 512 << 20
 
 
@@ -62,6 +68,22 @@ def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
     if not beta0:
         b += m * xbytes
     return b
+
+
+def kernel_alg_bytes(kernel, m, n, nnz, np_, vbytes, xbytes):
+    """Algorithmic bytes of one launch of a kernel of the SpMV path (one
+    launch covers the whole matrix): what its job must read and write, each
+    array once.  CSC products are FP64 for FP64 values and FP32 otherwise,
+    each with a 16-bit row offset."""
+    pbytes = 8 if xbytes == 8 else 4
+    return {
+        "spmv_csr_seg": alg_bytes("csr", m, n, nnz, vbytes, xbytes),
+        "spmv_coo_seg": alg_bytes("coo", m, n, nnz, vbytes, xbytes),
+        "merge_rows": np_ * (40 + 16),
+        "csc_count": nnz * 4,
+        "csc_scatter": nnz * (vbytes + 4) + (n + 1) * 4 + n * xbytes + nnz * (pbytes + 2),
+        "csc_reduce": nnz * (pbytes + 2) + m * xbytes,
+    }.get(kernel)
 
 
 COPY_CAL_BYTES = 256 << 20  # plain copy used to calibrate the byte counters
@@ -147,9 +169,10 @@ def pmc_summary(fetch_dir, write_dir, kernel, key, command):
     print(json.dumps(rec))
 
 
-def trace_summary(trace_dir, out_name, command):
+def trace_summary(trace_dir, out_name, command, bench_json=None):
     """Kernel-trace statistics (rocprofv3 --kernel-trace --stats, csv) as a
-    short text table under profiles/."""
+    short text table under profiles/; with the traced run's own JSON line,
+    also its event-measured average for the roofline kernel."""
     import csv
     import glob
     files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
@@ -159,11 +182,21 @@ def trace_summary(trace_dir, out_name, command):
     lines = ["# rocprofv3 kernel statistics", "# command: " + command, "",
              "%-72s %8s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_us", "pct")]
     for r in rows:
-        name = r.get("Name", r.get("KernelName", ""))
-        short = name.split("(")[0][-72:]
+        name = r.get("Name", r.get("KernelName", "")).replace("(anonymous namespace)::", "")
+        short = name.split("(")[0][:72]
         lines.append("%-72s %8s %12.2f %12.2f %7.2f" % (
             short, r.get("Calls"), float(r.get("AverageNs", 0)) / 1e3,
             float(r.get("TotalDurationNs", 0)) / 1e3, float(r.get("Percentage", 0))))
+    if bench_json:
+        rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        rf = rec.get("roofline", {})
+        lines += ["", "# the traced run's bench line: roofline kernel %s, %.2f us per launch by"
+                  " HIP events, %.1f GB/s algorithmic (%.4f of %g)" % (
+                      rf.get("kernel"), rf.get("kernel_avg_us", float("nan")),
+                      rf.get("achieved", float("nan")), rf.get("frac", float("nan")),
+                      rf.get("peak", float("nan")))]
+        for f, v in rec.get("per_format", {}).items():
+            lines.append("#   %s: %s" % (f, json.dumps(v.get("kernels_us", {}))))
     path = os.path.join(ROOT, "profiles", out_name)
     open(path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -209,17 +242,21 @@ def main():
     ap.add_argument("--pipeline", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune every format first")
+    ap.add_argument("--warm", action="store_true",
+                    help="also time back-to-back (cache-warm) SpMVs of each format")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "KEY"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"))
     ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--bench-json", default=None, help="the traced run's output (trace summary)")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, command=args.command)
         return 0
     if args.trace_summary:
-        trace_summary(*args.trace_summary, command=args.command)
+        trace_summary(*args.trace_summary, command=args.command, bench_json=args.bench_json)
         return 0
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
@@ -277,15 +314,20 @@ def main():
     x = torch.from_numpy(xs).to(dev)
     ydt = torch.float64 if vt == pk.F64 else torch.float32
     ys = {f: torch.zeros(A.m, dtype=ydt, device=dev) for f in fmts}
-    # launch shape and partition size per format: the autotuner's choice
-    # unless given on the command line
+    # launch shape and partition size per format: explicit flags, else the
+    # stored picks for this workload, else (or with --autotune) the tuner
     tunes, parts, part_ms = {}, {}, {}
     for f in fmts:
+        stored_t = DEFAULT_TUNES.get(args.workload, {}).get(f)
         if args.nnz_per_wave:
             tunes[f] = pk.Tune(k_per_lane=args.k, waves_per_wg=args.wpb,
                                nnz_per_wave=args.nnz_per_wave, pipeline=args.pipeline)
+        elif stored_t and not args.autotune:
+            tunes[f] = pk.Tune(k_per_lane=stored_t[1], waves_per_wg=stored_t[2],
+                               nnz_per_wave=stored_t[0], pipeline=stored_t[3])
         else:
             tunes[f] = pk.msrep_autotune(mats[f], x)
+            log("tuned %s: %s" % (f, tunes[f]))
         np_f = max(1, -(-A.nnz // tunes[f].nnz_per_wave))
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -301,8 +343,11 @@ def main():
     def spmv(f):
         pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tunes[f], ws=ws[f])
 
+    # warmup steps are cold too, so that every launch of a kernel in this run
+    # is alike (a profiler's per-kernel average then matches the timed one)
     for _ in range(args.warmup):
         for f in fmts:
+            scrub.fill_(1)
             spmv(f)
     if args.copy_calibration:
         src = torch.empty(COPY_CAL_BYTES, dtype=torch.uint8, device=dev)
@@ -312,23 +357,31 @@ def main():
         del src, dst
     torch.cuda.synchronize()
     # ---- timed region: K steps, each SpMV cold and bracketed by events
+    # (the library also brackets every kernel it launches with HIP events on
+    # the same stream: per-kernel durations for the roofline)
     ev = {f: [] for f in fmts}
+    ktime = {}
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     for _ in range(args.steps):
         for f in fmts:
             scrub.fill_(1)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            pk.msrep_timing(True)
             e0.record()
             spmv(f)
             e1.record()
+            for k, (c, t) in pk.msrep_timing_read().items():
+                kc, kt = ktime.get((f, k), (0, 0.0))
+                ktime[(f, k)] = (kc + c, kt + t)
             ev[f].append((e0, e1))
+    pk.msrep_timing(False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     cold_ms = {f: float(np.mean([a.elapsed_time(b) for a, b in ev[f]])) for f in fmts}
-    # ---- warm: back-to-back SpMVs of one format
+    # ---- warm (optional): back-to-back SpMVs of one format
     warm_ms = {}
-    for f in fmts:
+    for f in fmts if args.warm else []:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(args.steps):
@@ -341,19 +394,25 @@ def main():
     per_fmt = {}
     for f in fmts:
         b = alg_bytes(f, A.m, A.n, A.nnz, vbytes, xbytes)
-        per_fmt[f] = {"ms_cold": round(cold_ms[f], 4), "ms_warm": round(warm_ms[f], 4),
+        per_fmt[f] = {"ms_cold": round(cold_ms[f], 4),
                       "gflops_cold": round(2.0 * A.nnz / cold_ms[f] / 1e6, 2),
                       "gbs_cold": round(b / cold_ms[f] / 1e6, 1),
-                      "gbs_warm": round(b / warm_ms[f] / 1e6, 1),
                       "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4),
                       "np": parts[f].np,
                       "tune": {"k_per_lane": tunes[f].k_per_lane or 4,
                                "waves_per_wg": tunes[f].waves_per_wg or 4,
                                "nnz_per_wave": tunes[f].nnz_per_wave,
                                "pipeline": tunes[f].pipeline or 2}}
-    dom = max(fmts, key=lambda f: cold_ms[f])
-    kname = {"csr": "spmv_csr_seg", "csc": "spmv_csc_scatter", "coo": "spmv_coo_seg"}[dom]
-    achieved = per_fmt[dom]["alg_bytes"] / (cold_ms[dom] * 1e-3) / 1e9
+        if f in warm_ms:
+            per_fmt[f]["ms_warm"] = round(warm_ms[f], 4)
+            per_fmt[f]["gbs_warm"] = round(b / warm_ms[f] / 1e6, 1)
+        per_fmt[f]["kernels_us"] = {k: round(t / c * 1e3, 2) for (g, k), (c, t) in ktime.items()
+                                    if g == f}
+    # the dominant kernel: the largest share of the step's time
+    (dom_f, kname), (kc, kt) = max(ktime.items(), key=lambda kv: kv[1][1])
+    k_ms = kt / kc
+    k_bytes = kernel_alg_bytes(kname, A.m, A.n, A.nnz, parts[dom_f].np, vbytes, xbytes)
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9
     traffic = load_traffic("%s/%s/%s" % (kname, wl["workload"], args.vtype))
     out = {
         "metric": "SpMV GFLOP/s (cold HBM; CSR+CSC+COO per step)",
@@ -366,7 +425,8 @@ def main():
         "config": dict(wl, formats=fmts, value_type=args.vtype),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kname + "(+merge)"},
+                     "traffic": traffic, "kernel": kname, "format": dom_f,
+                     "kernel_avg_us": round(k_ms * 1e3, 2), "alg_bytes_per_launch": int(k_bytes)},
         "per_format": per_fmt,
         "wall_s_timed_region": round(wall, 3),
     }

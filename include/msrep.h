@@ -47,6 +47,30 @@ typedef int32_t msrep_status;
 /* Text of the last failure on this thread ("" after a success). */
 const char *msrep_last_error(void);
 
+/* ------------------------------------------------------------ kernel timing */
+/* A profiling aid for measuring single kernels of a call.  While enabled,
+ * every kernel msrep_spmv launches (the per-format SpMV kernel, the boundary
+ * merge, and the count, scan, scatter, plan, reduce and merge kernels of the
+ * CSC path) is bracketed by two HIP events recorded on the caller's stream.
+ * msrep_timing_read totals the event-measured durations by kernel name.
+ * Process-wide state, off by default; not meant for concurrent callers. */
+typedef struct msrep_kernel_time {
+  char name[48];   /* kernel name, e.g. "spmv_csr_seg", "csc_scatter"  */
+  int64_t calls;   /* launches timed since the last read               */
+  double total_ms; /* sum of their durations                           */
+} msrep_kernel_time; /* 64 bytes */
+
+/* Enable (nonzero) or disable timing; either way discards what was
+ * recorded.  Waits for recorded events that are still pending. */
+msrep_status msrep_timing(int32_t enable);
+
+/* Waits for the recorded events, writes up to cap entries (one per kernel
+ * name, in order of first launch) and discards the records.  Returns the
+ * number of distinct kernels (entries past cap are dropped), or a negative
+ * status (MSREP_ERR_ARG for cap < 0 or a NULL out with cap > 0,
+ * MSREP_ERR_HIP when an event cannot be read). */
+int32_t msrep_timing_read(msrep_kernel_time *out, int32_t cap);
+
 /* ------------------------------------------------------------ matrices */
 /* Storage formats of Sec. 2.1: CSR, CSC (the CSR of the transpose) and COO
  * sorted by row (the order Sec. 3.2.3 assumes for pCOO). */

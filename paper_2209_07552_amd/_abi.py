@@ -67,6 +67,10 @@ class _ServeStats(ctypes.Structure):
                 ("peak_bytes", c_i64), ("peak_active", c_i32), ("_pad", c_i32)]
 
 
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("calls", c_i64), ("total_ms", c_dbl)]
+
+
 PART_DTYPE = np.dtype([("start_idx", "<i8"), ("end_idx", "<i8"), ("start_row", "<i4"),
                        ("end_row", "<i4"), ("start_flag", "<i4"), ("end_flag", "<i4"),
                        ("lptr_off", "<i8")])
@@ -109,6 +113,8 @@ def load_library():
         "msrep_plan_destroy": (c_i32, [c_vp]),
         "msrep_serve": (c_i32, [P(_ServeCfg), P(_HostMat), c_i32, P(_Request), c_i64, P(_Result),
                                 P(_ServeStats)]),
+        "msrep_timing": (c_i32, [c_i32]),
+        "msrep_timing_read": (c_i32, [P(_KernelTime), c_i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -308,6 +314,23 @@ def _workspace(nbytes, device):
         buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         _ws_cache[key] = buf
     return buf
+
+
+def msrep_timing(enable: bool) -> None:
+    """Turn per-kernel event timing of msrep_spmv on or off (discards what
+    was recorded)."""
+    _check(load_library().msrep_timing(1 if enable else 0), "timing")
+
+
+def msrep_timing_read() -> dict:
+    """{kernel name: (launches, total ms)} recorded since the last read."""
+    L = load_library()
+    buf = (_KernelTime * 64)()
+    n = L.msrep_timing_read(buf, 64)
+    if n < 0:
+        raise MsrepError(n, msrep_last_error() or "timing read")
+    return {buf[i].name.decode(): (int(buf[i].calls), float(buf[i].total_ms))
+            for i in range(min(n, 64))}
 
 
 def msrep_spmv_ws_bytes(A: Mat, np_: int) -> int:

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmsrep.so")
 
 SOURCES = ["partition.hip", "spmv.hip", "convert.hip", "validate.hip", "batched.hip",
-           "autotune.hip", "serve.hip"]
+           "autotune.hip", "serve.hip", "timing.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -62,6 +62,7 @@ msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32
   using Tr = vt_traits<VT>;
   const size_t lds = seg_lds_per_wave<VT, K>() * wpb;
   const int grid = (np + wpb - 1) / wpb;
+  timing_begin(s);
   if (pf == 1)
     hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 1>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
                        static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
@@ -73,6 +74,7 @@ msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32
                        static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
                        A->m, A->n, alpha, beta, carry);
   MSREP_LAUNCHED("spmv_csr_seg");
+  timing_end("spmv_csr_seg", s);
   return MSREP_OK;
 }
 
@@ -83,11 +85,13 @@ msrep_status launch_coo(const msrep_mat *A, const msrep_part *parts, int32_t np,
   using Tr = vt_traits<VT>;
   const size_t lds = coo_lds_per_wave<VT, K>() * wpb;
   const int grid = (np + wpb - 1) / wpb;
+  timing_begin(s);
   hipLaunchKernelGGL((spmv_coo_seg<VT, K, B0>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
                      A->idx2, static_cast<const typename Tr::V *>(A->val), A->nnz, parts, np,
                      static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
                      A->m, A->n, alpha, beta, carry);
   MSREP_LAUNCHED("spmv_coo_seg");
+  timing_end("spmv_coo_seg", s);
   return MSREP_OK;
 }
 
@@ -111,29 +115,41 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   uint16_t *rlo = reinterpret_cast<uint16_t *>(b + L.rlo);
   double *part = reinterpret_cast<double *>(b + L.part);
   const size_t cur_lds = align_up(static_cast<size_t>(L.nb) * 4, 16);
+  timing_begin(s);
   hipLaunchKernelGGL(csc_count, dim3(L.P), dim3(kCscScatterWaves * kWave), cur_lds, s, A->idx, A->nnz, parts, np,
                      L.P, A->m, L.shift, L.nb, cnt);
   MSREP_LAUNCHED("csc_count");
+  timing_end("csc_count", s);
+  timing_begin(s);
   if (msrep_status st = scan::device_scan<int32_t, scan::SumOp>(
           cnt, cnt, static_cast<int64_t>(L.nb) * L.P + 1, agg, false, s))
     return st;
+  timing_end("csc_scan", s);
   (void)wpb;  // the scatter always runs one 16-wavefront producer per CU
+  timing_begin(s);
   hipLaunchKernelGGL((csc_scatter<VT, K>), dim3(L.P), dim3(kCscScatterWaves * kWave),
                      cur_lds + csc_lds_per_wave<K>() * kCscScatterWaves, s, A->idx,
                      static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
                      static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
   MSREP_LAUNCHED("csc_scatter");
+  timing_end("csc_scatter", s);
+  timing_begin(s);
   hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kCscBlock), 0, s, cnt, L.nb, L.P, pbase, mbase);
   MSREP_LAUNCHED("csc_plan");
+  timing_end("csc_plan", s);
+  timing_begin(s);
   hipLaunchKernelGGL((csc_reduce<T, Acc>), dim3(static_cast<uint32_t>(L.max_pieces)),
                      dim3(kCscBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
                      L.nb, L.P, L.shift, A->m, A->nnz, L.max_slots, part, static_cast<T *>(y),
                      alpha, beta);
   MSREP_LAUNCHED("csc_reduce");
+  timing_end("csc_reduce", s);
+  timing_begin(s);
   hipLaunchKernelGGL((csc_merge<T>), dim3(L.nb, (1 << L.shift) / kCscBlock), dim3(kCscBlock), 0, s,
                      pbase, mbase, L.shift, A->m, L.max_slots, part, static_cast<T *>(y), alpha,
                      beta);
   MSREP_LAUNCHED("csc_merge");
+  timing_end("csc_merge", s);
   return MSREP_OK;
 }
 
@@ -166,6 +182,7 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   if (st) return st;
   if (np > 1) {
     const int g = (np + 255) / 256;
+    timing_begin(s);
     if (b0)
       hipLaunchKernelGGL((merge_rows<T, true>), dim3(g), dim3(256), 0, s, parts, np, carry,
                          static_cast<T *>(y), A->m, alpha, beta);
@@ -173,6 +190,7 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
       hipLaunchKernelGGL((merge_rows<T, false>), dim3(g), dim3(256), 0, s, parts, np, carry,
                          static_cast<T *>(y), A->m, alpha, beta);
     MSREP_LAUNCHED("merge_rows");
+    timing_end("merge_rows", s);
   }
   return MSREP_OK;
 }

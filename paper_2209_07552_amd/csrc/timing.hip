@@ -1,0 +1,123 @@
+// Per-kernel timing for profiling: while enabled, the SpMV path brackets each
+// kernel it launches with a pair of HIP events recorded on the caller's
+// stream; msrep_timing_read waits for them and totals the elapsed times by
+// kernel name.  Off by default, so the SpMV path records nothing.
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace msrep {
+namespace {
+
+struct Mark {
+  const char *name;
+  hipEvent_t e0, e1;
+};
+
+struct Timing {
+  std::mutex mu;
+  std::atomic<bool> on{false};
+  std::vector<hipEvent_t> pool;  // events free for reuse
+  std::vector<Mark> marks;       // recorded, not yet read
+  hipEvent_t open = nullptr;     // begin event of the launch in progress
+};
+
+Timing &timing() {
+  static Timing t;
+  return t;
+}
+
+hipEvent_t take_event(Timing &t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void recycle(Timing &t) {
+  for (const Mark &m : t.marks) {
+    t.pool.push_back(m.e0);
+    t.pool.push_back(m.e1);
+  }
+  t.marks.clear();
+  if (t.open) t.pool.push_back(t.open);
+  t.open = nullptr;
+}
+
+}  // namespace
+
+void timing_begin(hipStream_t s) {
+  Timing &t = timing();
+  if (!t.on.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> g(t.mu);
+  if (t.open) t.pool.push_back(t.open);
+  t.open = nullptr;
+  hipEvent_t e = take_event(t);
+  if (e && hipEventRecord(e, s) == hipSuccess)
+    t.open = e;
+  else if (e)
+    t.pool.push_back(e);
+}
+
+void timing_end(const char *name, hipStream_t s) {
+  Timing &t = timing();
+  if (!t.on.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.open) return;
+  hipEvent_t e = take_event(t);
+  if (e && hipEventRecord(e, s) == hipSuccess) {
+    t.marks.push_back(Mark{name, t.open, e});
+  } else {
+    t.pool.push_back(t.open);
+    if (e) t.pool.push_back(e);
+  }
+  t.open = nullptr;
+}
+
+}  // namespace msrep
+
+using namespace msrep;
+
+extern "C" msrep_status msrep_timing(int32_t enable) {
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (const Mark &m : t.marks) (void)hipEventSynchronize(m.e1);
+  recycle(t);
+  t.on.store(enable != 0);
+  return ok();
+}
+
+extern "C" int32_t msrep_timing_read(msrep_kernel_time *out, int32_t cap) {
+  if (cap < 0 || (cap > 0 && !out)) return fail(MSREP_ERR_ARG, "msrep_timing_read: bad buffer");
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  std::vector<msrep_kernel_time> agg;
+  msrep_status err = MSREP_OK;
+  for (const Mark &m : t.marks) {
+    float ms = 0.f;
+    if (hipEventSynchronize(m.e1) != hipSuccess || hipEventElapsedTime(&ms, m.e0, m.e1) != hipSuccess) {
+      err = fail(MSREP_ERR_HIP, "msrep_timing_read: event timing failed");
+      break;
+    }
+    size_t i = 0;
+    while (i < agg.size() && std::strncmp(agg[i].name, m.name, sizeof agg[i].name) != 0) ++i;
+    if (i == agg.size()) {
+      msrep_kernel_time k{};
+      std::strncpy(k.name, m.name, sizeof k.name - 1);
+      agg.push_back(k);
+    }
+    agg[i].calls += 1;
+    agg[i].total_ms += ms;
+  }
+  recycle(t);
+  if (err) return err;
+  for (size_t i = 0; i < agg.size() && static_cast<int32_t>(i) < cap; ++i) out[i] = agg[i];
+  ok();
+  return static_cast<int32_t>(agg.size());
+}

@@ -31,6 +31,7 @@ def test_struct_sizes():
     assert ctypes.sizeof(_abi._Mat) == 56
     assert pk.PART_DTYPE.itemsize == 40
     assert ctypes.sizeof(_abi._Tune) == 24
+    assert ctypes.sizeof(_abi._KernelTime) == 64
 
 
 def test_lptr_bound_and_vtype_bytes():
@@ -97,3 +98,13 @@ def test_csc_workspace_and_row_limit():
     assert st == -7 and b"CSC" in L.msrep_last_error()
     ok = _desc(fmt=1, m=1 << 26, n=4, nnz=4)
     assert L.msrep_spmv_ws_bytes(ctypes.byref(ok), 8) > 0
+
+
+def test_timing_toggle_and_empty_read():
+    """Kernel timing is host state: enabling, reading with nothing recorded
+    and disabling work without a GPU; a bad buffer is an argument error."""
+    L = _lib()
+    pk.msrep_timing(True)
+    assert pk.msrep_timing_read() == {}
+    pk.msrep_timing(False)
+    assert L.msrep_timing_read(None, -1) == -1

@@ -250,3 +250,24 @@ def test_csc_many_buckets_and_pieces(vt):
         for np_ in (5, 4096, 100_000):
             y, ref, s = _run(A, x, "csc", vt, np_, 0.75, -1.5, y_in, M=M, v64=v64)
             assert_close(y, ref, s, tol, "%s csc vt%d np%d" % (A.name, vt, np_))
+
+
+def test_kernel_timing_records_each_launch():
+    """With timing on, every kernel of the call is bracketed by events: one
+    CSR SpMV at np > 1 records the SpMV kernel and the boundary merge once
+    each, the CSC path its five kernels and the scan; off records nothing."""
+    A, x = synth.rmat_csr(scale=12, edge_factor=8, seed=2)
+    pk.msrep_timing(True)
+    try:
+        _run(A, x, "csr", pk.F64, 64)
+        t = pk.msrep_timing_read()
+        assert set(t) == {"spmv_csr_seg", "merge_rows"}, t
+        assert all(c == 1 and ms > 0 for c, ms in t.values()), t
+        _run(A, x, "csc", pk.F64, 64)
+        t = pk.msrep_timing_read()
+        assert set(t) == {"csc_count", "csc_scan", "csc_scatter", "csc_plan", "csc_reduce",
+                          "csc_merge"}, t
+    finally:
+        pk.msrep_timing(False)
+    _run(A, x, "coo", pk.F64, 64)
+    assert pk.msrep_timing_read() == {}
