@@ -131,11 +131,98 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(const int3
   if (p == 0 && threadIdx.x == 0) cnt[static_cast<int64_t>(nb) * P] = 0;
 }
 
-// Products of producer p written into its run of each bucket.  The column of
-// every position comes from the partition's local column pointer: columns
-// that start inside a chunk mark their first position in LDS and a max-scan
-// carries the index forward.  Rows outside [0, m) are skipped here exactly
-// as csc_count skips them; a column outside [0, n) contributes 0.
+// One chunk of CH = 64*K positions [cb, cb+CH) of a pCSC partition (local
+// positions; the partition holds nloc nonzeros from global position s0, its
+// columns c0 .. c0+R-1 with local pointer lp).  The column of every position
+// comes from the local column pointer: columns that start inside the chunk
+// mark their first position in the wave's LDS array and a max-scan carries
+// the index forward.  Outputs, per item of this lane: ok (a position of the
+// partition whose row lies in [0, m)), its row and the product val*x[col]
+// (0 for a column outside [0, n)).  j0, the local column holding the chunk's
+// first position, advances to the next chunk's.
+template <int VT, int K>
+__device__ __forceinline__ void csc_chunk(
+    const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
+    int64_t s0, int32_t nloc, int32_t cb, int32_t c0, int32_t R, const int32_t *__restrict__ lp,
+    const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n, int32_t *s_col,
+    int lane, int32_t &j0, bool (&ok)[K], int32_t (&rows)[K],
+    typename vt_traits<VT>::A (&pr)[K]) {
+  using Tr = vt_traits<VT>;
+  using V = typename Tr::V;
+  using Acc = typename Tr::A;
+  constexpr int CH = kWave * K;
+  const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
+  const int32_t q0 = cb + lane * K;
+  V v[K];
+  const bool full = q0 >= 0 && q0 + K <= nloc;
+  if (full) {
+    load_vec<int32_t, K>(row_idx + s0 + q0, rows);
+    load_vec<V, K>(val + s0 + q0, v);
+  } else {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int32_t q = q0 + t;
+      rows[t] = -1;
+      v[t] = V(0);
+      if (q >= 0 && q < nloc) {
+        rows[t] = row_idx[s0 + q];
+        v[t] = val[s0 + q];
+      }
+    }
+  }
+  // columns starting inside the chunk mark their first position
+#pragma unroll
+  for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
+  wave_lds_sync();
+  int32_t jb = j0, cnt;
+  for (;;) {
+    const int32_t j = jb + lane;
+    const int32_t a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
+    const bool in = j <= R - 1 && a < ce;
+    if (in && j > j0) {
+      const int32_t pos = a - cb;
+      if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
+    }
+    cnt = __popcll(__ballot(in));
+    if (cnt < kWave) break;
+    jb += kWave;
+  }
+  const int32_t j1 = jb + cnt - 1;
+  wave_lds_sync();
+  int32_t cj[K];
+  int32_t mx = j0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const int32_t h = s_col[lane * K + t];
+    mx = h > mx ? h : mx;
+    cj[t] = mx;
+  }
+  int32_t agg = mx;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t o = shfl_up_i(agg, d);
+    if (lane >= d) agg = o > agg ? o : agg;
+  }
+  int32_t cin = shfl_up_i(agg, 1);
+  if (lane == 0) cin = j0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const int32_t q = q0 + t;
+    const int32_t j = cj[t] > cin ? cj[t] : cin;
+    const int32_t c = c0 + j;
+    ok[t] = q >= 0 && q < nloc && static_cast<uint32_t>(rows[t]) < static_cast<uint32_t>(m);
+    pr[t] = ok[t] && static_cast<uint32_t>(c) < static_cast<uint32_t>(n)
+                ? Tr::val(v[t]) * static_cast<Acc>(x[c])
+                : Acc(0);
+  }
+  // the column holding the chunk's last position continues, unless it ends
+  const int32_t nxt = (j1 + 1 >= 0 && j1 + 1 <= R) ? lp[j1 + 1] : nloc;
+  j0 = nxt > ce ? j1 : j1 + 1;
+  wave_lds_sync();
+}
+
+// Products of producer p go straight to their positions in its run of each
+// bucket (an LDS cursor per bucket hands out positions).
 template <int VT, int K>
 __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
@@ -143,9 +230,7 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     int32_t np, int32_t P, const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n,
     int shift, int32_t nb, const int32_t *__restrict__ off,
     typename vt_traits<VT>::A *__restrict__ prod, uint16_t *__restrict__ rlo) {
-  using Tr = vt_traits<VT>;
-  using V = typename Tr::V;
-  using Acc = typename Tr::A;
+  using Acc = typename vt_traits<VT>::A;
   constexpr int CH = kWave * K;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int32_t *cur = reinterpret_cast<int32_t *>(lds_raw);
@@ -161,94 +246,29 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   const uint32_t mask = (1u << shift) - 1u;
   int64_t pa, pb;
   producer_range(p, np, P, pa, pb);
-
   for (int64_t pi = pa + wid; pi < pb; pi += wpb) {
     const msrep_part *pp = parts + pi;
     const int64_t s0 = uniform(pp->start_idx);
-    const int64_t e0 = uniform(pp->end_idx);
+    const int32_t nloc = static_cast<int32_t>(uniform(pp->end_idx) - s0 + 1);
     const int32_t c0 = uniform(pp->start_row);  // first column
     const int32_t R = uniform(pp->end_row) - c0 + 1;
     const int32_t *__restrict__ lp = lptr + uniform(pp->lptr_off);
-    const int32_t nloc = static_cast<int32_t>(e0 - s0 + 1);
-    const int32_t lead = static_cast<int32_t>(s0 % K);
-    int32_t j0 = 0;  // local column containing the chunk's first position
-    for (int32_t cb = -lead; cb < nloc; cb += CH) {
-      const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
-      const int32_t q0 = cb + lane * K;
+    int32_t j0 = 0;
+    for (int32_t cb = -static_cast<int32_t>(s0 % K); cb < nloc; cb += CH) {
+      bool okk[K];
       int32_t rows[K];
-      V v[K];
-      const bool full = q0 >= 0 && q0 + K <= nloc;
-      if (full) {
-        load_vec<int32_t, K>(row_idx + s0 + q0, rows);
-        load_vec<V, K>(val + s0 + q0, v);
-      } else {
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-          const int32_t q = q0 + t;
-          rows[t] = -1;
-          v[t] = V(0);
-          if (q >= 0 && q < nloc) {
-            rows[t] = row_idx[s0 + q];
-            v[t] = val[s0 + q];
-          }
-        }
-      }
-      // columns starting inside the chunk mark their first position
-#pragma unroll
-      for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
-      wave_lds_sync();
-      int32_t jb = j0, cnt;
-      for (;;) {
-        const int32_t j = jb + lane;
-        const int32_t a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
-        const bool in = j <= R - 1 && a < ce;
-        if (in && j > j0) {
-          const int32_t pos = a - cb;
-          if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
-        }
-        cnt = __popcll(__ballot(in));
-        if (cnt < kWave) break;
-        jb += kWave;
-      }
-      const int32_t j1 = jb + cnt - 1;
-      wave_lds_sync();
-      int32_t cj[K];
-      int32_t mx = j0;
+      Acc pr[K];
+      csc_chunk<VT, K>(row_idx, val, s0, nloc, cb, c0, R, lp, x, m, n, s_col, lane, j0, okk, rows,
+                       pr);
 #pragma unroll
       for (int t = 0; t < K; ++t) {
-        const int32_t h = s_col[lane * K + t];
-        mx = h > mx ? h : mx;
-        cj[t] = mx;
-      }
-      int32_t agg = mx;
-#pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const int32_t o = shfl_up_i(agg, d);
-        if (lane >= d) agg = o > agg ? o : agg;
-      }
-      int32_t cin = shfl_up_i(agg, 1);
-      if (lane == 0) cin = j0;
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        const int32_t q = q0 + t;
-        const int32_t j = cj[t] > cin ? cj[t] : cin;
-        const int32_t c = c0 + j;
-        if (q < 0 || q >= nloc) continue;
-        const int32_t r = rows[t];
-        if (static_cast<uint32_t>(r) >= static_cast<uint32_t>(m)) continue;
-        const Acc pr = static_cast<uint32_t>(c) < static_cast<uint32_t>(n)
-                           ? Tr::val(v[t]) * static_cast<Acc>(x[c])
-                           : Acc(0);
-        const int32_t at = atomicAdd(&cur[static_cast<uint32_t>(r) >> shift], 1);
+        if (!okk[t]) continue;
+        const int32_t at = atomicAdd(&cur[static_cast<uint32_t>(rows[t]) >> shift], 1);
         if (static_cast<uint64_t>(at) < static_cast<uint64_t>(nnz)) {
-          prod[at] = pr;
-          rlo[at] = static_cast<uint16_t>(static_cast<uint32_t>(r) & mask);
+          prod[at] = pr[t];
+          rlo[at] = static_cast<uint16_t>(static_cast<uint32_t>(rows[t]) & mask);
         }
       }
-      // the column holding the chunk's last position continues, unless it ends
-      const int32_t nxt = (j1 + 1 >= 0 && j1 + 1 <= R) ? lp[j1 + 1] : nloc;
-      j0 = nxt > ce ? j1 : j1 + 1;
-      wave_lds_sync();
     }
   }
 }
