@@ -31,10 +31,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Launch shape per workload and format used unless --autotune or explicit
-# --nnz-per-wave/--k/--wpb/--pipeline are given: the tuner's picks on MI355X
-# (Tune fields: nnz_per_wave, k_per_lane, waves_per_wg, pipeline).
+# --nnz-per-wave/--k/--wpb/--pipeline/--resident are given: the tuner's picks
+# on MI355X (nnz_per_wave, k_per_lane, waves_per_wg, pipeline, resident).
 DEFAULT_TUNES = {
-    "rmat20": {"csr": (512, 4, 2, 2), "coo": (512, 4, 8, 2), "csc": (512, 4, 8, 2)},
+    "rmat20": {"csr": (512, 4, 2, 2, 1), "coo": (512, 4, 8, 2, 0), "csc": (512, 4, 8, 2, 0)},
+    "stencil256": {"csr": (2048, 4, 4, 1, 0), "coo": (1024, 4, 2, 2, 0),
+                   "csc": (4096, 4, 4, 2, 0)},
 }
 SCRUB_BYTES = 512 << 20
 
@@ -240,6 +242,7 @@ def main():
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--pipeline", type=int, default=0)
+    ap.add_argument("--resident", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune every format first")
@@ -321,10 +324,12 @@ def main():
         stored_t = DEFAULT_TUNES.get(args.workload, {}).get(f)
         if args.nnz_per_wave:
             tunes[f] = pk.Tune(k_per_lane=args.k, waves_per_wg=args.wpb,
-                               nnz_per_wave=args.nnz_per_wave, pipeline=args.pipeline)
+                               nnz_per_wave=args.nnz_per_wave, pipeline=args.pipeline,
+                               resident=args.resident)
         elif stored_t and not args.autotune:
             tunes[f] = pk.Tune(k_per_lane=stored_t[1], waves_per_wg=stored_t[2],
-                               nnz_per_wave=stored_t[0], pipeline=stored_t[3])
+                               nnz_per_wave=stored_t[0], pipeline=stored_t[3],
+                               resident=stored_t[4])
         else:
             tunes[f] = pk.msrep_autotune(mats[f], x)
             log("tuned %s: %s" % (f, tunes[f]))
@@ -402,7 +407,8 @@ def main():
                       "tune": {"k_per_lane": tunes[f].k_per_lane or 4,
                                "waves_per_wg": tunes[f].waves_per_wg or 4,
                                "nnz_per_wave": tunes[f].nnz_per_wave,
-                               "pipeline": tunes[f].pipeline or 2}}
+                               "pipeline": tunes[f].pipeline or 2,
+                               "resident": tunes[f].resident}}
         if f in warm_ms:
             per_fmt[f]["ms_warm"] = round(warm_ms[f], 4)
             per_fmt[f]["gbs_warm"] = round(b / warm_ms[f] / 1e6, 1)

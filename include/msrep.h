@@ -171,11 +171,11 @@ msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,
 /* Launch shape.  A zeroed struct (or NULL) selects the defaults. */
 typedef struct msrep_tune {
   int32_t k_per_lane;   /* nonzeros per lane per chunk: 4 (default) or 8       */
-  int32_t waves_per_wg; /* wavefronts per workgroup, 1..8 (default 4); each    */
-                        /* wavefront owns one partition                        */
-  int32_t rows_per_wave;/* 0: segmented-scan kernel (any row lengths);         */
-                        /* 1..64: row-group kernel, 64/rows_per_wave lanes per */
-                        /* row (CSR only; for short, even rows)                */
+  int32_t waves_per_wg; /* wavefronts per workgroup, 1..8 (default 4)          */
+  int32_t resident;     /* CSR, COO: 0 (default) one wavefront per partition,  */
+                        /* launched as the hardware frees slots; 1: as many    */
+                        /* wavefronts as the device holds at once, each taking */
+                        /* every W-th partition (W = their number)             */
   int32_t nnz_per_wave; /* partition size the autotuner recommends, so that    */
                         /* np = ceil(nnz / nnz_per_wave); not read by msrep_spmv */
   int32_t pipeline;     /* CSR: chunks of indices/values loaded ahead, 1 or 2  */

@@ -37,7 +37,7 @@ class _Mat(ctypes.Structure):
 
 
 class _Tune(ctypes.Structure):
-    _fields_ = [("k_per_lane", c_i32), ("waves_per_wg", c_i32), ("rows_per_wave", c_i32),
+    _fields_ = [("k_per_lane", c_i32), ("waves_per_wg", c_i32), ("resident", c_i32),
                 ("nnz_per_wave", c_i32), ("pipeline", c_i32), ("_pad", c_i32)]
 
 
@@ -256,12 +256,12 @@ def mat_from_csr(ptr, col, val, m, n, vtype=F64, device="cuda"):
 class Tune:
     k_per_lane: int = 0
     waves_per_wg: int = 0
-    rows_per_wave: int = 0
+    resident: int = 0
     nnz_per_wave: int = 0
     pipeline: int = 0
 
     def c(self) -> _Tune:
-        return _Tune(self.k_per_lane, self.waves_per_wg, self.rows_per_wave, self.nnz_per_wave,
+        return _Tune(self.k_per_lane, self.waves_per_wg, self.resident, self.nnz_per_wave,
                      self.pipeline, 0)
 
 
@@ -376,8 +376,7 @@ def msrep_autotune(A: Mat, x, stream=None) -> Tune:
     out = _Tune()
     _check(L.msrep_autotune(ctypes.byref(d), _ptr(x), _ptr(ws), ws.numel(), ctypes.byref(out),
                             _stream(stream)), "autotune")
-    return Tune(out.k_per_lane, out.waves_per_wg, out.rows_per_wave, out.nnz_per_wave,
-                out.pipeline)
+    return Tune(out.k_per_lane, out.waves_per_wg, out.resident, out.nnz_per_wave, out.pipeline)
 
 
 class Plan:

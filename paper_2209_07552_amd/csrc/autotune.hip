@@ -1,8 +1,8 @@
 // msrep_autotune: choose the partition size (nonzeros per wavefront, i.e. the
 // np of the equal-nnz split) and the launch shape (nonzeros per lane per
-// chunk, wavefronts per workgroup) for one matrix by timing every candidate
-// on the device: build the partitions, run the SpMV a few times, keep the
-// fastest median.  Synchronises the stream.
+// chunk, wavefronts per workgroup, CSR pipeline depth, resident grid) for one
+// matrix by timing every candidate on the device: build the partitions, run
+// the SpMV a few times, keep the fastest median.  Synchronises the stream.
 #include <algorithm>
 #include <vector>
 
@@ -11,7 +11,7 @@
 namespace msrep {
 msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
-                         int wpb, int pf, double *carry, hipStream_t s);
+                         int wpb, int pf, int resident, double *carry, hipStream_t s);
 size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t np);
 namespace {
 
@@ -19,6 +19,7 @@ constexpr int kNpw[] = {256, 512, 1024, 2048, 4096};
 constexpr int kK[] = {4, 8};
 constexpr int kWpb[] = {2, 4, 8};
 constexpr int kPf[] = {1, 2};
+constexpr int kResident[] = {0, 1};
 constexpr int kReps = 3;
 
 struct TuneWs {
@@ -86,29 +87,35 @@ extern "C" msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void
       break;
     for (int K : kK)
       for (int wpb : kWpb)
-        for (int pf : kPf) {
-        if (err) break;
-        if (A->fmt != MSREP_CSR && pf == 1) continue;  // only CSR has the choice
-        if ((err = spmv_launch(A, parts, lptr, np, x_d, y, 1.0, 0.0, K, wpb, pf, carry, s))) break;
-        std::vector<float> t;
-        for (int r = 0; r < kReps && !err; ++r) {
-          if (hipEventRecord(e0, s) != hipSuccess) err = fail(MSREP_ERR_HIP, "hipEventRecord");
-          if (!err) err = spmv_launch(A, parts, lptr, np, x_d, y, 1.0, 0.0, K, wpb, pf, carry, s);
-          if (!err && hipEventRecord(e1, s) != hipSuccess) err = fail(MSREP_ERR_HIP, "hipEventRecord");
-          float ms = 0.f;
-          if (!err && (hipEventSynchronize(e1) != hipSuccess ||
-                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            err = fail(MSREP_ERR_HIP, "timing failed");
-          t.push_back(ms);
-        }
-        if (err) break;
-        std::sort(t.begin(), t.end());
-        const float med = t[t.size() / 2];
-        if (med < best_ms) {
-          best_ms = med;
-          best = msrep_tune{K, wpb, 0, npw, pf, 0};
-        }
-      }
+        for (int pf : kPf)
+          for (int res : kResident) {
+            if (err) break;
+            // CSC has neither choice (its producer shapes are fixed)
+            if (A->fmt == MSREP_CSC && (res == 1 || wpb != kWpb[0])) continue;
+            if (A->fmt != MSREP_CSR && pf == 1) continue;  // only CSR pipelines
+            if ((err = spmv_launch(A, parts, lptr, np, x_d, y, 1.0, 0.0, K, wpb, pf, res, carry, s)))
+              break;
+            std::vector<float> t;
+            for (int r = 0; r < kReps && !err; ++r) {
+              if (hipEventRecord(e0, s) != hipSuccess) err = fail(MSREP_ERR_HIP, "hipEventRecord");
+              if (!err)
+                err = spmv_launch(A, parts, lptr, np, x_d, y, 1.0, 0.0, K, wpb, pf, res, carry, s);
+              if (!err && hipEventRecord(e1, s) != hipSuccess)
+                err = fail(MSREP_ERR_HIP, "hipEventRecord");
+              float ms = 0.f;
+              if (!err && (hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                err = fail(MSREP_ERR_HIP, "timing failed");
+              t.push_back(ms);
+            }
+            if (err) break;
+            std::sort(t.begin(), t.end());
+            const float med = t[t.size() / 2];
+            if (med < best_ms) {
+              best_ms = med;
+              best = msrep_tune{K, wpb, res, npw, pf, 0};
+            }
+          }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -17,7 +17,8 @@
 
 namespace msrep {
 
-msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, const char *who);
+msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, int *resident,
+                          const char *who);
 
 namespace {
 
@@ -167,8 +168,9 @@ extern "C" msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
     if (static_cast<uint64_t>(mats[k].n) * vec_bytes(mats[k].vtype) >= (uint64_t(1) << 32))
       return fail(MSREP_ERR_UNSUPPORTED, "msrep_plan_create: x of matrix %d exceeds 4 GiB", k);
   }
-  int K, wpb, pf;
-  if (msrep_status st = resolve_tune(tunes, &K, &wpb, &pf, "msrep_plan_create")) return st;
+  int K, wpb, pf, resident;  // (the batched kernel's grid is always resident)
+  if (msrep_status st = resolve_tune(tunes, &K, &wpb, &pf, &resident, "msrep_plan_create"))
+    return st;
   Layout L = layout(count, mats, tunes);
   if (!ws_d || ws_bytes < L.total)
     return fail(MSREP_ERR_SIZE, "msrep_plan_create: workspace of %zu bytes needed (got %zu)",

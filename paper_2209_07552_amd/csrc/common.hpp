@@ -127,6 +127,20 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Wavefronts over np partitions, without atomics: wavefront gw of W takes
+// partitions gw, gw + W, gw + 2W, ... (a single one when the grid has a
+// wavefront per partition).  The wavefront ids follow the XCD-aware block
+// order, so at any moment the resident wavefronts work on one contiguous
+// window of partitions and each XCD on a contiguous part of it.
+struct PartStride {
+  int32_t p, step, np;
+  __device__ __forceinline__ PartStride(int32_t np_) : np(np_) {
+    const int wpb = blockDim.x / kWave;
+    p = xcd_block(blockIdx.x, gridDim.x) * wpb + static_cast<int>(threadIdx.x / kWave);
+    step = gridDim.x * wpb;
+  }
+};
+
 // Keep the compiler from moving LDS accesses of one wavefront across this
 // point; a single wavefront's LDS operations execute in program order.
 __device__ __forceinline__ void wave_lds_sync() {

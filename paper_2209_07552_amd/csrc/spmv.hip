@@ -1,6 +1,8 @@
 // msrep_spmv: dispatch of the per-format SpMV kernels and of the boundary
 // merge, plus the shared C-ABI helpers (errors, descriptor checks).
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "common.hpp"
 #include "spmv_coo.hpp"
@@ -55,21 +57,56 @@ msrep_status check_mat(const msrep_mat *A, const char *who) {
 
 namespace {
 
+// Blocks of `threads` threads (dyn_lds bytes of LDS each) that the device
+// holds at once, capped at want; cached per kernel, shape and device.
+template <typename Kern>
+int resident_grid(Kern kernel, int threads, size_t dyn_lds, int64_t want) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void *, int, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const auto key = std::make_tuple(reinterpret_cast<const void *>(kernel), threads, dyn_lds, dev);
+  int g;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      g = it->second;
+    } else {
+      int per_cu = 0, cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn_lds) !=
+          hipSuccess)
+        per_cu = 1;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 1;
+      g = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+      cache.emplace(key, g);
+    }
+  }
+  return static_cast<int>(want < g ? (want > 0 ? want : 1) : g);
+}
+
 template <int VT, int K, bool B0>
 msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                         int32_t np, const void *x, void *y, double alpha, double beta, int wpb,
-                        int pf, double *carry, hipStream_t s) {
+                        int pf, int resident, double *carry, hipStream_t s) {
   using Tr = vt_traits<VT>;
   const size_t lds = seg_lds_per_wave<VT, K>() * wpb;
-  const int grid = (np + wpb - 1) / wpb;
+  const int64_t want = (np + wpb - 1) / wpb;  // one wavefront per partition
   timing_begin(s);
   if (pf == 1)
-    hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 1>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
+    hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 1>),
+                       dim3(resident ? resident_grid(spmv_csr_seg<VT, K, B0, 1>, wpb * kWave, lds, want)
+                                : want),
+                       dim3(wpb * kWave), lds, s, A->idx,
                        static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
                        static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
                        A->m, A->n, alpha, beta, carry);
   else
-    hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 2>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
+    hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 2>),
+                       dim3(resident ? resident_grid(spmv_csr_seg<VT, K, B0, 2>, wpb * kWave, lds, want)
+                                : want),
+                       dim3(wpb * kWave), lds, s, A->idx,
                        static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
                        static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
                        A->m, A->n, alpha, beta, carry);
@@ -80,14 +117,17 @@ msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32
 
 template <int VT, int K, bool B0>
 msrep_status launch_coo(const msrep_mat *A, const msrep_part *parts, int32_t np, const void *x,
-                        void *y, double alpha, double beta, int wpb, double *carry,
+                        void *y, double alpha, double beta, int wpb, int resident, double *carry,
                         hipStream_t s) {
   using Tr = vt_traits<VT>;
   const size_t lds = coo_lds_per_wave<VT, K>() * wpb;
-  const int grid = (np + wpb - 1) / wpb;
+  const int64_t want = (np + wpb - 1) / wpb;  // one wavefront per partition
   timing_begin(s);
-  hipLaunchKernelGGL((spmv_coo_seg<VT, K, B0>), dim3(grid), dim3(wpb * kWave), lds, s, A->idx,
-                     A->idx2, static_cast<const typename Tr::V *>(A->val), A->nnz, parts, np,
+  hipLaunchKernelGGL((spmv_coo_seg<VT, K, B0>),
+                     dim3(resident ? resident_grid(spmv_coo_seg<VT, K, B0>, wpb * kWave, lds, want)
+                                   : want),
+                     dim3(wpb * kWave), lds, s, A->idx, A->idx2,
+                     static_cast<const typename Tr::V *>(A->val), A->nnz, parts, np,
                      static_cast<const typename Tr::T *>(x), static_cast<typename Tr::T *>(y),
                      A->m, A->n, alpha, beta, carry);
   MSREP_LAUNCHED("spmv_coo_seg");
@@ -156,16 +196,17 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
 template <int VT, int K, bool B0>
 msrep_status dispatch_rows(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                            int32_t np, const void *x, void *y, double alpha, double beta,
-                           int wpb, int pf, double *carry, hipStream_t s) {
+                           int wpb, int pf, int resident, double *carry, hipStream_t s) {
   if (A->fmt == MSREP_CSR)
-    return launch_csr<VT, K, B0>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s);
-  return launch_coo<VT, K, B0>(A, parts, np, x, y, alpha, beta, wpb, carry, s);
+    return launch_csr<VT, K, B0>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry,
+                                 s);
+  return launch_coo<VT, K, B0>(A, parts, np, x, y, alpha, beta, wpb, resident, carry, s);
 }
 
 template <int VT>
 msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
-                         int wpb, int pf, double *carry, hipStream_t s) {
+                         int wpb, int pf, int resident, double *carry, hipStream_t s) {
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
@@ -174,11 +215,11 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
                   : launch_csc<VT, 4>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
   }
   if (K == 8)
-    st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s)
-            : dispatch_rows<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s);
+    st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s)
+            : dispatch_rows<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s);
   else
-    st = b0 ? dispatch_rows<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s)
-            : dispatch_rows<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, carry, s);
+    st = b0 ? dispatch_rows<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s)
+            : dispatch_rows<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s);
   if (st) return st;
   if (np > 1) {
     const int g = (np + 255) / 256;
@@ -197,10 +238,12 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
 
 }  // namespace
 
-msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, const char *who) {
+msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, int *resident,
+                          const char *who) {
   *K = 4;
   *wpb = 4;
   *pf = 2;
+  *resident = 0;
   if (!tune) return MSREP_OK;
   if (tune->pipeline < 0 || tune->pipeline > 2)
     return fail(MSREP_ERR_ARG, "%s: pipeline must be 0, 1 or 2 (got %d)", who, tune->pipeline);
@@ -209,23 +252,24 @@ msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, con
     return fail(MSREP_ERR_ARG, "%s: k_per_lane must be 4 or 8 (got %d)", who, tune->k_per_lane);
   if (tune->waves_per_wg < 0 || tune->waves_per_wg > 8)
     return fail(MSREP_ERR_ARG, "%s: waves_per_wg must be 1..8 (got %d)", who, tune->waves_per_wg);
-  if (tune->rows_per_wave < 0 || tune->rows_per_wave > 64)
-    return fail(MSREP_ERR_ARG, "%s: rows_per_wave must be 0..64", who);
+  if (tune->resident != 0 && tune->resident != 1)
+    return fail(MSREP_ERR_ARG, "%s: resident must be 0 or 1 (got %d)", who, tune->resident);
   if (tune->k_per_lane) *K = tune->k_per_lane;
   if (tune->waves_per_wg) *wpb = tune->waves_per_wg;
+  *resident = tune->resident;
   return MSREP_OK;
 }
 
 msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
-                         int wpb, int pf, double *carry, hipStream_t s) {
+                         int wpb, int pf, int resident, double *carry, hipStream_t s) {
   switch (A->vtype) {
     case MSREP_F64:
-      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, s);
+      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, s);
     case MSREP_F32:
-      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, s);
+      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, s);
     default:
-      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, s);
+      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, s);
   }
 }
 
@@ -266,10 +310,8 @@ extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d
   if (A->fmt != MSREP_COO && !lptr_d) return fail(MSREP_ERR_ARG, "msrep_spmv: lptr_d is NULL");
   if (A->m > 0 && !y_d) return fail(MSREP_ERR_ARG, "msrep_spmv: y_d is NULL");
   if (A->nnz > 0 && !x_d) return fail(MSREP_ERR_ARG, "msrep_spmv: x_d is NULL");
-  int K, wpb, pf;
-  if (msrep_status st = resolve_tune(tune, &K, &wpb, &pf, "msrep_spmv")) return st;
-  if (tune && tune->rows_per_wave > 0 && A->fmt != MSREP_CSR)
-    return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: rows_per_wave kernel is CSR only");
+  int K, wpb, pf, resident;
+  if (msrep_status st = resolve_tune(tune, &K, &wpb, &pf, &resident, "msrep_spmv")) return st;
   // x, y and the local pointers are addressed through 32-bit buffer offsets
   const uint64_t xb = static_cast<uint64_t>(A->n) * vec_bytes(A->vtype);
   const uint64_t yb = static_cast<uint64_t>(A->m) * vec_bytes(A->vtype);
@@ -287,7 +329,7 @@ extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d
     return fail(MSREP_ERR_SIZE, "msrep_spmv: workspace of %zu bytes needed (got %zu)", need,
                 ws_d ? ws_bytes : size_t(0));
   if (A->m == 0) return ok();
-  if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb, pf,
+  if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb, pf, resident,
                                     static_cast<double *>(ws_d), as_stream(stream)))
     return st;
   return ok();

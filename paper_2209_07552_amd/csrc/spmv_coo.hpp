@@ -36,26 +36,21 @@ constexpr size_t coo_lds_per_wave() {
   return 16;  // one FP64 slot: the sum carried into the next chunk
 }
 
+// One wavefront processes partition p of a row-sorted COO matrix; s_carry is
+// this wavefront's LDS slot.
 template <int VT, int K, bool BETA0>
-__global__ __launch_bounds__(512) void spmv_coo_seg(
+__device__ __forceinline__ void coo_partition(
     const int32_t *__restrict__ row_idx, const int32_t *__restrict__ col,
-    const typename vt_traits<VT>::V *__restrict__ val, int64_t nnz,
-    const msrep_part *__restrict__ parts, int32_t np,
-    const typename vt_traits<VT>::T *__restrict__ x, typename vt_traits<VT>::T *__restrict__ y,
-    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
+    const typename vt_traits<VT>::V *__restrict__ val, const msrep_part *__restrict__ parts,
+    int32_t np, int32_t p, const typename vt_traits<VT>::T *__restrict__ x,
+    typename vt_traits<VT>::T *__restrict__ y, int32_t m, int32_t n, double alpha, double beta,
+    double *__restrict__ carry, double *s_carry) {
   using Tr = vt_traits<VT>;
   using V = typename Tr::V;
   using T = typename Tr::T;
   using Acc = typename Tr::A;
   constexpr int CH = kWave * K;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-
   const int lane = lane_id();
-  const int wid = threadIdx.x / kWave;
-  const int wpb = blockDim.x / kWave;
-  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
-  if (p >= np) return;
-  double *s_carry = reinterpret_cast<double *>(lds_raw + wid * coo_lds_per_wave<VT, K>());
 
   const msrep_part *pp = parts + p;
   const int64_t s0 = uniform(pp->start_idx);
@@ -172,6 +167,24 @@ __global__ __launch_bounds__(512) void spmv_coo_seg(
   const int32_t gap_hi = gap_hi_raw < m ? gap_hi_raw : m;
   if (!eflag) scale_rows<T>(y, gap_lo > 0 ? gap_lo : 0, gap_hi, beta, BETA0);
   if (p == 0) scale_rows<T>(y, 0, r0 < m ? r0 : m, beta, BETA0);
+}
+
+// Wavefronts striding over the partitions (see PartStride).
+template <int VT, int K, bool BETA0>
+__global__ __launch_bounds__(512) void spmv_coo_seg(
+    const int32_t *__restrict__ row_idx, const int32_t *__restrict__ col,
+    const typename vt_traits<VT>::V *__restrict__ val, int64_t nnz,
+    const msrep_part *__restrict__ parts, int32_t np,
+    const typename vt_traits<VT>::T *__restrict__ x, typename vt_traits<VT>::T *__restrict__ y,
+    int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  (void)nnz;
+  const int wid = threadIdx.x / kWave;
+  double *s_carry = reinterpret_cast<double *>(lds_raw + wid * coo_lds_per_wave<VT, K>());
+  const PartStride ps(np);
+  for (int32_t p = ps.p; p < np; p += ps.step)
+    coo_partition<VT, K, BETA0>(row_idx, col, val, parts, np, p, x, y, m, n, alpha, beta, carry,
+                                s_carry);
 }
 
 }  // namespace msrep

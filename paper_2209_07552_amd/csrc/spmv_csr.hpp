@@ -264,8 +264,19 @@ __device__ __forceinline__ void csr_partition(
 #pragma unroll
       for (int t = 0; t < K; ++t) s_sum[lane * K + t] = prod[t];
       wave_lds_sync();
+      // eight independent LDS reads per round (indices clamped into the
+      // chunk; positions past the row add 0), summed in position order
       Acc acc = Acc(0);
-      for (int32_t q = aa; q < bb; ++q) acc += s_sum[q - cb];
+      for (int32_t q = aa; q < bb; q += 8) {
+        Acc v8[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int32_t qi = q + i < ce ? q + i : ce - 1;
+          v8[i] = s_sum[qi - cb];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc += q + i < bb ? v8[i] : Acc(0);
+      }
       double tot = static_cast<double>(acc);
       if (jl <= j1) finish_row(jl, tot);
       if (cont) {  // the open row's sum so far, from the lane that holds it
@@ -367,11 +378,12 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
     int32_t m, int32_t n, double alpha, double beta, double *__restrict__ carry) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int wid = threadIdx.x / kWave;
-  const int wpb = blockDim.x / kWave;
-  const int p = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
-  if (p >= np) return;  // whole wavefront; the kernel has no block barrier
-  csr_partition<VT, K, BETA0, PF>(col, val, parts, lptr, np, p, x, y, m, n, alpha, beta, carry,
-                                  lds_raw + wid * seg_lds_per_wave<VT, K>());
+  // one partition per wavefront, or (a grid of resident size) every W-th;
+  // there is no block barrier, so wavefronts run independently
+  const PartStride ps(np);
+  for (int32_t p = ps.p; p < np; p += ps.step)
+    csr_partition<VT, K, BETA0, PF>(col, val, parts, lptr, np, p, x, y, m, n, alpha, beta, carry,
+                                    lds_raw + wid * seg_lds_per_wave<VT, K>());
 }
 
 

@@ -78,6 +78,10 @@ def test_spmv_argument_errors():
     st = L.msrep_spmv(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0,
                       ctypes.byref(t), 0x8000, 1 << 20, None)
     assert st == -1 and b"k_per_lane" in L.msrep_last_error()
+    t = _abi._Tune(4, 4, 2, 0, 0, 0)
+    st = L.msrep_spmv(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0,
+                      ctypes.byref(t), 0x8000, 1 << 20, None)
+    assert st == -1 and b"resident" in L.msrep_last_error()
     assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 8) >= 16 * 8
     dc = _desc(fmt=1, vtype=1, m=1000)
     assert L.msrep_spmv_ws_bytes(ctypes.byref(dc), 8) >= 8 * 1000

@@ -138,10 +138,10 @@ def test_spmv_tiny_set(fmt, vt):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
-@pytest.mark.parametrize("tune", [(4, 4), (8, 4), (4, 1), (8, 8)])
+@pytest.mark.parametrize("tune", [(4, 4, 0), (8, 4, 0), (4, 1, 1), (8, 8, 1)])
 def test_spmv_uniform_4096(fmt, tune):
     A, x = synth.uniform_csr(4096, 4096, 16, seed=0)
-    t = pk.Tune(k_per_lane=tune[0], waves_per_wg=tune[1])
+    t = pk.Tune(k_per_lane=tune[0], waves_per_wg=tune[1], resident=tune[2])
     for np_ in (8, 7, 3, 1024):
         y, ref, s = _run(A, x, fmt, pk.F64, np_, tune=t)
         assert_close(y, ref, s, F64_TOL, "uniform %s np%d" % (fmt, np_))
@@ -156,10 +156,10 @@ def test_spmv_rmat14(fmt, vt):
     y_in = rng.uniform(-1, 1, A.m)
     M, v64 = device_mat(A, fmt, vt)
     for np_ in (1, 37, 256, 2048):
-        for k in (4, 8):
-            y, ref, s = _run(A, x, fmt, vt, np_, 1.25, 0.5, y_in, tune=pk.Tune(k_per_lane=k),
-                             M=M, v64=v64)
-            assert_close(y, ref, s, tol, "rmat14 %s vt%d np%d k%d" % (fmt, vt, np_, k))
+        for k, res in ((4, 0), (8, 0), (4, 1)):
+            y, ref, s = _run(A, x, fmt, vt, np_, 1.25, 0.5, y_in,
+                             tune=pk.Tune(k_per_lane=k, resident=res), M=M, v64=v64)
+            assert_close(y, ref, s, tol, "rmat14 %s vt%d np%d k%d res%d" % (fmt, vt, np_, k, res))
 
 
 @pytest.mark.parametrize("fmt", FMTS)
@@ -172,8 +172,9 @@ def test_dyadic_bit_exact_any_np(fmt):
     x = synth.dyadic(rng, A.n)
     M, v64 = device_mat(A, fmt, pk.F64)
     for np_ in (1, 5, 256, 4096, A.nnz + 7):
-        y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64)
-        assert np.array_equal(y, ref), (fmt, np_)
+        for res in (0, 1):
+            y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64, tune=pk.Tune(resident=res))
+            assert np.array_equal(y, ref), (fmt, np_, res)
 
 
 def test_stencil_times_ones_exact():
@@ -230,7 +231,7 @@ def test_autotune_returns_a_valid_tune_and_correct_results():
     M, v64 = device_mat(A, "csr", pk.F64)
     xd = torch.from_numpy(x).to(_dev())
     t = pk.msrep_autotune(M, xd)
-    assert t.k_per_lane in (4, 8) and t.waves_per_wg in (2, 4, 8)
+    assert t.k_per_lane in (4, 8) and t.waves_per_wg in (2, 4, 8) and t.resident in (0, 1)
     assert t.nnz_per_wave in (256, 512, 1024, 2048, 4096)
     np_ = max(1, -(-A.nnz // t.nnz_per_wave))
     y, ref, s = _run(A, x, "csr", pk.F64, np_, tune=t, M=M, v64=v64)
