@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 
 #include "msrep.h"
 
@@ -216,6 +217,8 @@ template <int CTRL, int ROWS = 0xF, typename A>
 __device__ __forceinline__ A dpp(A v) {
   if constexpr (sizeof(A) == 8)
     return dpp_d<CTRL, ROWS>(v);
+  else if constexpr (std::is_integral_v<A>)
+    return static_cast<A>(dpp_i<CTRL, ROWS>(static_cast<int>(v)));
   else
     return dpp_f<CTRL, ROWS>(v);
 }

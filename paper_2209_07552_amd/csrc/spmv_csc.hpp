@@ -33,10 +33,10 @@ namespace msrep {
 constexpr int kCscMinShift = 12;              // 4096-row buckets
 constexpr int kCscMaxShift = 13;              // 8192 rows: 64 KB of FP64 sums
 constexpr int32_t kCscMaxBuckets = 8192;      // LDS cursors of one producer
-// One resident producer per CU: the runs being written at once (producers x
-// buckets lines) then fit the L2, which merges the scattered stores into
-// whole lines before they reach HBM.
-constexpr int32_t kCscMaxProducers = 256;
+// Two resident producers per CU: the runs being written at once (producers
+// x buckets lines) still mostly fit the L2, which merges the scattered
+// stores into whole lines before they reach HBM.
+constexpr int32_t kCscMaxProducers = 512;
 constexpr int kCscScatterWaves = 16;
 constexpr int64_t kCscMaxCounters = int64_t(1) << 22;
 constexpr int64_t kCscPiece = 32768;          // products summed by one workgroup
@@ -98,14 +98,17 @@ __device__ __forceinline__ void producer_range(int p, int32_t np, int32_t P, int
 }
 
 // cnt[t*P + p] = nonzeros of producer p whose row lies in bucket t.
-__global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(const int32_t *__restrict__ row_idx,
-                                                       int64_t nnz,
-                                                       const msrep_part *__restrict__ parts,
-                                                       int32_t np, int32_t P, int32_t m,
-                                                       int shift, int32_t nb,
-                                                       int32_t *__restrict__ cnt) {
+// Row indices are read four per lane (16-byte loads, consecutive items), so
+// a lane adds runs of equal buckets at once; the bucket of the wavefront's
+// first item, which in banded matrices most lanes share, is then summed
+// across the wavefront (DPP scan) and added by one lane.  The unaligned head
+// and tail of the range go item by item.
+__global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(
+    const int32_t *__restrict__ row_idx, int64_t nnz, const msrep_part *__restrict__ parts,
+    int32_t np, int32_t P, int32_t m, int shift, int32_t nb, int32_t *__restrict__ cnt) {
   extern __shared__ int32_t hist[];
   const int p = blockIdx.x;
+  const int lane = lane_id();
   for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   int64_t pa, pb;
@@ -114,16 +117,65 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(const int3
     int64_t k0 = parts[pa].start_idx, k1 = parts[pb - 1].end_idx + 1;
     k0 = k0 < 0 ? 0 : k0;
     k1 = k1 > nnz ? nnz : k1;
-    const int64_t bd = blockDim.x;
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += kUnroll * bd) {
-      int32_t rr[kUnroll];
+    k1 = k1 < k0 ? k0 : k1;
+    const int64_t up4 = (k0 + 3) & ~int64_t(3), dn4 = k1 & ~int64_t(3);
+    const int64_t ka = up4 < k1 ? up4 : k1;  // [k0, ka) head, [ka, kb) groups of 4
+    const int64_t kb = dn4 > ka ? dn4 : ka;  // [kb, k1) tail
+    auto one = [&](int64_t k) {
+      const int32_t r = row_idx[k];
+      if (static_cast<uint32_t>(r) < static_cast<uint32_t>(m)) atomicAdd(&hist[r >> shift], 1);
+    };
+    for (int64_t k = k0 + threadIdx.x; k < ka; k += blockDim.x) one(k);
+    for (int64_t k = kb + threadIdx.x; k < k1; k += blockDim.x) one(k);
+    const u32x4 *__restrict__ body = reinterpret_cast<const u32x4 *>(row_idx + ka);
+    const int64_t ng = (kb - ka) / 4;  // groups of four items
+    const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    constexpr int U = 4;  // groups per lane in flight
+    for (int64_t g0 = static_cast<int64_t>(wid) * kWave * U; g0 < ng;
+         g0 += static_cast<int64_t>(nw) * kWave * U) {  // uniform per wavefront
+      u32x4 rv[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        rr[u] = k + u * bd < k1 ? __builtin_nontemporal_load(row_idx + k + u * bd) : -1;
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = g0 + u * kWave + lane;
+        rv[u] = g < ng ? __builtin_nontemporal_load(body + g) : u32x4{~0u, ~0u, ~0u, ~0u};
+      }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (static_cast<uint32_t>(rr[u]) < static_cast<uint32_t>(m))
-          atomicAdd(&hist[rr[u] >> shift], 1);
+      for (int u = 0; u < U; ++u) {
+        const int32_t r4[4] = {static_cast<int32_t>(rv[u].x), static_cast<int32_t>(rv[u].y),
+                               static_cast<int32_t>(rv[u].z), static_cast<int32_t>(rv[u].w)};
+        int32_t bk[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          bk[i] = static_cast<uint32_t>(r4[i]) < static_cast<uint32_t>(m) ? (r4[i] >> shift) : -1;
+        const int32_t lead = __builtin_amdgcn_readfirstlane(bk[0]);
+        int32_t mine = 0;  // this lane's items in the lead bucket
+        int32_t run_b = bk[0], run_n = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (bk[i] != run_b) {
+            if (run_b >= 0 && run_n) {
+              if (run_b == lead)
+                mine += run_n;
+              else
+                atomicAdd(&hist[run_b], run_n);
+            }
+            run_b = bk[i];
+            run_n = 0;
+          }
+          ++run_n;
+        }
+        if (run_b >= 0) {
+          if (run_b == lead)
+            mine += run_n;
+          else
+            atomicAdd(&hist[run_b], run_n);
+        }
+        // wavefront sum of the lead bucket's items
+        int32_t tot = mine, none = 0;
+        wave_seg_scan<int32_t>(tot, none);
+        tot = __builtin_amdgcn_readlane(tot, kWave - 1);
+        if (lead >= 0 && lane == 0 && tot) atomicAdd(&hist[lead], tot);
+      }
     }
   }
   __syncthreads();
