@@ -272,3 +272,27 @@ def test_kernel_timing_records_each_launch():
         pk.msrep_timing(False)
     _run(A, x, "coo", pk.F64, 64)
     assert pk.msrep_timing_read() == {}
+
+
+@pytest.mark.parametrize("vt", [0, 1])
+def test_csc_tall_matrix_uses_wide_buckets(vt):
+    """More than 2^25 rows: CSC row buckets widen to 8192 rows.  A tall
+    sparse matrix (rows concentrated at both ends and spread in between)
+    checked against the oracle with beta != 0."""
+    rng = np.random.default_rng(13)
+    m, n, nnz = (1 << 25) + 4097, 3000, 60_000
+    rows = np.concatenate([rng.integers(0, 50_000, nnz // 3), rng.integers(m - 50_000, m, nnz // 3),
+                           rng.integers(0, m, nnz - 2 * (nnz // 3))])
+    cols = rng.integers(0, n, nnz)
+    key = np.unique(rows.astype(np.int64) * n + cols)
+    rows, cols = (key // n).astype(np.int64), (key % n).astype(np.int32)
+    counts = np.bincount(rows, minlength=m)
+    ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    A = synth.Csr(m, n, ptr, cols, rng.uniform(-1, 1, len(cols)), name="tall")
+    x = rng.uniform(-1, 1, n)
+    y_in = rng.uniform(-1, 1, m)
+    tol = F64_TOL if vt == 0 else F32_TOL
+    M, v64 = device_mat(A, "csc", vt)
+    for np_ in (3, 1000):
+        y, ref, s = _run(A, x, "csc", vt, np_, 0.5, 2.0, y_in, M=M, v64=v64)
+        assert_close(y, ref, s, tol, "tall csc vt%d np%d" % (vt, np_))
