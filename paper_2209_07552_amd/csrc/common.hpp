@@ -247,6 +247,19 @@ __device__ __forceinline__ void wave_seg_scan(A &v, int &f) {
   seg_step<kDppRowBcast31, 0xC>(v, f);
 }
 
+// Inclusive max-scan across the 64 lanes of non-negative values (lanes with
+// no source contribute 0, which never wins).
+__device__ __forceinline__ int wave_max_scan_nonneg(int v) {
+  int o;
+  o = dpp_i<kDppRowShr1, 0xF>(v); v = v > o ? v : o;
+  o = dpp_i<kDppRowShr2, 0xF>(v); v = v > o ? v : o;
+  o = dpp_i<kDppRowShr4, 0xF>(v); v = v > o ? v : o;
+  o = dpp_i<kDppRowShr8, 0xF>(v); v = v > o ? v : o;
+  o = dpp_i<kDppRowBcast15, 0xA>(v); v = v > o ? v : o;
+  o = dpp_i<kDppRowBcast31, 0xC>(v); v = v > o ? v : o;
+  return v;
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(b) << 16);
 }

@@ -183,31 +183,17 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(
   if (p == 0 && threadIdx.x == 0) cnt[static_cast<int64_t>(nb) * P] = 0;
 }
 
-// One chunk of CH = 64*K positions [cb, cb+CH) of a pCSC partition (local
-// positions; the partition holds nloc nonzeros from global position s0, its
-// columns c0 .. c0+R-1 with local pointer lp).  The column of every position
-// comes from the local column pointer: columns that start inside the chunk
-// mark their first position in the wave's LDS array and a max-scan carries
-// the index forward.  Outputs, per item of this lane: ok (a position of the
-// partition whose row lies in [0, m)), its row and the product val*x[col]
-// (0 for a column outside [0, n)).  j0, the local column holding the chunk's
-// first position, advances to the next chunk's.
+// Rows and values of the chunk of CH = 64*K local positions [cb, cb+CH) of a
+// pCSC partition (nloc nonzeros from global position s0); positions outside
+// the partition read as row -1, value 0.
 template <int VT, int K>
-__device__ __forceinline__ void csc_chunk(
-    const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
-    int64_t s0, int32_t nloc, int32_t cb, int32_t c0, int32_t R, const int32_t *__restrict__ lp,
-    const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n, int32_t *s_col,
-    int lane, int32_t &j0, bool (&ok)[K], int32_t (&rows)[K],
-    typename vt_traits<VT>::A (&pr)[K]) {
-  using Tr = vt_traits<VT>;
-  using V = typename Tr::V;
-  using Acc = typename Tr::A;
-  constexpr int CH = kWave * K;
-  const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
-  const int32_t q0 = cb + lane * K;
-  V v[K];
-  const bool full = q0 >= 0 && q0 + K <= nloc;
-  if (full) {
+__device__ __forceinline__ void csc_load(const int32_t *__restrict__ row_idx,
+                                         const typename vt_traits<VT>::V *__restrict__ val,
+                                         int64_t s0, int32_t nloc, int32_t cb,
+                                         int32_t (&rows)[K], typename vt_traits<VT>::V (&v)[K]) {
+  using V = typename vt_traits<VT>::V;
+  const int32_t q0 = cb + lane_id() * K;
+  if (q0 >= 0 && q0 + K <= nloc) {
     load_vec<int32_t, K>(row_idx + s0 + q0, rows);
     load_vec<V, K>(val + s0 + q0, v);
   } else {
@@ -222,14 +208,35 @@ __device__ __forceinline__ void csc_chunk(
       }
     }
   }
-  // columns starting inside the chunk mark their first position
+}
+
+// The column of every position of a loaded chunk and its product val*x[col].
+// Columns that start inside the chunk mark their first position in the
+// wave's LDS array (the local column pointer lp, read 64 columns at a time
+// from j0, the column holding the chunk's first position); a max-scan (DPP)
+// carries the index forward.  ok: a position of the partition whose row lies
+// in [0, m); a column outside [0, n) gives product 0.  j0 advances to the
+// column holding the next chunk's first position, taken from the lane that
+// read the first column starting past the chunk (no extra load).
+template <int VT, int K>
+__device__ __forceinline__ void csc_columns(
+    int32_t nloc, int32_t cb, int32_t c0, int32_t R, const int32_t *__restrict__ lp,
+    const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n, int32_t *s_col,
+    int32_t &j0, const int32_t (&rows)[K], const typename vt_traits<VT>::V (&v)[K],
+    bool (&ok)[K], typename vt_traits<VT>::A (&pr)[K]) {
+  using Tr = vt_traits<VT>;
+  using Acc = typename Tr::A;
+  constexpr int CH = kWave * K;
+  const int lane = lane_id();
+  const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
+  const int32_t q0 = cb + lane * K;
 #pragma unroll
   for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
   wave_lds_sync();
-  int32_t jb = j0, cnt;
+  int32_t jb = j0, cnt, a;
   for (;;) {
     const int32_t j = jb + lane;
-    const int32_t a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
+    a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
     const bool in = j <= R - 1 && a < ce;
     if (in && j > j0) {
       const int32_t pos = a - cb;
@@ -240,6 +247,9 @@ __device__ __forceinline__ void csc_chunk(
     jb += kWave;
   }
   const int32_t j1 = jb + cnt - 1;
+  // lp[j1 + 1]: where the first column starting past the chunk starts (or
+  // past-the-end), from the lane that loaded it
+  const int32_t nxt = __builtin_amdgcn_readlane(a, cnt);
   wave_lds_sync();
   int32_t cj[K];
   int32_t mx = j0;
@@ -249,32 +259,48 @@ __device__ __forceinline__ void csc_chunk(
     mx = h > mx ? h : mx;
     cj[t] = mx;
   }
-  int32_t agg = mx;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t o = shfl_up_i(agg, d);
-    if (lane >= d) agg = o > agg ? o : agg;
-  }
-  int32_t cin = shfl_up_i(agg, 1);
+  const int32_t agg = wave_max_scan_nonneg(mx);  // values >= j0 >= 0
+  int32_t cin = dpp_i<kDppWaveShr1>(agg);
   if (lane == 0) cin = j0;
+  typename Tr::T xv[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) {
     const int32_t q = q0 + t;
-    const int32_t j = cj[t] > cin ? cj[t] : cin;
-    const int32_t c = c0 + j;
+    const int32_t c = c0 + (cj[t] > cin ? cj[t] : cin);
     ok[t] = q >= 0 && q < nloc && static_cast<uint32_t>(rows[t]) < static_cast<uint32_t>(m);
-    pr[t] = ok[t] && static_cast<uint32_t>(c) < static_cast<uint32_t>(n)
-                ? Tr::val(v[t]) * static_cast<Acc>(x[c])
-                : Acc(0);
+    xv[t] = ok[t] && static_cast<uint32_t>(c) < static_cast<uint32_t>(n) ? x[c] : typename Tr::T(0);
   }
+#pragma unroll
+  for (int t = 0; t < K; ++t) pr[t] = Tr::val(v[t]) * static_cast<Acc>(xv[t]);
   // the column holding the chunk's last position continues, unless it ends
-  const int32_t nxt = (j1 + 1 >= 0 && j1 + 1 <= R) ? lp[j1 + 1] : nloc;
   j0 = nxt > ce ? j1 : j1 + 1;
   wave_lds_sync();
 }
 
+// Partition record fields a wavefront needs (wave-uniform).
+struct CscPart {
+  int64_t s0;
+  int32_t nloc, c0, R;
+  const int32_t *lp;
+};
+
+__device__ __forceinline__ CscPart csc_part(const msrep_part *__restrict__ parts,
+                                            const int32_t *__restrict__ lptr, int64_t pi) {
+  const msrep_part *pp = parts + pi;
+  CscPart c;
+  c.s0 = uniform(pp->start_idx);
+  c.nloc = static_cast<int32_t>(uniform(pp->end_idx) - c.s0 + 1);
+  c.c0 = uniform(pp->start_row);
+  c.R = uniform(pp->end_row) - c.c0 + 1;
+  c.lp = lptr + uniform(pp->lptr_off);
+  return c;
+}
+
 // Products of producer p go straight to their positions in its run of each
-// bucket (an LDS cursor per bucket hands out positions).
+// bucket (an LDS cursor per bucket hands out positions).  Each wavefront
+// walks its partitions (pa+wid, pa+wid+W, ...) as one stream of chunks and
+// loads the next chunk's rows and values, and the next partition's record,
+// before working on the current chunk.
 template <int VT, int K>
 __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
@@ -282,12 +308,12 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     int32_t np, int32_t P, const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n,
     int shift, int32_t nb, const int32_t *__restrict__ off,
     typename vt_traits<VT>::A *__restrict__ prod, uint16_t *__restrict__ rlo) {
+  using V = typename vt_traits<VT>::V;
   using Acc = typename vt_traits<VT>::A;
   constexpr int CH = kWave * K;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int32_t *cur = reinterpret_cast<int32_t *>(lds_raw);
 
-  const int lane = lane_id();
   const int wid = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
   const int p = xcd_block(blockIdx.x, gridDim.x);
@@ -298,29 +324,58 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   const uint32_t mask = (1u << shift) - 1u;
   int64_t pa, pb;
   producer_range(p, np, P, pa, pb);
-  for (int64_t pi = pa + wid; pi < pb; pi += wpb) {
-    const msrep_part *pp = parts + pi;
-    const int64_t s0 = uniform(pp->start_idx);
-    const int32_t nloc = static_cast<int32_t>(uniform(pp->end_idx) - s0 + 1);
-    const int32_t c0 = uniform(pp->start_row);  // first column
-    const int32_t R = uniform(pp->end_row) - c0 + 1;
-    const int32_t *__restrict__ lp = lptr + uniform(pp->lptr_off);
-    int32_t j0 = 0;
-    for (int32_t cb = -static_cast<int32_t>(s0 % K); cb < nloc; cb += CH) {
-      bool okk[K];
-      int32_t rows[K];
-      Acc pr[K];
-      csc_chunk<VT, K>(row_idx, val, s0, nloc, cb, c0, R, lp, x, m, n, s_col, lane, j0, okk, rows,
-                       pr);
+
+  // skip empty partitions: the first non-empty one at or after pi (stride wpb)
+  auto first_nonempty = [&](int64_t pi, CscPart &c) {
+    for (; pi < pb; pi += wpb) {
+      c = csc_part(parts, lptr, pi);
+      if (c.nloc > 0) break;
+    }
+    return pi;
+  };
+  CscPart cp{}, np_meta{};
+  int64_t pi = first_nonempty(pa + wid, cp);
+  int64_t pn = pi < pb ? first_nonempty(pi + wpb, np_meta) : pb;  // the next partition
+  int32_t cb = pi < pb ? -static_cast<int32_t>(cp.s0 % K) : 0, j0 = 0;
+  int32_t rows[K];
+  V v[K];
+  if (pi < pb) csc_load<VT, K>(row_idx, val, cp.s0, cp.nloc, cb, rows, v);
+  while (pi < pb) {
+    // ---- the next chunk: the same partition, or the first of the next one
+    const bool same = cb + CH < cp.nloc;
+    const CscPart &cq = same ? cp : np_meta;
+    const int32_t cb_n = same ? cb + CH : -static_cast<int32_t>(np_meta.s0 % K);
+    const bool more = same || pn < pb;
+    int32_t rows_n[K];
+    V v_n[K];
+    if (more) csc_load<VT, K>(row_idx, val, cq.s0, cq.nloc, cb_n, rows_n, v_n);
+    // ---- this chunk
+    bool okk[K];
+    Acc pr[K];
+    csc_columns<VT, K>(cp.nloc, cb, cp.c0, cp.R, cp.lp, x, m, n, s_col, j0, rows, v, okk, pr);
 #pragma unroll
-      for (int t = 0; t < K; ++t) {
-        if (!okk[t]) continue;
-        const int32_t at = atomicAdd(&cur[static_cast<uint32_t>(rows[t]) >> shift], 1);
-        if (static_cast<uint64_t>(at) < static_cast<uint64_t>(nnz)) {
-          prod[at] = pr[t];
-          rlo[at] = static_cast<uint16_t>(static_cast<uint32_t>(rows[t]) & mask);
-        }
+    for (int t = 0; t < K; ++t) {
+      if (!okk[t]) continue;
+      const int32_t at = atomicAdd(&cur[static_cast<uint32_t>(rows[t]) >> shift], 1);
+      if (static_cast<uint64_t>(at) < static_cast<uint64_t>(nnz)) {
+        prod[at] = pr[t];
+        rlo[at] = static_cast<uint16_t>(static_cast<uint32_t>(rows[t]) & mask);
       }
+    }
+    // ---- advance
+    if (same) {
+      cb = cb_n;
+    } else {
+      pi = pn;
+      cp = np_meta;
+      cb = cb_n;
+      j0 = 0;
+      if (pi < pb) pn = first_nonempty(pi + wpb, np_meta);
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      rows[t] = rows_n[t];
+      v[t] = v_n[t];
     }
   }
 }
