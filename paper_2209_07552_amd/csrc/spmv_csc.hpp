@@ -233,18 +233,31 @@ __device__ __forceinline__ void csc_columns(
 #pragma unroll
   for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
   wave_lds_sync();
-  int32_t jb = j0, cnt, a;
-  for (;;) {
-    const int32_t j = jb + lane;
-    a = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
-    const bool in = j <= R - 1 && a < ce;
-    if (in && j > j0) {
-      const int32_t pos = a - cb;
-      if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
+  // the local column pointer from j0 on, kLpBatches batches of 64 columns
+  // loaded together (sparse regions put hundreds of columns in one chunk)
+  constexpr int kLpBatches = 4;
+  int32_t jb = j0, cnt = kWave, a = 0;
+  while (cnt == kWave) {
+    int32_t av[kLpBatches];
+#pragma unroll
+    for (int u = 0; u < kLpBatches; ++u) {
+      const int32_t j = jb + u * kWave + lane;
+      av[u] = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
     }
-    cnt = __popcll(__ballot(in));
-    if (cnt < kWave) break;
-    jb += kWave;
+#pragma unroll
+    for (int u = 0; u < kLpBatches; ++u) {
+      if (cnt < kWave) break;
+      if (u > 0) jb += kWave;
+      const int32_t j = jb + lane;
+      a = av[u];
+      const bool in = j <= R - 1 && a < ce;
+      if (in && j > j0) {
+        const int32_t pos = a - cb;
+        if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
+      }
+      cnt = __popcll(__ballot(in));
+    }
+    if (cnt == kWave) jb += kWave;
   }
   const int32_t j1 = jb + cnt - 1;
   // lp[j1 + 1]: where the first column starting past the chunk starts (or

@@ -222,15 +222,27 @@ __device__ __forceinline__ void csr_partition(
       lp_next = read_lane(lpv0, cnt & (kWave - 1));
     }
     if (cnt == kWave) {
-      for (;;) {
-        jb += kWave;
-        const int32_t j = jb + lane;
-        const int32_t v = buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u);
-        const bool in = j <= R - 1 && v < ce;
-        cnt = __popcll(__ballot(in));
-        if (cnt < kWave) {
-          lp_next = read_lane(v, cnt);
-          break;
+      // more than 64 rows start in the chunk (short or empty rows): read the
+      // following batches three at a time
+      constexpr int kMore = 3;
+      bool found = false;
+      while (!found) {
+        int32_t vv[kMore];
+#pragma unroll
+        for (int u = 0; u < kMore; ++u)
+          vv[u] = buf_load<int32_t>(
+              rl, static_cast<uint32_t>(jb + (u + 1) * kWave + lane) * 4u);
+#pragma unroll
+        for (int u = 0; u < kMore; ++u) {
+          if (found) break;
+          jb += kWave;
+          const int32_t j = jb + lane;
+          const bool in = j <= R - 1 && vv[u] < ce;
+          cnt = __popcll(__ballot(in));
+          if (cnt < kWave) {
+            lp_next = read_lane(vv[u], cnt);
+            found = true;
+          }
         }
       }
     }
