@@ -151,6 +151,7 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   int32_t *agg = reinterpret_cast<int32_t *>(b + L.agg);
   int32_t *pbase = reinterpret_cast<int32_t *>(b + L.pbase);
   int32_t *mbase = reinterpret_cast<int32_t *>(b + L.mbase);
+  int32_t *mlist = reinterpret_cast<int32_t *>(b + L.mlist);
   Acc *prod = reinterpret_cast<Acc *>(b + L.prod);
   uint16_t *rlo = reinterpret_cast<uint16_t *>(b + L.rlo);
   double *part = reinterpret_cast<double *>(b + L.part);
@@ -174,7 +175,8 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   MSREP_LAUNCHED("csc_scatter");
   timing_end("csc_scatter", s);
   timing_begin(s);
-  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kCscBlock), 0, s, cnt, L.nb, L.P, pbase, mbase);
+  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kPlanBlock), 0, s, cnt, L.nb, L.P, pbase, mbase,
+                     mlist);
   MSREP_LAUNCHED("csc_plan");
   timing_end("csc_plan", s);
   timing_begin(s);
@@ -185,9 +187,14 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   MSREP_LAUNCHED("csc_reduce");
   timing_end("csc_reduce", s);
   timing_begin(s);
-  hipLaunchKernelGGL((csc_merge<T>), dim3(L.nb, (1 << L.shift) / kCscBlock), dim3(kCscBlock), 0, s,
-                     pbase, mbase, L.shift, A->m, L.max_slots, part, static_cast<T *>(y), alpha,
-                     beta);
+  {
+    // buckets of several pieces hold more than kCscPiece products each
+    const int64_t most = std::min<int64_t>(L.nb, A->nnz / kCscPiece + 1);
+    const int64_t blocks = std::min<int64_t>(most * ((1 << L.shift) / kCscBlock), 2048);
+    hipLaunchKernelGGL((csc_merge<T>), dim3(static_cast<uint32_t>(blocks > 0 ? blocks : 1)),
+                       dim3(kCscBlock), 0, s, pbase, mbase, mlist, L.nb, L.shift, A->m,
+                       L.max_slots, part, static_cast<T *>(y), alpha, beta);
+  }
   MSREP_LAUNCHED("csc_merge");
   timing_end("csc_merge", s);
   return MSREP_OK;

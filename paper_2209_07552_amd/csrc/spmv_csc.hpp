@@ -19,8 +19,8 @@
 //   csc_reduce   one workgroup per piece adds its products into an LDS row
 //                array; a bucket of one piece writes y = alpha*sum + beta*y
 //                directly, a bucket of several stores the arrays;
-//   csc_merge    one thread per row of those buckets adds the pieces' arrays
-//                in piece order.
+//   csc_merge    one thread per row of those buckets (listed by csc_plan)
+//                adds the pieces' arrays in piece order.
 // Streaming traffic: about (s_v + 4) + 2*(s_p + 2) + 4 bytes per nonzero
 // (s_p the product size), no global atomics on y.
 #pragma once
@@ -48,7 +48,7 @@ struct CscLayout {
   int shift = 0;
   int32_t nb = 0, P = 0;
   int64_t max_pieces = 0, max_slots = 0;
-  size_t cnt = 0, agg = 0, pbase = 0, mbase = 0, prod = 0, rlo = 0, part = 0, total = 0;
+  size_t cnt = 0, agg = 0, pbase = 0, mbase = 0, mlist = 0, prod = 0, rlo = 0, part = 0, total = 0;
 };
 
 // false when m needs more buckets than one producer's LDS holds
@@ -78,6 +78,7 @@ inline bool csc_layout(int32_t m, int64_t nnz, int32_t np, int prod_bytes, CscLa
   L.agg = take(4 * static_cast<size_t>(scan::tiles(ncnt)));
   L.pbase = take(4 * static_cast<size_t>(nb + 1));
   L.mbase = take(4 * static_cast<size_t>(nb + 1));
+  L.mlist = take(4 * static_cast<size_t>(nb + 1));
   L.prod = take(static_cast<size_t>(prod_bytes) * static_cast<size_t>(nnz));
   L.rlo = take(2 * static_cast<size_t>(nnz));
   L.part = take(8 * static_cast<size_t>(L.max_slots) << shift);
@@ -393,36 +394,69 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   }
 }
 
+// Exclusive scan of one int per thread over a block of kPlanBlock threads
+// (DPP within wavefronts, wavefront totals through LDS); returns the total.
+constexpr int kPlanBlock = 1024;
+
+__device__ __forceinline__ int32_t plan_exscan(int32_t v, int32_t &excl, int32_t *sh) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  int32_t inc = v, none = 0;
+  wave_seg_scan<int32_t>(inc, none);
+  if (lane == kWave - 1) sh[w] = inc;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+  for (int i = 0; i < kPlanBlock / kWave; ++i) {
+    before += i < w ? sh[i] : 0;
+    total += sh[i];
+  }
+  excl = before + inc - v;
+  __syncthreads();
+  return total;
+}
+
 // Pieces of every bucket: pbase = exclusive scan of max(1, ceil(c_t/S)),
 // mbase = exclusive scan of the piece counts of buckets with more than one
-// piece (their partial-array slots).  One block of kCscBlock threads.
-__global__ __launch_bounds__(kCscBlock) void csc_plan(const int32_t *__restrict__ off, int32_t nb,
-                                                      int32_t P, int32_t *__restrict__ pbase,
-                                                      int32_t *__restrict__ mbase) {
-  __shared__ int32_t sh[scan::kBlock / 64];
-  int32_t carry_p = 0, carry_m = 0;
-  for (int32_t t0 = 0; t0 < nb; t0 += kCscBlock) {
-    const int32_t t = t0 + threadIdx.x;
-    int32_t np_t = 0, ms_t = 0;
-    if (t < nb) {
-      const int64_t c = static_cast<int64_t>(off[static_cast<int64_t>(t + 1) * P]) -
-                        off[static_cast<int64_t>(t) * P];
-      np_t = c > 0 ? static_cast<int32_t>((c + kCscPiece - 1) / kCscPiece) : 1;
-      ms_t = np_t > 1 ? np_t : 0;
+// piece (their partial-array slots); mlist = those buckets in order, their
+// number in mlist[nb].  One block of kPlanBlock threads, each taking a run
+// of consecutive buckets.
+__global__ __launch_bounds__(kPlanBlock) void csc_plan(const int32_t *__restrict__ off, int32_t nb,
+                                                       int32_t P, int32_t *__restrict__ pbase,
+                                                       int32_t *__restrict__ mbase,
+                                                       int32_t *__restrict__ mlist) {
+  __shared__ int32_t sh[kPlanBlock / kWave];
+  const int32_t per = (nb + kPlanBlock - 1) / kPlanBlock;
+  const int32_t t0 = threadIdx.x * per;
+  const int32_t t1 = t0 + per < nb ? t0 + per : nb;
+  auto pieces = [&](int32_t t) {
+    const int64_t c = static_cast<int64_t>(off[static_cast<int64_t>(t + 1) * P]) -
+                      off[static_cast<int64_t>(t) * P];
+    return c > 0 ? static_cast<int32_t>((c + kCscPiece - 1) / kCscPiece) : 1;
+  };
+  int32_t sp = 0, sm = 0, sn = 0;
+  for (int32_t t = t0; t < t1; ++t) {
+    const int32_t k = pieces(t);
+    sp += k;
+    sm += k > 1 ? k : 0;
+    sn += k > 1 ? 1 : 0;
+  }
+  int32_t ep, em, en;
+  const int32_t tp = plan_exscan(sp, ep, sh);
+  const int32_t tm = plan_exscan(sm, em, sh);
+  const int32_t tn = plan_exscan(sn, en, sh);
+  for (int32_t t = t0; t < t1; ++t) {
+    const int32_t k = pieces(t);
+    pbase[t] = ep;
+    mbase[t] = em;
+    ep += k;
+    if (k > 1) {
+      em += k;
+      mlist[en++] = t;
     }
-    int32_t ex_p, ex_m;
-    const int32_t tot_p = scan::block_exscan<int32_t, scan::SumOp>(np_t, ex_p, sh);
-    const int32_t tot_m = scan::block_exscan<int32_t, scan::SumOp>(ms_t, ex_m, sh);
-    if (t < nb) {
-      pbase[t] = carry_p + ex_p;
-      mbase[t] = carry_m + ex_m;
-    }
-    carry_p += tot_p;
-    carry_m += tot_m;
   }
   if (threadIdx.x == 0) {
-    pbase[nb] = carry_p;
-    mbase[nb] = carry_m;
+    pbase[nb] = tp;
+    mbase[nb] = tm;
+    mlist[nb] = tn;
   }
 }
 
@@ -489,35 +523,40 @@ __global__ __launch_bounds__(kCscBlock) void csc_reduce(
 }
 
 // Rows of buckets cut into several pieces: the pieces' arrays added in piece
-// order.  Grid (nb, 2^shift / kCscBlock): one thread per row of every bucket;
-// buckets of one piece were finished by csc_reduce.
+// order, one thread per row.  Only the mlist[nb] buckets listed by csc_plan
+// have rows here; the blocks stride over (listed bucket, 256-row block).
 template <typename T>
 __global__ __launch_bounds__(kCscBlock) void csc_merge(const int32_t *__restrict__ pbase,
                                                       const int32_t *__restrict__ mbase,
-                                                      int shift, int32_t m, int64_t max_slots,
+                                                      const int32_t *__restrict__ mlist,
+                                                      int32_t nb, int shift, int32_t m,
+                                                      int64_t max_slots,
                                                       const double *__restrict__ part,
                                                       T *__restrict__ y, double alpha,
                                                       double beta) {
-  const int32_t t = blockIdx.x;
-  const int32_t npc = pbase[t + 1] - pbase[t];
-  if (npc <= 1) return;
-  if (mbase[t] < 0 || static_cast<int64_t>(mbase[t]) + npc > max_slots) return;
-  const int32_t r = blockIdx.y * blockDim.x + threadIdx.x;
-  const int32_t r0 = t << shift;
-  if (r >= (1 << shift) || r0 + r >= m) return;
-  const double *base = part + (static_cast<int64_t>(mbase[t]) << shift) + r;
-  double s = 0.0;
-  int32_t q = 0;
-  for (; q + kUnroll <= npc; q += kUnroll) {
-    double v[kUnroll];
+  const int32_t nlist = mlist[nb];
+  const int32_t rb = (1 << shift) / kCscBlock;  // row blocks per bucket
+  for (int64_t w = blockIdx.x; w < static_cast<int64_t>(nlist) * rb; w += gridDim.x) {
+    const int32_t t = mlist[w / rb];
+    const int32_t npc = pbase[t + 1] - pbase[t];
+    if (npc <= 1 || mbase[t] < 0 || static_cast<int64_t>(mbase[t]) + npc > max_slots) continue;
+    const int32_t r = static_cast<int32_t>(w % rb) * kCscBlock + threadIdx.x;
+    const int32_t r0 = t << shift;
+    if (r0 + r >= m) continue;
+    const double *base = part + (static_cast<int64_t>(mbase[t]) << shift) + r;
+    double s = 0.0;
+    int32_t q = 0;
+    for (; q + kUnroll <= npc; q += kUnroll) {
+      double v[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = base[static_cast<int64_t>(q + u) << shift];
+      for (int u = 0; u < kUnroll; ++u) v[u] = base[static_cast<int64_t>(q + u) << shift];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) s += v[u];
+      for (int u = 0; u < kUnroll; ++u) s += v[u];
+    }
+    for (; q < npc; ++q) s += base[static_cast<int64_t>(q) << shift];
+    const double b = beta == 0.0 ? 0.0 : beta * static_cast<double>(y[r0 + r]);
+    y[r0 + r] = static_cast<T>(alpha * s + b);
   }
-  for (; q < npc; ++q) s += base[static_cast<int64_t>(q) << shift];
-  const double b = beta == 0.0 ? 0.0 : beta * static_cast<double>(y[r0 + r]);
-  y[r0 + r] = static_cast<T>(alpha * s + b);
 }
 
 }  // namespace msrep
