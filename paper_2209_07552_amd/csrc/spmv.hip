@@ -181,7 +181,7 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   timing_end("csc_plan", s);
   timing_begin(s);
   hipLaunchKernelGGL((csc_reduce<T, Acc>), dim3(static_cast<uint32_t>(L.max_pieces)),
-                     dim3(kCscBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
+                     dim3(kReduceBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
                      L.nb, L.P, L.shift, A->m, A->nnz, L.max_slots, part, static_cast<T *>(y),
                      alpha, beta);
   MSREP_LAUNCHED("csc_reduce");

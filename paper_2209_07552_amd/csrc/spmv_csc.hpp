@@ -30,7 +30,7 @@
 
 namespace msrep {
 
-constexpr int kCscMinShift = 12;              // 4096-row buckets
+constexpr int kCscMinShift = 13;              // 8192-row buckets
 constexpr int kCscMaxShift = 13;              // 8192 rows: 64 KB of FP64 sums
 constexpr int32_t kCscMaxBuckets = 8192;      // LDS cursors of one producer
 // Two resident producers per CU: the runs being written at once (producers
@@ -39,8 +39,9 @@ constexpr int32_t kCscMaxBuckets = 8192;      // LDS cursors of one producer
 constexpr int32_t kCscMaxProducers = 512;
 constexpr int kCscScatterWaves = 16;
 constexpr int64_t kCscMaxCounters = int64_t(1) << 22;
-constexpr int64_t kCscPiece = 32768;          // products summed by one workgroup
-constexpr int kCscBlock = 256;                // count / plan / reduce blocks
+constexpr int64_t kCscPiece = 65536;          // products summed by one workgroup (8 per row)
+constexpr int kCscBlock = 256;                // merge blocks
+constexpr int kReduceBlock = 1024;            // reduce: 64 KB of LDS rows per block
 constexpr int kUnroll = 8;                    // loads in flight per thread
 
 // Workspace carve-up of the bucketed CSC path (byte offsets).
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(kPlanBlock) void csc_plan(const int32_t *__restrict
 // metadata that does not match the matrix cannot move an access outside the
 // workspace.
 template <typename T, typename PT>
-__global__ __launch_bounds__(kCscBlock) void csc_reduce(
+__global__ __launch_bounds__(kReduceBlock) void csc_reduce(
     const PT *__restrict__ prod, const uint16_t *__restrict__ rlo, const int32_t *__restrict__ off,
     const int32_t *__restrict__ pbase, const int32_t *__restrict__ mbase, int32_t nb, int32_t P,
     int shift, int32_t m, int64_t nnz, int64_t max_slots, double *__restrict__ part,
