@@ -183,8 +183,14 @@ typedef struct msrep_tune {
   int32_t _pad;
 } msrep_tune;
 
-/* Workspace bytes msrep_spmv needs for np partitions (16*np: two FP64 partial
- * sums per partition for the boundary merge). */
+/* Workspace bytes msrep_spmv needs for A split into np partitions.
+ *   CSR, COO: two FP64 partial sums per partition for the boundary merge
+ *     (16*np, rounded up to 256).
+ *   CSC: bucket counters (buckets x producers int32), per-bucket piece
+ *     tables, one product per nonzero (8 bytes for F64 values, 4 otherwise)
+ *     with its 16-bit row offset, and the partial row arrays of buckets cut
+ *     into several pieces: about (s_p + 2)*nnz bytes.
+ * Returns 0 when A is not supported (CSC with more than 2^26 rows). */
 size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
 
 /*
