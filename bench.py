@@ -334,6 +334,7 @@ def main():
             tunes[f] = pk.msrep_autotune(mats[f], x)
             log("tuned %s: %s" % (f, tunes[f]))
         np_f = max(1, -(-A.nnz // tunes[f].nnz_per_wave))
+        pk.msrep_build_partition(mats[f], np_f)  # first launches load the code
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -414,8 +415,11 @@ def main():
             per_fmt[f]["gbs_warm"] = round(b / warm_ms[f] / 1e6, 1)
         per_fmt[f]["kernels_us"] = {k: round(t / c * 1e3, 2) for (g, k), (c, t) in ktime.items()
                                     if g == f}
-    # the dominant kernel: the largest share of the step's time
-    (dom_f, kname), (kc, kt) = max(ktime.items(), key=lambda kv: kv[1][1])
+    # the dominant kernel: the largest share of the step's time among the
+    # kernels whose algorithmic bytes are defined (the SpMV kernels proper)
+    priced = {fk: v for fk, v in ktime.items()
+              if kernel_alg_bytes(fk[1], A.m, A.n, A.nnz, 1, vbytes, xbytes) is not None}
+    (dom_f, kname), (kc, kt) = max(priced.items(), key=lambda kv: kv[1][1])
     k_ms = kt / kc
     k_bytes = kernel_alg_bytes(kname, A.m, A.n, A.nnz, parts[dom_f].np, vbytes, xbytes)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
