@@ -65,32 +65,42 @@ __device__ __forceinline__ void coo_partition(
   bool carry_on = false;
   const int32_t lead = static_cast<int32_t>(s0 % K);
   const rsrc_t rx = make_rsrc(x, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(T)));
-  // rows, columns and values of a chunk are loaded one chunk ahead
-  int32_t row_cur[K], c_cur[K];
-  V v_cur[K];
+  auto gather = [&](const int32_t(&c)[K], T(&xv)[K]) {
+    // (index -1 and columns >= n read as 0 through the x resource)
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      xv[t] = buf_load<T>(rx, static_cast<uint32_t>(c[t]) * static_cast<uint32_t>(sizeof(T)));
+  };
+  // software pipeline: rows, columns and values two chunks ahead, the x
+  // gather one chunk ahead.  The rows next to a chunk (the last one before
+  // it, the first one after it) come from the neighbouring chunks' registers.
+  int32_t row_cur[K], c_cur[K], row_nxt[K], c_nxt[K];
+  V v_cur[K], v_nxt[K];
+  T xv_cur[K];
   load_items<V, K>(col, val, s0, -lead, nloc, c_cur, v_cur);
   load_rows<K>(row_idx, s0, -lead, nloc, r0, rE, row_cur);
+  gather(c_cur, xv_cur);
+  load_items<V, K>(col, val, s0, -lead + CH, nloc, c_nxt, v_nxt);
+  load_rows<K>(row_idx, s0, -lead + CH, nloc, r0, rE, row_nxt);
+  int32_t before = -1;  // row of the position just before the chunk (none for the first)
   for (int32_t cb = -lead; cb < nloc; cb += CH) {
     const int32_t cs = cb > 0 ? cb : 0;
     const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
     const int32_t q0 = cb + lane * K;
-    T xv[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t)
-      xv[t] = buf_load<T>(rx, static_cast<uint32_t>(c_cur[t]) * static_cast<uint32_t>(sizeof(T)));
-    // rows of the nonzeros just before and just after the chunk
-    const int32_t before = cs > 0 ? row_idx[s0 + cs - 1] : -1;
-    const int32_t after = ce < nloc ? row_idx[s0 + ce] : -1;
-    int32_t row_nxt[K], c_nxt[K];
-    V v_nxt[K];
-    load_items<V, K>(col, val, s0, cb + CH, nloc, c_nxt, v_nxt);
-    load_rows<K>(row_idx, s0, cb + CH, nloc, r0, rE, row_nxt);
+    T xv_nxt[K];
+    gather(c_nxt, xv_nxt);
+    int32_t row_nn[K], c_nn[K];
+    V v_nn[K];
+    load_items<V, K>(col, val, s0, cb + 2 * CH, nloc, c_nn, v_nn);
+    load_rows<K>(row_idx, s0, cb + 2 * CH, nloc, r0, rE, row_nn);
+    // row of the position just after the chunk: the next chunk's first item
+    const int32_t after = ce < nloc ? __builtin_amdgcn_readlane(row_nxt[0], 0) : -1;
     int32_t row[K];
     Acc prod[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       row[t] = row_cur[t];
-      prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv[t]);
+      prod[t] = Tr::val(v_cur[t]) * static_cast<Acc>(xv_cur[t]);
     }
     // previous / next row of every item
     const int32_t up = shfl_up_i(row[K - 1], 1);
@@ -151,14 +161,20 @@ __device__ __forceinline__ void coo_partition(
       }
     }
     wave_lds_sync();
-    const int32_t last_row = row_idx[s0 + ce - 1];
-    carry_on = after == last_row && ce < nloc;
+    // the chunk's last position is lane 63's last item when the chunk is full
+    const int32_t last_row = __builtin_amdgcn_readlane(row[K - 1], kWave - 1);
+    carry_on = ce < nloc && after == last_row;
     carry_v = carry_on ? *s_carry : 0.0;
+    before = last_row;
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       row_cur[t] = row_nxt[t];
       c_cur[t] = c_nxt[t];
       v_cur[t] = v_nxt[t];
+      xv_cur[t] = xv_nxt[t];
+      row_nxt[t] = row_nn[t];
+      c_nxt[t] = c_nn[t];
+      v_nxt[t] = v_nn[t];
     }
     wave_lds_sync();
   }
