@@ -195,17 +195,26 @@ size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
 
 /*
  * y = alpha*A*x + beta*y over the np partitions built by msrep_build_partition
- * (Algorithms 3, 5, 7).  One wavefront streams each partition's nonzeros;
- * rows inside a partition are written directly; a row split between
- * partitions is merged by summing its partial sums in partition order with a
- * compensated FP64 sum and applying beta once; rows covered by no partition
- * get beta*y.  CSC scatters into y with atomics (after y <- beta*y), as the
- * paper's column-based merge sums partial vectors; its summation order is
- * not deterministic.  CSR and COO results are deterministic for a given np
- * and tune.
+ * (Algorithms 3, 5, 7).
+ *   CSR, COO: one wavefront streams each partition's nonzeros; rows inside a
+ *     partition are written directly; a row split between partitions is
+ *     merged by summing its partial sums in partition order with a
+ *     compensated FP64 sum and applying beta once; rows covered by no
+ *     partition get beta*y.  Deterministic for a given np and tune.
+ *   CSC: the partitions' partial vectors (Algorithm 5, Sec. 4.3 column
+ *     merge) are kept sparse: every product is written once, grouped by row
+ *     bucket, and each bucket is summed in LDS; no atomics on y.  The order
+ *     of the sums within a bucket varies between runs.
  *   x_d: n values, y_d: m values (FP64 for F64 matrices, FP32 otherwise).
  *   beta == 0: y is not read.
- *   ws_d: msrep_spmv_ws_bytes(A, np) bytes.
+ *   ws_d: msrep_spmv_ws_bytes(A, np) bytes, caller-owned, contents free.
+ *   tune: NULL for the defaults (see msrep_tune).
+ * The call only launches kernels on the stream (no allocation, memset or
+ * host synchronisation), so it can be captured into a graph; capture after
+ * one uncaptured call with the same launch shape, which fills host-side
+ * caches.  Errors: MSREP_ERR_ARG (NULL arrays, np <= 0, bad tune),
+ * MSREP_ERR_SIZE (workspace too small), MSREP_ERR_UNSUPPORTED (x or y over
+ * 4 GiB, CSC with more than 2^26 rows), MSREP_ERR_HIP (a launch failed).
  */
 msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
                         const int32_t *lptr_d, int32_t np, const void *x_d,

@@ -296,3 +296,36 @@ def test_csc_tall_matrix_uses_wide_buckets(vt):
     for np_ in (3, 1000):
         y, ref, s = _run(A, x, "csc", vt, np_, 0.5, 2.0, y_in, M=M, v64=v64)
         assert_close(y, ref, s, tol, "tall csc vt%d np%d" % (vt, np_))
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_spmv_replays_under_graph_capture(fmt):
+    """msrep_spmv launches kernels only (no memsets), so a caller can capture
+    it: three replays with new x contents, eager work and synchronisation in
+    between, each equal to the eager call on the same x."""
+    A, x0 = synth.rmat_csr(scale=13, edge_factor=8, seed=21)
+    M, v64 = device_mat(A, fmt, pk.F64)
+    P = pk.msrep_build_partition(M, 300)
+    dev = _dev()
+    x = torch.from_numpy(x0).to(dev)
+    y = torch.zeros(A.m, dtype=torch.float64, device=dev)
+    ws = torch.zeros(pk.msrep_spmv_ws_bytes(M, P.np), dtype=torch.uint8, device=dev)
+    pk.msrep_spmv(M, P, x, y, 1.0, 0.0, ws=ws)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.msrep_spmv(M, P, x, y, 1.0, 0.0, ws=ws)
+    rng = np.random.default_rng(22)
+    for rep in range(3):
+        xn = rng.uniform(-1, 1, A.n)
+        x.copy_(torch.from_numpy(xn))
+        g.replay()
+        torch.cuda.synchronize()
+        got = y.cpu().numpy().copy()
+        y_eager = torch.zeros_like(y)
+        pk.msrep_spmv(M, P, x, y_eager, 1.0, 0.0, ws=torch.zeros_like(ws))
+        torch.cuda.synchronize()
+        ref, s = oracle_y(A, fmt, v64, xn)
+        assert_close(got, ref, s, F64_TOL, "%s replay %d" % (fmt, rep))
+        if fmt != "csc":  # CSC sums in an order that varies between runs
+            assert np.array_equal(got, y_eager.cpu().numpy()), (fmt, rep)
