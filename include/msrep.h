@@ -222,9 +222,14 @@ msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
                         const msrep_tune *tune, void *ws_d, size_t ws_bytes,
                         void *stream);
 
-/* Launch shape and partition size the autotuner picks for A by timing the
- * candidates on the stream (synchronises; uses ws_d of at least
- * msrep_autotune_ws_bytes(A) bytes for partitions and scratch output). */
+/* Launch shape and partition size for A, picked by timing every candidate on
+ * the stream and keeping the fastest median of three runs:
+ *   nnz_per_wave in {256, 512, 1024, 2048, 4096} (the equal-nnz np follows),
+ *   k_per_lane in {4, 8}, waves_per_wg in {2, 4, 8} (CSR, COO),
+ *   pipeline in {1, 2} (CSR), resident in {0, 1} (CSR, COO).
+ * x_d holds n values for the timed SpMVs.  Synchronises the stream.
+ * ws_d: at least msrep_autotune_ws_bytes(A) bytes (partitions, local
+ * pointers, a y and the SpMV workspace of the largest np). */
 size_t msrep_autotune_ws_bytes(const msrep_mat *A);
 msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void *ws_d,
                             size_t ws_bytes, msrep_tune *out, void *stream);
