@@ -398,13 +398,8 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
                                     lds_raw + wid * seg_lds_per_wave<VT, K>());
 }
 
-
-// Boundary merge for row-split formats (CSR, COO): one thread per partition.
-// The partition that holds a split row's first nonzero (end_flag set, not a
-// middle piece) sums its tail partial and the head partials of the following
-// partitions, in partition order, with TwoSum compensation, then applies
-// alpha and beta once (msRep Algorithm 3 lines on merging, Sec. 4.3).
-// Total of a row split across partitions, owned by partition p (the one
+// Boundary merge of the batched paths (one thread per work item, see
+// merge_batched).  Total of a row split across partitions, owned by partition p (the one
 // holding the row's first piece): p's tail plus the heads of the following
 // partitions that continue row r, added in partition order with TwoSum.  The
 // chain is read kChain partitions per round (only their row and flag words,
@@ -449,19 +444,180 @@ __device__ __forceinline__ double split_row_total(const msrep_part *__restrict__
   return s + c;
 }
 
+// ---- boundary merge for the row-split formats (CSR, COO) ----
+// The partial sums of split rows are combined as a segmented sum over the
+// partitions in partition order (msRep Algorithm 3 merging step, Sec. 4.3).
+// Partition q contributes two elements, in order: its head partial carry[2q]
+// (the rest of the row split at its left edge, when start_flag is set) and
+// its tail partial carry[2q+1] (the first piece of the row split at its right
+// edge, when q holds that row's first piece).  The tail element starts a
+// segment; a partition without start_flag, or one that ends on a row end,
+// breaks the chain (a segment start with value 0).  The total of split row r
+// is the segmented sum at the head element of the partition where r ends, and
+// that partition's thread applies alpha and beta once.  Sums are kept as
+// compensated pairs (s, c) combined with TwoSum.
+struct MSeg {
+  double s, c;  // value s + c
+  int f;        // a segment starts in the range
+};
+
+// a before b
+__device__ __forceinline__ MSeg mseg_cat(const MSeg &a, const MSeg &b) {
+  if (b.f) return b;
+  MSeg r;
+  double e;
+  two_sum(a.s, b.s, r.s, e);
+  r.c = a.c + b.c + e;
+  r.f = a.f;
+  return r;
+}
+
+struct MPart {
+  int32_t sr, er, sf, ef;  // start_row, end_row, start_flag, end_flag
+};
+
+__device__ __forceinline__ MPart mpart_load(const msrep_part *__restrict__ parts, int32_t q) {
+  const int32_t *w = &parts[q].start_row;  // 8-byte aligned (40-byte records)
+  return MPart{w[0], w[1], w[2], w[3]};
+}
+
+// The head and tail elements of one partition, combined.  An empty partition
+// (end_row < start_row) is the identity.
+__device__ __forceinline__ MSeg mpart_seg(const MPart &P, double head, double tail) {
+  MSeg a{0.0, 0.0, 0};
+  if (P.er < P.sr) return a;
+  if (P.sf)
+    a.s = head;
+  else
+    a.f = 1;
+  const bool middle = P.sf && P.sr == P.er;  // inside one split row: its sum is the head
+  if (!P.ef) return MSeg{0.0, 0.0, 1};
+  if (!middle) return MSeg{tail, 0.0, 1};
+  return a;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void mseg_step(MSeg &v) {
+  MSeg p;
+  p.s = dpp<CTRL, ROWS>(v.s);
+  p.c = dpp<CTRL, ROWS>(v.c);
+  p.f = dpp_i<CTRL, ROWS>(v.f);
+  v = mseg_cat(p, v);  // lanes with no source get (0, 0, 0): the identity
+}
+
+constexpr int kMergeBlock = 256;  // partitions per block, one per thread
+constexpr int kMergeLook = 4;     // partitions per thread in a look-back window
+constexpr int kMergeWaves = kMergeBlock / kWave;
+
+// Inclusive segmented scan across the 64 lanes.
+__device__ __forceinline__ void wave_mseg_scan(MSeg &v) {
+  mseg_step<kDppRowShr1, 0xF>(v);
+  mseg_step<kDppRowShr2, 0xF>(v);
+  mseg_step<kDppRowShr4, 0xF>(v);
+  mseg_step<kDppRowShr8, 0xF>(v);
+  mseg_step<kDppRowBcast15, 0xA>(v);
+  mseg_step<kDppRowBcast31, 0xC>(v);
+}
+
+// Block-wide segmented scan in thread order: returns the block's total and
+// sets excl to the sum of the threads before this one.  Ends with a barrier,
+// so the LDS slots can be reused at once.
+__device__ __forceinline__ MSeg block_mseg_scan(MSeg v, MSeg &excl, double *sh_s, double *sh_c,
+                                                int *sh_f) {
+  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  wave_mseg_scan(v);
+  MSeg wex;  // exclusive within the wave
+  wex.s = dpp<kDppWaveShr1>(v.s);
+  wex.c = dpp<kDppWaveShr1>(v.c);
+  wex.f = dpp_i<kDppWaveShr1>(v.f);
+  if (lane == kWave - 1) {
+    sh_s[wid] = v.s;
+    sh_c[wid] = v.c;
+    sh_f[wid] = v.f;
+  }
+  __syncthreads();
+  MSeg pre{0.0, 0.0, 0}, tot{0.0, 0.0, 0};
+#pragma unroll
+  for (int w = 0; w < kMergeWaves; ++w) {
+    const MSeg ww{sh_s[w], sh_c[w], sh_f[w]};
+    if (w == wid) pre = tot;
+    tot = mseg_cat(tot, ww);
+  }
+  excl = mseg_cat(pre, wex);
+  __syncthreads();
+  return tot;
+}
+
 template <typename T, bool BETA0>
-__global__ __launch_bounds__(256) void merge_rows(const msrep_part *__restrict__ parts, int32_t np,
-                                                  const double *__restrict__ carry,
-                                                  T *__restrict__ y, int32_t m, double alpha,
-                                                  double beta) {
-  const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
-  const msrep_part P = parts[p];
-  if (P.end_idx < P.start_idx || !P.end_flag) return;
-  if (P.start_flag && P.start_row == P.end_row) return;  // a later piece, not the owner
-  const int32_t r = P.end_row;
-  const double tot = split_row_total(parts, np, carry, p, r);
+__global__ __launch_bounds__(kMergeBlock) void merge_rows(const msrep_part *__restrict__ parts,
+                                                          int32_t np,
+                                                          const double *__restrict__ carry,
+                                                          T *__restrict__ y, int32_t m,
+                                                          double alpha, double beta) {
+  __shared__ double sh_s[kMergeWaves], sh_c[kMergeWaves];
+  __shared__ int sh_f[kMergeWaves];
+  const int t = threadIdx.x;
+  const int32_t base = blockIdx.x * kMergeBlock;
+  const int32_t q = base + t;
+  MPart P{0, -1, 0, 0};
+  double hd = 0.0, tl = 0.0;
+  if (q < np) {
+    P = mpart_load(parts, q);
+    hd = carry[2 * static_cast<int64_t>(q)];
+    tl = carry[2 * static_cast<int64_t>(q) + 1];
+  }
+  // the 64 partitions just before the block, loaded up front by wave 0: a
+  // split row reaching into the block usually starts among them
+  const int32_t near = base > kWave ? base - kWave : 0;
+  MSeg look{0.0, 0.0, 0};
+  if (t < kWave && near + t < base) {
+    const int32_t qq = near + t;
+    look = mpart_seg(mpart_load(parts, qq), carry[2 * static_cast<int64_t>(qq)],
+                     carry[2 * static_cast<int64_t>(qq) + 1]);
+  }
+
+  MSeg excl;
+  (void)block_mseg_scan(mpart_seg(P, hd, tl), excl, sh_s, sh_c, sh_f);
+  const bool last = P.er >= P.sr && P.sf && !(P.ef && P.sr == P.er);  // a split row ends here
+  MSeg at = mseg_cat(excl, MSeg{hd, 0.0, 0});  // segmented sum at the head element
+  const bool need = last && !at.f;             // the row began before this block
+  if (__syncthreads_or(need)) {
+    // the segment open at the block's left edge: first the near window,
+    // then windows of kMergeBlock * kMergeLook partitions further left
+    // (block-uniform: every thread sees the same window totals)
+    if (t < kWave) {
+      wave_mseg_scan(look);
+      if (t == kWave - 1) {
+        sh_s[0] = look.s;
+        sh_c[0] = look.c;
+        sh_f[0] = look.f;
+      }
+    }
+    __syncthreads();
+    MSeg acc{sh_s[0], sh_c[0], sh_f[0]};
+    __syncthreads();
+    constexpr int32_t kSpan = kMergeBlock * kMergeLook;
+    int32_t hi = near;
+    while (hi > 0 && !acc.f) {
+      const int32_t lo = hi > kSpan ? hi - kSpan : 0;
+      MSeg w{0.0, 0.0, 0};
+#pragma unroll
+      for (int j = 0; j < kMergeLook; ++j) {
+        const int32_t qq = lo + t * kMergeLook + j;
+        if (qq < hi)
+          w = mseg_cat(w, mpart_seg(mpart_load(parts, qq), carry[2 * static_cast<int64_t>(qq)],
+                                    carry[2 * static_cast<int64_t>(qq) + 1]));
+      }
+      MSeg wex;
+      acc = mseg_cat(block_mseg_scan(w, wex, sh_s, sh_c, sh_f), acc);
+      hi = lo;
+    }
+    if (need) at = mseg_cat(acc, at);
+  }
+  if (!last) return;
+  const int32_t r = P.sr;
   if (r < 0 || r >= m) return;
+  const double tot = at.s + at.c;
   y[r] = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(y[r]));
 }
 

@@ -190,6 +190,27 @@ def test_stencil_times_ones_exact():
 
 
 @pytest.mark.parametrize("fmt", ["csr", "coo"])
+@pytest.mark.parametrize("vt", [0, 1])
+def test_merge_rows_spanning_many_blocks(fmt, vt):
+    """Rows split over thousands of partitions: the boundary merge must carry
+    a row's sum across many blocks of partitions and across empty ones."""
+    rng = np.random.default_rng(8)
+    counts = np.array([0, 40000, 3, 0, 9000, 1, 0, 70000, 2, 5], np.int64)
+    n = 80000
+    cols = np.concatenate([np.sort(rng.choice(n, c, replace=False)) for c in counts])
+    ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    A = synth.Csr(len(counts), n, ptr, cols.astype(np.int32), rng.uniform(-1, 1, cols.size),
+                  name="many-blocks")
+    x = rng.uniform(-1, 1, n)
+    y_in = rng.uniform(-1, 1, A.m)
+    tol = F64_TOL if vt == 0 else F32_TOL
+    M, v64 = device_mat(A, fmt, vt)
+    for np_ in (A.nnz // 3, A.nnz // 64, 1000, A.nnz + 300):
+        y, ref, s = _run(A, x, fmt, vt, np_, -1.5, -0.75, y_in, M=M, v64=v64)
+        assert_close(y, ref, s, tol, "many-blocks %s vt%d np%d" % (fmt, vt, np_))
+
+
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
 def test_deterministic(fmt):
     A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=5)
     M, v64 = device_mat(A, fmt, pk.F64)
