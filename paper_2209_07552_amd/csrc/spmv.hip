@@ -169,7 +169,7 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   (void)wpb;  // the scatter always runs one 16-wavefront producer per CU
   timing_begin(s);
   hipLaunchKernelGGL((csc_scatter<VT, K>), dim3(L.P), dim3(kCscScatterWaves * kWave),
-                     cur_lds + csc_lds_per_wave<K>() * kCscScatterWaves, s, A->idx,
+                     csc_scatter_lds<K>(L.nb), s, A->idx,
                      static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
                      static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
   MSREP_LAUNCHED("csc_scatter");

@@ -80,8 +80,9 @@ inline bool csc_layout(int32_t m, int64_t nnz, int32_t np, int prod_bytes, CscLa
   L.pbase = take(4 * static_cast<size_t>(nb + 1));
   L.mbase = take(4 * static_cast<size_t>(nb + 1));
   L.mlist = take(4 * static_cast<size_t>(nb + 1));
-  L.prod = take(static_cast<size_t>(prod_bytes) * static_cast<size_t>(nnz));
-  L.rlo = take(2 * static_cast<size_t>(nnz));
+  // one spare slot past nnz takes the stores of masked lanes
+  L.prod = take(static_cast<size_t>(prod_bytes) * static_cast<size_t>(nnz + 1));
+  L.rlo = take(2 * static_cast<size_t>(nnz + 1));
   L.part = take(8 * static_cast<size_t>(L.max_slots) << shift);
   L.total = o;
   return true;
@@ -185,49 +186,34 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(
   if (p == 0 && threadIdx.x == 0) cnt[static_cast<int64_t>(nb) * P] = 0;
 }
 
-// Rows and values of the chunk of CH = 64*K local positions [cb, cb+CH) of a
-// pCSC partition (nloc nonzeros from global position s0); positions outside
-// the partition read as row -1, value 0.
-template <int VT, int K>
-__device__ __forceinline__ void csc_load(const int32_t *__restrict__ row_idx,
-                                         const typename vt_traits<VT>::V *__restrict__ val,
-                                         int64_t s0, int32_t nloc, int32_t cb,
-                                         int32_t (&rows)[K], typename vt_traits<VT>::V (&v)[K]) {
-  using V = typename vt_traits<VT>::V;
-  const int32_t q0 = cb + lane_id() * K;
-  if (q0 >= 0 && q0 + K <= nloc) {
-    load_vec<int32_t, K>(row_idx + s0 + q0, rows);
-    load_vec<V, K>(val + s0 + q0, v);
-  } else {
+constexpr int kLpBatches = 4;  // local column pointer words read ahead: 4*64 columns
+
+// The local column pointer words lp[j] of columns j = jb + u*64 + lane,
+// u < kLpBatches, through a resource covering lp[0..R] (0 outside; the
+// caller masks j > R).
+__device__ __forceinline__ void lp_words(rsrc_t rl, int32_t jb, int32_t R,
+                                         int32_t (&av)[kLpBatches]) {
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const int32_t q = q0 + t;
-      rows[t] = -1;
-      v[t] = V(0);
-      if (q >= 0 && q < nloc) {
-        rows[t] = row_idx[s0 + q];
-        v[t] = val[s0 + q];
-      }
-    }
+  for (int u = 0; u < kLpBatches; ++u) {
+    const int32_t j = jb + u * kWave + lane_id();
+    av[u] = buf_load<int32_t>(rl, j >= 0 && j <= R ? static_cast<uint32_t>(j) * 4u : ~0u);
   }
 }
 
-// The column of every position of a loaded chunk and its product val*x[col].
-// Columns that start inside the chunk mark their first position in the
-// wave's LDS array (the local column pointer lp, read 64 columns at a time
-// from j0, the column holding the chunk's first position); a max-scan (DPP)
-// carries the index forward.  ok: a position of the partition whose row lies
-// in [0, m); a column outside [0, n) gives product 0.  j0 advances to the
-// column holding the next chunk's first position, taken from the lane that
-// read the first column starting past the chunk (no extra load).
-template <int VT, int K>
-__device__ __forceinline__ void csc_columns(
-    int32_t nloc, int32_t cb, int32_t c0, int32_t R, const int32_t *__restrict__ lp,
-    const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n, int32_t *s_col,
-    int32_t &j0, const int32_t (&rows)[K], const typename vt_traits<VT>::V (&v)[K],
-    bool (&ok)[K], typename vt_traits<VT>::A (&pr)[K]) {
-  using Tr = vt_traits<VT>;
-  using Acc = typename Tr::A;
+// The column of every position of a loaded chunk.  Columns that start inside
+// the chunk mark their first position in the wave's LDS array (the local
+// column pointer lp from j0, the column holding the chunk's first position:
+// the kLpBatches*64 words read ahead in av0, then kLpWide words per round);
+// a max-scan (DPP) carries the index forward.  ok: a position of the
+// partition whose row lies in [0, m).  j0 advances to the column holding the
+// next chunk's first position, taken from the lane that read the first
+// column starting past the chunk (no extra load).
+template <int K>
+__device__ __forceinline__ void csc_columns(int32_t nloc, int32_t cb, int32_t c0, int32_t R,
+                                            rsrc_t rl, int32_t m, int32_t *s_col, int32_t &j0,
+                                            const int32_t (&av0)[kLpBatches],
+                                            const int32_t (&rows)[K], int32_t (&col)[K],
+                                            bool (&ok)[K]) {
   constexpr int CH = kWave * K;
   const int lane = lane_id();
   const int32_t ce = cb + CH < nloc ? cb + CH : nloc;
@@ -235,36 +221,44 @@ __device__ __forceinline__ void csc_columns(
 #pragma unroll
   for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
   wave_lds_sync();
-  // the local column pointer from j0 on, kLpBatches batches of 64 columns
-  // loaded together (sparse regions put hundreds of columns in one chunk)
-  constexpr int kLpBatches = 4;
+  // first the kLpBatches*64 words read ahead, 64 columns at a time
   int32_t jb = j0, cnt = kWave, a = 0;
-  while (cnt == kWave) {
-    int32_t av[kLpBatches];
 #pragma unroll
-    for (int u = 0; u < kLpBatches; ++u) {
-      const int32_t j = jb + u * kWave + lane;
-      av[u] = (j >= 0 && j <= R) ? lp[j] : 0x7fffffff;
+  for (int u = 0; u < kLpBatches; ++u) {
+    if (cnt < kWave) break;
+    if (u > 0) jb += kWave;
+    const int32_t j = jb + lane;
+    a = (j >= 0 && j <= R) ? av0[u] : 0x7fffffff;
+    const bool in = j <= R - 1 && a < ce;
+    if (in && j > j0) {
+      const int32_t pos = a - cb;
+      if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
     }
-#pragma unroll
-    for (int u = 0; u < kLpBatches; ++u) {
-      if (cnt < kWave) break;
-      if (u > 0) jb += kWave;
-      const int32_t j = jb + lane;
-      a = av[u];
-      const bool in = j <= R - 1 && a < ce;
-      if (in && j > j0) {
-        const int32_t pos = a - cb;
-        if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
-      }
-      cnt = __popcll(__ballot(in));
-    }
-    if (cnt == kWave) jb += kWave;
+    cnt = __popcll(__ballot(in));
   }
-  const int32_t j1 = jb + cnt - 1;
-  // lp[j1 + 1]: where the first column starting past the chunk starts (or
-  // past-the-end), from the lane that loaded it
-  const int32_t nxt = __builtin_amdgcn_readlane(a, cnt);
+  int32_t j1, nxt;
+  if (cnt < kWave) {
+    j1 = jb + cnt - 1;
+    // lp[j1 + 1]: where the first column starting past the chunk starts (or
+    // past-the-end), from the lane that loaded it
+    nxt = __builtin_amdgcn_readlane(a, cnt);
+  } else {
+    // sparse region (runs of empty columns): wide rounds
+    jb += kWave;
+    for (;;) {
+      const int32_t tot = lp_wide_round(rl, jb, R, ce, nxt, [&](int32_t j, int32_t aw, bool in) {
+        if (in && j > j0) {
+          const int32_t pos = aw - cb;
+          if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);
+        }
+      });
+      if (tot < kLpWide) {
+        j1 = jb + tot - 1;
+        break;
+      }
+      jb += kLpWide;
+    }
+  }
   wave_lds_sync();
   int32_t cj[K];
   int32_t mx = j0;
@@ -277,16 +271,12 @@ __device__ __forceinline__ void csc_columns(
   const int32_t agg = wave_max_scan_nonneg(mx);  // values >= j0 >= 0
   int32_t cin = dpp_i<kDppWaveShr1>(agg);
   if (lane == 0) cin = j0;
-  typename Tr::T xv[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) {
     const int32_t q = q0 + t;
-    const int32_t c = c0 + (cj[t] > cin ? cj[t] : cin);
+    col[t] = c0 + (cj[t] > cin ? cj[t] : cin);
     ok[t] = q >= 0 && q < nloc && static_cast<uint32_t>(rows[t]) < static_cast<uint32_t>(m);
-    xv[t] = ok[t] && static_cast<uint32_t>(c) < static_cast<uint32_t>(n) ? x[c] : typename Tr::T(0);
   }
-#pragma unroll
-  for (int t = 0; t < K; ++t) pr[t] = Tr::val(v[t]) * static_cast<Acc>(xv[t]);
   // the column holding the chunk's last position continues, unless it ends
   j0 = nxt > ce ? j1 : j1 + 1;
   wave_lds_sync();
@@ -311,11 +301,26 @@ __device__ __forceinline__ CscPart csc_part(const msrep_part *__restrict__ parts
   return c;
 }
 
+__device__ __forceinline__ rsrc_t lp_rsrc(const CscPart &c, bool live) {
+  return make_rsrc(c.lp, live && c.R >= 0 ? static_cast<uint32_t>(c.R + 1) * 4u : 0u);
+}
+
+// LDS of one scatter producer: a cursor per bucket, a spare cursor per lane
+// (masked lanes), then each wavefront's column array.
+template <int K>
+constexpr size_t csc_scatter_lds(int32_t nb) {
+  return align_up((static_cast<size_t>(nb) + kWave) * 4, 16) + csc_lds_per_wave<K>() * kCscScatterWaves;
+}
+
 // Products of producer p go straight to their positions in its run of each
 // bucket (an LDS cursor per bucket hands out positions).  Each wavefront
-// walks its partitions (pa+wid, pa+wid+W, ...) as one stream of chunks and
-// loads the next chunk's rows and values, and the next partition's record,
-// before working on the current chunk.
+// walks its partitions (pa+wid, pa+wid+W, ...) as one stream of chunks.  Per
+// chunk it finds the columns and issues the x gathers, then the previous
+// chunk's stores and the next chunk's loads (rows, values, local column
+// pointer words), and only then waits for x.  Every load is a bounds-checked
+// buffer load and every lane stores (masked lanes to the spare slot at index
+// nnz), so the code between the waits has no branch and the only memory
+// latency left on a chunk's path is its x gather.
 template <int VT, int K>
 __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
@@ -323,20 +328,26 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     int32_t np, int32_t P, const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n,
     int shift, int32_t nb, const int32_t *__restrict__ off,
     typename vt_traits<VT>::A *__restrict__ prod, uint16_t *__restrict__ rlo) {
-  using V = typename vt_traits<VT>::V;
-  using Acc = typename vt_traits<VT>::A;
+  using Tr = vt_traits<VT>;
+  using V = typename Tr::V;
+  using T = typename Tr::T;
+  using Acc = typename Tr::A;
   constexpr int CH = kWave * K;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int32_t *cur = reinterpret_cast<int32_t *>(lds_raw);
 
   const int wid = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
+  const int lane = lane_id();
   const int p = xcd_block(blockIdx.x, gridDim.x);
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) cur[i] = off[static_cast<int64_t>(i) * P + p];
+  for (int i = threadIdx.x; i < nb + kWave; i += blockDim.x)
+    cur[i] = i < nb ? off[static_cast<int64_t>(i) * P + p] : 0;
   __syncthreads();
-  int32_t *s_col = reinterpret_cast<int32_t *>(lds_raw + align_up(static_cast<size_t>(nb) * 4, 16) +
-                                               wid * csc_lds_per_wave<K>());
+  int32_t *s_col = reinterpret_cast<int32_t *>(
+      lds_raw + align_up((static_cast<size_t>(nb) + kWave) * 4, 16) + wid * csc_lds_per_wave<K>());
   const uint32_t mask = (1u << shift) - 1u;
+  const int32_t spare = static_cast<int32_t>(nnz);  // nnz < 2^31
+  const rsrc_t rx = make_rsrc(x, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(T)));
   int64_t pa, pb;
   producer_range(p, np, P, pa, pb);
 
@@ -352,34 +363,65 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   int64_t pi = first_nonempty(pa + wid, cp);
   int64_t pn = pi < pb ? first_nonempty(pi + wpb, np_meta) : pb;  // the next partition
   int32_t cb = pi < pb ? -static_cast<int32_t>(cp.s0 % K) : 0, j0 = 0;
-  int32_t rows[K];
+  int32_t rows[K], av[kLpBatches];
   V v[K];
-  if (pi < pb) csc_load<VT, K>(row_idx, val, cp.s0, cp.nloc, cb, rows, v);
-  while (pi < pb) {
-    // ---- the next chunk: the same partition, or the first of the next one
-    const bool same = cb + CH < cp.nloc;
-    const CscPart &cq = same ? cp : np_meta;
-    const int32_t cb_n = same ? cb + CH : -static_cast<int32_t>(np_meta.s0 % K);
-    const bool more = same || pn < pb;
-    int32_t rows_n[K];
-    V v_n[K];
-    if (more) csc_load<VT, K>(row_idx, val, cq.s0, cq.nloc, cb_n, rows_n, v_n);
-    // ---- this chunk
-    bool okk[K];
-    Acc pr[K];
-    csc_columns<VT, K>(cp.nloc, cb, cp.c0, cp.R, cp.lp, x, m, n, s_col, j0, rows, v, okk, pr);
+  rsrc_t rl = lp_rsrc(cp, pi < pb);
+  load_items<V, K>(row_idx, val, cp.s0, cb, pi < pb ? cp.nloc : cb, rows, v);
+  lp_words(rl, 0, pi < pb ? cp.R : -1, av);
+  // the previous chunk's products, positions and row bits (none yet: spare)
+  Acc pr_p[K];
+  int32_t at_p[K], lo_p[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    pr_p[t] = Acc(0);
+    at_p[t] = spare;
+    lo_p[t] = 0;
+  }
+  auto store_prev = [&]() {
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-      if (!okk[t]) continue;
-      const int32_t at = atomicAdd(&cur[static_cast<uint32_t>(rows[t]) >> shift], 1);
-      if (static_cast<uint64_t>(at) < static_cast<uint64_t>(nnz)) {
-        prod[at] = pr[t];
-        rlo[at] = static_cast<uint16_t>(static_cast<uint32_t>(rows[t]) & mask);
-      }
+      prod[at_p[t]] = pr_p[t];
+      rlo[at_p[t]] = static_cast<uint16_t>(lo_p[t]);
+    }
+  };
+  while (pi < pb) {
+    // ---- this chunk: columns, then the x gathers
+    int32_t col[K];
+    bool okk[K];
+    csc_columns<K>(cp.nloc, cb, cp.c0, cp.R, rl, m, s_col, j0, av, rows, col, okk);
+    T xv[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      xv[t] = buf_load<T>(rx, okk[t] && static_cast<uint32_t>(col[t]) < static_cast<uint32_t>(n)
+                                  ? static_cast<uint32_t>(col[t]) * static_cast<uint32_t>(sizeof(T))
+                                  : ~0u);
+    store_prev();
+    // ---- the next chunk (the same partition, or the first of the next
+    // one); nothing is read past the last chunk
+    const bool same = cb + CH < cp.nloc;
+    const bool more = same || pn < pb;
+    const CscPart &cq = same ? cp : np_meta;
+    const int32_t cb_n = same ? cb + CH : -static_cast<int32_t>(np_meta.s0 % K);
+    const int32_t j0_n = same ? j0 : 0;
+    const rsrc_t rl_n = lp_rsrc(cq, more);
+    int32_t rows_n[K], av_n[kLpBatches];
+    V v_n[K];
+    load_items<V, K>(row_idx, val, cq.s0, cb_n, more ? cq.nloc : cb_n, rows_n, v_n);
+    lp_words(rl_n, j0_n, more ? cq.R : -1, av_n);
+    // ---- products and their positions in the buckets' runs
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      pr_p[t] = Tr::val(v[t]) * static_cast<Acc>(xv[t]);
+      const int32_t slot = okk[t] ? static_cast<int32_t>(static_cast<uint32_t>(rows[t]) >> shift)
+                                  : nb + lane;
+      const int32_t a = atomicAdd(&cur[slot], 1);
+      at_p[t] = okk[t] && static_cast<uint32_t>(a) < static_cast<uint32_t>(spare) ? a : spare;
+      lo_p[t] = static_cast<int32_t>(static_cast<uint32_t>(rows[t]) & mask);
     }
     // ---- advance
     if (same) {
       cb = cb_n;
+      j0 = j0_n;
     } else {
       pi = pn;
       cp = np_meta;
@@ -387,12 +429,16 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
       j0 = 0;
       if (pi < pb) pn = first_nonempty(pi + wpb, np_meta);
     }
+    rl = rl_n;
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       rows[t] = rows_n[t];
       v[t] = v_n[t];
     }
+#pragma unroll
+    for (int u = 0; u < kLpBatches; ++u) av[u] = av_n[u];
   }
+  store_prev();
 }
 
 // Exclusive scan of one int per thread over a block of kPlanBlock threads

@@ -118,6 +118,62 @@ __device__ __forceinline__ void load_items(const int32_t *__restrict__ idx,
 // lane each; a chunk holding a longer row uses the segmented scan.
 constexpr int kShortRow = 32;
 
+// One round over the local pointer words of kLpWide consecutive rows (CSR)
+// or columns (CSC) from jb: lane L holds jb + 256*i + 4*L + e (kLpWideLoads
+// 16-byte loads), words past R read as INT_MAX.  visit(j, word, in) sees every word;
+// in = j <= R-1 and the word lies before ce.  Returns how many are in (a
+// prefix, the pointer being non-decreasing) and, when that is below
+// kLpWide, sets nxt to the word just past them.  Chunks over runs of empty
+// rows or columns span thousands of them; this reads them in few dependent
+// rounds.
+constexpr int kLpWideLoads = 2;
+constexpr int kLpWide = kLpWideLoads * 4 * kWave;
+
+template <typename F>
+__device__ __forceinline__ int32_t lp_wide_round(rsrc_t rl, int32_t jb, int32_t R, int32_t ce,
+                                                 int32_t &nxt, F &&visit) {
+  const int lane = lane_id();
+  int32_t w[kLpWide / kWave];
+#pragma unroll
+  for (int i = 0; i < kLpWideLoads; ++i) {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(
+        rl, static_cast<uint32_t>(jb + i * 4 * kWave + 4 * lane) * 4u, 0, 0);
+    w[4 * i] = static_cast<int32_t>(q.x);
+    w[4 * i + 1] = static_cast<int32_t>(q.y);
+    w[4 * i + 2] = static_cast<int32_t>(q.z);
+    w[4 * i + 3] = static_cast<int32_t>(q.w);
+  }
+  int32_t tot = 0;
+#pragma unroll
+  for (int i = 0; i < kLpWideLoads; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int32_t j = jb + i * 4 * kWave + 4 * lane + e;
+      const int32_t aw = j <= R ? w[4 * i + e] : 0x7fffffff;
+      w[4 * i + e] = aw;
+      const bool in = j <= R - 1 && aw < ce;
+      visit(j, aw, in);
+      tot += __popcll(__ballot(in));
+    }
+  }
+  if (tot < kLpWide) {
+    // the word of row jb + tot: load tot / 256, lane (tot % 256) / 4, element tot % 4
+    const int i_sel = tot / (4 * kWave), e_sel = tot % 4;
+    int32_t pick = 0;
+#pragma unroll
+    for (int i = 0; i < kLpWideLoads; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i == i_sel && e == e_sel) pick = w[4 * i + e];
+    nxt = __builtin_amdgcn_readlane(pick, (tot % (4 * kWave)) / 4);
+  }
+  return tot;
+}
+
+// Rows handled per round of the loops over many rows of one chunk (loads in
+// flight per lane).
+constexpr int kRowBatch = 4;
+
 // Per-wave LDS footprint of the CSR/COO kernels.
 template <int VT, int K>
 constexpr size_t seg_lds_per_wave() {
@@ -222,28 +278,13 @@ __device__ __forceinline__ void csr_partition(
       lp_next = read_lane(lpv0, cnt & (kWave - 1));
     }
     if (cnt == kWave) {
-      // more than 64 rows start in the chunk (short or empty rows): read the
-      // following batches three at a time
-      constexpr int kMore = 3;
-      bool found = false;
-      while (!found) {
-        int32_t vv[kMore];
-#pragma unroll
-        for (int u = 0; u < kMore; ++u)
-          vv[u] = buf_load<int32_t>(
-              rl, static_cast<uint32_t>(jb + (u + 1) * kWave + lane) * 4u);
-#pragma unroll
-        for (int u = 0; u < kMore; ++u) {
-          if (found) break;
-          jb += kWave;
-          const int32_t j = jb + lane;
-          const bool in = j <= R - 1 && vv[u] < ce;
-          cnt = __popcll(__ballot(in));
-          if (cnt < kWave) {
-            lp_next = read_lane(vv[u], cnt);
-            found = true;
-          }
-        }
+      // more than 64 rows start in the chunk (short or empty rows): wide
+      // rounds from the next batch on
+      jb += kWave;
+      for (;;) {
+        cnt = lp_wide_round(rl, jb, R, ce, lp_next, [](int32_t, int32_t, bool) {});
+        if (cnt < kLpWide) break;
+        jb += kLpWide;
       }
     }
     const int32_t j1 = jb + cnt - 1;  // last row starting before ce
@@ -305,11 +346,17 @@ __device__ __forceinline__ void csr_partition(
 #pragma unroll
       for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
       wave_lds_sync();
-      for (int32_t jr = j0; jr <= j1; jr += kWave) {
-        const int32_t j = jr + lane;
-        const int32_t v = jr == j0 ? lpv0 : buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u);
-        const int32_t pos = v - cb;
-        if (j > j0 && j <= j1 && pos > 0 && pos < CH) s_head[pos] = 1;
+      for (int32_t jr = j0; jr <= j1; jr += kRowBatch * kWave) {
+        int32_t v[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          v[u] = buf_load<int32_t>(rl, static_cast<uint32_t>(jr + u * kWave + lane) * 4u);
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          const int32_t j = jr + u * kWave + lane;
+          const int32_t pos = v[u] - cb;
+          if (j > j0 && j <= j1 && pos > 0 && pos < CH) s_head[pos] = 1;
+        }
       }
       wave_lds_sync();
       uint32_t hb[K / 4];
@@ -347,11 +394,19 @@ __device__ __forceinline__ void csr_partition(
       if (one_batch) {
         if (jl <= j1) finish_row(jl, scanned(lpv0, bl));
       } else {
-        for (int32_t jr = j0; jr <= j1; jr += kWave) {
-          const int32_t j = jr + lane;
-          if (j >= 0 && j <= j1)
-            finish_row(j, scanned(buf_load<int32_t>(rl, static_cast<uint32_t>(j) * 4u),
-                                  buf_load<int32_t>(rl, static_cast<uint32_t>(j + 1) * 4u)));
+        for (int32_t jr = j0; jr <= j1; jr += kRowBatch * kWave) {
+          int32_t a[kRowBatch], b[kRowBatch];
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u) {
+            const uint32_t j = static_cast<uint32_t>(jr + u * kWave + lane);
+            a[u] = buf_load<int32_t>(rl, j * 4u);
+            b[u] = buf_load<int32_t>(rl, (j + 1u) * 4u);
+          }
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u) {
+            const int32_t j = jr + u * kWave + lane;
+            if (j >= 0 && j <= j1) finish_row(j, scanned(a[u], b[u]));
+          }
         }
       }
       if (cont) {
