@@ -210,6 +210,36 @@ def test_merge_rows_spanning_many_blocks(fmt, vt):
         assert_close(y, ref, s, tol, "many-blocks %s vt%d np%d" % (fmt, vt, np_))
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("vt", [0, 1])
+def test_runs_of_empty_rows_and_columns(fmt, vt):
+    """Nonzeros separated by thousands of empty rows and columns: one chunk
+    of a partition spans many rounds of pointer words, and the rows between
+    its nonzeros must still get beta*y."""
+    rng = np.random.default_rng(9)
+    m = n = 300_000
+    rows = np.sort(rng.choice(m, 700, replace=False))
+    rows = np.concatenate([rows, np.full(40, rows[350])])  # one row with 41 entries
+    cols = rng.choice(n, rows.size, replace=True)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    keep = np.ones(rows.size, bool)
+    keep[1:] = (rows[1:] != rows[:-1]) | (cols[1:] != cols[:-1])
+    rows, cols = rows[keep], cols[keep]
+    ptr = np.zeros(m + 1, np.int64)
+    np.add.at(ptr, rows + 1, 1)
+    ptr = np.cumsum(ptr).astype(np.int32)
+    A = synth.Csr(m, n, ptr, cols.astype(np.int32), rng.uniform(-1, 1, rows.size), name="empty-runs")
+    x = rng.uniform(-1, 1, n)
+    y_in = rng.uniform(-1, 1, m)
+    tol = F64_TOL if vt == 0 else F32_TOL
+    M, v64 = device_mat(A, fmt, vt)
+    for np_ in (1, 3, 64, A.nnz + 5):
+        for beta in (0.0, 0.5):
+            y, ref, s = _run(A, x, fmt, vt, np_, 2.0, beta, y_in, M=M, v64=v64)
+            assert_close(y, ref, s, tol, "empty-runs %s vt%d np%d b%g" % (fmt, vt, np_, beta))
+
+
 @pytest.mark.parametrize("fmt", ["csr", "coo"])
 def test_deterministic(fmt):
     A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=5)
