@@ -135,7 +135,9 @@ msrep_status launch_coo(const msrep_mat *A, const msrep_part *parts, int32_t np,
   return MSREP_OK;
 }
 
-template <int VT, int K>
+// PACK: one record per product (msrep_tune.pipeline == 1), else value and
+// row-offset arrays.
+template <int VT, int K, bool PACK>
 msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                         int32_t np, const void *x, void *y, double alpha, double beta, int wpb,
                         void *ws, hipStream_t s) {
@@ -168,7 +170,7 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   timing_end("csc_scan", s);
   (void)wpb;  // the scatter always runs one 16-wavefront producer per CU
   timing_begin(s);
-  hipLaunchKernelGGL((csc_scatter<VT, K>), dim3(L.P), dim3(kCscScatterWaves * kWave),
+  hipLaunchKernelGGL((csc_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
                      csc_scatter_lds<K>(L.nb), s, A->idx,
                      static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
                      static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
@@ -180,7 +182,7 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   MSREP_LAUNCHED("csc_plan");
   timing_end("csc_plan", s);
   timing_begin(s);
-  hipLaunchKernelGGL((csc_reduce<T, Acc>), dim3(static_cast<uint32_t>(L.max_pieces)),
+  hipLaunchKernelGGL((csc_reduce<T, Acc, PACK>), dim3(static_cast<uint32_t>(L.max_pieces)),
                      dim3(kReduceBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
                      L.nb, L.P, L.shift, A->m, A->nnz, L.max_slots, part, static_cast<T *>(y),
                      alpha, beta);
@@ -218,8 +220,11 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   const bool b0 = beta == 0.0;
   msrep_status st;
   if (A->fmt == MSREP_CSC) {  // carry is the whole workspace here
-    return K == 8 ? launch_csc<VT, 8>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
-                  : launch_csc<VT, 4>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+    if (pf == 1)
+      return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
+                    : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+    return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
+                  : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
   }
   if (K == 8)
     st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s)

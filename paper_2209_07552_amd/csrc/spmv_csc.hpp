@@ -80,9 +80,13 @@ inline bool csc_layout(int32_t m, int64_t nnz, int32_t np, int prod_bytes, CscLa
   L.pbase = take(4 * static_cast<size_t>(nb + 1));
   L.mbase = take(4 * static_cast<size_t>(nb + 1));
   L.mlist = take(4 * static_cast<size_t>(nb + 1));
-  // one spare slot past nnz takes the stores of masked lanes
-  L.prod = take(static_cast<size_t>(prod_bytes) * static_cast<size_t>(nnz + 1));
-  L.rlo = take(2 * static_cast<size_t>(nnz + 1));
+  // products: either one record per product (value, then a 32-bit row
+  // offset) or two arrays in the same region (values, then 16-bit row
+  // offsets at L.rlo); one spare slot past nnz takes the stores of masked
+  // lanes
+  const size_t slots = static_cast<size_t>(nnz + 1);
+  L.prod = take((static_cast<size_t>(prod_bytes) + 4) * slots + 256);
+  L.rlo = L.prod + align_up(static_cast<size_t>(prod_bytes) * slots, 256);
   L.part = take(8 * static_cast<size_t>(L.max_slots) << shift);
   L.total = o;
   return true;
@@ -91,6 +95,46 @@ inline bool csc_layout(int32_t m, int64_t nnz, int32_t np, int prod_bytes, CscLa
 template <int K>
 constexpr size_t csc_lds_per_wave() {
   return align_up(kWave * K * sizeof(int32_t), 16);
+}
+
+// Product records of the packed layout: the value and the row's offset in
+// its bucket, written and read with one memory instruction (12 bytes for
+// FP64 values, 8 for FP32).  Scattered stores cost the memory pipeline per
+// instruction and cache line, so on matrices whose rows scatter widely one
+// record store beats a value store plus a 16-bit row store, at 2 more bytes.
+typedef uint32_t u32x3a __attribute__((ext_vector_type(3), aligned(4)));
+
+template <typename A>
+constexpr size_t rec_bytes() {
+  return sizeof(A) + 4;
+}
+
+template <typename A>
+__device__ __forceinline__ void rec_store(unsigned char *__restrict__ base, int32_t at, A v,
+                                          uint32_t lo) {
+  unsigned char *p = base + static_cast<int64_t>(at) * static_cast<int64_t>(rec_bytes<A>());
+  if constexpr (sizeof(A) == 8) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    *reinterpret_cast<u32x3a *>(p) =
+        u32x3a{static_cast<uint32_t>(u), static_cast<uint32_t>(u >> 32), lo};
+  } else {
+    *reinterpret_cast<u32x2 *>(p) = u32x2{__builtin_bit_cast(uint32_t, v), lo};
+  }
+}
+
+template <typename A>
+__device__ __forceinline__ void rec_load(const unsigned char *__restrict__ base, int64_t k, A &v,
+                                         uint32_t &lo) {
+  const unsigned char *p = base + k * static_cast<int64_t>(rec_bytes<A>());
+  if constexpr (sizeof(A) == 8) {
+    const u32x3a w = __builtin_nontemporal_load(reinterpret_cast<const u32x3a *>(p));
+    v = __builtin_bit_cast(A, (static_cast<uint64_t>(w.y) << 32) | w.x);
+    lo = w.z;
+  } else {
+    const u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+    v = __builtin_bit_cast(A, w.x);
+    lo = w.y;
+  }
 }
 
 // Partitions [pa, pb) of producer p: an equal share of the np partitions.
@@ -321,7 +365,7 @@ constexpr size_t csc_scatter_lds(int32_t nb) {
 // buffer load and every lane stores (masked lanes to the spare slot at index
 // nnz), so the code between the waits has no branch and the only memory
 // latency left on a chunk's path is its x gather.
-template <int VT, int K>
+template <int VT, int K, bool PACK>
 __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     const int32_t *__restrict__ row_idx, const typename vt_traits<VT>::V *__restrict__ val,
     int64_t nnz, const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr,
@@ -380,8 +424,13 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   auto store_prev = [&]() {
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-      prod[at_p[t]] = pr_p[t];
-      rlo[at_p[t]] = static_cast<uint16_t>(lo_p[t]);
+      if constexpr (PACK) {
+        rec_store<Acc>(reinterpret_cast<unsigned char *>(prod), at_p[t], pr_p[t],
+                       static_cast<uint32_t>(lo_p[t]));
+      } else {
+        prod[at_p[t]] = pr_p[t];
+        rlo[at_p[t]] = static_cast<uint16_t>(lo_p[t]);
+      }
     }
   };
   while (pi < pb) {
@@ -511,7 +560,7 @@ __global__ __launch_bounds__(kPlanBlock) void csc_plan(const int32_t *__restrict
 // Offsets are clamped to nnz and partial slots to max_slots, so partition
 // metadata that does not match the matrix cannot move an access outside the
 // workspace.
-template <typename T, typename PT>
+template <typename T, typename PT, bool PACK>
 __global__ __launch_bounds__(kReduceBlock) void csc_reduce(
     const PT *__restrict__ prod, const uint16_t *__restrict__ rlo, const int32_t *__restrict__ off,
     const int32_t *__restrict__ pbase, const int32_t *__restrict__ mbase, int32_t nb, int32_t P,
@@ -548,8 +597,16 @@ __global__ __launch_bounds__(kReduceBlock) void csc_reduce(
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t k = i + u * bd;
-      rr[u] = k < i1 ? __builtin_nontemporal_load(rlo + k) : 0u;
-      pv[u] = k < i1 ? static_cast<double>(__builtin_nontemporal_load(prod + k)) : 0.0;
+      if constexpr (PACK) {
+        PT v = PT(0);
+        uint32_t lo = 0u;
+        if (k < i1) rec_load<PT>(reinterpret_cast<const unsigned char *>(prod), k, v, lo);
+        rr[u] = lo;
+        pv[u] = static_cast<double>(v);
+      } else {
+        rr[u] = k < i1 ? __builtin_nontemporal_load(rlo + k) : 0u;
+        pv[u] = k < i1 ? static_cast<double>(__builtin_nontemporal_load(prod + k)) : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)

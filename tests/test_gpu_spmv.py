@@ -172,8 +172,9 @@ def test_dyadic_bit_exact_any_np(fmt):
     x = synth.dyadic(rng, A.n)
     M, v64 = device_mat(A, fmt, pk.F64)
     for np_ in (1, 5, 256, 4096, A.nnz + 7):
-        for res in (0, 1):
-            y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64, tune=pk.Tune(resident=res))
+        for res in (0, 1):  # CSC: the two product layouts
+            t = pk.Tune(pipeline=1 + res) if fmt == "csc" else pk.Tune(resident=res)
+            y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64, tune=t)
             assert np.array_equal(y, ref), (fmt, np_, res)
 
 
@@ -300,8 +301,10 @@ def test_csc_many_buckets_and_pieces(vt):
         M, v64 = device_mat(A, "csc", vt)
         y_in = rng.uniform(-1, 1, A.m)
         for np_ in (5, 4096, 100_000):
-            y, ref, s = _run(A, x, "csc", vt, np_, 0.75, -1.5, y_in, M=M, v64=v64)
-            assert_close(y, ref, s, tol, "%s csc vt%d np%d" % (A.name, vt, np_))
+            for pf in (1, 2):  # product records / value and row-offset arrays
+                y, ref, s = _run(A, x, "csc", vt, np_, 0.75, -1.5, y_in, M=M, v64=v64,
+                                 tune=pk.Tune(pipeline=pf))
+                assert_close(y, ref, s, tol, "%s csc vt%d np%d pf%d" % (A.name, vt, np_, pf))
 
 
 def test_kernel_timing_records_each_launch():
@@ -327,9 +330,9 @@ def test_kernel_timing_records_each_launch():
 
 @pytest.mark.parametrize("vt", [0, 1])
 def test_csc_tall_matrix_uses_wide_buckets(vt):
-    """More than 2^25 rows: CSC row buckets widen to 8192 rows.  A tall
+    """More than 2^25 rows: over 4096 row buckets of 8192 rows.  A tall
     sparse matrix (rows concentrated at both ends and spread in between)
-    checked against the oracle with beta != 0."""
+    checked against the oracle with beta != 0, in both product layouts."""
     rng = np.random.default_rng(13)
     m, n, nnz = (1 << 25) + 4097, 3000, 60_000
     rows = np.concatenate([rng.integers(0, 50_000, nnz // 3), rng.integers(m - 50_000, m, nnz // 3),
@@ -345,8 +348,10 @@ def test_csc_tall_matrix_uses_wide_buckets(vt):
     tol = F64_TOL if vt == 0 else F32_TOL
     M, v64 = device_mat(A, "csc", vt)
     for np_ in (3, 1000):
-        y, ref, s = _run(A, x, "csc", vt, np_, 0.5, 2.0, y_in, M=M, v64=v64)
-        assert_close(y, ref, s, tol, "tall csc vt%d np%d" % (vt, np_))
+        for pf in (1, 2):
+            y, ref, s = _run(A, x, "csc", vt, np_, 0.5, 2.0, y_in, M=M, v64=v64,
+                             tune=pk.Tune(pipeline=pf))
+            assert_close(y, ref, s, tol, "tall csc vt%d np%d pf%d" % (vt, np_, pf))
 
 
 @pytest.mark.parametrize("fmt", FMTS)
