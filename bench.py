@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune every format first")
+    ap.add_argument("--unprepared", action="store_true",
+                    help="time msrep_spmv (structure work in every call) instead of "
+                         "msrep_spmv_prepare once + msrep_spmv_prepared")
     ap.add_argument("--warm", action="store_true",
                     help="also time back-to-back (cache-warm) SpMVs of each format")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -346,8 +349,26 @@ def main():
     ws = {f: torch.zeros(max(256, pk.msrep_spmv_ws_bytes(mats[f], parts[f].np)), dtype=torch.uint8,
                          device=dev) for f in fmts}
 
+    # the structure-only work (CSC: bucket counts, run offsets, pieces) is
+    # done once per matrix and partitioning, like the partition build; the
+    # timed SpMVs reuse it (msrep_spmv_prepared).  --unprepared times plain
+    # msrep_spmv, which redoes it every call.
+    prep_ms = {}
+    for f in fmts:
+        pk.msrep_spmv_prepare(mats[f], parts[f], ws=ws[f])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pk.msrep_spmv_prepare(mats[f], parts[f], ws=ws[f])
+        e1.record()
+        torch.cuda.synchronize()
+        prep_ms[f] = e0.elapsed_time(e1)
+
     def spmv(f):
-        pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tunes[f], ws=ws[f])
+        if args.unprepared:
+            pk.msrep_spmv(mats[f], parts[f], x, ys[f], 1.0, 0.0, tunes[f], ws=ws[f])
+        else:
+            pk.msrep_spmv_prepared(mats[f], parts[f], x, ys[f], ws[f], 1.0, 0.0, tunes[f])
 
     # warmup steps are cold too, so that every launch of a kernel in this run
     # is alike (a profiler's per-kernel average then matches the timed one)
@@ -404,6 +425,8 @@ def main():
                       "gflops_cold": round(2.0 * A.nnz / cold_ms[f] / 1e6, 2),
                       "gbs_cold": round(b / cold_ms[f] / 1e6, 1),
                       "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4),
+                      "prepare_ms": round(prep_ms[f], 4),
+                      "entry": "msrep_spmv" if args.unprepared else "msrep_spmv_prepared",
                       "np": parts[f].np,
                       "tune": {"k_per_lane": tunes[f].k_per_lane or 4,
                                "waves_per_wg": tunes[f].waves_per_wg or 4,

@@ -227,6 +227,32 @@ msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
                         const msrep_tune *tune, void *ws_d, size_t ws_bytes,
                         void *stream);
 
+/*
+ * msrep_spmv in two parts, for a matrix multiplied many times with the same
+ * partitions (an inspector / executor split of Algorithm 5's CSC path).
+ * msrep_spmv_prepare runs the structure-only kernels, which read A's indices
+ * and the partitions but neither x nor the values: for CSC, the count of
+ * every producer's nonzeros per row bucket, their scan into run offsets and
+ * the bucket pieces, written to the front of ws_d; for CSR and COO it does
+ * nothing.  msrep_spmv_prepared then computes y = alpha*A*x + beta*y like
+ * msrep_spmv, using that part of ws_d instead of recomputing it.
+ *   Same arguments, checks and errors as msrep_spmv.  ws_d of
+ *   msrep_spmv_ws_bytes(A, np) bytes must hold what msrep_spmv_prepare wrote
+ *   for the same A structure (m, n, nnz, indices), parts_d and np; calls of
+ *   msrep_spmv_prepared leave it intact, a call of msrep_spmv on the same
+ *   workspace rewrites it the same way.  Preparing once and calling
+ *   msrep_spmv_prepared gives the same y as msrep_spmv up to the order of
+ *   the sums within a CSC bucket.  Both only launch kernels on the stream.
+ */
+msrep_status msrep_spmv_prepare(const msrep_mat *A, const msrep_part *parts_d,
+                                const int32_t *lptr_d, int32_t np, void *ws_d,
+                                size_t ws_bytes, void *stream);
+msrep_status msrep_spmv_prepared(const msrep_mat *A, const msrep_part *parts_d,
+                                 const int32_t *lptr_d, int32_t np, const void *x_d,
+                                 void *y_d, double alpha, double beta,
+                                 const msrep_tune *tune, void *ws_d, size_t ws_bytes,
+                                 void *stream);
+
 /* Launch shape and partition size for A, picked by timing every candidate on
  * the stream and keeping the fastest median of three runs:
  *   nnz_per_wave in {256, 512, 1024, 2048, 4096} (the equal-nnz np follows),

@@ -103,6 +103,9 @@ def load_library():
         "msrep_spmv_ws_bytes": (c_sz, [P(_Mat), c_i32]),
         "msrep_spmv": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_vp, c_dbl, c_dbl, P(_Tune),
                                c_vp, c_sz, c_vp]),
+        "msrep_spmv_prepare": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
+        "msrep_spmv_prepared": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_vp, c_dbl, c_dbl,
+                                        P(_Tune), c_vp, c_sz, c_vp]),
         "msrep_autotune_ws_bytes": (c_sz, [P(_Mat)]),
         "msrep_autotune": (c_i32, [P(_Mat), c_vp, c_vp, c_sz, P(_Tune), c_vp]),
         "msrep_plan_ws_bytes": (c_sz, [c_i32, P(_Mat), P(_Tune)]),
@@ -351,6 +354,36 @@ def msrep_spmv(A: Mat, P: Partition, x, y, alpha=1.0, beta=0.0, tune: Optional[T
     _check(L.msrep_spmv(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(x), _ptr(y),
                         float(alpha), float(beta), ctypes.byref(t) if t is not None else None,
                         _ptr(ws), ws.numel(), _stream(stream)), "spmv")
+    return y
+
+
+def msrep_spmv_prepare(A: Mat, P: Partition, ws=None, stream=None):
+    """The structure-only part of msrep_spmv (CSC: bucket counts, offsets and
+    pieces) into the workspace ws (a new one of its own if None, never the
+    shared cache that msrep_spmv uses); returns ws, to be passed to
+    msrep_spmv_prepared with the same A structure, P and np."""
+    torch = _require_gpu()
+    L = load_library()
+    d = A.desc()
+    need = L.msrep_spmv_ws_bytes(ctypes.byref(d), P.np)
+    if ws is None:
+        ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=P.parts.device)
+    _check(L.msrep_spmv_prepare(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(ws),
+                                ws.numel(), _stream(stream)), "spmv_prepare")
+    return ws
+
+
+def msrep_spmv_prepared(A: Mat, P: Partition, x, y, ws, alpha=1.0, beta=0.0,
+                        tune: Optional[Tune] = None, stream=None):
+    """msrep_spmv with ws prepared by msrep_spmv_prepare(A, P); returns y."""
+    _require_gpu()
+    L = load_library()
+    d = A.desc()
+    t = tune.c() if tune is not None else None
+    _check(L.msrep_spmv_prepared(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(x),
+                                 _ptr(y), float(alpha), float(beta),
+                                 ctypes.byref(t) if t is not None else None, _ptr(ws),
+                                 ws.numel(), _stream(stream)), "spmv_prepared")
     return y
 
 

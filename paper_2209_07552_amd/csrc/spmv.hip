@@ -135,12 +135,44 @@ msrep_status launch_coo(const msrep_mat *A, const msrep_part *parts, int32_t np,
   return MSREP_OK;
 }
 
+constexpr int kPhaseAll = 0, kPhaseStructure = 1, kPhaseNumeric = 2;
+
+// The structure-only kernels of the CSC path: per-bucket counts of every
+// producer, their scan into run offsets, and the bucket pieces.  They depend
+// on A's row indices, the partitions and np, not on x or the values.
+msrep_status csc_structure(const msrep_mat *A, const msrep_part *parts, int32_t np,
+                           const CscLayout &L, char *b, hipStream_t s) {
+  int32_t *cnt = reinterpret_cast<int32_t *>(b + L.cnt);
+  int32_t *agg = reinterpret_cast<int32_t *>(b + L.agg);
+  int32_t *pbase = reinterpret_cast<int32_t *>(b + L.pbase);
+  int32_t *mbase = reinterpret_cast<int32_t *>(b + L.mbase);
+  int32_t *mlist = reinterpret_cast<int32_t *>(b + L.mlist);
+  const size_t cur_lds = align_up(static_cast<size_t>(L.nb) * 4, 16);
+  timing_begin(s);
+  hipLaunchKernelGGL(csc_count, dim3(L.P), dim3(kCscScatterWaves * kWave), cur_lds, s, A->idx,
+                     A->nnz, parts, np, L.P, A->m, L.shift, L.nb, cnt);
+  MSREP_LAUNCHED("csc_count");
+  timing_end("csc_count", s);
+  timing_begin(s);
+  if (msrep_status st = scan::device_scan<int32_t, scan::SumOp>(
+          cnt, cnt, static_cast<int64_t>(L.nb) * L.P + 1, agg, false, s))
+    return st;
+  timing_end("csc_scan", s);
+  timing_begin(s);
+  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kPlanBlock), 0, s, cnt, L.nb, L.P, pbase, mbase,
+                     mlist);
+  MSREP_LAUNCHED("csc_plan");
+  timing_end("csc_plan", s);
+  return MSREP_OK;
+}
+
 // PACK: one record per product (msrep_tune.pipeline == 1), else value and
-// row-offset arrays.
+// row-offset arrays.  phase: kPhaseAll, kPhaseStructure (csc_structure only)
+// or kPhaseNumeric (the workspace already holds csc_structure's output).
 template <int VT, int K, bool PACK>
 msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                         int32_t np, const void *x, void *y, double alpha, double beta, int wpb,
-                        void *ws, hipStream_t s) {
+                        void *ws, int phase, hipStream_t s) {
   using Tr = vt_traits<VT>;
   using T = typename Tr::T;
   using Acc = typename Tr::A;
@@ -149,26 +181,17 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
     return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: CSC supports at most %d rows",
                 kCscMaxBuckets << kCscMaxShift);
   char *b = static_cast<char *>(ws);
+  if (phase != kPhaseNumeric)
+    if (msrep_status st = csc_structure(A, parts, np, L, b, s)) return st;
+  if (phase == kPhaseStructure) return MSREP_OK;
   int32_t *cnt = reinterpret_cast<int32_t *>(b + L.cnt);
-  int32_t *agg = reinterpret_cast<int32_t *>(b + L.agg);
   int32_t *pbase = reinterpret_cast<int32_t *>(b + L.pbase);
   int32_t *mbase = reinterpret_cast<int32_t *>(b + L.mbase);
   int32_t *mlist = reinterpret_cast<int32_t *>(b + L.mlist);
   Acc *prod = reinterpret_cast<Acc *>(b + L.prod);
   uint16_t *rlo = reinterpret_cast<uint16_t *>(b + L.rlo);
   double *part = reinterpret_cast<double *>(b + L.part);
-  const size_t cur_lds = align_up(static_cast<size_t>(L.nb) * 4, 16);
-  timing_begin(s);
-  hipLaunchKernelGGL(csc_count, dim3(L.P), dim3(kCscScatterWaves * kWave), cur_lds, s, A->idx, A->nnz, parts, np,
-                     L.P, A->m, L.shift, L.nb, cnt);
-  MSREP_LAUNCHED("csc_count");
-  timing_end("csc_count", s);
-  timing_begin(s);
-  if (msrep_status st = scan::device_scan<int32_t, scan::SumOp>(
-          cnt, cnt, static_cast<int64_t>(L.nb) * L.P + 1, agg, false, s))
-    return st;
-  timing_end("csc_scan", s);
-  (void)wpb;  // the scatter always runs one 16-wavefront producer per CU
+  (void)wpb;  // the scatter always runs 16-wavefront producers
   timing_begin(s);
   hipLaunchKernelGGL((csc_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
                      csc_scatter_lds<K>(L.nb), s, A->idx,
@@ -176,11 +199,6 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
                      static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
   MSREP_LAUNCHED("csc_scatter");
   timing_end("csc_scatter", s);
-  timing_begin(s);
-  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kPlanBlock), 0, s, cnt, L.nb, L.P, pbase, mbase,
-                     mlist);
-  MSREP_LAUNCHED("csc_plan");
-  timing_end("csc_plan", s);
   timing_begin(s);
   hipLaunchKernelGGL((csc_reduce<T, Acc, PACK>), dim3(static_cast<uint32_t>(L.max_pieces)),
                      dim3(kReduceBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
@@ -215,17 +233,18 @@ msrep_status dispatch_rows(const msrep_mat *A, const msrep_part *parts, const in
 template <int VT>
 msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
-                         int wpb, int pf, int resident, double *carry, hipStream_t s) {
+                         int wpb, int pf, int resident, double *carry, int phase, hipStream_t s) {
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
   if (A->fmt == MSREP_CSC) {  // carry is the whole workspace here
     if (pf == 1)
-      return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
-                    : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
-    return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s)
-                  : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, s);
+      return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s)
+                    : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s);
+    return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s)
+                  : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s);
   }
+  if (phase == kPhaseStructure) return MSREP_OK;  // CSR, COO: no structure-only work
   if (K == 8)
     st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s)
             : dispatch_rows<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s);
@@ -272,17 +291,25 @@ msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, int
   return MSREP_OK;
 }
 
+msrep_status spmv_launch_phase(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                               int32_t np, const void *x, void *y, double alpha, double beta,
+                               int K, int wpb, int pf, int resident, double *carry, int phase,
+                               hipStream_t s) {
+  switch (A->vtype) {
+    case MSREP_F64:
+      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, phase, s);
+    case MSREP_F32:
+      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, phase, s);
+    default:
+      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, phase, s);
+  }
+}
+
 msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                          int32_t np, const void *x, void *y, double alpha, double beta, int K,
                          int wpb, int pf, int resident, double *carry, hipStream_t s) {
-  switch (A->vtype) {
-    case MSREP_F64:
-      return dispatch_vt<MSREP_F64>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, s);
-    case MSREP_F32:
-      return dispatch_vt<MSREP_F32>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, s);
-    default:
-      return dispatch_vt<MSREP_BF16>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry, s);
-  }
+  return spmv_launch_phase(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, resident, carry,
+                           kPhaseAll, s);
 }
 
 }  // namespace msrep
@@ -312,37 +339,70 @@ extern "C" size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np) {
   return spmv_ws_bytes(A->fmt, A->vtype, A->m, A->nnz, np);
 }
 
-extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
-                                   const int32_t *lptr_d, int32_t np, const void *x_d, void *y_d,
-                                   double alpha, double beta, const msrep_tune *tune, void *ws_d,
-                                   size_t ws_bytes, void *stream) {
-  if (msrep_status st = check_mat(A, "msrep_spmv")) return st;
-  if (np <= 0) return fail(MSREP_ERR_ARG, "msrep_spmv: np must be positive (got %d)", np);
-  if (!parts_d) return fail(MSREP_ERR_ARG, "msrep_spmv: parts_d is NULL");
-  if (A->fmt != MSREP_COO && !lptr_d) return fail(MSREP_ERR_ARG, "msrep_spmv: lptr_d is NULL");
-  if (A->m > 0 && !y_d) return fail(MSREP_ERR_ARG, "msrep_spmv: y_d is NULL");
-  if (A->nnz > 0 && !x_d) return fail(MSREP_ERR_ARG, "msrep_spmv: x_d is NULL");
+namespace {
+
+// msrep_spmv and its prepare / prepared split: the same checks, then the
+// kernels of `phase`.
+msrep_status spmv_entry(const msrep_mat *A, const msrep_part *parts_d, const int32_t *lptr_d,
+                        int32_t np, const void *x_d, void *y_d, double alpha, double beta,
+                        const msrep_tune *tune, void *ws_d, size_t ws_bytes, void *stream,
+                        int phase, const char *who) {
+  if (msrep_status st = check_mat(A, who)) return st;
+  if (np <= 0) return fail(MSREP_ERR_ARG, "%s: np must be positive (got %d)", who, np);
+  if (!parts_d) return fail(MSREP_ERR_ARG, "%s: parts_d is NULL", who);
+  if (A->fmt != MSREP_COO && !lptr_d) return fail(MSREP_ERR_ARG, "%s: lptr_d is NULL", who);
+  if (phase != kPhaseStructure) {
+    if (A->m > 0 && !y_d) return fail(MSREP_ERR_ARG, "%s: y_d is NULL", who);
+    if (A->nnz > 0 && !x_d) return fail(MSREP_ERR_ARG, "%s: x_d is NULL", who);
+  }
   int K, wpb, pf, resident;
-  if (msrep_status st = resolve_tune(tune, &K, &wpb, &pf, &resident, "msrep_spmv")) return st;
+  if (msrep_status st = resolve_tune(tune, &K, &wpb, &pf, &resident, who)) return st;
   // x, y and the local pointers are addressed through 32-bit buffer offsets
   const uint64_t xb = static_cast<uint64_t>(A->n) * vec_bytes(A->vtype);
   const uint64_t yb = static_cast<uint64_t>(A->m) * vec_bytes(A->vtype);
   if (xb >= (uint64_t(1) << 32) || yb >= (uint64_t(1) << 32) ||
       (static_cast<uint64_t>(major_dim(A)) + 1) * 4 >= (uint64_t(1) << 32))
-    return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: x or y larger than 4 GiB");
+    return fail(MSREP_ERR_UNSUPPORTED, "%s: x or y larger than 4 GiB", who);
   if (A->fmt == MSREP_CSC) {
     CscLayout L;
     if (!csc_layout(A->m, A->nnz, np, 8, L))
-      return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: CSC supports at most %d rows",
+      return fail(MSREP_ERR_UNSUPPORTED, "%s: CSC supports at most %d rows", who,
                   kCscMaxBuckets << kCscMaxShift);
   }
   const size_t need = msrep_spmv_ws_bytes(A, np);
   if (!ws_d || ws_bytes < need)
-    return fail(MSREP_ERR_SIZE, "msrep_spmv: workspace of %zu bytes needed (got %zu)", need,
+    return fail(MSREP_ERR_SIZE, "%s: workspace of %zu bytes needed (got %zu)", who, need,
                 ws_d ? ws_bytes : size_t(0));
   if (A->m == 0) return ok();
-  if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb, pf, resident,
-                                    static_cast<double *>(ws_d), as_stream(stream)))
+  if (msrep_status st = spmv_launch_phase(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, K, wpb,
+                                          pf, resident, static_cast<double *>(ws_d), phase,
+                                          as_stream(stream)))
     return st;
   return ok();
+}
+
+}  // namespace
+
+extern "C" msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
+                                   const int32_t *lptr_d, int32_t np, const void *x_d, void *y_d,
+                                   double alpha, double beta, const msrep_tune *tune, void *ws_d,
+                                   size_t ws_bytes, void *stream) {
+  return spmv_entry(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, tune, ws_d, ws_bytes, stream,
+                    kPhaseAll, "msrep_spmv");
+}
+
+extern "C" msrep_status msrep_spmv_prepare(const msrep_mat *A, const msrep_part *parts_d,
+                                           const int32_t *lptr_d, int32_t np, void *ws_d,
+                                           size_t ws_bytes, void *stream) {
+  return spmv_entry(A, parts_d, lptr_d, np, nullptr, nullptr, 1.0, 0.0, nullptr, ws_d, ws_bytes,
+                    stream, kPhaseStructure, "msrep_spmv_prepare");
+}
+
+extern "C" msrep_status msrep_spmv_prepared(const msrep_mat *A, const msrep_part *parts_d,
+                                            const int32_t *lptr_d, int32_t np, const void *x_d,
+                                            void *y_d, double alpha, double beta,
+                                            const msrep_tune *tune, void *ws_d, size_t ws_bytes,
+                                            void *stream) {
+  return spmv_entry(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, tune, ws_d, ws_bytes, stream,
+                    kPhaseNumeric, "msrep_spmv_prepared");
 }

@@ -87,14 +87,33 @@ def test_spmv_argument_errors():
     assert L.msrep_spmv_ws_bytes(ctypes.byref(dc), 8) >= 8 * 1000
 
 
+def test_spmv_prepare_argument_errors():
+    """The prepare / prepared split checks its arguments like msrep_spmv,
+    before any launch."""
+    L = _lib()
+    for fmt in (0, 1, 2):
+        d = _desc(fmt=fmt, idx2=0x2800 if fmt == 2 else None)
+        st = L.msrep_spmv_prepare(ctypes.byref(d), 0x4000, 0x5000, 8, 0x8000, 16, None)
+        assert st == -3 and b"msrep_spmv_prepare" in L.msrep_last_error()
+        st = L.msrep_spmv_prepare(ctypes.byref(d), 0x4000, 0x5000, 0, 0x8000, 1 << 20, None)
+        assert st == -1
+        st = L.msrep_spmv_prepared(ctypes.byref(d), 0x4000, 0x5000, 8, None, 0x7000, 1.0, 0.0,
+                                   None, 0x8000, 1 << 20, None)
+        assert st == -1 and b"x_d" in L.msrep_last_error()
+        st = L.msrep_spmv_prepared(ctypes.byref(d), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0,
+                                   None, 0x8000, 16, None)
+        assert st == -3 and b"msrep_spmv_prepared" in L.msrep_last_error()
+
+
 def test_csc_workspace_and_row_limit():
-    """The CSC path keeps one product and a 16-bit row offset per nonzero in
-    its workspace; its row buckets cap m at 2^26 (UNSUPPORTED beyond)."""
+    """The CSC path keeps one product and its row offset per nonzero in its
+    workspace (room for the 12-byte FP64 / 8-byte FP32 records); its row
+    buckets cap m at 2^26 (UNSUPPORTED beyond)."""
     L = _lib()
     d = _desc(fmt=1, m=1 << 20, n=1 << 20, nnz=1 << 24)
-    assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 16384) >= 10 * (1 << 24)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 16384) >= 12 * (1 << 24)
     d32 = _desc(fmt=1, vtype=1, m=1 << 20, n=1 << 20, nnz=1 << 24)
-    assert L.msrep_spmv_ws_bytes(ctypes.byref(d32), 16384) >= 6 * (1 << 24)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(d32), 16384) >= 8 * (1 << 24)
     big = _desc(fmt=1, m=(1 << 26) + 1, n=4, nnz=4)
     assert L.msrep_spmv_ws_bytes(ctypes.byref(big), 8) == 0
     st = L.msrep_spmv(ctypes.byref(big), 0x4000, 0x5000, 8, 0x6000, 0x7000, 1.0, 0.0, None,

@@ -241,6 +241,42 @@ def test_runs_of_empty_rows_and_columns(fmt, vt):
             assert_close(y, ref, s, tol, "empty-runs %s vt%d np%d b%g" % (fmt, vt, np_, beta))
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("vt", [0, 1])
+def test_prepared_spmv_repeats_with_fresh_x(fmt, vt):
+    """msrep_spmv_prepare once, then msrep_spmv_prepared with fresh x, alpha
+    and beta (CSC in both product layouts), with plain msrep_spmv calls on
+    another matrix in between: every result matches the oracle."""
+    A, _ = synth.rmat_csr(scale=14, edge_factor=16, seed=12)
+    B, xb = synth.uniform_csr(3000, 3000, 9, seed=2)
+    tol = F64_TOL if vt == 0 else F32_TOL
+    xdt = np.float64 if vt == 0 else np.float32
+    tdt = torch.float64 if vt == 0 else torch.float32
+    M, v64 = device_mat(A, fmt, vt)
+    MB, _ = device_mat(B, fmt, vt)
+    rng = np.random.default_rng(21)
+    for np_ in (7, 2048):
+        P = pk.msrep_build_partition(M, np_)
+        PB = pk.msrep_build_partition(MB, 33)
+        ws = pk.msrep_spmv_prepare(M, P)
+        for it in range(4):
+            x = rng.uniform(-1, 1, A.n).astype(xdt)
+            y_in = rng.uniform(-1, 1, A.m).astype(xdt)
+            alpha, beta = (1.0, 0.0) if it % 2 == 0 else (-2.0, 0.25)
+            xd = torch.from_numpy(x).to(_dev())
+            yd = torch.from_numpy(y_in.copy()).to(_dev())
+            tune = pk.Tune(pipeline=1 + it % 2) if fmt == "csc" else None
+            pk.msrep_spmv_prepared(M, P, xd, yd, ws, alpha, beta, tune)
+            # an unprepared SpMV of another matrix on the shared workspace
+            yb = torch.zeros(B.m, dtype=tdt, device=_dev())
+            pk.msrep_spmv(MB, PB, torch.from_numpy(xb.astype(xdt)).to(_dev()), yb)
+            torch.cuda.synchronize()
+            yi = None if beta == 0.0 else y_in.astype(np.float64)
+            ref, sc = oracle_y(A, fmt, v64, x.astype(np.float64), alpha, beta, yi)
+            assert_close(yd.cpu().numpy().astype(np.float64), ref, sc, tol,
+                          "prepared %s vt%d np%d it%d" % (fmt, vt, np_, it))
+
+
 @pytest.mark.parametrize("fmt", ["csr", "coo"])
 def test_deterministic(fmt):
     A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=5)
