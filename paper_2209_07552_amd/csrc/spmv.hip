@@ -159,8 +159,8 @@ msrep_status csc_structure(const msrep_mat *A, const msrep_part *parts, int32_t 
     return st;
   timing_end("csc_scan", s);
   timing_begin(s);
-  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kPlanBlock), 0, s, cnt, L.nb, L.P, pbase, mbase,
-                     mlist);
+  hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kPlanBlock), 0, s, cnt, L.nb, L.P, L.piece, pbase,
+                     mbase, mlist);
   MSREP_LAUNCHED("csc_plan");
   timing_end("csc_plan", s);
   return MSREP_OK;
@@ -202,14 +202,14 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   timing_begin(s);
   hipLaunchKernelGGL((csc_reduce<T, Acc, PACK>), dim3(static_cast<uint32_t>(L.max_pieces)),
                      dim3(kReduceBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
-                     L.nb, L.P, L.shift, A->m, A->nnz, L.max_slots, part, static_cast<T *>(y),
+                     L.nb, L.P, L.shift, A->m, A->nnz, L.piece, L.max_slots, part, static_cast<T *>(y),
                      alpha, beta);
   MSREP_LAUNCHED("csc_reduce");
   timing_end("csc_reduce", s);
   timing_begin(s);
   {
-    // buckets of several pieces hold more than kCscPiece products each
-    const int64_t most = std::min<int64_t>(L.nb, A->nnz / kCscPiece + 1);
+    // buckets of several pieces hold more than L.piece products each
+    const int64_t most = std::min<int64_t>(L.nb, A->nnz / L.piece + 1);
     const int64_t blocks = std::min<int64_t>(most * ((1 << L.shift) / kCscBlock), 2048);
     hipLaunchKernelGGL((csc_merge<T>), dim3(static_cast<uint32_t>(blocks > 0 ? blocks : 1)),
                        dim3(kCscBlock), 0, s, pbase, mbase, mlist, L.nb, L.shift, A->m,

@@ -15,7 +15,7 @@
 //   csc_scatter  the producer's wavefronts walk its partitions, form the
 //                products val*x[col] and write them, with the row's low
 //                bits, into the producer's run of each bucket;
-//   csc_plan     each bucket is cut into pieces of at most kCscPiece items;
+//   csc_plan     each bucket is cut into pieces of at most L.piece items;
 //   csc_reduce   one workgroup per piece adds its products into an LDS row
 //                array; a bucket of one piece writes y = alpha*sum + beta*y
 //                directly, a bucket of several stores the arrays;
@@ -39,7 +39,12 @@ constexpr int32_t kCscMaxBuckets = 8192;      // LDS cursors of one producer
 constexpr int32_t kCscMaxProducers = 512;
 constexpr int kCscScatterWaves = 16;
 constexpr int64_t kCscMaxCounters = int64_t(1) << 22;
-constexpr int64_t kCscPiece = 65536;          // products summed by one workgroup (8 per row)
+// Products summed by one workgroup: 65536 (8 per row of a bucket), or 32768
+// for matrices under 2^25 nonzeros, whose few pieces otherwise leave CUs
+// idle while the largest buckets' pieces finish.
+constexpr int64_t kCscPiece = 65536;
+constexpr int64_t kCscPieceSmall = 32768;
+constexpr int64_t kCscSmallNnz = int64_t(1) << 25;
 constexpr int kCscBlock = 256;                // merge blocks
 constexpr int kReduceBlock = 1024;            // reduce: 64 KB of LDS rows per block
 constexpr int kUnroll = 8;                    // loads in flight per thread
@@ -49,6 +54,7 @@ struct CscLayout {
   int shift = 0;
   int32_t nb = 0, P = 0;
   int64_t max_pieces = 0, max_slots = 0;
+  int64_t piece = 0;  // products per piece
   size_t cnt = 0, agg = 0, pbase = 0, mbase = 0, mlist = 0, prod = 0, rlo = 0, part = 0, total = 0;
 };
 
@@ -66,8 +72,9 @@ inline bool csc_layout(int32_t m, int64_t nnz, int32_t np, int prod_bytes, CscLa
                             kCscMaxCounters / nb})));
   // sum over buckets of max(1, ceil(c/S)) < nb + nnz/S; buckets of several
   // pieces hold fewer than 2*nnz/S pieces in all
-  L.max_pieces = nb + nnz / kCscPiece + 1;
-  L.max_slots = 2 * (nnz / kCscPiece) + 1;
+  L.piece = nnz < kCscSmallNnz ? kCscPieceSmall : kCscPiece;
+  L.max_pieces = nb + nnz / L.piece + 1;
+  L.max_slots = 2 * (nnz / L.piece) + 1;
   const int64_t ncnt = nb * L.P + 1;
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -516,7 +523,8 @@ __device__ __forceinline__ int32_t plan_exscan(int32_t v, int32_t &excl, int32_t
 // number in mlist[nb].  One block of kPlanBlock threads, each taking a run
 // of consecutive buckets.
 __global__ __launch_bounds__(kPlanBlock) void csc_plan(const int32_t *__restrict__ off, int32_t nb,
-                                                       int32_t P, int32_t *__restrict__ pbase,
+                                                       int32_t P, int64_t piece,
+                                                       int32_t *__restrict__ pbase,
                                                        int32_t *__restrict__ mbase,
                                                        int32_t *__restrict__ mlist) {
   __shared__ int32_t sh[kPlanBlock / kWave];
@@ -526,7 +534,7 @@ __global__ __launch_bounds__(kPlanBlock) void csc_plan(const int32_t *__restrict
   auto pieces = [&](int32_t t) {
     const int64_t c = static_cast<int64_t>(off[static_cast<int64_t>(t + 1) * P]) -
                       off[static_cast<int64_t>(t) * P];
-    return c > 0 ? static_cast<int32_t>((c + kCscPiece - 1) / kCscPiece) : 1;
+    return c > 0 ? static_cast<int32_t>((c + piece - 1) / piece) : 1;
   };
   int32_t sp = 0, sm = 0, sn = 0;
   for (int32_t t = t0; t < t1; ++t) {
@@ -564,7 +572,7 @@ template <typename T, typename PT, bool PACK>
 __global__ __launch_bounds__(kReduceBlock) void csc_reduce(
     const PT *__restrict__ prod, const uint16_t *__restrict__ rlo, const int32_t *__restrict__ off,
     const int32_t *__restrict__ pbase, const int32_t *__restrict__ mbase, int32_t nb, int32_t P,
-    int shift, int32_t m, int64_t nnz, int64_t max_slots, double *__restrict__ part,
+    int shift, int32_t m, int64_t nnz, int64_t piece, int64_t max_slots, double *__restrict__ part,
     T *__restrict__ y, double alpha, double beta) {
   extern __shared__ double acc[];
   const int32_t g = blockIdx.x;
@@ -581,8 +589,8 @@ __global__ __launch_bounds__(kReduceBlock) void csc_reduce(
   int64_t b0 = off[static_cast<int64_t>(t) * P], b1 = off[static_cast<int64_t>(t + 1) * P];
   b0 = b0 < 0 ? 0 : (b0 > nnz ? nnz : b0);
   b1 = b1 < b0 ? b0 : (b1 > nnz ? nnz : b1);
-  const int64_t i0 = b0 + static_cast<int64_t>(j) * kCscPiece;
-  const int64_t i1 = i0 + kCscPiece < b1 ? i0 + kCscPiece : b1;
+  const int64_t i0 = b0 + static_cast<int64_t>(j) * piece;
+  const int64_t i1 = i0 + piece < b1 ? i0 + piece : b1;
   const int32_t span = 1 << shift;
   const uint32_t mask = static_cast<uint32_t>(span) - 1u;
   const int32_t r0 = t << shift;
