@@ -237,24 +237,18 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_count(
   if (p == 0 && threadIdx.x == 0) cnt[static_cast<int64_t>(nb) * P] = 0;
 }
 
-constexpr int kLpBatches = 4;  // local column pointer words read ahead: 4*64 columns
+// Local column pointer words read one chunk ahead: one 16-byte load per lane,
+// 256 consecutive columns (see lp_round_load).
+constexpr int kLpAhead = 4;
 
-// The local column pointer words lp[j] of columns j = jb + u*64 + lane,
-// u < kLpBatches, through a resource covering lp[0..R] (0 outside; the
-// caller masks j > R).
-__device__ __forceinline__ void lp_words(rsrc_t rl, int32_t jb, int32_t R,
-                                         int32_t (&av)[kLpBatches]) {
-#pragma unroll
-  for (int u = 0; u < kLpBatches; ++u) {
-    const int32_t j = jb + u * kWave + lane_id();
-    av[u] = buf_load<int32_t>(rl, j >= 0 && j <= R ? static_cast<uint32_t>(j) * 4u : ~0u);
-  }
+__device__ __forceinline__ void lp_words(rsrc_t rl, int32_t jb, int32_t (&av)[kLpAhead]) {
+  lp_round_load<1>(rl, jb, av);
 }
 
 // The column of every position of a loaded chunk.  Columns that start inside
 // the chunk mark their first position in the wave's LDS array (the local
 // column pointer lp from j0, the column holding the chunk's first position:
-// the kLpBatches*64 words read ahead in av0, then kLpWide words per round);
+// the 256 words read ahead in av0, then kLpWide words per round);
 // a max-scan (DPP) carries the index forward.  ok: a position of the
 // partition whose row lies in [0, m).  j0 advances to the column holding the
 // next chunk's first position, taken from the lane that read the first
@@ -262,7 +256,7 @@ __device__ __forceinline__ void lp_words(rsrc_t rl, int32_t jb, int32_t R,
 template <int K>
 __device__ __forceinline__ void csc_columns(int32_t nloc, int32_t cb, int32_t c0, int32_t R,
                                             rsrc_t rl, int32_t m, int32_t *s_col, int32_t &j0,
-                                            const int32_t (&av0)[kLpBatches],
+                                            const int32_t (&av0)[kLpAhead],
                                             const int32_t (&rows)[K], int32_t (&col)[K],
                                             bool (&ok)[K]) {
   constexpr int CH = kWave * K;
@@ -272,44 +266,28 @@ __device__ __forceinline__ void csc_columns(int32_t nloc, int32_t cb, int32_t c0
 #pragma unroll
   for (int t = 0; t < K; ++t) s_col[lane * K + t] = -1;
   wave_lds_sync();
-  // first the kLpBatches*64 words read ahead, 64 columns at a time
-  int32_t jb = j0, cnt = kWave, a = 0;
-#pragma unroll
-  for (int u = 0; u < kLpBatches; ++u) {
-    if (cnt < kWave) break;
-    if (u > 0) jb += kWave;
-    const int32_t j = jb + lane;
-    a = (j >= 0 && j <= R) ? av0[u] : 0x7fffffff;
-    const bool in = j <= R - 1 && a < ce;
+  // first the 256 words read ahead, then wide rounds
+  auto mark = [&](int32_t j, int32_t aw, bool in) {
     if (in && j > j0) {
-      const int32_t pos = a - cb;
+      const int32_t pos = aw - cb;
       if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);  // the non-empty column wins
     }
-    cnt = __popcll(__ballot(in));
-  }
-  int32_t j1, nxt;
-  if (cnt < kWave) {
-    j1 = jb + cnt - 1;
-    // lp[j1 + 1]: where the first column starting past the chunk starts (or
-    // past-the-end), from the lane that loaded it
-    nxt = __builtin_amdgcn_readlane(a, cnt);
-  } else {
+  };
+  int32_t w0[kLpAhead];
+#pragma unroll
+  for (int i = 0; i < kLpAhead; ++i) w0[i] = av0[i];
+  int32_t jb = j0, nxt = 0;
+  int32_t tot = lp_round_scan<1>(w0, jb, R, ce, nxt, mark);
+  if (tot == 4 * kWave) {
     // sparse region (runs of empty columns): wide rounds
-    jb += kWave;
+    jb += 4 * kWave;
     for (;;) {
-      const int32_t tot = lp_wide_round(rl, jb, R, ce, nxt, [&](int32_t j, int32_t aw, bool in) {
-        if (in && j > j0) {
-          const int32_t pos = aw - cb;
-          if (pos >= 0 && pos < CH) atomicMax(&s_col[pos], j);
-        }
-      });
-      if (tot < kLpWide) {
-        j1 = jb + tot - 1;
-        break;
-      }
+      tot = lp_wide_round(rl, jb, R, ce, nxt, mark);
+      if (tot < kLpWide) break;
       jb += kLpWide;
     }
   }
+  const int32_t j1 = jb + tot - 1;
   wave_lds_sync();
   int32_t cj[K];
   int32_t mx = j0;
@@ -414,11 +392,11 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   int64_t pi = first_nonempty(pa + wid, cp);
   int64_t pn = pi < pb ? first_nonempty(pi + wpb, np_meta) : pb;  // the next partition
   int32_t cb = pi < pb ? -static_cast<int32_t>(cp.s0 % K) : 0, j0 = 0;
-  int32_t rows[K], av[kLpBatches];
+  int32_t rows[K], av[kLpAhead];
   V v[K];
   rsrc_t rl = lp_rsrc(cp, pi < pb);
   load_items<V, K>(row_idx, val, cp.s0, cb, pi < pb ? cp.nloc : cb, rows, v);
-  lp_words(rl, 0, pi < pb ? cp.R : -1, av);
+  lp_words(rl, 0, av);
   // the previous chunk's products, positions and row bits (none yet: spare)
   Acc pr_p[K];
   int32_t at_p[K], lo_p[K];
@@ -460,10 +438,10 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
     const int32_t cb_n = same ? cb + CH : -static_cast<int32_t>(np_meta.s0 % K);
     const int32_t j0_n = same ? j0 : 0;
     const rsrc_t rl_n = lp_rsrc(cq, more);
-    int32_t rows_n[K], av_n[kLpBatches];
+    int32_t rows_n[K], av_n[kLpAhead];
     V v_n[K];
     load_items<V, K>(row_idx, val, cq.s0, cb_n, more ? cq.nloc : cb_n, rows_n, v_n);
-    lp_words(rl_n, j0_n, more ? cq.R : -1, av_n);
+    lp_words(rl_n, j0_n, av_n);
     // ---- products and their positions in the buckets' runs
 #pragma unroll
     for (int t = 0; t < K; ++t) {
@@ -492,7 +470,7 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
       v[t] = v_n[t];
     }
 #pragma unroll
-    for (int u = 0; u < kLpBatches; ++u) av[u] = av_n[u];
+    for (int u = 0; u < kLpAhead; ++u) av[u] = av_n[u];
   }
   store_prev();
 }

@@ -129,13 +129,13 @@ constexpr int kShortRow = 32;
 constexpr int kLpWideLoads = 2;
 constexpr int kLpWide = kLpWideLoads * 4 * kWave;
 
-template <typename F>
-__device__ __forceinline__ int32_t lp_wide_round(rsrc_t rl, int32_t jb, int32_t R, int32_t ce,
-                                                 int32_t &nxt, F &&visit) {
+// The words of a round of L 16-byte loads per lane from jb (lane L holds
+// jb + 256*i + 4*L + e).
+template <int L>
+__device__ __forceinline__ void lp_round_load(rsrc_t rl, int32_t jb, int32_t (&w)[4 * L]) {
   const int lane = lane_id();
-  int32_t w[kLpWide / kWave];
 #pragma unroll
-  for (int i = 0; i < kLpWideLoads; ++i) {
+  for (int i = 0; i < L; ++i) {
     const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(
         rl, static_cast<uint32_t>(jb + i * 4 * kWave + 4 * lane) * 4u, 0, 0);
     w[4 * i] = static_cast<int32_t>(q.x);
@@ -143,9 +143,16 @@ __device__ __forceinline__ int32_t lp_wide_round(rsrc_t rl, int32_t jb, int32_t 
     w[4 * i + 2] = static_cast<int32_t>(q.z);
     w[4 * i + 3] = static_cast<int32_t>(q.w);
   }
+}
+
+// Scan of a loaded round (see lp_wide_round).
+template <int L, typename F>
+__device__ __forceinline__ int32_t lp_round_scan(int32_t (&w)[4 * L], int32_t jb, int32_t R,
+                                                 int32_t ce, int32_t &nxt, F &&visit) {
+  const int lane = lane_id();
   int32_t tot = 0;
 #pragma unroll
-  for (int i = 0; i < kLpWideLoads; ++i) {
+  for (int i = 0; i < L; ++i) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int32_t j = jb + i * 4 * kWave + 4 * lane + e;
@@ -156,18 +163,26 @@ __device__ __forceinline__ int32_t lp_wide_round(rsrc_t rl, int32_t jb, int32_t 
       tot += __popcll(__ballot(in));
     }
   }
-  if (tot < kLpWide) {
+  if (tot < L * 4 * kWave) {
     // the word of row jb + tot: load tot / 256, lane (tot % 256) / 4, element tot % 4
     const int i_sel = tot / (4 * kWave), e_sel = tot % 4;
     int32_t pick = 0;
 #pragma unroll
-    for (int i = 0; i < kLpWideLoads; ++i)
+    for (int i = 0; i < L; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (i == i_sel && e == e_sel) pick = w[4 * i + e];
     nxt = __builtin_amdgcn_readlane(pick, (tot % (4 * kWave)) / 4);
   }
   return tot;
+}
+
+template <typename F>
+__device__ __forceinline__ int32_t lp_wide_round(rsrc_t rl, int32_t jb, int32_t R, int32_t ce,
+                                                 int32_t &nxt, F &&visit) {
+  int32_t w[4 * kLpWideLoads];
+  lp_round_load<kLpWideLoads>(rl, jb, w);
+  return lp_round_scan<kLpWideLoads>(w, jb, R, ce, nxt, static_cast<F &&>(visit));
 }
 
 // Rows handled per round of the loops over many rows of one chunk (loads in
