@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # on MI355X (nnz_per_wave, k_per_lane, waves_per_wg, pipeline, resident).
 DEFAULT_TUNES = {
     "rmat20": {"csr": (512, 4, 8, 2, 1), "coo": (512, 4, 8, 2, 1), "csc": (1024, 4, 2, 1, 0)},
-    "stencil256": {"csr": (2048, 4, 4, 2, 0), "coo": (512, 4, 4, 2, 0),
+    "stencil256": {"csr": (2048, 4, 4, 2, 0), "coo": (1024, 4, 2, 2, 0),
                    "csc": (1024, 4, 2, 2, 0)},
 }
 SCRUB_BYTES = 512 << 20
