@@ -177,16 +177,18 @@ __device__ __forceinline__ int32_t lp_round_scan(int32_t (&w)[4 * L], int32_t jb
   return tot;
 }
 
-template <typename F>
+template <int L = kLpWideLoads, typename F>
 __device__ __forceinline__ int32_t lp_wide_round(rsrc_t rl, int32_t jb, int32_t R, int32_t ce,
                                                  int32_t &nxt, F &&visit) {
-  int32_t w[4 * kLpWideLoads];
-  lp_round_load<kLpWideLoads>(rl, jb, w);
-  return lp_round_scan<kLpWideLoads>(w, jb, R, ce, nxt, static_cast<F &&>(visit));
+  int32_t w[4 * L];
+  lp_round_load<L>(rl, jb, w);
+  return lp_round_scan<L>(w, jb, R, ce, nxt, static_cast<F &&>(visit));
 }
 
 // Rows handled per round of the loops over many rows of one chunk (loads in
-// flight per lane).
+// flight per lane).  The register-lean CSR variant (one chunk loaded ahead,
+// also the batched kernel's) takes one batch and one-load rounds, keeping
+// its occupancy.
 constexpr int kRowBatch = 4;
 
 // Per-wave LDS footprint of the CSR/COO kernels.
@@ -226,6 +228,8 @@ __device__ __forceinline__ void csr_partition(
   using T = typename Tr::T;
   using Acc = typename Tr::A;
   constexpr int CH = kWave * K;
+  constexpr int RB = PF == 2 ? kRowBatch : 1;      // see kRowBatch
+  constexpr int WL = PF == 2 ? kLpWideLoads : 1;
   const int lane = lane_id();
   Acc *s_sum = reinterpret_cast<Acc *>(my);
   unsigned char *s_head = my + align_up(CH * sizeof(Acc), 16);
@@ -297,9 +301,9 @@ __device__ __forceinline__ void csr_partition(
       // rounds from the next batch on
       jb += kWave;
       for (;;) {
-        cnt = lp_wide_round(rl, jb, R, ce, lp_next, [](int32_t, int32_t, bool) {});
-        if (cnt < kLpWide) break;
-        jb += kLpWide;
+        cnt = lp_wide_round<WL>(rl, jb, R, ce, lp_next, [](int32_t, int32_t, bool) {});
+        if (cnt < WL * 4 * kWave) break;
+        jb += WL * 4 * kWave;
       }
     }
     const int32_t j1 = jb + cnt - 1;  // last row starting before ce
@@ -361,13 +365,13 @@ __device__ __forceinline__ void csr_partition(
 #pragma unroll
       for (int w = 0; w < K / 4; ++w) reinterpret_cast<uint32_t *>(s_head)[lane * (K / 4) + w] = 0u;
       wave_lds_sync();
-      for (int32_t jr = j0; jr <= j1; jr += kRowBatch * kWave) {
-        int32_t v[kRowBatch];
+      for (int32_t jr = j0; jr <= j1; jr += RB * kWave) {
+        int32_t v[RB];
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u)
+        for (int u = 0; u < RB; ++u)
           v[u] = buf_load<int32_t>(rl, static_cast<uint32_t>(jr + u * kWave + lane) * 4u);
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) {
+        for (int u = 0; u < RB; ++u) {
           const int32_t j = jr + u * kWave + lane;
           const int32_t pos = v[u] - cb;
           if (j > j0 && j <= j1 && pos > 0 && pos < CH) s_head[pos] = 1;
@@ -409,16 +413,16 @@ __device__ __forceinline__ void csr_partition(
       if (one_batch) {
         if (jl <= j1) finish_row(jl, scanned(lpv0, bl));
       } else {
-        for (int32_t jr = j0; jr <= j1; jr += kRowBatch * kWave) {
-          int32_t a[kRowBatch], b[kRowBatch];
+        for (int32_t jr = j0; jr <= j1; jr += RB * kWave) {
+          int32_t a[RB], b[RB];
 #pragma unroll
-          for (int u = 0; u < kRowBatch; ++u) {
+          for (int u = 0; u < RB; ++u) {
             const uint32_t j = static_cast<uint32_t>(jr + u * kWave + lane);
             a[u] = buf_load<int32_t>(rl, j * 4u);
             b[u] = buf_load<int32_t>(rl, (j + 1u) * 4u);
           }
 #pragma unroll
-          for (int u = 0; u < kRowBatch; ++u) {
+          for (int u = 0; u < RB; ++u) {
             const int32_t j = jr + u * kWave + lane;
             if (j >= 0 && j <= j1) finish_row(j, scanned(a[u], b[u]));
           }
