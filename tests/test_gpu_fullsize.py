@@ -59,3 +59,76 @@ def test_full_size_bench_configuration(workload, fmt):
     assert_close(y2.cpu().numpy(), ref, s, F64_TOL, what)
     del M, P, ws, xd, y1, y2
     torch.cuda.empty_cache()
+
+
+def _mat(A, H, fmt, vt, val=None):
+    from gpu_common import stored_values
+    a, b, v = H[fmt]
+    if val is not None:
+        v = val
+    sv, v64 = stored_values(v, vt)
+    kind = {"csr": pk.CSR, "csc": pk.CSC, "coo": pk.COO}[fmt]
+    if fmt == "coo":
+        return pk.Mat(kind, vt, A.m, A.n, idx=a, idx2=b, val=sv), v64
+    return pk.Mat(kind, vt, A.m, A.n, ptr=a, idx=b, val=sv), v64
+
+
+def _spmv_bench_config(workload, fmt, M, nnz, x, vt):
+    import bench
+    npw, k, wpb, pf, res = bench.DEFAULT_TUNES[workload][fmt]
+    P = pk.msrep_build_partition(M, -(-nnz // npw))
+    tune = pk.Tune(k_per_lane=k, waves_per_wg=wpb, pipeline=pf, resident=res)
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    ws = pk.msrep_spmv_prepare(M, P)
+    y = torch.full((M.m,), float("nan"), dtype=xd.dtype, device=dev)
+    pk.msrep_spmv_prepared(M, P, xd, y, ws, 1.0, 0.0, tune)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy().astype(np.float64)
+    del P, ws, xd, y
+    return out
+
+
+@pytest.mark.parametrize("vt", [0, 1, 2])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "coo"])
+def test_full_size_stencil_times_ones_exact(fmt, vt):
+    """256^3 stencil times ones: y_i = 6 - (in-grid neighbours of i), a small
+    integer, exact in every value type at the full 16.7M rows."""
+    A, _, H = _workload("stencil256")
+    M, _ = _mat(A, H, fmt, vt)
+    xdt = np.float64 if vt == 0 else np.float32
+    y = _spmv_bench_config("stencil256", fmt, M, A.nnz, np.ones(A.n, xdt), vt)
+    g = 256
+    r = np.arange(A.m)
+    want = np.zeros(A.m)
+    for c in (r % g, (r // g) % g, r // (g * g)):
+        want += (c == 0).astype(np.float64) + (c == g - 1).astype(np.float64)
+    assert np.array_equal(y, want), (fmt, vt)
+    del M
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("workload", ["rmat20", "stencil256"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "coo"])
+def test_full_size_dyadic_bit_exact(workload, fmt):
+    """Dyadic values and x (k/256, |k| <= 256): every partial sum is exact in
+    FP64, so the full-size result must equal the oracle's bit for bit, which
+    pins the partition split and the boundary merge at the benchmark's
+    configuration."""
+    A, _, H = _workload(workload)
+    rng = np.random.default_rng(31)
+    x = synth.dyadic(rng, A.n)
+    val = None
+    if workload == "rmat20":  # the stencil's 6 and -1 are dyadic already
+        v_csr = synth.dyadic(rng, A.nnz)
+        val = v_csr
+        if fmt == "csc":
+            import oracle
+            _, _, _, p = oracle.transpose(A.m, A.n, A.ptr, A.col)
+            val = v_csr[p]
+    M, v64 = _mat(A, H, fmt, pk.F64, val)
+    y = _spmv_bench_config(workload, fmt, M, A.nnz, x, pk.F64)
+    ref, _ = oracle_y(A, fmt, v64, x)
+    assert np.array_equal(y, ref), (workload, fmt, int(np.sum(y != ref)))
+    del M
+    torch.cuda.empty_cache()
