@@ -421,7 +421,10 @@ def main():
     per_fmt = {}
     for f in fmts:
         b = alg_bytes(f, A.m, A.n, A.nnz, vbytes, xbytes)
+        each = sorted(a.elapsed_time(b) for a, b in ev[f])
         per_fmt[f] = {"ms_cold": round(cold_ms[f], 4),
+                      "ms_cold_median": round(float(np.median(each)), 4),
+                      "ms_cold_min": round(each[0], 4),
                       "gflops_cold": round(2.0 * A.nnz / cold_ms[f] / 1e6, 2),
                       "gbs_cold": round(b / cold_ms[f] / 1e6, 1),
                       "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4),
