@@ -203,8 +203,8 @@ size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
  * (Algorithms 3, 5, 7).
  *   CSR, COO: one wavefront streams each partition's nonzeros; rows inside a
  *     partition are written directly; a row split between partitions is
- *     merged by summing its partial sums in partition order with a
- *     compensated FP64 sum and applying beta once; rows covered by no
+ *     merged by a segmented sum of its partial sums over the partitions
+ *     (FP64, TwoSum-compensated) and applying beta once; rows covered by no
  *     partition get beta*y.  Deterministic for a given np and tune.
  *   CSC: the partitions' partial vectors (Algorithm 5, Sec. 4.3 column
  *     merge) are kept sparse: every product is written once, grouped by row
