@@ -5,7 +5,9 @@
 // holds a segment's last nonzero writes the row's y (or its partial sum to
 // the carry buffer for a row split across partitions), and the lane holding
 // a segment's first nonzero writes beta*y for the empty rows between it and
-// the previous segment.
+// the previous segment.  With beta == 0, a chunk spanning more than 2*64*K
+// rows (mostly empty ones in power-law matrices) is cleared by the whole
+// wavefront first, which beats one lane per gap.
 #pragma once
 
 #include "spmv_csr.hpp"
@@ -95,6 +97,17 @@ __device__ __forceinline__ void coo_partition(
     load_rows<K>(row_idx, s0, cb + 2 * CH, nloc, r0, rE, row_nn);
     // row of the position just after the chunk: the next chunk's first item
     const int32_t after = ce < nloc ? __builtin_amdgcn_readlane(row_nxt[0], 0) : -1;
+    // a chunk over a long run of rows (most of them empty): the wavefront
+    // clears the rows between its first and last row, then its lanes store
+    // only the rows that hold nonzeros
+    const int32_t last_row_c = __builtin_amdgcn_readlane(row_cur[K - 1], kWave - 1);
+    const int32_t fill_lo = cb > 0 ? before + 1 : r0;
+    const bool fill = BETA0 && last_row_c - fill_lo > 2 * CH;
+    if (fill) {
+      const int32_t hi = last_row_c < m ? last_row_c : m;
+      for (int32_t g = (fill_lo > 0 ? fill_lo : 0) + lane; g < hi; g += kWave) y[g] = T(0);
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // the clears land before the rows' values
+    }
     int32_t row[K];
     Acc prod[K];
 #pragma unroll
@@ -142,7 +155,7 @@ __device__ __forceinline__ void coo_partition(
       const int32_t rr = row[t];
       const int32_t pr = t == 0 ? prev0 : row[t - 1];
       // empty rows between the previous nonzero's row and this one
-      if ((q > 0) && rr > pr + 1) {
+      if (!fill && (q > 0) && rr > pr + 1) {
         const int32_t lo = pr + 1 > 0 ? pr + 1 : 0, hi = rr < m ? rr : m;
         for (int32_t g = lo; g < hi; ++g)
           y[g] = BETA0 ? T(0) : static_cast<T>(beta * static_cast<double>(y[g]));
