@@ -370,12 +370,40 @@ def main():
         else:
             pk.msrep_spmv_prepared(mats[f], parts[f], x, ys[f], ws[f], 1.0, 0.0, tunes[f])
 
+    def priced_of(kt):
+        return {fk: v for fk, v in kt.items()
+                if kernel_alg_bytes(fk[1], A.m, A.n, A.nnz, 1, vbytes, xbytes) is not None}
+
+    def timed_steps(steps, only=None):
+        """steps cold steps; each SpMV bracketed by events.  only=None: the
+        library times every kernel; only=(fmt, kernel): just that kernel in
+        that format's SpMV (one event pair, so the step is barely
+        perturbed); only=False: no kernel timing."""
+        ev = {f: [] for f in fmts}
+        kt = {}
+        for _ in range(steps):
+            for f in fmts:
+                scrub.fill_(1)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                on = only is None or (only and only[0] == f)
+                pk.msrep_timing(on)
+                pk.msrep_timing_only(only[1] if only else None)
+                e0.record()
+                spmv(f)
+                e1.record()
+                if on:
+                    for k, (c, t) in pk.msrep_timing_read().items():
+                        kc, ktt = kt.get((f, k), (0, 0.0))
+                        kt[(f, k)] = (kc + c, ktt + t)
+                ev[f].append((e0, e1))
+        pk.msrep_timing(False)
+        pk.msrep_timing_only(None)
+        return ev, kt
+
     # warmup steps are cold too, so that every launch of a kernel in this run
-    # is alike (a profiler's per-kernel average then matches the timed one)
-    for _ in range(args.warmup):
-        for f in fmts:
-            scrub.fill_(1)
-            spmv(f)
+    # is alike (a profiler's per-kernel average then matches the timed one);
+    # they time every kernel, to find the dominant one
+    _, kt_warm = timed_steps(args.warmup)
     if args.copy_calibration:
         src = torch.empty(COPY_CAL_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -383,28 +411,23 @@ def main():
         dst.copy_(src)
         del src, dst
     torch.cuda.synchronize()
-    # ---- timed region: K steps, each SpMV cold and bracketed by events
-    # (the library also brackets every kernel it launches with HIP events on
-    # the same stream: per-kernel durations for the roofline)
-    ev = {f: [] for f in fmts}
-    ktime = {}
+    # the dominant kernel: the largest share of the step's time among the
+    # kernels whose algorithmic bytes are defined (the SpMV kernels proper)
+    dom = None
+    if priced_of(kt_warm):
+        dom = max(priced_of(kt_warm).items(), key=lambda kv: kv[1][1])[0]
+    # ---- timed region: K steps, each SpMV cold and bracketed by events; the
+    # library brackets the dominant kernel with HIP events on the same stream
+    # (its duration for the roofline)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        for f in fmts:
-            scrub.fill_(1)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            pk.msrep_timing(True)
-            e0.record()
-            spmv(f)
-            e1.record()
-            for k, (c, t) in pk.msrep_timing_read().items():
-                kc, kt = ktime.get((f, k), (0, 0.0))
-                ktime[(f, k)] = (kc + c, kt + t)
-            ev[f].append((e0, e1))
-    pk.msrep_timing(False)
+    ev, ktime = timed_steps(args.steps, only=dom)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    # ---- after it: the per-kernel breakdown of every format (all kernels
+    # timed, so these steps are slower than the timed ones)
+    _, kt_all = timed_steps(args.steps)
+    torch.cuda.synchronize()
     cold_ms = {f: float(np.mean([a.elapsed_time(b) for a, b in ev[f]])) for f in fmts}
     # ---- warm (optional): back-to-back SpMVs of one format
     warm_ms = {}
@@ -439,12 +462,11 @@ def main():
         if f in warm_ms:
             per_fmt[f]["ms_warm"] = round(warm_ms[f], 4)
             per_fmt[f]["gbs_warm"] = round(b / warm_ms[f] / 1e6, 1)
-        per_fmt[f]["kernels_us"] = {k: round(t / c * 1e3, 2) for (g, k), (c, t) in ktime.items()
+        per_fmt[f]["kernels_us"] = {k: round(t / c * 1e3, 2) for (g, k), (c, t) in kt_all.items()
                                     if g == f}
-    # the dominant kernel: the largest share of the step's time among the
-    # kernels whose algorithmic bytes are defined (the SpMV kernels proper)
-    priced = {fk: v for fk, v in ktime.items()
-              if kernel_alg_bytes(fk[1], A.m, A.n, A.nnz, 1, vbytes, xbytes) is not None}
+    priced = priced_of(ktime)
+    if not priced:  # no warmup: take the dominant kernel from the breakdown
+        priced = priced_of(kt_all)
     (dom_f, kname), (kc, kt) = max(priced.items(), key=lambda kv: kv[1][1])
     k_ms = kt / kc
     k_bytes = kernel_alg_bytes(kname, A.m, A.n, A.nnz, parts[dom_f].np, vbytes, xbytes)

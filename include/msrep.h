@@ -64,6 +64,11 @@ typedef struct msrep_kernel_time {
  * recorded.  Waits for recorded events that are still pending. */
 msrep_status msrep_timing(int32_t enable);
 
+/* Restrict timing to the kernel of this name (NULL or "" = every kernel).
+ * Each event record adds a gap of a few microseconds before the next
+ * kernel, so timing one kernel perturbs a call far less than timing all. */
+msrep_status msrep_timing_only(const char *kernel);
+
 /* Waits for the recorded events, writes up to cap entries (one per kernel
  * name, in order of first launch) and discards the records.  Returns the
  * number of distinct kernels (entries past cap are dropped), or a negative

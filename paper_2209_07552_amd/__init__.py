@@ -15,6 +15,6 @@ from ._abi import (  # noqa: F401
     load_library, msrep_autotune, msrep_build_partition, msrep_convert, msrep_last_error,
     msrep_lptr_bound, msrep_plan_create, msrep_serve, msrep_spmv, msrep_spmv_batched,
     msrep_spmv_prepare, msrep_spmv_prepared, msrep_spmv_ws_bytes, msrep_timing,
-    msrep_timing_read,
+    msrep_timing_only, msrep_timing_read,
     msrep_validate, mat_from_csr, exported_symbols,
 )

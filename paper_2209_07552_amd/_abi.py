@@ -117,6 +117,7 @@ def load_library():
         "msrep_serve": (c_i32, [P(_ServeCfg), P(_HostMat), c_i32, P(_Request), c_i64, P(_Result),
                                 P(_ServeStats)]),
         "msrep_timing": (c_i32, [c_i32]),
+        "msrep_timing_only": (c_i32, [ctypes.c_char_p]),
         "msrep_timing_read": (c_i32, [P(_KernelTime), c_i32]),
     }
     for name, (res, args) in sig.items():
@@ -323,6 +324,11 @@ def msrep_timing(enable: bool) -> None:
     """Turn per-kernel event timing of msrep_spmv on or off (discards what
     was recorded)."""
     _check(load_library().msrep_timing(1 if enable else 0), "timing")
+
+
+def msrep_timing_only(kernel: Optional[str] = None) -> None:
+    """Time only the kernel of this name (None: every kernel)."""
+    _check(load_library().msrep_timing_only(kernel.encode() if kernel else None), "timing_only")
 
 
 def msrep_timing_read() -> dict:

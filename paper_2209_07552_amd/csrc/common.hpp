@@ -46,7 +46,7 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 // Event pair around one kernel launch while msrep_timing is enabled (no-ops
 // otherwise); name must be a string literal.
-void timing_begin(hipStream_t s);
+void timing_begin(const char *name, hipStream_t s);
 void timing_end(const char *name, hipStream_t s);
 
 // O(1) descriptor checks shared by every entry point.

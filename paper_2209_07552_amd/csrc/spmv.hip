@@ -93,7 +93,7 @@ msrep_status launch_csr(const msrep_mat *A, const msrep_part *parts, const int32
   using Tr = vt_traits<VT>;
   const size_t lds = seg_lds_per_wave<VT, K>() * wpb;
   const int64_t want = (np + wpb - 1) / wpb;  // one wavefront per partition
-  timing_begin(s);
+  timing_begin("spmv_csr_seg", s);
   if (pf == 1)
     hipLaunchKernelGGL((spmv_csr_seg<VT, K, B0, 1>),
                        dim3(resident ? resident_grid(spmv_csr_seg<VT, K, B0, 1>, wpb * kWave, lds, want)
@@ -122,7 +122,7 @@ msrep_status launch_coo(const msrep_mat *A, const msrep_part *parts, int32_t np,
   using Tr = vt_traits<VT>;
   const size_t lds = coo_lds_per_wave<VT, K>() * wpb;
   const int64_t want = (np + wpb - 1) / wpb;  // one wavefront per partition
-  timing_begin(s);
+  timing_begin("spmv_coo_seg", s);
   hipLaunchKernelGGL((spmv_coo_seg<VT, K, B0>),
                      dim3(resident ? resident_grid(spmv_coo_seg<VT, K, B0>, wpb * kWave, lds, want)
                                    : want),
@@ -148,17 +148,17 @@ msrep_status csc_structure(const msrep_mat *A, const msrep_part *parts, int32_t 
   int32_t *mbase = reinterpret_cast<int32_t *>(b + L.mbase);
   int32_t *mlist = reinterpret_cast<int32_t *>(b + L.mlist);
   const size_t cur_lds = align_up(static_cast<size_t>(L.nb) * 4, 16);
-  timing_begin(s);
+  timing_begin("csc_count", s);
   hipLaunchKernelGGL(csc_count, dim3(L.P), dim3(kCscScatterWaves * kWave), cur_lds, s, A->idx,
                      A->nnz, parts, np, L.P, A->m, L.shift, L.nb, cnt);
   MSREP_LAUNCHED("csc_count");
   timing_end("csc_count", s);
-  timing_begin(s);
+  timing_begin("csc_scan", s);
   if (msrep_status st = scan::device_scan<int32_t, scan::SumOp>(
           cnt, cnt, static_cast<int64_t>(L.nb) * L.P + 1, agg, false, s))
     return st;
   timing_end("csc_scan", s);
-  timing_begin(s);
+  timing_begin("csc_plan", s);
   hipLaunchKernelGGL(csc_plan, dim3(1), dim3(kPlanBlock), 0, s, cnt, L.nb, L.P, L.piece, pbase,
                      mbase, mlist);
   MSREP_LAUNCHED("csc_plan");
@@ -192,21 +192,21 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   uint16_t *rlo = reinterpret_cast<uint16_t *>(b + L.rlo);
   double *part = reinterpret_cast<double *>(b + L.part);
   (void)wpb;  // the scatter always runs 16-wavefront producers
-  timing_begin(s);
+  timing_begin("csc_scatter", s);
   hipLaunchKernelGGL((csc_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
                      csc_scatter_lds<K>(L.nb), s, A->idx,
                      static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
                      static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
   MSREP_LAUNCHED("csc_scatter");
   timing_end("csc_scatter", s);
-  timing_begin(s);
+  timing_begin("csc_reduce", s);
   hipLaunchKernelGGL((csc_reduce<T, Acc, PACK>), dim3(static_cast<uint32_t>(L.max_pieces)),
                      dim3(kReduceBlock), sizeof(double) << L.shift, s, prod, rlo, cnt, pbase, mbase,
                      L.nb, L.P, L.shift, A->m, A->nnz, L.piece, L.max_slots, part, static_cast<T *>(y),
                      alpha, beta);
   MSREP_LAUNCHED("csc_reduce");
   timing_end("csc_reduce", s);
-  timing_begin(s);
+  timing_begin("csc_merge", s);
   {
     // buckets of several pieces hold more than L.piece products each
     const int64_t most = std::min<int64_t>(L.nb, A->nnz / L.piece + 1);
@@ -254,7 +254,7 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   if (st) return st;
   if (np > 1) {
     const int g = (np + 255) / 256;
-    timing_begin(s);
+    timing_begin("merge_rows", s);
     if (b0)
       hipLaunchKernelGGL((merge_rows<T, true>), dim3(g), dim3(256), 0, s, parts, np, carry,
                          static_cast<T *>(y), A->m, alpha, beta);

@@ -1,10 +1,13 @@
 // Per-kernel timing for profiling: while enabled, the SpMV path brackets each
-// kernel it launches with a pair of HIP events recorded on the caller's
-// stream; msrep_timing_read waits for them and totals the elapsed times by
-// kernel name.  Off by default, so the SpMV path records nothing.
+// kernel it launches (or only the kernel named by msrep_timing_only) with a
+// pair of HIP events recorded on the caller's stream; msrep_timing_read
+// waits for them and totals the elapsed times by kernel name.  Off by
+// default, so the SpMV path records nothing.  Every event record adds a gap
+// of a few microseconds between kernels, hence the filter.
 #include <atomic>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -23,6 +26,7 @@ struct Timing {
   std::vector<hipEvent_t> pool;  // events free for reuse
   std::vector<Mark> marks;       // recorded, not yet read
   hipEvent_t open = nullptr;     // begin event of the launch in progress
+  std::string only;              // the one kernel to time ("" = all)
 };
 
 Timing &timing() {
@@ -52,10 +56,11 @@ void recycle(Timing &t) {
 
 }  // namespace
 
-void timing_begin(hipStream_t s) {
+void timing_begin(const char *name, hipStream_t s) {
   Timing &t = timing();
   if (!t.on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(t.mu);
+  if (!t.only.empty() && t.only != name) return;
   if (t.open) t.pool.push_back(t.open);
   t.open = nullptr;
   hipEvent_t e = take_event(t);
@@ -69,6 +74,7 @@ void timing_end(const char *name, hipStream_t s) {
   Timing &t = timing();
   if (!t.on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(t.mu);
+  if (!t.only.empty() && t.only != name) return;
   if (!t.open) return;
   hipEvent_t e = take_event(t);
   if (e && hipEventRecord(e, s) == hipSuccess) {
@@ -90,6 +96,13 @@ extern "C" msrep_status msrep_timing(int32_t enable) {
   for (const Mark &m : t.marks) (void)hipEventSynchronize(m.e1);
   recycle(t);
   t.on.store(enable != 0);
+  return ok();
+}
+
+extern "C" msrep_status msrep_timing_only(const char *kernel) {
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.only = kernel ? kernel : "";
   return ok();
 }
 

@@ -358,7 +358,14 @@ def test_kernel_timing_records_each_launch():
         t = pk.msrep_timing_read()
         assert set(t) == {"csc_count", "csc_scan", "csc_scatter", "csc_plan", "csc_reduce",
                           "csc_merge"}, t
+        pk.msrep_timing_only("csc_scatter")  # one kernel only
+        _run(A, x, "csc", pk.F64, 64)
+        t = pk.msrep_timing_read()
+        assert set(t) == {"csc_scatter"} and t["csc_scatter"][0] == 1, t
+        _run(A, x, "csr", pk.F64, 64)
+        assert pk.msrep_timing_read() == {}
     finally:
+        pk.msrep_timing_only(None)
         pk.msrep_timing(False)
     _run(A, x, "coo", pk.F64, 64)
     assert pk.msrep_timing_read() == {}
