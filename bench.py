@@ -57,6 +57,56 @@ def host_formats(A):
             "coo": (rows, A.col, A.val)}
 
 
+def equal_rows_partition(M, H, fmt, np_, dev):
+    """The paper's baseline split (equal rows, or equal columns for CSC,
+    unequal nonzeros) as partition records the SpMV kernels take: partition
+    i starts at major index floor(i*rows/np); its fields follow the same
+    definitions as the equal-nnz build (row containing start_idx and end_idx,
+    local pointer clamped to the partition, start_row + 2i offsets), and its
+    flags are 0 since it never splits a row.  Host numpy, for comparison
+    runs only."""
+    import torch
+    import paper_2209_07552_amd as pk
+    a, b, _ = H[fmt]
+    rows = M.major
+    nnz = int(M.nnz)
+    bnd = (np.arange(np_ + 1, dtype=np.int64) * rows) // np_
+    if fmt == "coo":
+        first = np.searchsorted(np.asarray(a, np.int64), bnd, "left").astype(np.int64)
+        ptr = None
+    else:
+        ptr = np.asarray(a, np.int64)
+        first = ptr[bnd]
+    rec = np.zeros(np_, pk.PART_DTYPE)
+    s0, e0 = first[:-1], first[1:] - 1
+    rec["start_idx"], rec["end_idx"] = s0, e0
+    if fmt == "coo":
+        ri = np.asarray(a, np.int64)
+        srow = np.where(s0 < nnz, ri[np.minimum(s0, nnz - 1)], rows) if nnz else np.full(np_, rows)
+        erow = np.where(e0 >= s0, ri[np.maximum(e0, 0)] if nnz else 0, srow - 1)
+    else:
+        def bs(k):  # the row containing nonzero k: max r with ptr[r] <= k
+            return np.searchsorted(ptr, k, "right") - 1
+        srow = np.where(s0 < nnz, bs(s0), rows)
+        erow = np.where(e0 >= s0, bs(np.maximum(e0, 0)), srow - 1)
+    rec["start_row"], rec["end_row"] = srow, erow
+    rec["lptr_off"] = srow + 2 * np.arange(np_, dtype=np.int64)
+    parts = torch.from_numpy(rec.view(np.uint8).copy()).to(dev)
+    if fmt == "coo":
+        return pk.Partition(M, np_, parts, None, torch.zeros(1, dtype=torch.int64, device=dev))
+    cap = rows + 2 * np_
+    lp = np.zeros(cap, np.int32)
+    for i in range(np_):
+        R = int(erow[i] - srow[i] + 1)
+        if R <= 0:
+            lp[rec["lptr_off"][i]] = 0
+            continue
+        seg = ptr[srow[i]:srow[i] + R + 1]
+        lp[rec["lptr_off"][i]:rec["lptr_off"][i] + R + 1] = np.clip(seg, s0[i], e0[i] + 1) - s0[i]
+    ln = torch.tensor([cap], dtype=torch.int64, device=dev)
+    return pk.Partition(M, np_, parts, torch.from_numpy(lp).to(dev), ln)
+
+
 def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
     """Bytes the method must move for one SpMV (values, indices, pointer, x
     read once, y written once; y read too when beta != 0)."""
@@ -246,6 +296,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune every format first")
+    ap.add_argument("--split", default="nnz", choices=["nnz", "rows"],
+                    help="rows: the paper's equal-rows baseline partitions (same np)")
     ap.add_argument("--unprepared", action="store_true",
                     help="time msrep_spmv (structure work in every call) instead of "
                          "msrep_spmv_prepare once + msrep_spmv_prepared")
@@ -315,7 +367,8 @@ def main():
             mats[f] = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=stored(v))
         else:
             mats[f] = pk.Mat(pk.COO, vt, A.m, A.n, idx=a, idx2=b, val=stored(v))
-    del H
+    if args.split != "rows":
+        del H  # (the equal-rows baseline builds its partitions from it)
     xs = x64 if vt == pk.F64 else x64.astype(np.float32)
     x = torch.from_numpy(xs).to(dev)
     ydt = torch.float64 if vt == pk.F64 else torch.float32
@@ -345,6 +398,9 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         part_ms[f] = e0.elapsed_time(e1)
+        if args.split == "rows":  # the paper's baseline split, same np
+            parts[f] = equal_rows_partition(mats[f], H, f, np_f, dev)
+            torch.cuda.synchronize()
     scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
     ws = {f: torch.zeros(max(256, pk.msrep_spmv_ws_bytes(mats[f], parts[f].np)), dtype=torch.uint8,
                          device=dev) for f in fmts}
@@ -480,7 +536,7 @@ def main():
         "ms_per_step": round(step_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.vtype, "data": "synthetic",
-        "config": dict(wl, formats=fmts, value_type=args.vtype),
+        "config": dict(wl, formats=fmts, value_type=args.vtype, split=args.split),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname, "format": dom_f,

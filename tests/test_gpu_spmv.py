@@ -277,6 +277,28 @@ def test_prepared_spmv_repeats_with_fresh_x(fmt, vt):
                           "prepared %s vt%d np%d it%d" % (fmt, vt, np_, it))
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+def test_equal_rows_baseline_partitions(fmt):
+    """The kernels take any consistent partition records: the paper's
+    equal-rows baseline split (unequal nonzeros, no split rows) built on the
+    host gives the oracle's result too."""
+    import bench
+    rng = np.random.default_rng(17)
+    for A, x in (synth.rmat_csr(scale=14, edge_factor=16, seed=8), synth.stencil7_csr(48)):
+        H = host_formats(A)
+        M, v64 = device_mat(A, fmt, pk.F64)
+        y_in = rng.uniform(-1, 1, A.m)
+        for np_ in (1, 7, 300):
+            P = bench.equal_rows_partition(M, H, fmt, np_, _dev())
+            xd = torch.from_numpy(x).to(_dev())
+            yd = torch.from_numpy(y_in.copy()).to(_dev())
+            ws = pk.msrep_spmv_prepare(M, P)
+            pk.msrep_spmv_prepared(M, P, xd, yd, ws, 1.5, -0.5)
+            torch.cuda.synchronize()
+            ref, sc = oracle_y(A, fmt, v64, x, 1.5, -0.5, y_in)
+            assert_close(yd.cpu().numpy(), ref, sc, F64_TOL, "rows %s %s np%d" % (A.name, fmt, np_))
+
+
 @pytest.mark.parametrize("fmt", ["csr", "coo"])
 def test_deterministic(fmt):
     A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=5)
