@@ -254,6 +254,37 @@ def trace_summary(trace_dir, out_name, command, bench_json=None):
     print("\n".join(lines))
 
 
+def overheads(args, mats, part_ms, prep_ms, cold_ms, kt_all):
+    """The paper's overhead breakdown (its partition and merge time figures)
+    on one GPU: format conversion from CSR on the GPU, partition build, the
+    CSC structure work and the boundary merge, each also as a share of that
+    format's SpMV time."""
+    import torch
+    import paper_2209_07552_amd as pk
+    out = {}
+    if "csr" in mats:
+        for dst, name in ((pk.CSC, "csc"), (pk.COO, "coo")):
+            pk.msrep_convert(mats["csr"], dst)  # first launch loads the code
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            B = pk.msrep_convert(mats["csr"], dst)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            del B
+            out["convert_csr_to_" + name] = {"ms": round(ms, 4), "pct_of_spmv":
+                                             round(100 * ms / cold_ms[name], 1) if name in cold_ms else None}
+    for f in cold_ms:
+        merge = [t / c for (g, k), (c, t) in kt_all.items() if g == f and k in ("merge_rows", "csc_merge")]
+        out[f] = {"partition_ms": round(part_ms[f], 4),
+                  "partition_pct_of_spmv": round(100 * part_ms[f] / cold_ms[f], 1),
+                  "prepare_ms": round(prep_ms[f], 4),
+                  "merge_ms": round(sum(merge), 4),
+                  "merge_pct_of_spmv": round(100 * sum(merge) / cold_ms[f], 1)}
+    return out
+
+
 def cpu_baseline(A, x, y_gpu, budget_s):
     """The FP64 oracle (Dot2 CSR SpMV, one thread) timed on this host over
     whole SpMVs of the same matrix, repeated for about budget_s seconds; also
@@ -296,6 +327,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune every format first")
+    ap.add_argument("--overheads", action="store_true",
+                    help="also time conversion, partition build and merge against the SpMV")
     ap.add_argument("--split", default="nnz", choices=["nnz", "rows"],
                     help="rows: the paper's equal-rows baseline partitions (same np)")
     ap.add_argument("--unprepared", action="store_true",
@@ -544,6 +577,8 @@ def main():
         "per_format": per_fmt,
         "wall_s_timed_region": round(wall, 3),
     }
+    if args.overheads:
+        out["overheads"] = overheads(args, mats, part_ms, prep_ms, cold_ms, kt_all)
     if not args.no_cpu:
         f0 = "csr" if "csr" in fmts else fmts[0]
         yg = ys[f0].double().cpu().numpy()
