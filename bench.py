@@ -34,9 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # --nnz-per-wave/--k/--wpb/--pipeline/--resident are given: the tuner's picks
 # on MI355X (nnz_per_wave, k_per_lane, waves_per_wg, pipeline, resident).
 DEFAULT_TUNES = {
-    "rmat20": {"csr": (512, 4, 8, 2, 1), "coo": (512, 4, 8, 2, 1), "csc": (1024, 4, 2, 1, 0)},
+    "rmat20": {"csr": (512, 4, 8, 2, 1), "coo": (512, 4, 8, 2, 1), "csc": (1024, 4, 2, 1, 0),
+               "coo_any": (1024, 4, 2, 1, 0)},
     "stencil256": {"csr": (2048, 4, 4, 2, 0), "coo": (1024, 4, 2, 2, 0),
-                   "csc": (1024, 4, 2, 2, 0)},
+                   "csc": (1024, 4, 2, 2, 0), "coo_any": (1024, 4, 2, 2, 0)},
 }
 SCRUB_BYTES = 512 << 20
 
@@ -45,16 +46,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def host_formats(A):
+def host_formats(A, any_order=False):
     """CSC and row-sorted COO arrays of a CSR matrix (plain numpy input
-    preparation: stable sort by column)."""
+    preparation: stable sort by column), and with any_order the COO in a
+    seeded random order."""
     rows = np.repeat(np.arange(A.m, dtype=np.int32), np.diff(A.ptr))
     perm = np.argsort(A.col, kind="stable")
     cptr = np.zeros(A.n + 1, np.int64)
     np.cumsum(np.bincount(A.col, minlength=A.n), out=cptr[1:])
-    return {"csr": (A.ptr, A.col, A.val),
-            "csc": (cptr.astype(np.int32), rows[perm], A.val[perm]),
-            "coo": (rows, A.col, A.val)}
+    out = {"csr": (A.ptr, A.col, A.val),
+           "csc": (cptr.astype(np.int32), rows[perm], A.val[perm]),
+           "coo": (rows, A.col, A.val)}
+    if any_order:  # COO in a seeded random order
+        shuf = np.random.default_rng(0).permutation(A.nnz)
+        out["coo_any"] = (rows[shuf], A.col[shuf], A.val[shuf])
+    return out
 
 
 def equal_rows_partition(M, H, fmt, np_, dev):
@@ -122,18 +128,20 @@ def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
     return b
 
 
-def kernel_alg_bytes(kernel, m, n, nnz, np_, vbytes, xbytes):
+def kernel_alg_bytes(kernel, m, n, nnz, np_, vbytes, xbytes, fmt="csc"):
     """Algorithmic bytes of one launch of a kernel of the SpMV path (one
     launch covers the whole matrix): what its job must read and write, each
-    array once.  CSC products are FP64 for FP64 values and FP32 otherwise,
-    each with a 16-bit row offset."""
+    array once.  Bucketed products are FP64 for FP64 values and FP32
+    otherwise, each with a 16-bit row offset; for COO in any order the
+    scatter reads a column index per nonzero instead of the column pointer."""
     pbytes = 8 if xbytes == 8 else 4
+    cols = nnz * 4 if fmt == "coo_any" else (n + 1) * 4
     return {
         "spmv_csr_seg": alg_bytes("csr", m, n, nnz, vbytes, xbytes),
         "spmv_coo_seg": alg_bytes("coo", m, n, nnz, vbytes, xbytes),
         "merge_rows": np_ * (40 + 16),
         "csc_count": nnz * 4,
-        "csc_scatter": nnz * (vbytes + 4) + (n + 1) * 4 + n * xbytes + nnz * (pbytes + 2),
+        "csc_scatter": nnz * (vbytes + 4) + cols + n * xbytes + nnz * (pbytes + 2),
         "csc_reduce": nnz * (pbytes + 2) + m * xbytes,
     }.get(kernel)
 
@@ -381,7 +389,7 @@ def main():
         wl = {"workload": "uniform-4096-16perrow", "rows": A.m, "cols": A.n, "nnz": A.nnz}
     log("generated %s in %.1fs" % (wl["workload"], time.time() - t0))
     fmts = [f for f in args.formats.split(",") if f]
-    H = host_formats(A)
+    H = host_formats(A, any_order="coo_any" in fmts)
     vbytes = pk._abi.VALUE_BYTES[vt]
     xbytes = 8 if vt == pk.F64 else 4
 
@@ -399,7 +407,8 @@ def main():
         elif f == "csc":
             mats[f] = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=stored(v))
         else:
-            mats[f] = pk.Mat(pk.COO, vt, A.m, A.n, idx=a, idx2=b, val=stored(v))
+            kind = pk.COO_ANY if f == "coo_any" else pk.COO
+            mats[f] = pk.Mat(kind, vt, A.m, A.n, idx=a, idx2=b, val=stored(v))
     if args.split != "rows":
         del H  # (the equal-rows baseline builds its partitions from it)
     xs = x64 if vt == pk.F64 else x64.astype(np.float32)
@@ -431,7 +440,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         part_ms[f] = e0.elapsed_time(e1)
-        if args.split == "rows":  # the paper's baseline split, same np
+        if args.split == "rows" and f != "coo_any":  # the paper's baseline split, same np
             parts[f] = equal_rows_partition(mats[f], H, f, np_f, dev)
             torch.cuda.synchronize()
     scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
@@ -461,7 +470,7 @@ def main():
 
     def priced_of(kt):
         return {fk: v for fk, v in kt.items()
-                if kernel_alg_bytes(fk[1], A.m, A.n, A.nnz, 1, vbytes, xbytes) is not None}
+                if kernel_alg_bytes(fk[1], A.m, A.n, A.nnz, 1, vbytes, xbytes, fk[0]) is not None}
 
     def timed_steps(steps, only=None):
         """steps cold steps; each SpMV bracketed by events.  only=None: the
@@ -558,7 +567,7 @@ def main():
         priced = priced_of(kt_all)
     (dom_f, kname), (kc, kt) = max(priced.items(), key=lambda kv: kv[1][1])
     k_ms = kt / kc
-    k_bytes = kernel_alg_bytes(kname, A.m, A.n, A.nnz, parts[dom_f].np, vbytes, xbytes)
+    k_bytes = kernel_alg_bytes(kname, A.m, A.n, A.nnz, parts[dom_f].np, vbytes, xbytes, dom_f)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     traffic = load_traffic("%s/%s/%s" % (kname, wl["workload"], args.vtype))
     out = {

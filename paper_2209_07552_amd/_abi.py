@@ -15,9 +15,9 @@ ROOT = os.path.dirname(HERE)
 _LIB_PATH = os.path.join(HERE, "libmsrep.so")
 HEADER = os.path.join(ROOT, "include", "msrep.h")
 
-CSR, CSC, COO = 0, 1, 2
+CSR, CSC, COO, COO_ANY = 0, 1, 2, 3  # COO_ANY: COO in any order
 F64, F32, BF16 = 0, 1, 2
-FMT_NAMES = {CSR: "csr", CSC: "csc", COO: "coo"}
+FMT_NAMES = {CSR: "csr", CSC: "csc", COO: "coo", COO_ANY: "coo_any"}
 VT_NAMES = {F64: "f64", F32: "f32", BF16: "bf16"}
 VALUE_BYTES = {F64: 8, F32: 4, BF16: 2}
 
@@ -233,9 +233,11 @@ class Mat:
         M = cls.__new__(cls)
         M.fmt, M.vtype, M.m, M.n, M.nnz = int(fmt), int(vtype), int(m), int(n), int(nnz)
         major = n if fmt == CSC else m
-        M.ptr = None if fmt == COO else torch.empty(major + 1, dtype=torch.int32, device=device)
+        M.ptr = None if fmt in (COO, COO_ANY) else torch.empty(major + 1, dtype=torch.int32,
+                                                               device=device)
         M.idx = torch.empty(nnz, dtype=torch.int32, device=device)
-        M.idx2 = torch.empty(nnz, dtype=torch.int32, device=device) if fmt == COO else None
+        M.idx2 = (torch.empty(nnz, dtype=torch.int32, device=device) if fmt in (COO, COO_ANY)
+                  else None)
         M.val = torch.empty(nnz, dtype=value_dtype(vtype), device=device)
         return M
 
@@ -293,7 +295,7 @@ def msrep_build_partition(A: Mat, np_: int, stream=None) -> Partition:
     L = load_library()
     dev = A.idx.device if A.idx is not None else A.ptr.device
     parts = torch.empty(max(np_, 1) * PART_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    if A.fmt == COO:
+    if A.fmt in (COO, COO_ANY):
         lptr, cap = None, 0
     else:
         cap = L.msrep_lptr_bound(A.major, np_)

@@ -272,8 +272,11 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
                                       size_t ws_bytes, void *stream) {
   if (msrep_status st = check_mat(src, "msrep_convert")) return st;
   if (!dst) return fail(MSREP_ERR_ARG, "msrep_convert: dst is NULL");
-  if (dst->fmt < MSREP_CSR || dst->fmt > MSREP_COO)
+  if (dst->fmt < MSREP_CSR || dst->fmt > MSREP_COO_ANY)
     return fail(MSREP_ERR_ARG, "msrep_convert: unknown target format %d", dst->fmt);
+  if (src->fmt == MSREP_COO_ANY || dst->fmt == MSREP_COO_ANY)
+    return fail(MSREP_ERR_UNSUPPORTED,
+                "msrep_convert: COO in any order is taken by msrep_spmv as it is, not converted");
   if (dst->m != src->m || dst->n != src->n || dst->nnz != src->nnz || dst->vtype != src->vtype)
     return fail(MSREP_ERR_ARG, "msrep_convert: dst shape/nnz/vtype differ from src");
   const int64_t nnz = src->nnz;

@@ -111,6 +111,23 @@ __global__ __launch_bounds__(256) void part_meta_coo(const int32_t *__restrict__
   parts[i] = P;
 }
 
+// COO in any order: equal-nnz position ranges only (rows are not grouped,
+// so no partition has rows of its own): start_row 0, end_row -1, flags 0.
+__global__ __launch_bounds__(256) void part_meta_any(int64_t nnz, int32_t np,
+                                                     msrep_part *__restrict__ parts) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  msrep_part P;
+  P.start_idx = (static_cast<int64_t>(i) * nnz) / np;
+  P.end_idx = (static_cast<int64_t>(i + 1) * nnz) / np - 1;
+  P.start_row = 0;
+  P.end_row = -1;
+  P.start_flag = 0;
+  P.end_flag = 0;
+  P.lptr_off = 0;
+  parts[i] = P;
+}
+
 __global__ void store_i64(int64_t *p, int64_t v) { *p = v; }
 
 }  // namespace
@@ -131,9 +148,15 @@ extern "C" msrep_status msrep_build_partition(const msrep_mat *A, int32_t np, ms
   if (!parts_d) return fail(MSREP_ERR_ARG, "msrep_build_partition: parts_d is NULL");
   hipStream_t s = as_stream(stream);
   const int grid = (np + 255) / 256;
-  if (A->fmt == MSREP_COO) {
-    hipLaunchKernelGGL(part_meta_coo, dim3(grid), dim3(256), 0, s, A->idx, A->m, A->nnz, np, parts_d);
-    MSREP_LAUNCHED("part_meta_coo");
+  if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY) {
+    if (A->fmt == MSREP_COO) {
+      hipLaunchKernelGGL(part_meta_coo, dim3(grid), dim3(256), 0, s, A->idx, A->m, A->nnz, np,
+                         parts_d);
+      MSREP_LAUNCHED("part_meta_coo");
+    } else {
+      hipLaunchKernelGGL(part_meta_any, dim3(grid), dim3(256), 0, s, A->nnz, np, parts_d);
+      MSREP_LAUNCHED("part_meta_any");
+    }
     if (lptr_len_d) {
       hipLaunchKernelGGL(store_i64, dim3(1), dim3(1), 0, s, lptr_len_d, int64_t(0));
       MSREP_LAUNCHED("store_i64");

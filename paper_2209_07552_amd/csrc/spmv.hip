@@ -37,7 +37,7 @@ int value_bytes(int32_t vtype) {
 
 msrep_status check_mat(const msrep_mat *A, const char *who) {
   if (!A) return fail(MSREP_ERR_ARG, "%s: matrix descriptor is NULL", who);
-  if (A->fmt < MSREP_CSR || A->fmt > MSREP_COO)
+  if (A->fmt < MSREP_CSR || A->fmt > MSREP_COO_ANY)
     return fail(MSREP_ERR_ARG, "%s: unknown format %d", who, A->fmt);
   if (!value_bytes(A->vtype)) return fail(MSREP_ERR_ARG, "%s: unknown value type %d", who, A->vtype);
   if (A->m < 0 || A->n < 0 || A->nnz < 0)
@@ -48,9 +48,10 @@ msrep_status check_mat(const msrep_mat *A, const char *who) {
                 static_cast<long long>(A->nnz));
   if (A->nnz > 0 && (A->m == 0 || A->n == 0))
     return fail(MSREP_ERR_ARG, "%s: nonzeros in a matrix with no rows or columns", who);
-  if (A->fmt != MSREP_COO && !A->ptr) return fail(MSREP_ERR_ARG, "%s: ptr is NULL", who);
+  const bool coo = A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY;
+  if (!coo && !A->ptr) return fail(MSREP_ERR_ARG, "%s: ptr is NULL", who);
   if (A->nnz > 0 && (!A->idx || !A->val)) return fail(MSREP_ERR_ARG, "%s: idx/val is NULL", who);
-  if (A->fmt == MSREP_COO && A->nnz > 0 && !A->idx2)
+  if (coo && A->nnz > 0 && !A->idx2)
     return fail(MSREP_ERR_ARG, "%s: COO col_idx (idx2) is NULL", who);
   return MSREP_OK;
 }
@@ -193,10 +194,16 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   double *part = reinterpret_cast<double *>(b + L.part);
   (void)wpb;  // the scatter always runs 16-wavefront producers
   timing_begin("csc_scatter", s);
-  hipLaunchKernelGGL((csc_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
-                     csc_scatter_lds<K>(L.nb), s, A->idx,
-                     static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
-                     static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
+  if (A->fmt == MSREP_COO_ANY)  // columns read from col_idx
+    hipLaunchKernelGGL((coo_any_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
+                       align_up((static_cast<size_t>(L.nb) + kWave) * 4, 16), s, A->idx, A->idx2,
+                       static_cast<const typename Tr::V *>(A->val), A->nnz, parts, np, L.P,
+                       static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
+  else
+    hipLaunchKernelGGL((csc_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
+                       csc_scatter_lds<K>(L.nb), s, A->idx,
+                       static_cast<const typename Tr::V *>(A->val), A->nnz, parts, lptr, np, L.P,
+                       static_cast<const T *>(x), A->m, A->n, L.shift, L.nb, cnt, prod, rlo);
   MSREP_LAUNCHED("csc_scatter");
   timing_end("csc_scatter", s);
   timing_begin("csc_reduce", s);
@@ -237,7 +244,7 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
-  if (A->fmt == MSREP_CSC) {  // carry is the whole workspace here
+  if (A->fmt == MSREP_CSC || A->fmt == MSREP_COO_ANY) {  // carry is the whole workspace here
     if (pf == 1)
       return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s)
                     : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s);
@@ -324,7 +331,7 @@ namespace msrep {
 
 
 size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t np) {
-  if (fmt == MSREP_CSC) {
+  if (fmt == MSREP_CSC || fmt == MSREP_COO_ANY) {
     CscLayout L;
     const int pb = vtype == MSREP_F64 ? 8 : 4;
     return csc_layout(m, nnz, np, pb, L) ? L.total : 0;
@@ -350,7 +357,8 @@ msrep_status spmv_entry(const msrep_mat *A, const msrep_part *parts_d, const int
   if (msrep_status st = check_mat(A, who)) return st;
   if (np <= 0) return fail(MSREP_ERR_ARG, "%s: np must be positive (got %d)", who, np);
   if (!parts_d) return fail(MSREP_ERR_ARG, "%s: parts_d is NULL", who);
-  if (A->fmt != MSREP_COO && !lptr_d) return fail(MSREP_ERR_ARG, "%s: lptr_d is NULL", who);
+  if ((A->fmt == MSREP_CSR || A->fmt == MSREP_CSC) && !lptr_d)
+    return fail(MSREP_ERR_ARG, "%s: lptr_d is NULL", who);
   if (phase != kPhaseStructure) {
     if (A->m > 0 && !y_d) return fail(MSREP_ERR_ARG, "%s: y_d is NULL", who);
     if (A->nnz > 0 && !x_d) return fail(MSREP_ERR_ARG, "%s: x_d is NULL", who);
@@ -363,11 +371,11 @@ msrep_status spmv_entry(const msrep_mat *A, const msrep_part *parts_d, const int
   if (xb >= (uint64_t(1) << 32) || yb >= (uint64_t(1) << 32) ||
       (static_cast<uint64_t>(major_dim(A)) + 1) * 4 >= (uint64_t(1) << 32))
     return fail(MSREP_ERR_UNSUPPORTED, "%s: x or y larger than 4 GiB", who);
-  if (A->fmt == MSREP_CSC) {
+  if (A->fmt == MSREP_CSC || A->fmt == MSREP_COO_ANY) {
     CscLayout L;
     if (!csc_layout(A->m, A->nnz, np, 8, L))
-      return fail(MSREP_ERR_UNSUPPORTED, "%s: CSC supports at most %d rows", who,
-                  kCscMaxBuckets << kCscMaxShift);
+      return fail(MSREP_ERR_UNSUPPORTED, "%s: CSC and unsorted COO support at most %d rows",
+                  who, kCscMaxBuckets << kCscMaxShift);
   }
   const size_t need = msrep_spmv_ws_bytes(A, np);
   if (!ws_d || ws_bytes < need)

@@ -475,6 +475,141 @@ __global__ __launch_bounds__(kCscScatterWaves * kWave) void csc_scatter(
   store_prev();
 }
 
+// The same bucketed SpMV on COO in any order (MSREP_COO_ANY): every
+// partition's partial vector is kept sparse exactly as for CSC (the
+// column-style merge the paper names for COO that is not row-sorted), but
+// each nonzero's column is read from col_idx instead of being found from a
+// local column pointer.  Partitions are equal-nnz position ranges.
+template <int K>
+__device__ __forceinline__ void load_cols(const int32_t *__restrict__ idx, int64_t s0, int32_t cb,
+                                          int32_t nloc, int32_t (&c)[K]) {
+  constexpr int CH = kWave * K;
+  const int32_t span = nloc - cb < CH ? nloc - cb : CH;
+  const int32_t n_ok = span > 0 ? span : 0;
+  const rsrc_t ri = make_rsrc(idx + s0 + cb, static_cast<uint32_t>(n_ok) * 4u);
+  const uint32_t l = static_cast<uint32_t>(lane_id() * K);
+  buf_load_vec<int32_t, K, kNt>(ri, l * 4u, c);
+}
+
+template <int VT, int K, bool PACK>
+__global__ __launch_bounds__(kCscScatterWaves * kWave) void coo_any_scatter(
+    const int32_t *__restrict__ row_idx, const int32_t *__restrict__ col_idx,
+    const typename vt_traits<VT>::V *__restrict__ val, int64_t nnz,
+    const msrep_part *__restrict__ parts, int32_t np, int32_t P,
+    const typename vt_traits<VT>::T *__restrict__ x, int32_t m, int32_t n, int shift, int32_t nb,
+    const int32_t *__restrict__ off, typename vt_traits<VT>::A *__restrict__ prod,
+    uint16_t *__restrict__ rlo) {
+  using Tr = vt_traits<VT>;
+  using V = typename Tr::V;
+  using T = typename Tr::T;
+  using Acc = typename Tr::A;
+  constexpr int CH = kWave * K;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  int32_t *cur = reinterpret_cast<int32_t *>(lds_raw);
+  const int wid = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int lane = lane_id();
+  const int p = xcd_block(blockIdx.x, gridDim.x);
+  for (int i = threadIdx.x; i < nb + kWave; i += blockDim.x)
+    cur[i] = i < nb ? off[static_cast<int64_t>(i) * P + p] : 0;
+  __syncthreads();
+  const uint32_t mask = (1u << shift) - 1u;
+  const int32_t spare = static_cast<int32_t>(nnz);  // nnz < 2^31
+  const rsrc_t rx = make_rsrc(x, static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(T)));
+  int64_t pa, pb;
+  producer_range(p, np, P, pa, pb);
+  // partition pi's first position and length (an empty one has none)
+  auto range = [&](int64_t pi, int64_t &s0, int32_t &nloc) {
+    s0 = uniform(parts[pi].start_idx);
+    nloc = static_cast<int32_t>(uniform(parts[pi].end_idx) - s0 + 1);
+  };
+  auto first_nonempty = [&](int64_t pi, int64_t &s0, int32_t &nloc) {
+    for (; pi < pb; pi += wpb) {
+      range(pi, s0, nloc);
+      if (nloc > 0) break;
+    }
+    return pi;
+  };
+  int64_t s_c = 0, s_n = 0;
+  int32_t n_c = 0, n_n = 0;
+  int64_t pi = first_nonempty(pa + wid, s_c, n_c);
+  int64_t pn = pi < pb ? first_nonempty(pi + wpb, s_n, n_n) : pb;
+  int32_t cb = pi < pb ? -static_cast<int32_t>(s_c % K) : 0;
+  int32_t rows[K], cols[K];
+  V v[K];
+  load_items<V, K>(row_idx, val, s_c, cb, pi < pb ? n_c : cb, rows, v);
+  load_cols<K>(col_idx, s_c, cb, pi < pb ? n_c : cb, cols);
+  // the previous chunk's products, positions and row bits (none yet: spare)
+  Acc pr_p[K];
+  int32_t at_p[K], lo_p[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    pr_p[t] = Acc(0);
+    at_p[t] = spare;
+    lo_p[t] = 0;
+  }
+  auto store_prev = [&]() {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      if constexpr (PACK) {
+        rec_store<Acc>(reinterpret_cast<unsigned char *>(prod), at_p[t], pr_p[t],
+                       static_cast<uint32_t>(lo_p[t]));
+      } else {
+        prod[at_p[t]] = pr_p[t];
+        rlo[at_p[t]] = static_cast<uint16_t>(lo_p[t]);
+      }
+    }
+  };
+  while (pi < pb) {
+    bool okk[K];
+    T xv[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int32_t q = cb + lane * K + t;
+      okk[t] = q >= 0 && q < n_c && static_cast<uint32_t>(rows[t]) < static_cast<uint32_t>(m);
+      xv[t] = buf_load<T>(rx, okk[t] && static_cast<uint32_t>(cols[t]) < static_cast<uint32_t>(n)
+                                  ? static_cast<uint32_t>(cols[t]) * static_cast<uint32_t>(sizeof(T))
+                                  : ~0u);
+    }
+    store_prev();
+    // the next chunk (the same partition, or the first of the next one)
+    const bool same = cb + CH < n_c;
+    const bool more = same || pn < pb;
+    const int64_t sq = same ? s_c : s_n;
+    const int32_t nq = same ? n_c : n_n;
+    const int32_t cb_n = same ? cb + CH : -static_cast<int32_t>(s_n % K);
+    int32_t rows_n[K], cols_n[K];
+    V v_n[K];
+    load_items<V, K>(row_idx, val, sq, cb_n, more ? nq : cb_n, rows_n, v_n);
+    load_cols<K>(col_idx, sq, cb_n, more ? nq : cb_n, cols_n);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      pr_p[t] = Tr::val(v[t]) * static_cast<Acc>(xv[t]);
+      const int32_t slot = okk[t] ? static_cast<int32_t>(static_cast<uint32_t>(rows[t]) >> shift)
+                                  : nb + lane;
+      const int32_t a = atomicAdd(&cur[slot], 1);
+      at_p[t] = okk[t] && static_cast<uint32_t>(a) < static_cast<uint32_t>(spare) ? a : spare;
+      lo_p[t] = static_cast<int32_t>(static_cast<uint32_t>(rows[t]) & mask);
+    }
+    if (same) {
+      cb = cb_n;
+    } else {
+      pi = pn;
+      s_c = s_n;
+      n_c = n_n;
+      cb = cb_n;
+      if (pi < pb) pn = first_nonempty(pi + wpb, s_n, n_n);
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      rows[t] = rows_n[t];
+      cols[t] = cols_n[t];
+      v[t] = v_n[t];
+    }
+  }
+  store_prev();
+}
+
 // Exclusive scan of one int per thread over a block of kPlanBlock threads
 // (DPP within wavefronts, wavefront totals through LDS); returns the total.
 constexpr int kPlanBlock = 1024;

@@ -35,11 +35,12 @@ __global__ void check_compressed(const int32_t *__restrict__ ptr, int32_t rows,
 }
 
 __global__ void check_coo(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
-                          int64_t nnz, int32_t m, int32_t n, unsigned long long *first) {
+                          int64_t nnz, int32_t m, int32_t n, bool sorted,
+                          unsigned long long *first) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < nnz; k += stride) {
     if (static_cast<uint32_t>(row[k]) >= static_cast<uint32_t>(m)) report(first, k, kRowRange);
-    if (k > 0 && row[k - 1] > row[k]) report(first, k, kRowOrder);
+    if (sorted && k > 0 && row[k - 1] > row[k]) report(first, k, kRowOrder);
     if (static_cast<uint32_t>(col[k]) >= static_cast<uint32_t>(n)) report(first, k, kIdxRange);
   }
 }
@@ -77,10 +78,10 @@ extern "C" msrep_status msrep_validate(const msrep_mat *A, void *stream) {
   MSREP_LAUNCHED("set_u64");
   const int64_t work = (A->nnz > A->m ? A->nnz : A->m) + 1;
   const int grid = static_cast<int>((work + 255) / 256 < 8192 ? (work + 255) / 256 : 8192);
-  if (A->fmt == MSREP_COO) {
+  if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY) {
     if (A->nnz > 0) {
       hipLaunchKernelGGL(check_coo, dim3(grid), dim3(256), 0, s, A->idx, A->idx2, A->nnz, A->m,
-                         A->n, word);
+                         A->n, A->fmt == MSREP_COO, word);
       MSREP_LAUNCHED("check_coo");
     }
   } else {

@@ -105,6 +105,25 @@ def test_spmv_prepare_argument_errors():
         assert st == -3 and b"msrep_spmv_prepared" in L.msrep_last_error()
 
 
+def test_coo_any_order_checks():
+    """COO in any order: workspace like CSC, col_idx required, no conversion."""
+    L = _lib()
+    d = _desc(fmt=3, m=1 << 20, n=1 << 20, nnz=1 << 24, idx2=0x2800)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(d), 16384) >= 12 * (1 << 24)
+    bad = _desc(fmt=3, idx2=None)
+    st = L.msrep_build_partition(ctypes.byref(bad), 4, 0x4000, None, 0, None, None)
+    assert st == -1 and b"idx2" in L.msrep_last_error()
+    src = _desc(fmt=3, idx2=0x2800)
+    dst = _desc(fmt=0)
+    st = L.msrep_convert(ctypes.byref(src), ctypes.byref(dst), 0x9000, 1 << 20, None)
+    assert st == -7 and b"any order" in L.msrep_last_error()
+    st = L.msrep_convert(ctypes.byref(_desc(fmt=0)), ctypes.byref(_desc(fmt=3, idx2=0x2800)),
+                         0x9000, 1 << 20, None)
+    assert st == -7
+    big = _desc(fmt=3, m=(1 << 26) + 1, n=4, nnz=4, idx2=0x2800)
+    assert L.msrep_spmv_ws_bytes(ctypes.byref(big), 8) == 0
+
+
 def test_csc_workspace_and_row_limit():
     """The CSC path keeps one product and its row offset per nonzero in its
     workspace (room for the 12-byte FP64 / 8-byte FP32 records); its row

@@ -299,6 +299,74 @@ def test_equal_rows_baseline_partitions(fmt):
             assert_close(yd.cpu().numpy(), ref, sc, F64_TOL, "rows %s %s np%d" % (A.name, fmt, np_))
 
 
+def _coo_any(A, vt, seed):
+    """A as COO in a seeded random order: device Mat, and the shuffled host
+    arrays with the FP64 image of the stored values."""
+    from gpu_common import stored_values
+    rows = oracle.csr_to_coo(A.m, A.ptr)
+    perm = np.random.default_rng(seed).permutation(A.nnz)
+    r, c, v = rows[perm], A.col[perm], A.val[perm]
+    sv, v64 = stored_values(v, vt)
+    M = pk.Mat(pk.COO_ANY, vt, A.m, A.n, idx=r, idx2=c, val=sv)
+    return M, r, c, v64
+
+
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_coo_any_order(vt):
+    """COO in any order runs the bucketed (column-style merge) path: every
+    result matches the oracle on the same shuffled arrays, for many np,
+    both product layouts, alpha and beta; partitions are equal-nnz ranges."""
+    tol = F64_TOL if vt == 0 else F32_TOL
+    rng = np.random.default_rng(23)
+    sets = _tiny_set()[1:] + [synth.rmat_csr(scale=14, edge_factor=16, seed=9),
+                              synth.stencil7_csr(32)]
+    for k, (A, x) in enumerate(sets):
+        M, r, c, v64 = _coo_any(A, vt, 100 + k)
+        xs = np.asarray(x, np.float64 if vt == pk.F64 else np.float32)
+        xd = torch.from_numpy(np.ascontiguousarray(xs)).to(_dev())
+        y_in = rng.uniform(-1, 1, A.m).astype(xs.dtype)
+        for np_ in sorted({1, 7, 1000, A.nnz + 3}):
+            P = pk.msrep_build_partition(M, np_)
+            rec, _ = P.host()
+            i = np.arange(np_, dtype=np.int64)
+            assert np.array_equal(rec["start_idx"], i * A.nnz // np_)
+            assert np.array_equal(rec["end_idx"], (i + 1) * A.nnz // np_ - 1)
+            for pf in (1, 2):
+                for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
+                    y = torch.from_numpy(y_in.copy()).to(_dev())
+                    pk.msrep_spmv(M, P, xd, y, alpha, beta, pk.Tune(pipeline=pf))
+                    torch.cuda.synchronize()
+                    yi = None if beta == 0.0 else y_in.astype(np.float64)
+                    ref, sc = oracle.spmv_coo(A.m, A.n, r, c, v64, xs.astype(np.float64), alpha,
+                                              beta, yi)
+                    assert_close(y.cpu().numpy(), ref, sc, tol,
+                                 "%s coo_any vt%d np%d pf%d b%g" % (A.name, vt, np_, pf, beta))
+
+
+def test_coo_any_dyadic_bit_exact_and_prepared():
+    """Dyadic inputs: bit-exact against the oracle for every np, also through
+    msrep_spmv_prepare / msrep_spmv_prepared."""
+    A, _ = synth.rmat_csr(scale=15, edge_factor=16, seed=4)
+    rng = np.random.default_rng(4)
+    A.val = synth.dyadic(rng, A.nnz)
+    x = synth.dyadic(rng, A.n)
+    M, r, c, v64 = _coo_any(A, pk.F64, 7)
+    ref, _ = oracle.spmv_coo(A.m, A.n, r, c, v64, x)
+    xd = torch.from_numpy(x).to(_dev())
+    for np_ in (1, 5, 4096, A.nnz + 7):
+        P = pk.msrep_build_partition(M, np_)
+        y = torch.full((A.m,), float("nan"), dtype=torch.float64, device=_dev())
+        pk.msrep_spmv(M, P, xd, y)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), ref), np_
+        ws = pk.msrep_spmv_prepare(M, P)
+        for pf in (1, 2):
+            y2 = torch.full((A.m,), float("nan"), dtype=torch.float64, device=_dev())
+            pk.msrep_spmv_prepared(M, P, xd, y2, ws, tune=pk.Tune(pipeline=pf))
+            torch.cuda.synchronize()
+            assert np.array_equal(y2.cpu().numpy(), ref), (np_, pf)
+
+
 @pytest.mark.parametrize("fmt", ["csr", "coo"])
 def test_deterministic(fmt):
     A, x = synth.rmat_csr(scale=14, edge_factor=16, seed=5)
