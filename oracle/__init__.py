@@ -10,6 +10,9 @@ Every function cites, in the C source, the passage of the paper it follows.
 
 Pins (tests/test_oracle_*.py check this oracle against values fixed by the
 paper or by mathematics, never against itself):
+  * SpMM (several right-hand sides): numpy dense products and exact
+    rational arithmetic on small cases, and its columns against the SpMV
+    pins' closed forms (stencil times ones).
   * SpMV: exact rational arithmetic (fractions) on small random matrices,
     numpy dense products, scipy.sparse, identity / permutation / diagonal
     special cases, the 7-point stencil times ones in closed form, dyadic
@@ -61,6 +64,8 @@ def _load():
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         vp = ctypes.c_void_p
         _lib.oracle_spmv_csr.argtypes = [i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
+        _lib.oracle_spmm_csr.argtypes = [i32, i32, i32, vp, vp, vp, vp, i64, dbl, dbl, vp, i64,
+                                         vp, vp]
         _lib.oracle_spmv_csc.argtypes = [i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
         _lib.oracle_spmv_coo.argtypes = [i32, i32, i64, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
         _lib.oracle_partition_ptr.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
@@ -68,7 +73,7 @@ def _load():
         _lib.oracle_csr_to_coo.argtypes = [i32, vp, vp]
         _lib.oracle_coo_to_csr.argtypes = [i32, i64, vp, vp]
         _lib.oracle_transpose.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
-        for f in ("oracle_spmv_csr", "oracle_spmv_csc", "oracle_spmv_coo",
+        for f in ("oracle_spmv_csr", "oracle_spmm_csr", "oracle_spmv_csc", "oracle_spmv_coo",
                   "oracle_partition_ptr", "oracle_partition_coo", "oracle_csr_to_coo",
                   "oracle_coo_to_csr", "oracle_transpose"):
             getattr(_lib, f).restype = ctypes.c_int
@@ -106,6 +111,29 @@ def spmv_csr(m, n, row_ptr, col_idx, val, x, alpha=1.0, beta=0.0, y_in=None):
     _check(lib.oracle_spmv_csr(m, n, _p(row_ptr), _p(col_idx), _p(val), _p(x), alpha, beta,
                                _p(yi), _p(y), _p(s)), "spmv_csr")
     return y, s
+
+
+def spmm_csr(m, n, row_ptr, col_idx, val, X, alpha=1.0, beta=0.0, Y_in=None):
+    """Y = alpha*A*X + beta*Y_in for CSR A and the k columns of X (n x k);
+    returns (Y, scale), both m x k, scale = |alpha|*(|A||X|) + |beta|*|Y_in|."""
+    lib = _load()
+    row_ptr, col_idx = _c(row_ptr, np.int32), _c(col_idx, np.int32)
+    val = _c(val, np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim != 2 or X.shape[0] != n:
+        raise ValueError("X must be n x k")
+    k = X.shape[1]
+    if beta != 0.0:
+        Yi = np.ascontiguousarray(Y_in, dtype=np.float64)
+        if Yi.shape != (m, k):
+            raise ValueError("Y_in must be m x k")
+    else:
+        Yi = np.zeros((m, k), np.float64)
+    Y = np.empty((m, k), np.float64)
+    S = np.empty((m, k), np.float64)
+    _check(lib.oracle_spmm_csr(m, n, k, _p(row_ptr), _p(col_idx), _p(val), _p(X), k, alpha,
+                               beta, _p(Yi), k, _p(Y), _p(S)), "spmm_csr")
+    return Y, S
 
 
 def spmv_csc(m, n, col_ptr, row_idx, val, x, alpha=1.0, beta=0.0, y_in=None):

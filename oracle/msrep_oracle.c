@@ -17,6 +17,8 @@
  *     Algorithm 1; CSC swaps the roles of x and y; COO is a single loop over
  *     the nonzeros), every row's dot product accumulated with Dot2 so the
  *     oracle's own error is negligible next to any tolerance.
+ *   - The same product for k right-hand sides (a row-major block X), every
+ *     column as Algorithm 1.
  *   - The partition metadata of pCSR / pCSC / pCOO (Sec. 3.2.1-3.2.3,
  *     Algorithms 2, 4 and 6) including each partition's local row pointer.
  *   - Format conversions between CSR, CSC and row-sorted COO (Sec. 2.1).
@@ -141,6 +143,38 @@ int oracle_spmv_csr(int32_t m, int32_t n, const int32_t *row_ptr,
     double yi = (beta != 0.0) ? y_in[i] : 0.0;
     y_out[i] = dot2_finish(&acc, alpha, beta, yi);
     if (scale_out) scale_out[i] = row_scale(abs_dot, alpha, beta, yi);
+  }
+  return ORACLE_OK;
+}
+
+/* Several right-hand sides (the multi-vector product that Sec. 2 names
+ * beside SpMV): Y = alpha*A*X + beta*Y_in for the k columns of the row-major
+ * X (n x k, row c at X + c*ldx) and Y (m x k, row i at Y + i*ldy), i.e.
+ * Algorithm 1 once per column, each (row, column) dot product kept in its own
+ * Dot2 accumulator.  Columns beyond k are not touched.  scale_out (m x k,
+ * leading dimension k) may be NULL. */
+int oracle_spmm_csr(int32_t m, int32_t n, int32_t k, const int32_t *row_ptr,
+                    const int32_t *col_idx, const double *val, const double *X,
+                    int64_t ldx, double alpha, double beta, const double *Y_in,
+                    int64_t ldy, double *Y_out, double *scale_out) {
+  if (m < 0 || n < 0 || k < 0 || !row_ptr || ldx < k || ldy < k) return ORACLE_ERR_ARG;
+  if (k == 0 || m == 0) return ORACLE_OK;
+  if (!Y_out) return ORACLE_ERR_ARG;
+  for (int64_t i = 0; i < m; ++i) {
+    for (int64_t t = 0; t < k; ++t) {
+      dot2_acc acc = {0.0, 0.0};
+      double abs_dot = 0.0;
+      for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
+        int32_t c = col_idx[j];
+        if (c < 0 || c >= n) return ORACLE_ERR_FORMAT;
+        double xv = X[(int64_t)c * ldx + t];
+        dot2_add_prod(&acc, val[j], xv);
+        abs_dot += fabs(val[j]) * fabs(xv);
+      }
+      double yi = (beta != 0.0) ? Y_in[i * ldy + t] : 0.0;
+      Y_out[i * ldy + t] = dot2_finish(&acc, alpha, beta, yi);
+      if (scale_out) scale_out[i * k + t] = row_scale(abs_dot, alpha, beta, yi);
+    }
   }
   return ORACLE_OK;
 }
