@@ -321,6 +321,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20",
                     choices=["rmat20", "stencil256", "uniform4096", "batched", "serve"])
+    ap.add_argument("--rhs", type=int, default=0,
+                    help="k > 0: time msrep_spmm with k right-hand sides (CSR) instead")
     ap.add_argument("--count", type=int, default=512, help="batched / serving pool size")
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     ap.add_argument("--rates", default="0.1,0.5,0.9,1.2", help="serving: fractions of capacity")
@@ -372,6 +374,8 @@ def main():
         return 1
     dev = torch.device("cuda:0")
     vt = {"f64": pk.F64, "f32": pk.F32, "bf16": pk.BF16}[args.vtype]
+    if args.rhs > 0:
+        return bench_spmm(args, vt)
     if args.workload == "batched":
         return bench_batched(args, vt)
     if args.workload == "serve":
@@ -612,6 +616,138 @@ def _timed(fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def bench_spmm(args, vt):
+    """Y = A*X for k right-hand sides (msrep_spmm, CSR) on the R-MAT or
+    stencil workload, each call cold in HBM, against k single-vector CSR
+    SpMVs (msrep_spmv, the tuned launch shape) over the same columns after
+    one scrub.  The roofline is that of the spmm_csr kernel: A, its row
+    pointer, X and Y each moved once per pass of up to eight columns."""
+    import torch
+
+    import oracle
+    import paper_2209_07552_amd as pk
+    import synth
+    dev = torch.device("cuda:0")
+    k = args.rhs
+    t0 = time.time()
+    if args.workload == "stencil256":
+        A, _ = synth.stencil7_csr(256, seed=0)
+        wl = {"workload": "laplace3d-7pt-256^3", "rows": A.m, "cols": A.n, "nnz": A.nnz}
+    else:
+        A, _ = synth.rmat_csr(scale=20, edge_factor=16, seed=0)
+        wl = {"workload": "rmat-scale20-ef16", "rows": A.m, "cols": A.n, "nnz": A.nnz,
+              "abcd": [0.57, 0.19, 0.19, 0.05]}
+    log("generated %s in %.1fs" % (wl["workload"], time.time() - t0))
+    vdt = np.float64 if vt == pk.F64 else np.float32
+    tdt = torch.float64 if vt == pk.F64 else torch.float32
+    vb, xb = pk._abi.VALUE_BYTES[vt], (8 if vt == pk.F64 else 4)
+    sv = A.val.astype(vdt) if vt != pk.BF16 else synth.bf16_bits(A.val.astype(np.float32))
+    M = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=A.ptr, idx=A.col, val=sv)
+    npw = args.nnz_per_wave or {"stencil256": 2048}.get(args.workload, 512)
+    P = pk.msrep_build_partition(M, max(1, -(-A.nnz // npw)))
+    rng = np.random.default_rng(1)
+    X64 = rng.uniform(-1, 1, (A.n, k))
+    Xd = torch.from_numpy(X64.astype(vdt)).to(dev)
+    Yd = torch.zeros((A.m, k), dtype=tdt, device=dev)
+    ws = torch.zeros(max(256, pk.msrep_spmm_ws_bytes(M, P.np, k)), dtype=torch.uint8, device=dev)
+    scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
+
+    def spmm():
+        pk.msrep_spmm(M, P, Xd, Yd, 1.0, 0.0, ws=ws)
+
+    def steps(n_, timing):
+        evs, kt = [], (0, 0.0)
+        for _ in range(n_):
+            scrub.fill_(1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            pk.msrep_timing(timing)
+            pk.msrep_timing_only("spmm_csr" if timing else None)
+            e0.record()
+            spmm()
+            e1.record()
+            if timing:
+                for name, (c, t) in pk.msrep_timing_read().items():
+                    if name == "spmm_csr":
+                        kt = (kt[0] + c, kt[1] + t)
+            evs.append((e0, e1))
+        pk.msrep_timing(False)
+        pk.msrep_timing_only(None)
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs], kt
+
+    steps(args.warmup, False)
+    wall0 = time.perf_counter()
+    ms, kt = steps(args.steps, True)
+    wall = time.perf_counter() - wall0
+    ms_spmm = float(np.mean(ms))
+    passes = []
+    left = k
+    while left > 0:
+        nr = 8 if left >= 8 else 4 if left >= 4 else 2 if left >= 2 else 1
+        passes.append(nr)
+        left -= nr
+    k_us = kt[1] / kt[0] * 1e3 if kt[0] else float("nan")  # per pass launch
+    pass_bytes = [A.nnz * (vb + 4) + (A.m + 1) * 4 + nr * (A.n + A.m) * xb for nr in passes]
+    k_bytes = float(np.mean(pass_bytes))
+    achieved = k_bytes / (k_us * 1e-6) / 1e9
+    call_bytes = sum(pass_bytes)
+    # comparator: k single-vector SpMVs (tuned CSR launch shape and partitions)
+    st = DEFAULT_TUNES.get(args.workload, {}).get("csr", (512, 4, 8, 2, 1))
+    tune = pk.Tune(k_per_lane=st[1], waves_per_wg=st[2], nnz_per_wave=st[0], pipeline=st[3],
+                   resident=st[4])
+    P1 = pk.msrep_build_partition(M, max(1, -(-A.nnz // st[0])))
+    ws1 = torch.zeros(max(256, pk.msrep_spmv_ws_bytes(M, P1.np)), dtype=torch.uint8, device=dev)
+    xs = [Xd[:, j].contiguous() for j in range(k)]
+    ys = [torch.zeros(A.m, dtype=tdt, device=dev) for _ in range(k)]
+
+    def spmvs():
+        for j in range(k):
+            pk.msrep_spmv(M, P1, xs[j], ys[j], 1.0, 0.0, tune, ws=ws1)
+    ms_v = []
+    for i in range(args.warmup + args.steps):
+        scrub.fill_(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        spmvs()
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            ms_v.append(e0.elapsed_time(e1))
+    ms_spmv = float(np.mean(ms_v))
+    flops = 2.0 * A.nnz * k
+    out = {"metric": "SpMM GFLOP/s (k right-hand sides, CSR, cold HBM)",
+           "value": round(flops / (ms_spmm * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_spmm, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.vtype, "data": "synthetic",
+           "config": dict(wl, rhs=k, layout="row-major X (n x k), Y (m x k)", np=P.np,
+                          nnz_per_wave=npw, passes=passes),
+           "alg_gbs": round(call_bytes / (ms_spmm * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": load_traffic("spmm_csr/%s/%s/k%d" % (wl["workload"], args.vtype, k)),
+                        "kernel": "spmm_csr", "kernel_avg_us": round(k_us, 2),
+                        "alg_bytes_per_launch": int(k_bytes)},
+           "k_spmv": {"ms": round(ms_spmv, 4), "gflops": round(flops / (ms_spmv * 1e-3) / 1e9, 3),
+                      "entry": "msrep_spmv x %d" % k, "np": P1.np},
+           "speedup_vs_k_spmv": round(ms_spmv / ms_spmm, 3),
+           "wall_s_timed_region": round(wall, 3)}
+    # correctness of this run's Y against the oracle, and the oracle's own
+    # rate (its whole product, one thread) as the CPU baseline
+    if not args.no_cpu and vt == pk.F64:
+        c0 = time.perf_counter()
+        ref, sc = oracle.spmm_csr(A.m, A.n, A.ptr, A.col, A.val, X64)
+        cpu_s = time.perf_counter() - c0
+        yg = Yd.double().cpu().numpy()
+        err = float(np.max(np.abs(yg - ref) / np.where(sc > 0, sc, 1.0)))
+        out["cpu_baseline"] = {"value": round(flops / cpu_s / 1e9, 4), "unit": "GFLOP/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "one whole product (%d columns), FP64 Dot2" % k}
+        out["max_scaled_error_vs_oracle"] = err
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def bench_batched(args, vt):

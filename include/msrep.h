@@ -281,6 +281,35 @@ size_t msrep_autotune_ws_bytes(const msrep_mat *A);
 msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void *ws_d,
                             size_t ws_bytes, msrep_tune *out, void *stream);
 
+/* --------------------------------------------- several right-hand sides */
+/*
+ * Y = alpha*A*X + beta*Y for k right-hand sides at once (a multi-vector
+ * SpMV, the SpMM mentioned beside SpMV in the paper's Sec. 2): the same
+ * equal-nnz CSR partitions and boundary merge as msrep_spmv (Algorithm 3,
+ * Sec. 4.3), applied to every column.  A is read once per pass of up to
+ * eight columns instead of once per column.
+ *   A: CSR only (others: MSREP_ERR_UNSUPPORTED); parts_d, lptr_d, np as
+ *   built by msrep_build_partition for A.
+ *   X_d: n x k, row-major, leading dimension ldx >= k elements (row i at
+ *   X_d + i*ldx); Y_d: m x k, row-major, ldy >= k.  Element type FP64 for
+ *   F64 values, FP32 for F32 and BF16 values, as for msrep_spmv.  Columns
+ *   k..ld-1 are neither read nor written.  beta == 0: Y is not read.
+ *   ws_d: msrep_spmm_ws_bytes(A, np, k) bytes of device memory (the FP64
+ *   partial sums of split rows, 16 bytes per partition and column of a
+ *   pass), caller-owned; its contents need not be kept between calls.
+ *   All buffers are caller-owned device memory; kernels are launched on
+ *   stream and nothing is synchronised.  k == 0 or m == 0 is a no-op.
+ * Errors: MSREP_ERR_ARG (NULL pointers, np <= 0, k < 0, ld < k),
+ * MSREP_ERR_SIZE (workspace too small), MSREP_ERR_UNSUPPORTED (format).
+ * Column j of Y equals msrep_spmv with x = column j of X up to the order of
+ * the additions inside a partition.
+ */
+size_t msrep_spmm_ws_bytes(const msrep_mat *A, int32_t np, int32_t k);
+msrep_status msrep_spmm(const msrep_mat *A, const msrep_part *parts_d, const int32_t *lptr_d,
+                        int32_t np, int32_t k, const void *X_d, int64_t ldx, void *Y_d,
+                        int64_t ldy, double alpha, double beta, void *ws_d, size_t ws_bytes,
+                        void *stream);
+
 /* ------------------------------------------------------------- batched */
 /*
  * A plan runs y_k = alpha*A_k*x_k + beta*y_k for count matrices in one

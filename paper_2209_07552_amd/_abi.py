@@ -106,6 +106,9 @@ def load_library():
         "msrep_spmv_prepare": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
         "msrep_spmv_prepared": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_vp, c_dbl, c_dbl,
                                         P(_Tune), c_vp, c_sz, c_vp]),
+        "msrep_spmm_ws_bytes": (c_sz, [P(_Mat), c_i32, c_i32]),
+        "msrep_spmm": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64,
+                               c_dbl, c_dbl, c_vp, c_sz, c_vp]),
         "msrep_autotune_ws_bytes": (c_sz, [P(_Mat)]),
         "msrep_autotune": (c_i32, [P(_Mat), c_vp, c_vp, c_sz, P(_Tune), c_vp]),
         "msrep_plan_ws_bytes": (c_sz, [c_i32, P(_Mat), P(_Tune)]),
@@ -393,6 +396,32 @@ def msrep_spmv_prepared(A: Mat, P: Partition, x, y, ws, alpha=1.0, beta=0.0,
                                  ctypes.byref(t) if t is not None else None, _ptr(ws),
                                  ws.numel(), _stream(stream)), "spmv_prepared")
     return y
+
+
+def msrep_spmm_ws_bytes(A: Mat, np_: int, k: int) -> int:
+    """Bytes of device workspace msrep_spmm needs for k right-hand sides."""
+    return int(load_library().msrep_spmm_ws_bytes(ctypes.byref(A.desc()), int(np_), int(k)))
+
+
+def msrep_spmm(A: Mat, P: Partition, X, Y, alpha=1.0, beta=0.0, ws=None, stream=None):
+    """Y <- alpha*A*X + beta*Y for the k columns of the row-major device
+    tensors X (n x k) and Y (m x k, updated in place; both may be column
+    slices of wider tensors, rows strided by their stride(0)); returns Y."""
+    torch = _require_gpu()
+    L = load_library()
+    d = A.desc()
+    if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y must be 2-D with the same number of columns")
+    if X.stride(1) != 1 or Y.stride(1) != 1:
+        raise ValueError("X and Y must have unit column stride (row-major)")
+    k = int(X.shape[1])
+    need = L.msrep_spmm_ws_bytes(ctypes.byref(d), P.np, k)
+    if ws is None:
+        ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=Y.device)
+    _check(L.msrep_spmm(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, k, _ptr(X),
+                        int(X.stride(0)), _ptr(Y), int(Y.stride(0)), float(alpha), float(beta),
+                        _ptr(ws), ws.numel(), _stream(stream)), "spmm")
+    return Y
 
 
 def msrep_convert(A: Mat, dst_fmt: int, stream=None) -> Mat:

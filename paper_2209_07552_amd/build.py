@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmsrep.so")
 
-SOURCES = ["partition.hip", "spmv.hip", "convert.hip", "validate.hip", "batched.hip",
+SOURCES = ["partition.hip", "spmv.hip", "spmm.hip", "convert.hip", "validate.hip", "batched.hip",
            "autotune.hip", "serve.hip", "timing.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -51,6 +51,11 @@ void timing_end(const char *name, hipStream_t s);
 
 // O(1) descriptor checks shared by every entry point.
 msrep_status check_mat(const msrep_mat *A, const char *who);
+// Boundary merge of the row-split formats over ncols right-hand sides: column
+// j of y (row stride ldy) from the carries at carry + j*cstride.
+msrep_status launch_merge_rows(const msrep_mat *A, const msrep_part *parts, int32_t np,
+                               const double *carry, void *y, double alpha, double beta,
+                               int64_t ldy, int64_t cstride, int ncols, hipStream_t s);
 int value_bytes(int32_t vtype);
 // x / y element size for a matrix of this value type.
 inline int vec_bytes(int32_t vtype) { return vtype == MSREP_F64 ? 8 : 4; }

@@ -259,22 +259,37 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
     st = b0 ? dispatch_rows<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s)
             : dispatch_rows<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s);
   if (st) return st;
-  if (np > 1) {
-    const int g = (np + 255) / 256;
-    timing_begin("merge_rows", s);
-    if (b0)
-      hipLaunchKernelGGL((merge_rows<T, true>), dim3(g), dim3(256), 0, s, parts, np, carry,
-                         static_cast<T *>(y), A->m, alpha, beta);
-    else
-      hipLaunchKernelGGL((merge_rows<T, false>), dim3(g), dim3(256), 0, s, parts, np, carry,
-                         static_cast<T *>(y), A->m, alpha, beta);
-    MSREP_LAUNCHED("merge_rows");
-    timing_end("merge_rows", s);
-  }
+  if (np > 1) return launch_merge_rows(A, parts, np, carry, y, alpha, beta, 1, 0, 1, s);
   return MSREP_OK;
 }
 
 }  // namespace
+
+msrep_status launch_merge_rows(const msrep_mat *A, const msrep_part *parts, int32_t np,
+                               const double *carry, void *y, double alpha, double beta,
+                               int64_t ldy, int64_t cstride, int ncols, hipStream_t s) {
+  const int g = (np + kMergeBlock - 1) / kMergeBlock;
+  const bool b0 = beta == 0.0;
+  timing_begin("merge_rows", s);
+  if (A->vtype == MSREP_F64) {
+    if (b0)
+      hipLaunchKernelGGL((merge_rows<double, true>), dim3(g, ncols), dim3(kMergeBlock), 0, s,
+                         parts, np, carry, static_cast<double *>(y), A->m, alpha, beta, ldy, cstride);
+    else
+      hipLaunchKernelGGL((merge_rows<double, false>), dim3(g, ncols), dim3(kMergeBlock), 0, s,
+                         parts, np, carry, static_cast<double *>(y), A->m, alpha, beta, ldy, cstride);
+  } else {
+    if (b0)
+      hipLaunchKernelGGL((merge_rows<float, true>), dim3(g, ncols), dim3(kMergeBlock), 0, s,
+                         parts, np, carry, static_cast<float *>(y), A->m, alpha, beta, ldy, cstride);
+    else
+      hipLaunchKernelGGL((merge_rows<float, false>), dim3(g, ncols), dim3(kMergeBlock), 0, s,
+                         parts, np, carry, static_cast<float *>(y), A->m, alpha, beta, ldy, cstride);
+  }
+  MSREP_LAUNCHED("merge_rows");
+  timing_end("merge_rows", s);
+  return MSREP_OK;
+}
 
 msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, int *resident,
                           const char *who) {

@@ -627,7 +627,12 @@ __global__ __launch_bounds__(kMergeBlock) void merge_rows(const msrep_part *__re
                                                           int32_t np,
                                                           const double *__restrict__ carry,
                                                           T *__restrict__ y, int32_t m,
-                                                          double alpha, double beta) {
+                                                          double alpha, double beta,
+                                                          int64_t ldy, int64_t cstride) {
+  // several right-hand sides: column blockIdx.y of y (stride ldy between
+  // rows) from its own block of carries
+  carry += blockIdx.y * cstride;
+  y += blockIdx.y;
   __shared__ double sh_s[kMergeWaves], sh_c[kMergeWaves];
   __shared__ int sh_f[kMergeWaves];
   const int t = threadIdx.x;
@@ -692,7 +697,8 @@ __global__ __launch_bounds__(kMergeBlock) void merge_rows(const msrep_part *__re
   const int32_t r = P.sr;
   if (r < 0 || r >= m) return;
   const double tot = at.s + at.c;
-  y[r] = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(y[r]));
+  T *yr = y + static_cast<int64_t>(r) * ldy;
+  *yr = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(*yr));
 }
 
 }  // namespace msrep

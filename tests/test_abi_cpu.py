@@ -150,3 +150,31 @@ def test_timing_toggle_and_empty_read():
     assert pk.msrep_timing_read() == {}
     pk.msrep_timing(False)
     assert L.msrep_timing_read(None, -1) == -1
+
+
+def test_spmm_argument_errors():
+    """msrep_spmm: CSR only, ld >= k, k >= 0, workspace per pass width, all
+    checked before any launch."""
+    L = _lib()
+    d = _desc(fmt=0)
+    assert L.msrep_spmm_ws_bytes(ctypes.byref(d), 100, 3) >= 16 * 100 * 3
+    assert L.msrep_spmm_ws_bytes(ctypes.byref(d), 100, 20) >= 16 * 100 * 8
+    assert L.msrep_spmm_ws_bytes(ctypes.byref(d), 0, 3) == 0
+    st = L.msrep_spmm(ctypes.byref(d), 0x4000, 0x5000, 8, 4, 0x6000, 3, 0x7000, 4, 1.0, 0.0,
+                      0x8000, 1 << 20, None)
+    assert st == -1 and b"ldx" in L.msrep_last_error()
+    st = L.msrep_spmm(ctypes.byref(d), 0x4000, 0x5000, 8, -1, 0x6000, 3, 0x7000, 4, 1.0, 0.0,
+                      0x8000, 1 << 20, None)
+    assert st == -1
+    st = L.msrep_spmm(ctypes.byref(d), 0x4000, 0x5000, 8, 4, 0x6000, 4, 0x7000, 4, 1.0, 0.0,
+                      0x8000, 16, None)
+    assert st == -3 and b"workspace" in L.msrep_last_error()
+    for fmt in (1, 2, 3):
+        e = _desc(fmt=fmt, idx2=0x2800 if fmt >= 2 else None)
+        st = L.msrep_spmm(ctypes.byref(e), 0x4000, 0x5000, 8, 4, 0x6000, 4, 0x7000, 4, 1.0,
+                          0.0, 0x8000, 1 << 20, None)
+        assert st == -7 and b"CSR" in L.msrep_last_error()
+    # k == 0: nothing to do, nothing launched
+    st = L.msrep_spmm(ctypes.byref(d), 0x4000, 0x5000, 8, 0, None, 0, None, 0, 1.0, 0.0, None, 0,
+                      None)
+    assert st == 0
