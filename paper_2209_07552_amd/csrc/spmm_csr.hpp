@@ -25,6 +25,9 @@
 // completes column by column.
 #pragma once
 
+#include <climits>
+#include <type_traits>
+
 #include "spmv_csr.hpp"
 
 namespace msrep {
@@ -144,6 +147,10 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
       const rsrc_t rv = make_rsrc(val + off, cnt * static_cast<uint32_t>(sizeof(V)));
       ci = buf_load<int32_t, kNt>(rc, static_cast<uint32_t>(lane) * 4u);
       vi = buf_load<V, kNt>(rv, static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(V)));
+      // past the partition: column -1, whose X offset lies past X's
+      // resource (the host keeps (n + 1) * ldx elements below 4 GiB), so
+      // x = 0 and value = 0 there and the product is exactly 0
+      ci = static_cast<uint32_t>(lane) < cnt ? ci : -1;
     };
     auto gather = [&](int32_t ci, T(&xv)[NR]) {
 #pragma unroll
@@ -225,12 +232,14 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
       const int32_t mk = s_mark[lane];
       int32_t rr = wave_max_scan_nonneg(mk);
       rr = rr > j0 ? rr : j0;
-      s_rows[lane] = rr;
+      // positions past the chunk's end get a row that no row equals
+      constexpr int32_t kNoRow = INT32_MIN;
+      s_rows[lane] = lane < nv ? rr : kNoRow;
       wave_lds_sync();
       int32_t rw[NR + 1];
 #pragma unroll
       for (int u = 0; u < NR; ++u) rw[u] = s_rows[q * NR + u];
-      rw[NR] = q + 1 < G ? s_rows[(q + 1) * NR] : -1;
+      rw[NR] = q + 1 < G ? s_rows[(q + 1) * NR] : kNoRow;
       const int32_t rprev = q > 0 ? s_rows[q * NR - 1] : rw[0];
       wave_lds_sync();  // s_mark / s_rows are rewritten by the next chunk
       // ---- 2. products, sequential segmented sums over the lane's positions
@@ -247,13 +256,16 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
           any = true;
         }
         const V vu = lane_pick(v_use, P);
-        const Acc pr = P < nv ? Tr::val(vu) * static_cast<Acc>(xv_use[u]) : Acc(0);
-        acc += pr;
+        acc += Tr::val(vu) * static_cast<Acc>(xv_use[u]);
         run[u] = acc;
         seen[u] = any;
       }
-      // segmented scan of the slot totals across slots (stride NR lanes)
-      Acc agg = acc;
+      // segmented scan of the slot totals across slots (stride NR lanes).
+      // FP64: the sum carried from the previous chunk enters as slot 0's
+      // incoming value; FP32 keeps it apart in FP64 and adds it at the end.
+      constexpr bool kFold = sizeof(Acc) == 8;
+      const Acc cvin = kFold && con ? static_cast<Acc>(cv) : Acc(0);
+      Acc agg = (q == 0 && !any) ? acc + cvin : acc;
       int f = any ? 1 : 0;
 #pragma unroll
       for (int d = NR; d < kWave; d *= 2) {
@@ -262,7 +274,8 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
         if (!f) agg += pv;
         f |= pf;
       }
-      const Acc cin = shift_up(agg, NR);  // the open segment up to the previous slot
+      const Acc cin0 = shift_up(agg, NR);  // the open segment up to the previous slot
+      const Acc cin = q == 0 ? cvin : cin0;
       // ---- 3. rows ending at this lane's positions: one buffer store per
       //         position on every lane (dropped where no row ends), so the
       //         number of stores after the next chunks' loads is fixed and
@@ -272,28 +285,41 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
       // position of a lane holds each)
       double hval = 0.0, tval = 0.0;
       bool hset = false, tset = false;
+      const int32_t skip_row = cont ? j1 : kNoRow + 1;  // the open row is carried, not written
+      // only the chunks holding the partition's first or last row can hold a
+      // partial row; the others take the short path
+      const bool edge = (sflag && j0 == 0) || (eflag && j1 == R - 1);
+      auto finish = [&](auto edge_c) {
+        constexpr bool EDGE = decltype(edge_c)::value;
 #pragma unroll
-      for (int u = 0; u < NR; ++u) {
-        const int32_t P = q * NR + u;
-        const int32_t rj = rw[u];
-        const bool tail = P < nv && (P == nv - 1 || rw[u + 1] != rj);
-        const bool done = tail && !(rj == j1 && cont);
-        double tot = static_cast<double>(seen[u] ? run[u] : run[u] + cin);
-        if (rj == j0 && con) tot += cv;
-        const bool head_c = done && rj == 0 && sflag;
-        const bool tail_c = done && !head_c && rj == R - 1 && eflag;
-        hval = head_c ? tot : hval;
-        tval = tail_c ? tot : tval;
-        hset = hset || head_c;
-        tset = tset || tail_c;
-        const bool to_y = done && !head_c && !tail_c;
-        const uint32_t off = to_y ? static_cast<uint32_t>(r0 + rj) * yrow + xcol : kNoStore;
-        double out = alpha * tot;
-        if (!BETA0) out += beta * static_cast<double>(buf_load<T>(ry, off));
-        buf_store<T>(ry, off, static_cast<T>(out));
+        for (int u = 0; u < NR; ++u) {
+          const int32_t rj = rw[u];
+          const bool done = rw[u + 1] != rj && rj != skip_row;
+          double tot = static_cast<double>(seen[u] ? run[u] : run[u] + cin);
+          if (!kFold && rj == j0 && con) tot += cv;
+          bool to_y = done;
+          if constexpr (EDGE) {
+            const bool head_c = done && rj == 0 && sflag;
+            const bool tail_c = done && !head_c && rj == R - 1 && eflag;
+            hval = head_c ? tot : hval;
+            tval = tail_c ? tot : tval;
+            hset = hset || head_c;
+            tset = tset || tail_c;
+            to_y = done && !head_c && !tail_c;
+          }
+          const uint32_t off = to_y ? static_cast<uint32_t>(r0 + rj) * yrow + xcol : kNoStore;
+          double out = alpha * tot;
+          if (!BETA0) out += beta * static_cast<double>(buf_load<T>(ry, off));
+          buf_store<T>(ry, off, static_cast<T>(out));
+        }
+      };
+      if (edge) {
+        finish(std::true_type{});
+        if (hset) cp[0] = hval;
+        if (tset) cp[1] = tval;
+      } else {
+        finish(std::false_type{});
       }
-      if (hset) cp[0] = hval;
-      if (tset) cp[1] = tval;
       if (cont) {  // column c of the open row, from the lane holding the chunk's last position
         const int ul = (nv - 1) % NR;
         Acc lv = Acc(0);
@@ -301,7 +327,7 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
         for (int u = 0; u < NR; ++u)
           if (u == ul) lv = seen[u] ? run[u] : run[u] + cin;
         const double open = static_cast<double>(lane_pick(lv, ((nv - 1) / NR) * NR + c));
-        cv = open + ((j1 == j0 && con) ? cv : 0.0);
+        cv = open + ((!kFold && j1 == j0 && con) ? cv : 0.0);
       }
       con = cont;
       j0 = j0n;
