@@ -79,7 +79,7 @@ __device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, E v) {
   else
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
 }
-constexpr uint32_t kNoStore = 0xFFFFFFF0u;  // offsets down to kNoStore - 255 are past every resource
+constexpr uint32_t kNoStore = 0xFFFFFFF0u;  // offsets down to kNoStore - 511 are past every resource
 
 // Rows [lo, hi) x columns [0, NR) get beta*Y (0 when beta == 0), lanes
 // striding over the elements.
@@ -147,16 +147,17 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
       const rsrc_t rv = make_rsrc(val + off, cnt * static_cast<uint32_t>(sizeof(V)));
       ci = buf_load<int32_t, kNt>(rc, static_cast<uint32_t>(lane) * 4u);
       vi = buf_load<V, kNt>(rv, static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(V)));
-      // past the partition: column -1, whose X offset lies past X's
-      // resource (the host keeps (n + 1) * ldx elements below 4 GiB), so
-      // x = 0 and value = 0 there and the product is exactly 0
-      ci = static_cast<uint32_t>(lane) < cnt ? ci : -1;
+      // the byte offset of the item's X row; past the partition an offset
+      // past X's resource, so x = 0 and value = 0 there and the product is
+      // exactly 0
+      ci = static_cast<uint32_t>(lane) < cnt ? static_cast<int32_t>(static_cast<uint32_t>(ci) * xrow)
+                                              : static_cast<int32_t>(kNoStore - 256u);
     };
     auto gather = [&](int32_t ci, T(&xv)[NR]) {
 #pragma unroll
       for (int u = 0; u < NR; ++u) {
-        const int32_t cu = lane_pick(ci, q * NR + u);  // past the partition: column 0
-        xv[u] = buf_load<T>(rx, static_cast<uint32_t>(cu) * xrow + xcol);
+        const uint32_t ro = static_cast<uint32_t>(lane_pick(ci, q * NR + u));  // X row offset
+        xv[u] = buf_load<T>(rx, ro + xcol);
       }
     };
     // two sets of pipeline registers used in turn by consecutive chunks (no
