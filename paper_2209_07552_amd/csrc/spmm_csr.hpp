@@ -95,7 +95,7 @@ __device__ __forceinline__ void spmm_scale_rows(T *__restrict__ Y, int64_t ldy, 
 }
 
 template <int VT, int NR, bool BETA0>
-__global__ __launch_bounds__(kSpmmWaves * kWave) void spmm_csr(
+__global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void spmm_csr(
     const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
     const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
     const typename vt_traits<VT>::T *__restrict__ X, int64_t ldx,
