@@ -678,6 +678,13 @@ def bench_spmm(args, vt):
         return [a.elapsed_time(b) for a, b in evs], kt
 
     steps(args.warmup, False)
+    if args.copy_calibration:  # a plain copy of known size for the byte counters
+        src = torch.empty(COPY_CAL_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        scrub.fill_(1)
+        dst.copy_(src)
+        del src, dst
+    torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ms, kt = steps(args.steps, True)
     wall = time.perf_counter() - wall0
