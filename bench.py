@@ -700,7 +700,12 @@ def bench_spmm(args, vt):
     k_bytes = float(np.mean(pass_bytes))
     achieved = k_bytes / (k_us * 1e-6) / 1e9
     call_bytes = sum(pass_bytes)
-    # comparator: k single-vector SpMVs (tuned CSR launch shape and partitions)
+    # comparator: k single-vector SpMVs (tuned CSR launch shape and partitions).
+    # Skipped in counter runs (--copy-calibration): its column copies are
+    # copy kernels too and would blur the calibration copy's readings.
+    if args.copy_calibration:
+        print(json.dumps({"metric": "SpMM counter run", "ms_per_step": round(ms_spmm, 4)}), flush=True)
+        return 0
     st = DEFAULT_TUNES.get(args.workload, {}).get("csr", (512, 4, 8, 2, 1))
     tune = pk.Tune(k_per_lane=st[1], waves_per_wg=st[2], nnz_per_wave=st[0], pipeline=st[3],
                    resident=st[4])
