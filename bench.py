@@ -695,10 +695,10 @@ def bench_spmm(args, vt):
         nr = 8 if left >= 8 else 4 if left >= 4 else 2 if left >= 2 else 1
         passes.append(nr)
         left -= nr
-    k_us = kt[1] / kt[0] * 1e3 if kt[0] else float("nan")  # per pass launch
+    k_us = kt[1] / kt[0] * 1e3 if kt[0] else None  # per pass launch (None: k = 1 ran the SpMV kernel)
     pass_bytes = [A.nnz * (vb + 4) + (A.m + 1) * 4 + nr * (A.n + A.m) * xb for nr in passes]
     k_bytes = float(np.mean(pass_bytes))
-    achieved = k_bytes / (k_us * 1e-6) / 1e9
+    achieved = k_bytes / (k_us * 1e-6) / 1e9 if k_us else None
     call_bytes = sum(pass_bytes)
     # comparator: k single-vector SpMVs (tuned CSR launch shape and partitions).
     # Skipped in counter runs (--copy-calibration): its column copies are
@@ -737,11 +737,12 @@ def bench_spmm(args, vt):
            "config": dict(wl, rhs=k, layout="row-major X (n x k), Y (m x k)", np=P.np,
                           nnz_per_wave=npw, passes=passes),
            "alg_gbs": round(call_bytes / (ms_spmm * 1e-3) / 1e9, 1),
-           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": load_traffic("spmm_csr/%s/%s/k%d" % (wl["workload"], args.vtype, k)),
-                        "kernel": "spmm_csr", "kernel_avg_us": round(k_us, 2),
-                        "alg_bytes_per_launch": int(k_bytes)},
+           "roofline": None if k_us is None else {
+               "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+               "traffic": load_traffic("spmm_csr/%s/%s/k%d" % (wl["workload"], args.vtype, k)),
+               "kernel": "spmm_csr", "kernel_avg_us": round(k_us, 2),
+               "alg_bytes_per_launch": int(k_bytes)},
            "k_spmv": {"ms": round(ms_spmv, 4), "gflops": round(flops / (ms_spmv * 1e-3) / 1e9, 3),
                       "entry": "msrep_spmv x %d" % k, "np": P1.np},
            "speedup_vs_k_spmv": round(ms_spmv / ms_spmm, 3),

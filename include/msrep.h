@@ -302,7 +302,8 @@ msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void *ws_d,
  * Errors: MSREP_ERR_ARG (NULL pointers, np <= 0, k < 0, ld < k),
  * MSREP_ERR_SIZE (workspace too small), MSREP_ERR_UNSUPPORTED (format).
  * Column j of Y equals msrep_spmv with x = column j of X up to the order of
- * the additions inside a partition.
+ * the additions inside a partition.  k == 1 with ldx == ldy == 1 runs the
+ * single-vector CSR kernel of msrep_spmv (default launch shape).
  */
 size_t msrep_spmm_ws_bytes(const msrep_mat *A, int32_t np, int32_t k);
 msrep_status msrep_spmm(const msrep_mat *A, const msrep_part *parts_d, const int32_t *lptr_d,

@@ -5,6 +5,11 @@
 #include "spmm_csr.hpp"
 
 namespace msrep {
+
+msrep_status spmv_launch(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                         int32_t np, const void *x, void *y, double alpha, double beta, int K,
+                         int wpb, int pf, int resident, double *carry, hipStream_t s);
+
 namespace {
 
 int spmm_pass_cols(int32_t left) { return left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1; }
@@ -106,6 +111,14 @@ extern "C" msrep_status msrep_spmm(const msrep_mat *A, const msrep_part *parts_d
                 ws_d ? ws_bytes : size_t(0));
   double *carry = static_cast<double *>(ws_d);
   const hipStream_t s = as_stream(stream);
+  // one contiguous column: the single-vector kernel (four nonzeros per lane)
+  // is the faster one; its workspace is the same two slots per partition
+  if (k == 1 && ldx == 1 && ldy == 1) {
+    if (msrep_status st = spmv_launch(A, parts_d, lptr_d, np, X_d, Y_d, alpha, beta, 4, 4, 2, 0,
+                                      carry, s))
+      return st;
+    return ok();
+  }
   msrep_status st;
   switch (A->vtype) {
     case MSREP_F64: st = spmm_vt<MSREP_F64>(A, parts_d, lptr_d, np, k, X_d, ldx, Y_d, ldy, alpha, beta, carry, s); break;
