@@ -293,14 +293,17 @@ msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void *ws_d,
  *   X_d: n x k, row-major, leading dimension ldx >= k elements (row i at
  *   X_d + i*ldx); Y_d: m x k, row-major, ldy >= k.  Element type FP64 for
  *   F64 values, FP32 for F32 and BF16 values, as for msrep_spmv.  Columns
- *   k..ld-1 are neither read nor written.  beta == 0: Y is not read.
+ *   k..ld-1 are neither read nor written.  beta == 0: Y is not read.  X
+ *   and Y must not overlap.  Each of X (n x ldx) and Y (m x ldy) must stay
+ *   below 4 GiB (32-bit buffer offsets; MSREP_ERR_UNSUPPORTED otherwise).
  *   ws_d: msrep_spmm_ws_bytes(A, np, k) bytes of device memory (the FP64
  *   partial sums of split rows, 16 bytes per partition and column of a
  *   pass), caller-owned; its contents need not be kept between calls.
  *   All buffers are caller-owned device memory; kernels are launched on
  *   stream and nothing is synchronised.  k == 0 or m == 0 is a no-op.
  * Errors: MSREP_ERR_ARG (NULL pointers, np <= 0, k < 0, ld < k),
- * MSREP_ERR_SIZE (workspace too small), MSREP_ERR_UNSUPPORTED (format).
+ * MSREP_ERR_SIZE (workspace too small), MSREP_ERR_UNSUPPORTED (format, X or
+ * Y of 4 GiB or more).
  * Column j of Y equals msrep_spmv with x = column j of X up to the order of
  * the additions inside a partition.  k == 1 with ldx == ldy == 1 runs the
  * single-vector CSR kernel of msrep_spmv (default launch shape).

@@ -178,3 +178,12 @@ def test_spmm_argument_errors():
     st = L.msrep_spmm(ctypes.byref(d), 0x4000, 0x5000, 8, 0, None, 0, None, 0, 1.0, 0.0, None, 0,
                       None)
     assert st == 0
+    # Y (m x ldy) or X (n x ldx) of 4 GiB or more: refused before any launch
+    big = _desc(fmt=0, m=1 << 26, n=4)
+    st = L.msrep_spmm(ctypes.byref(big), 0x4000, 0x5000, 8, 8, 0x6000, 8, 0x7000, 8, 1.0, 0.0,
+                      0x8000, 1 << 30, None)
+    assert st == -7 and b"4 GiB" in L.msrep_last_error()
+    wide = _desc(fmt=0, m=4, n=1 << 26)
+    st = L.msrep_spmm(ctypes.byref(wide), 0x4000, 0x5000, 8, 8, 0x6000, 8, 0x7000, 8, 1.0, 0.0,
+                      0x8000, 1 << 30, None)
+    assert st == -7 and b"4 GiB" in L.msrep_last_error()
