@@ -360,8 +360,8 @@ def main():
         trace_summary(*args.trace_summary, command=args.command, bench_json=args.bench_json)
         return 0
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
-              "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: one GPU only; --gpus %d is not supported (how the path would "
+              "shard across GPUs is a design note, not code)" % args.gpus, file=sys.stderr)
         return 2
 
     import torch
