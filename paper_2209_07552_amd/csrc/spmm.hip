@@ -14,7 +14,7 @@ namespace {
 
 int spmm_pass_cols(int32_t left) { return left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1; }
 
-template <int VT, int NR, bool BETA0>
+template <int VT, int NR, bool BETA0, int CPL>
 msrep_status launch_spmm_pass(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                               int32_t np, const void *X, int64_t ldx, void *Y, int64_t ldy,
                               double alpha, double beta, double *carry, hipStream_t s) {
@@ -27,7 +27,7 @@ msrep_status launch_spmm_pass(const msrep_mat *A, const msrep_part *parts, const
   const uint32_t xbytes = static_cast<uint32_t>(
       ((static_cast<int64_t>(A->n > 0 ? A->n : 1) - 1) * ldx + NR) * static_cast<int64_t>(sizeof(T)));
   timing_begin("spmm_csr", s);
-  hipLaunchKernelGGL((spmm_csr<VT, NR, BETA0>), dim3(g), dim3(kSpmmWaves * kWave), 0, s, A->idx,
+  hipLaunchKernelGGL((spmm_csr<VT, NR, BETA0, CPL>), dim3(g), dim3(kSpmmWaves * kWave), 0, s, A->idx,
                      static_cast<const typename Tr::V *>(A->val), parts, lptr, np,
                      static_cast<const T *>(X), ldx, static_cast<T *>(Y), ldy, A->m, alpha, beta,
                      carry, 2 * static_cast<int64_t>(np), xbytes, ybytes);
@@ -43,11 +43,21 @@ template <int VT, bool BETA0>
 msrep_status spmm_pass(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                        int32_t np, int nr, const void *X, int64_t ldx, void *Y, int64_t ldy,
                        double alpha, double beta, double *carry, hipStream_t s) {
+  // eight columns: two per lane (one 8- or 16-byte X load and Y store per
+  // position, four lanes per slot) when X and Y rows keep such pairs aligned
+  using T = typename vt_traits<VT>::T;
+  const size_t pair = 2 * sizeof(T);
+  const bool two = ldx % 2 == 0 && ldy % 2 == 0 && reinterpret_cast<uintptr_t>(X) % pair == 0 &&
+                   reinterpret_cast<uintptr_t>(Y) % pair == 0;
   switch (nr) {
-    case 8: return launch_spmm_pass<VT, 8, BETA0>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
-    case 4: return launch_spmm_pass<VT, 4, BETA0>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
-    case 2: return launch_spmm_pass<VT, 2, BETA0>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
-    default: return launch_spmm_pass<VT, 1, BETA0>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
+    case 8:
+      return two ? launch_spmm_pass<VT, 8, BETA0, 2>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s)
+                 : launch_spmm_pass<VT, 8, BETA0, 1>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
+    // (four columns: one per lane; two per lane left two lanes per slot and
+    // measured slower on the stencil)
+    case 4: return launch_spmm_pass<VT, 4, BETA0, 1>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
+    case 2: return launch_spmm_pass<VT, 2, BETA0, 1>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
+    default: return launch_spmm_pass<VT, 1, BETA0, 1>(A, parts, lptr, np, X, ldx, Y, ldy, alpha, beta, carry, s);
   }
 }
 

@@ -5,21 +5,23 @@
 //
 // X is n x k and Y is m x k, both row-major with leading dimensions ldx and
 // ldy (elements), so the k values a nonzero multiplies are contiguous.  A pass
-// covers NR columns (8, 4, 2 or 1).  One wavefront owns one partition and
-// walks its nonzeros in chunks of 64.  Lane (q, c) of a chunk takes slot
-// q = lane / NR, i.e. the NR consecutive nonzeros q*NR .. q*NR+NR-1, and
-// column c = lane % NR: the NR lanes of a slot read one X row as one
-// contiguous NR-element segment, so a gather instruction touches 64/NR rows
-// of X instead of 64.  Per chunk:
+// covers NR columns (8, 4, 2 or 1), CPL of them per lane (1, or 2 for eight
+// columns when X and Y keep column pairs aligned), so LPS = NR / CPL lanes
+// share a slot.  One wavefront owns one partition and walks its nonzeros in
+// chunks of 64.  Lane (q, cl) of a chunk takes slot q = lane / LPS, i.e. the
+// LPS consecutive nonzeros q*LPS .. q*LPS+LPS-1, and columns cl*CPL ..
+// cl*CPL+CPL-1: the LPS lanes of a slot read one X row as one contiguous
+// NR-element segment, so a gather instruction touches 64/LPS rows of X
+// instead of 64.  Per chunk:
 //   1. rows of the chunk from the partition's local pointer (one row per lane
 //      per round): a row starting inside the chunk writes its number at its
 //      first position in LDS, a max-scan over the 64 positions gives every
 //      position its row; empty rows get beta*Y here;
 //   2. products val*X[col, c] in registers, summed sequentially over the
-//      lane's NR positions with restarts at row changes, then a segmented
-//      scan across the slots (shifts of NR, 2NR, ... lanes);
+//      lane's LPS positions with restarts at row changes, then a segmented
+//      scan across the slots (shifts of LPS, 2LPS, ... lanes);
 //   3. the lane holding a row's last position in the chunk writes that row's
-//      column c; the row open at the end of the chunk is carried in FP64.
+//      columns; the row open at the end of the chunk is carried (in FP64).
 // Head and tail rows of a partition (start_flag / end_flag) go to the carry
 // buffer, one block of 2*np doubles per column, which the boundary merge
 // completes column by column.
@@ -79,6 +81,46 @@ __device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, E v) {
   else
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
 }
+// CPL consecutive elements at byte offset `off` (one 8- or 16-byte access;
+// `off` a multiple of its size).
+template <typename T, int CPL>
+__device__ __forceinline__ void buf_load_n(rsrc_t r, uint32_t off, T (&out)[CPL]) {
+  if constexpr (CPL == 1) {
+    out[0] = buf_load<T>(r, off);
+  } else {
+    static_assert(CPL == 2, "one or two elements");
+    // (elements are copied out of the vector into scalars before the bit
+    // casts: hipcc has folded a bit cast of `w.y` into one of `w.x`)
+    if constexpr (sizeof(T) == 8) {
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+      const uint64_t a = static_cast<uint64_t>(static_cast<uint32_t>(w[0])) |
+                         (static_cast<uint64_t>(static_cast<uint32_t>(w[1])) << 32);
+      const uint64_t b = static_cast<uint64_t>(static_cast<uint32_t>(w[2])) |
+                         (static_cast<uint64_t>(static_cast<uint32_t>(w[3])) << 32);
+      out[0] = __builtin_bit_cast(T, a);
+      out[1] = __builtin_bit_cast(T, b);
+    } else {
+      const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+      const uint32_t a = w[0], b = w[1];
+      out[0] = __builtin_bit_cast(T, a);
+      out[1] = __builtin_bit_cast(T, b);
+    }
+  }
+}
+template <typename T, int CPL>
+__device__ __forceinline__ void buf_store_n(rsrc_t r, uint32_t off, const T (&v)[CPL]) {
+  if constexpr (CPL == 1) {
+    buf_store<T>(r, off, v[0]);
+  } else if constexpr (sizeof(T) == 8) {
+    const uint64_t a = __builtin_bit_cast(uint64_t, v[0]), b = __builtin_bit_cast(uint64_t, v[1]);
+    const u32x4 w = {static_cast<uint32_t>(a), static_cast<uint32_t>(a >> 32),
+                     static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b64(
+        u32x2{__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1])}, r, off, 0, 0);
+  }
+}
 constexpr uint32_t kNoStore = 0xFFFFFFF0u;  // offsets down to kNoStore - 511 are past every resource
 
 // Rows [lo, hi) x columns [0, NR) get beta*Y (0 when beta == 0), lanes
@@ -94,7 +136,7 @@ __device__ __forceinline__ void spmm_scale_rows(T *__restrict__ Y, int64_t ldy, 
   }
 }
 
-template <int VT, int NR, bool BETA0>
+template <int VT, int NR, bool BETA0, int CPL>
 __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void spmm_csr(
     const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
     const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
@@ -106,16 +148,19 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
   using T = typename Tr::T;
   using Acc = typename Tr::A;
   static_assert(NR == 1 || NR == 2 || NR == 4 || NR == 8, "columns per pass");
-  constexpr int G = kWave / NR;  // slots per chunk
+  static_assert(CPL == 1 || (CPL == 2 && NR >= 2), "one or two columns per lane");
+  constexpr int LPS = NR / CPL;   // lanes per slot
+  constexpr int U = LPS;          // positions per slot
+  constexpr int G = kWave / LPS;  // slots per chunk
   __shared__ int32_t s_mark_all[kSpmmWaves][kWave];
   __shared__ int32_t s_rows_all[kSpmmWaves][kWave];
   const int wid = threadIdx.x / kWave;
   int32_t *s_mark = s_mark_all[wid];
   int32_t *s_rows = s_rows_all[wid];
   const int lane = lane_id();
-  const int q = lane / NR, c = lane % NR;
+  const int q = lane / LPS, cl = lane % LPS;  // slot, and the lane's first column / CPL
   // byte offsets of X and Y elements (32-bit)
-  const uint32_t xrow = static_cast<uint32_t>(ldx) * sizeof(T), xcol = c * sizeof(T);
+  const uint32_t xrow = static_cast<uint32_t>(ldx) * sizeof(T), xcol = cl * CPL * sizeof(T);
   const uint32_t yrow = static_cast<uint32_t>(ldy) * sizeof(T);
   const PartStride ps(np);
   for (int32_t p = ps.p; p < np; p += ps.step) {
@@ -131,14 +176,17 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
     const rsrc_t rl = make_rsrc(lp, static_cast<uint32_t>(R + 1 > 0 ? R + 1 : 0) * 4u);
     const rsrc_t ry = make_rsrc(Y, ybytes);  // X and Y are below 4 GiB (checked by the host)
     const rsrc_t rx = make_rsrc(X, xbytes);
-    double *cp = carry + c * cstride + 2 * static_cast<int64_t>(p);  // column c's head, tail
-    double cv = 0.0;  // column c of the row continuing from the previous chunk
+    // the lane's columns' head and tail carries
+    double *cp = carry + static_cast<int64_t>(cl * CPL) * cstride + 2 * static_cast<int64_t>(p);
+    double cv[CPL];  // the lane's columns of the row continuing from the previous chunk
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) cv[e] = 0.0;
     bool con = false;
     int32_t j0 = 0;   // first local row of the chunk
     // software pipeline: every lane loads one nonzero (column index and
     // value) of the chunk after next, coalesced, and the X gather of the next
-    // chunk is issued before this chunk's rows are worked out.  Lane (q, c)
-    // takes the index and value of position q*NR + u from lane q*NR + u.
+    // chunk is issued before this chunk's rows are worked out.  Lane (q, cl)
+    // takes the index and value of position q*U + u from lane q*U + u.
     auto load_item = [&](int32_t cbx, int32_t &ci, V &vi) {
       const int32_t left = nloc - cbx;
       const uint32_t cnt = static_cast<uint32_t>(left <= 0 ? 0 : left < kWave ? left : kWave);
@@ -153,18 +201,18 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
       ci = static_cast<uint32_t>(lane) < cnt ? static_cast<int32_t>(static_cast<uint32_t>(ci) * xrow)
                                               : static_cast<int32_t>(kNoStore - 256u);
     };
-    auto gather = [&](int32_t ci, T(&xv)[NR]) {
+    auto gather = [&](int32_t ci, T(&xv)[U][CPL]) {
 #pragma unroll
-      for (int u = 0; u < NR; ++u) {
-        const uint32_t ro = static_cast<uint32_t>(lane_pick(ci, q * NR + u));  // X row offset
-        xv[u] = buf_load<T>(rx, ro + xcol);
+      for (int u = 0; u < U; ++u) {
+        const uint32_t ro = static_cast<uint32_t>(lane_pick(ci, q * U + u));  // X row offset
+        buf_load_n<T, CPL>(rx, ro + xcol, xv[u]);
       }
     };
     // two sets of pipeline registers used in turn by consecutive chunks (no
     // copies between them, which would wait for the loads in flight)
     int32_t cA = 0, cB = 0;
     V vA = V(0), vB = V(0);
-    T xvA[NR], xvB[NR];
+    T xvA[U][CPL], xvB[U][CPL];
     int32_t a0 = 0, b0 = 0;  // first round of row pointers of the chunk
     if (nloc > 0) {
       a0 = buf_load<int32_t>(rl, static_cast<uint32_t>(lane) * 4u);
@@ -176,13 +224,16 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
       load_item(kWave, cA, vdummy);  // (the value is loaded again one chunk later)
       // as many (dropped) stores as a chunk issues, so that the memory
       // operations after each load are as many here as in the loop
+      T zero[CPL];
 #pragma unroll
-      for (int u = 0; u < NR; ++u) buf_store<T>(ry, kNoStore - 16u * u, T(0));
+      for (int e = 0; e < CPL; ++e) zero[e] = T(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) buf_store_n<T, CPL>(ry, kNoStore - 32u * (u + 1), zero);
     }
     // one chunk at cb: X values xv_use and values v_use of this chunk in
     // hand, c_use the column indices of the next one; fills xv_fill (next
     // chunk's X), v_fill (next chunk's values) and c_fill (the chunk after)
-    auto chunk = [&](int32_t cb, T(&xv_use)[NR], T(&xv_fill)[NR], V &v_use, V &v_fill,
+    auto chunk = [&](int32_t cb, T(&xv_use)[U][CPL], T(&xv_fill)[U][CPL], V &v_use, V &v_fill,
                      int32_t &c_use, int32_t &c_fill) {
       const int32_t ce = cb + kWave < nloc ? cb + kWave : nloc;
       const int32_t nv = ce - cb;  // valid positions of the chunk
@@ -237,46 +288,63 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
       constexpr int32_t kNoRow = INT32_MIN;
       s_rows[lane] = lane < nv ? rr : kNoRow;
       wave_lds_sync();
-      int32_t rw[NR + 1];
+      int32_t rw[U + 1];
 #pragma unroll
-      for (int u = 0; u < NR; ++u) rw[u] = s_rows[q * NR + u];
-      rw[NR] = q + 1 < G ? s_rows[(q + 1) * NR] : kNoRow;
-      const int32_t rprev = q > 0 ? s_rows[q * NR - 1] : rw[0];
+      for (int u = 0; u < U; ++u) rw[u] = s_rows[q * U + u];
+      rw[U] = q + 1 < G ? s_rows[(q + 1) * U] : kNoRow;
+      const int32_t rprev = q > 0 ? s_rows[q * U - 1] : rw[0];
       wave_lds_sync();  // s_mark / s_rows are rewritten by the next chunk
       // ---- 2. products, sequential segmented sums over the lane's positions
-      Acc run[NR];
-      bool seen[NR];
-      Acc acc = Acc(0);
+      Acc run[U][CPL];
+      bool seen[U];
+      Acc acc[CPL];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) acc[e] = Acc(0);
       bool any = false;
 #pragma unroll
-      for (int u = 0; u < NR; ++u) {
-        const int32_t P = q * NR + u;
+      for (int u = 0; u < U; ++u) {
+        const int32_t P = q * U + u;
         const bool h = rw[u] != (u == 0 ? rprev : rw[u - 1]);
         if (h) {
-          acc = Acc(0);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) acc[e] = Acc(0);
           any = true;
         }
         const V vu = lane_pick(v_use, P);
-        acc += Tr::val(vu) * static_cast<Acc>(xv_use[u]);
-        run[u] = acc;
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          acc[e] += Tr::val(vu) * static_cast<Acc>(xv_use[u][e]);
+          run[u][e] = acc[e];
+        }
         seen[u] = any;
       }
-      // segmented scan of the slot totals across slots (stride NR lanes).
+      // segmented scan of the slot totals across slots (stride LPS lanes).
       // FP64: the sum carried from the previous chunk enters as slot 0's
       // incoming value; FP32 keeps it apart in FP64 and adds it at the end.
       constexpr bool kFold = sizeof(Acc) == 8;
-      const Acc cvin = kFold && con ? static_cast<Acc>(cv) : Acc(0);
-      Acc agg = (q == 0 && !any) ? acc + cvin : acc;
+      Acc cvin[CPL], agg[CPL], cin[CPL];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        cvin[e] = kFold && con ? static_cast<Acc>(cv[e]) : Acc(0);
+        agg[e] = (q == 0 && !any) ? acc[e] + cvin[e] : acc[e];
+      }
       int f = any ? 1 : 0;
 #pragma unroll
-      for (int d = NR; d < kWave; d *= 2) {
-        const Acc pv = shift_up(agg, d);
+      for (int d = LPS; d < kWave; d *= 2) {
+        Acc pv[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) pv[e] = shift_up(agg[e], d);
         const int pf = shift_up_i(f, d);
-        if (!f) agg += pv;
+#pragma unroll
+        for (int e = 0; e < CPL; ++e)
+          if (!f) agg[e] += pv[e];
         f |= pf;
       }
-      const Acc cin0 = shift_up(agg, NR);  // the open segment up to the previous slot
-      const Acc cin = q == 0 ? cvin : cin0;
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        const Acc cin0 = shift_up(agg[e], LPS);  // the open segment up to the previous slot
+        cin[e] = q == 0 ? cvin[e] : cin0;
+      }
       // ---- 3. rows ending at this lane's positions: one buffer store per
       //         position on every lane (dropped where no row ends), so the
       //         number of stores after the next chunks' loads is fixed and
@@ -284,7 +352,9 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
       // (the partial sums of the partition's first and last rows, when they
       // are split, are kept aside and stored after the loop: at most one
       // position of a lane holds each)
-      double hval = 0.0, tval = 0.0;
+      double hval[CPL], tval[CPL];
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) hval[e] = tval[e] = 0.0;
       bool hset = false, tset = false;
       const int32_t skip_row = cont ? j1 : kNoRow + 1;  // the open row is carried, not written
       // only the chunks holding the partition's first or last row can hold a
@@ -293,42 +363,62 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
       auto finish = [&](auto edge_c) {
         constexpr bool EDGE = decltype(edge_c)::value;
 #pragma unroll
-        for (int u = 0; u < NR; ++u) {
+        for (int u = 0; u < U; ++u) {
           const int32_t rj = rw[u];
           const bool done = rw[u + 1] != rj && rj != skip_row;
-          double tot = static_cast<double>(seen[u] ? run[u] : run[u] + cin);
-          if (!kFold && rj == j0 && con) tot += cv;
+          double tot[CPL];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            tot[e] = static_cast<double>(seen[u] ? run[u][e] : run[u][e] + cin[e]);
+            if (!kFold && rj == j0 && con) tot[e] += cv[e];
+          }
           bool to_y = done;
           if constexpr (EDGE) {
             const bool head_c = done && rj == 0 && sflag;
             const bool tail_c = done && !head_c && rj == R - 1 && eflag;
-            hval = head_c ? tot : hval;
-            tval = tail_c ? tot : tval;
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) {
+              hval[e] = head_c ? tot[e] : hval[e];
+              tval[e] = tail_c ? tot[e] : tval[e];
+            }
             hset = hset || head_c;
             tset = tset || tail_c;
             to_y = done && !head_c && !tail_c;
           }
           const uint32_t off = to_y ? static_cast<uint32_t>(r0 + rj) * yrow + xcol : kNoStore;
-          double out = alpha * tot;
-          if (!BETA0) out += beta * static_cast<double>(buf_load<T>(ry, off));
-          buf_store<T>(ry, off, static_cast<T>(out));
+          T old[CPL], out[CPL];
+          if (!BETA0) buf_load_n<T, CPL>(ry, off, old);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            double o = alpha * tot[e];
+            if (!BETA0) o += beta * static_cast<double>(old[e]);
+            out[e] = static_cast<T>(o);
+          }
+          buf_store_n<T, CPL>(ry, off, out);
         }
       };
       if (edge) {
         finish(std::true_type{});
-        if (hset) cp[0] = hval;
-        if (tset) cp[1] = tval;
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+          if (hset) cp[e * cstride] = hval[e];
+          if (tset) cp[e * cstride + 1] = tval[e];
+        }
       } else {
         finish(std::false_type{});
       }
-      if (cont) {  // column c of the open row, from the lane holding the chunk's last position
-        const int ul = (nv - 1) % NR;
-        Acc lv = Acc(0);
+      if (cont) {  // the lane's columns of the open row, from the lane holding the chunk's last position
+        const int ul = (nv - 1) % U;
+        const int src = ((nv - 1) / U) * LPS + cl;
 #pragma unroll
-        for (int u = 0; u < NR; ++u)
-          if (u == ul) lv = seen[u] ? run[u] : run[u] + cin;
-        const double open = static_cast<double>(lane_pick(lv, ((nv - 1) / NR) * NR + c));
-        cv = open + ((!kFold && j1 == j0 && con) ? cv : 0.0);
+        for (int e = 0; e < CPL; ++e) {
+          Acc lv = Acc(0);
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (u == ul) lv = seen[u] ? run[u][e] : run[u][e] + cin[e];
+          const double open = static_cast<double>(lane_pick(lv, src));
+          cv[e] = open + ((!kFold && j1 == j0 && con) ? cv[e] : 0.0);
+        }
       }
       con = cont;
       j0 = j0n;

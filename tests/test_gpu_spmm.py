@@ -128,6 +128,24 @@ def test_spmm_dyadic_bit_exact():
             assert np.array_equal(y, ref), (A.name, np_, int(np.sum(y != ref)))
 
 
+@pytest.mark.parametrize("vt", [0, 1])
+def test_spmm_column_pairs_and_single_columns(vt):
+    """Eight columns run two per lane when X and Y rows keep column pairs
+    aligned (even leading dimensions) and one per lane otherwise; both
+    layouts must give the oracle's result (dyadic inputs: bit for bit)."""
+    rng = np.random.default_rng(77)
+    A, _ = synth.rmat_csr(scale=11, edge_factor=8, seed=4)
+    val = synth.dyadic(rng, A.nnz)
+    X = synth.dyadic(rng, A.n * 8).reshape(A.n, 8)
+    for extra in (0, 1, 2, 3):  # ldx = ldy = 8, 9, 10, 11
+        y, ref, s = _run(A, vt, 8, max(1, A.nnz // 300), X64=X, val=val, ld_extra=extra,
+                         alpha=0.5, beta=0.25 if extra % 2 else 0.0, seed=extra)
+        if vt == pk.F64:
+            assert np.array_equal(y, ref), (extra, int(np.sum(y != ref)))
+        else:
+            assert_close(y.ravel(), ref.ravel(), s.ravel(), F32_TOL, "ld %d" % (8 + extra))
+
+
 def test_spmm_columns_match_spmv():
     """Column j of msrep_spmm equals msrep_spmv with x = X[:, j] (dyadic, so
     both are exact and must agree bit for bit)."""
