@@ -283,8 +283,8 @@ msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void *ws_d,
 
 /* --------------------------------------------- several right-hand sides */
 /*
- * Y = alpha*A*X + beta*Y for k right-hand sides at once (a multi-vector
- * SpMV, the SpMM mentioned beside SpMV in the paper's Sec. 2): the same
+ * Y = alpha*A*X + beta*Y for k right-hand sides at once (the sparse matrix
+ * times several dense vectors that Sec. 2.3 groups with SpMV): the same
  * equal-nnz CSR partitions and boundary merge as msrep_spmv (Algorithm 3,
  * Sec. 4.3), applied to every column.  A is read once per pass of up to
  * eight columns instead of once per column.

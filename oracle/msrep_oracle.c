@@ -147,8 +147,8 @@ int oracle_spmv_csr(int32_t m, int32_t n, const int32_t *row_ptr,
   return ORACLE_OK;
 }
 
-/* Several right-hand sides (the multi-vector product that Sec. 2 names
- * beside SpMV): Y = alpha*A*X + beta*Y_in for the k columns of the row-major
+/* Several right-hand sides (the sparse matrix times several dense vectors
+ * that Sec. 2.3 groups with SpMV): Y = alpha*A*X + beta*Y_in for the k columns of the row-major
  * X (n x k, row c at X + c*ldx) and Y (m x k, row i at Y + i*ldy), i.e.
  * Algorithm 1 once per column, each (row, column) dot product kept in its own
  * Dot2 accumulator.  Columns beyond k are not touched.  scale_out (m x k,

@@ -1,7 +1,8 @@
 // Multi-right-hand-side CSR SpMV (Y = alpha*A*X + beta*Y for k columns of X
 // at once) over the same equal-nnz partitions as the single-vector pCSR path
-// (msRep Algorithm 3, with the multiplication of Sec. 3 generalised from one
-// vector to a row-major block of vectors).
+// (msRep Algorithm 3): the product of Sec. 2.2 (Algorithm 1) applied to every
+// column of a row-major block of vectors, the sparse-times-several-dense-
+// vectors case that Sec. 2.3 groups with SpMV.
 //
 // X is n x k and Y is m x k, both row-major with leading dimensions ldx and
 // ldy (elements), so the k values a nonzero multiplies are contiguous.  A pass
