@@ -197,6 +197,39 @@ def test_spmm_rmat_full_size():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("k", [8, 5])
+def test_spmm_replays_under_graph_capture(k):
+    """msrep_spmm launches kernels only (no memsets, no allocation when the
+    workspace is passed), so a caller can capture it: three replays with new
+    X contents, eager work and synchronisation in between, each equal to the
+    eager call on the same X and within tolerance of the oracle."""
+    A, _ = synth.rmat_csr(scale=13, edge_factor=8, seed=23)
+    M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val)
+    P = pk.msrep_build_partition(M, 300)
+    dev = _dev()
+    X = torch.zeros((A.n, k), dtype=torch.float64, device=dev)
+    Y = torch.zeros((A.m, k), dtype=torch.float64, device=dev)
+    ws = torch.zeros(pk.msrep_spmm_ws_bytes(M, P.np, k), dtype=torch.uint8, device=dev)
+    pk.msrep_spmm(M, P, X, Y, ws=ws)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.msrep_spmm(M, P, X, Y, ws=ws)
+    rng = np.random.default_rng(24)
+    for rep in range(3):
+        Xn = rng.uniform(-1, 1, (A.n, k))
+        X.copy_(torch.from_numpy(Xn))
+        g.replay()
+        torch.cuda.synchronize()
+        got = Y.cpu().numpy().copy()
+        Y_eager = torch.zeros_like(Y)
+        pk.msrep_spmm(M, P, X, Y_eager, ws=torch.zeros_like(ws))
+        torch.cuda.synchronize()
+        ref, sc = oracle.spmm_csr(A.m, A.n, A.ptr, A.col, A.val, Xn)
+        assert_close(got.ravel(), ref.ravel(), sc.ravel(), F64_TOL, "k%d replay %d" % (k, rep))
+        assert np.array_equal(got, Y_eager.cpu().numpy()), (k, rep)
+
+
 def test_spmm_errors():
     A = synth.stencil7_csr(4, seed=0)[0]
     M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val)
