@@ -165,25 +165,30 @@ def test_spmm_columns_match_spmv():
 
 
 @pytest.mark.slow
-def test_spmm_stencil_full_size_exact():
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_spmm_stencil_full_size_exact(vt):
     """256^3 stencil (16.7M rows) times column t = t+1: (t+1)*(6 - in-grid
-    neighbours), exact, at the partition size the benchmark uses."""
+    neighbours), exact in every value type (6 and -1 and the small integer
+    results are exact in BF16 and FP32), at the partition size the benchmark
+    uses."""
     A, _ = synth.stencil7_csr(256, seed=0)
     k = 8
-    M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val)
+    sv, _ = stored_values(A.val, vt)
+    M = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=A.ptr, idx=A.col, val=sv)
     P = pk.msrep_build_partition(M, -(-A.nnz // 2048))
-    Xd = torch.arange(1, k + 1, dtype=torch.float64, device=_dev()).repeat(A.n, 1)
-    Yd = torch.full((A.m, k), float("nan"), dtype=torch.float64, device=_dev())
+    dt = torch.float64 if vt == pk.F64 else torch.float32
+    Xd = torch.arange(1, k + 1, dtype=dt, device=_dev()).repeat(A.n, 1)
+    Yd = torch.full((A.m, k), float("nan"), dtype=dt, device=_dev())
     pk.msrep_spmm(M, P, Xd, Yd)
     torch.cuda.synchronize()
     g = 256
     r = torch.arange(A.m, device=_dev())
-    base = torch.zeros(A.m, dtype=torch.float64, device=_dev())
+    base = torch.zeros(A.m, dtype=dt, device=_dev())
     for c in (r % g, (r // g) % g, r // (g * g)):
-        base += (c == 0).double() + (c == g - 1).double()
-    want = base[:, None] * torch.arange(1, k + 1, dtype=torch.float64, device=_dev())[None, :]
-    assert torch.equal(Yd, want)
-    del M, P, Xd, Yd, want
+        base += (c == 0).to(dt) + (c == g - 1).to(dt)
+    want = base[:, None] * torch.arange(1, k + 1, dtype=dt, device=_dev())[None, :]
+    assert torch.equal(Yd, want), vt
+    del M, P, Xd, Yd, want, base, r
     torch.cuda.empty_cache()
 
 
