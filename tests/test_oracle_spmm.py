@@ -105,3 +105,29 @@ def test_empty_and_argument_errors(oracle_lib):
     assert Y.shape == (2, 0)
     with pytest.raises(ValueError):
         oracle.spmm_csr(2, 3, ptr, np.zeros(0, np.int32), np.zeros(0), np.ones((4, 2)))
+
+
+def test_leading_dimensions_wider_than_k(oracle_lib):
+    """The C routine with ldx, ldy > k: NaN in the columns past k of X must
+    not reach Y, Y's columns past k stay as they were, and columns < k equal
+    the dense product."""
+    import ctypes
+    rng = np.random.default_rng(12)
+    A, dense = _random_csr(rng, 20, 15, 0.3)
+    k, ldx, ldy = 3, 5, 7
+    X = np.full((15, ldx), np.nan)
+    X[:, :k] = rng.uniform(-1, 1, (15, k))
+    Y = np.full((20, ldy), 4.0)
+    lib = oracle._load()
+    ptr = np.ascontiguousarray(A.indptr, np.int32)
+    col = np.ascontiguousarray(A.indices, np.int32)
+    val = np.ascontiguousarray(A.data, np.float64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.oracle_spmm_csr(20, 15, k, p(ptr), p(col), p(val), p(X), ldx, 1.0, 0.0, None, ldy,
+                             p(Y), None)
+    assert rc == 0
+    assert np.all(Y[:, k:] == 4.0)
+    want = dense @ X[:, :k]
+    assert np.all(np.abs(Y[:, :k] - want) <= 4 * 15 * EPS * (np.abs(dense) @ np.abs(X[:, :k])) + 1e-300)
+    assert lib.oracle_spmm_csr(20, 15, k, p(ptr), p(col), p(val), p(X), 2, 1.0, 0.0, None, ldy,
+                               p(Y), None) == oracle.ERR_ARG
