@@ -2,12 +2,15 @@
 """Benchmark of the equal-nnz partitioned SpMV (msRep, arXiv 2209.07552) on
 one MI355X.
 
-Default workload: the power-law FP64 configuration -- an R-MAT scale-20
-matrix (1,048,576 rows and columns, edge factor 16, a/b/c/d =
-.57/.19/.19/.05, duplicates merged; values and x ~ U(-1, 1), seed 0) stored
-as CSR, CSC and COO, each split into equal-nnz partitions over the CUs.  One
-step is y = A*x in each of the three formats (partitions and matrices
-resident in HBM, boundary merges included).  Every SpMV of the timed region
+Default workload: the 3-D 7-point Laplacian on a 256^3 grid in FP64
+(16,777,216 rows, 117,047,296 nonzeros, diagonal 6, neighbours -1, x ~
+U(-1, 1), seed 0) stored as CSR, CSC and COO, each split into equal-nnz
+partitions over the CUs.  One step is y = A*x in each of the three formats
+(partitions and matrices resident in HBM, boundary merges included).  The
+same line carries the same step with FP32 and BF16 stored values
+("precision") and on the power-law R-MAT scale-20 matrix (1,048,576 rows,
+edge factor 16, a/b/c/d = .57/.19/.19/.05, duplicates merged; "rmat20"),
+every result checked against the FP64 oracle.  Every SpMV of the timed region
 runs cache-cold: a 512 MiB scrub write between SpMVs evicts the 256 MB
 Infinity Cache, and HIP events on the library's stream bracket each SpMV, so
 the reported throughput is the SpMV time alone.  A warm (back-to-back) figure
@@ -63,56 +66,6 @@ def host_formats(A, any_order=False):
     return out
 
 
-def equal_rows_partition(M, H, fmt, np_, dev):
-    """The paper's baseline split (equal rows, or equal columns for CSC,
-    unequal nonzeros) as partition records the SpMV kernels take: partition
-    i starts at major index floor(i*rows/np); its fields follow the same
-    definitions as the equal-nnz build (row containing start_idx and end_idx,
-    local pointer clamped to the partition, start_row + 2i offsets), and its
-    flags are 0 since it never splits a row.  Host numpy, for comparison
-    runs only."""
-    import torch
-    import paper_2209_07552_amd as pk
-    a, b, _ = H[fmt]
-    rows = M.major
-    nnz = int(M.nnz)
-    bnd = (np.arange(np_ + 1, dtype=np.int64) * rows) // np_
-    if fmt == "coo":
-        first = np.searchsorted(np.asarray(a, np.int64), bnd, "left").astype(np.int64)
-        ptr = None
-    else:
-        ptr = np.asarray(a, np.int64)
-        first = ptr[bnd]
-    rec = np.zeros(np_, pk.PART_DTYPE)
-    s0, e0 = first[:-1], first[1:] - 1
-    rec["start_idx"], rec["end_idx"] = s0, e0
-    if fmt == "coo":
-        ri = np.asarray(a, np.int64)
-        srow = np.where(s0 < nnz, ri[np.minimum(s0, nnz - 1)], rows) if nnz else np.full(np_, rows)
-        erow = np.where(e0 >= s0, ri[np.maximum(e0, 0)] if nnz else 0, srow - 1)
-    else:
-        def bs(k):  # the row containing nonzero k: max r with ptr[r] <= k
-            return np.searchsorted(ptr, k, "right") - 1
-        srow = np.where(s0 < nnz, bs(s0), rows)
-        erow = np.where(e0 >= s0, bs(np.maximum(e0, 0)), srow - 1)
-    rec["start_row"], rec["end_row"] = srow, erow
-    rec["lptr_off"] = srow + 2 * np.arange(np_, dtype=np.int64)
-    parts = torch.from_numpy(rec.view(np.uint8).copy()).to(dev)
-    if fmt == "coo":
-        return pk.Partition(M, np_, parts, None, torch.zeros(1, dtype=torch.int64, device=dev))
-    cap = rows + 2 * np_
-    lp = np.zeros(cap, np.int32)
-    for i in range(np_):
-        R = int(erow[i] - srow[i] + 1)
-        if R <= 0:
-            lp[rec["lptr_off"][i]] = 0
-            continue
-        seg = ptr[srow[i]:srow[i] + R + 1]
-        lp[rec["lptr_off"][i]:rec["lptr_off"][i] + R + 1] = np.clip(seg, s0[i], e0[i] + 1) - s0[i]
-    ln = torch.tensor([cap], dtype=torch.int64, device=dev)
-    return pk.Partition(M, np_, parts, torch.from_numpy(lp).to(dev), ln)
-
-
 def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
     """Bytes the method must move for one SpMV (values, indices, pointer, x
     read once, y written once; y read too when beta != 0)."""
@@ -126,24 +79,6 @@ def alg_bytes(fmt, m, n, nnz, vbytes, xbytes, beta0=True):
     if not beta0:
         b += m * xbytes
     return b
-
-
-def kernel_alg_bytes(kernel, m, n, nnz, np_, vbytes, xbytes, fmt="csc"):
-    """Algorithmic bytes of one launch of a kernel of the SpMV path (one
-    launch covers the whole matrix): what its job must read and write, each
-    array once.  Bucketed products are FP64 for FP64 values and FP32
-    otherwise, each with a 16-bit row offset; for COO in any order the
-    scatter reads a column index per nonzero instead of the column pointer."""
-    pbytes = 8 if xbytes == 8 else 4
-    cols = nnz * 4 if fmt == "coo_any" else (n + 1) * 4
-    return {
-        "spmv_csr_seg": alg_bytes("csr", m, n, nnz, vbytes, xbytes),
-        "spmv_coo_seg": alg_bytes("coo", m, n, nnz, vbytes, xbytes),
-        "merge_rows": np_ * (40 + 16),
-        "csc_count": nnz * 4,
-        "csc_scatter": nnz * (vbytes + 4) + cols + n * xbytes + nnz * (pbytes + 2),
-        "csc_reduce": nnz * (pbytes + 2) + m * xbytes,
-    }.get(kernel)
 
 
 COPY_CAL_BYTES = 256 << 20  # plain copy used to calibrate the byte counters
@@ -293,137 +228,119 @@ def overheads(args, mats, part_ms, prep_ms, cold_ms, kt_all):
     return out
 
 
-def cpu_baseline(A, x, y_gpu, budget_s):
-    """The FP64 oracle (Dot2 CSR SpMV, one thread) timed on this host over
-    whole SpMVs of the same matrix, repeated for about budget_s seconds; also
-    the GPU result's largest error relative to (|A||x|)_i."""
+def cpu_baseline(A, x, reps=5):
+    """The CPU baseline of the FP64 SpMV on this host, as the measurement plan
+    states it: the oracle's plain (uncompensated) CSR row loop, OpenMP
+    row-parallel with a static schedule, on every core this process may run
+    on and on one core, median of `reps` whole SpMVs each; the oracle's
+    compensated (Dot2) mode timed separately on one core.  Same matrix and x
+    as the GPU run; the same flop count (2 nnz per SpMV)."""
     import oracle
     oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+
+    def med(threads, n_):
+        ts = []
+        for _ in range(n_):
+            t0 = time.perf_counter()
+            oracle.spmv_csr_plain(A.m, A.n, A.ptr, A.col, A.val, x, threads=threads)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+    med(cores, 1)  # first touch of the arrays
+    t_all = med(cores, reps)
+    t_one = med(1, reps)
     t0 = time.perf_counter()
-    y, s = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
-    one = time.perf_counter() - t0
-    reps = max(1, int(budget_s / max(one, 1e-3)) - 1)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
-    per = (time.perf_counter() - t0) / reps if reps else one
-    err = float(np.max(np.abs(y_gpu - y) / np.where(s > 0, s, 1.0)))
-    return {"value": round(2.0 * A.nnz / per / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+    oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
+    t_dot2 = time.perf_counter() - t0
+    fl = 2.0 * A.nnz
+    return {"value": round(fl / t_all / 1e9, 4), "unit": "GFLOP/s", "cores": cores,
             "kind": "oracle",
-            "sample": "%d full CSR SpMVs of the same matrix (%d nnz), Dot2 FP64, 1 thread"
-                      % (reps + 1, A.nnz)}, err
+            "sample": "the whole FP64 CSR SpMV of the same matrix (%d nnz): plain row loop, "
+                      "OpenMP static over %d threads, median of %d; also on 1 thread (median of "
+                      "%d) and the compensated Dot2 mode on 1 thread (one SpMV)"
+                      % (A.nnz, cores, reps, reps),
+            "ms_all_cores": round(t_all * 1e3, 3),
+            "one_core_gflops": round(fl / t_one / 1e9, 4), "ms_one_core": round(t_one * 1e3, 3),
+            "dot2_one_core_gflops": round(fl / t_dot2 / 1e9, 4),
+            "ms_dot2_one_core": round(t_dot2 * 1e3, 3)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20",
-                    choices=["rmat20", "stencil256", "uniform4096", "batched", "serve"])
-    ap.add_argument("--rhs", type=int, default=0,
-                    help="k > 0: time msrep_spmm with k right-hand sides (CSR) instead")
-    ap.add_argument("--count", type=int, default=512, help="batched / serving pool size")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
-    ap.add_argument("--rates", default="0.1,0.5,0.9,1.2", help="serving: fractions of capacity")
-    ap.add_argument("--budget-gb", type=float, default=200.0)
-    ap.add_argument("--vtype", default="f64", choices=["f64", "f32", "bf16"])
-    ap.add_argument("--formats", default="csr,csc,coo")
-    ap.add_argument("--nnz-per-wave", type=int, default=0, help="partition size (0: tuned)")
-    ap.add_argument("--k", type=int, default=0)
-    ap.add_argument("--wpb", type=int, default=0)
-    ap.add_argument("--pipeline", type=int, default=0)
-    ap.add_argument("--resident", type=int, default=0)
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="tune every format first")
-    ap.add_argument("--overheads", action="store_true",
-                    help="also time conversion, partition build and merge against the SpMV")
-    ap.add_argument("--split", default="nnz", choices=["nnz", "rows"],
-                    help="rows: the paper's equal-rows baseline partitions (same np)")
-    ap.add_argument("--unprepared", action="store_true",
-                    help="time msrep_spmv (structure work in every call) instead of "
-                         "msrep_spmv_prepare once + msrep_spmv_prepared")
-    ap.add_argument("--warm", action="store_true",
-                    help="also time back-to-back (cache-warm) SpMVs of each format")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 256 MiB copy (counter calibration)")
-    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "KEY"))
-    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"))
-    ap.add_argument("--command", default="", help="command line recorded in a summary")
-    ap.add_argument("--bench-json", default=None, help="the traced run's output (trace summary)")
-    args = ap.parse_args()
-    if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, command=args.command)
-        return 0
-    if args.trace_summary:
-        trace_summary(*args.trace_summary, command=args.command, bench_json=args.bench_json)
-        return 0
-    if args.gpus != 1:
-        print("bench.py: one GPU only; --gpus %d is not supported (how the path would "
-              "shard across GPUs is a design note, not code)" % args.gpus, file=sys.stderr)
-        return 2
-
-    import torch
-
-    import paper_2209_07552_amd as pk
+def gen_workload(name):
+    """(Csr, x, workload description) of a named benchmark matrix."""
     import synth
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 1
-    dev = torch.device("cuda:0")
-    vt = {"f64": pk.F64, "f32": pk.F32, "bf16": pk.BF16}[args.vtype]
-    if args.rhs > 0:
-        return bench_spmm(args, vt)
-    if args.workload == "batched":
-        return bench_batched(args, vt)
-    if args.workload == "serve":
-        return bench_serve(args, vt)
     t0 = time.time()
-    if args.workload == "rmat20":
+    if name == "rmat20":
         A, x64 = synth.rmat_csr(scale=20, edge_factor=16, seed=0)
         wl = {"workload": "rmat-scale20-ef16", "rows": A.m, "cols": A.n, "nnz": A.nnz,
               "abcd": [0.57, 0.19, 0.19, 0.05]}
-    elif args.workload == "stencil256":
+    elif name == "stencil256":
         A, x64 = synth.stencil7_csr(256, seed=0)
         wl = {"workload": "laplace3d-7pt-256^3", "rows": A.m, "cols": A.n, "nnz": A.nnz}
     else:
         A, x64 = synth.uniform_csr(4096, 4096, 16, seed=0)
         wl = {"workload": "uniform-4096-16perrow", "rows": A.m, "cols": A.n, "nnz": A.nnz}
     log("generated %s in %.1fs" % (wl["workload"], time.time() - t0))
-    fmts = [f for f in args.formats.split(",") if f]
+    return A, x64, wl
+
+
+def stored_values(v, vt):
+    """FP64 values as the stored type: FP32 rounded once, BF16 from that FP32
+    (round to nearest even), as raw bits."""
+    import paper_2209_07552_amd as pk
+    import synth
+    if vt == pk.F64:
+        return v
+    v32 = np.asarray(v, np.float32)
+    return v32 if vt == pk.F32 else synth.bf16_bits(v32)
+
+
+def stored_as_f64(sv, vt):
+    """Stored values (FP64, FP32 or BF16 bits) back in FP64, exactly."""
+    import paper_2209_07552_amd as pk
+    if vt == pk.BF16:
+        return (np.asarray(sv, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return np.asarray(sv, np.float64)
+
+
+def measure_matrix(args, A, x64, wl, wkey, vt, fmts, ref=None):
+    """Time one step (one cold SpMV per format in fmts) of matrix A on the
+    GPU and check every format's y against the FP64 oracle.
+
+    Returns a dict: step time and GFLOP/s, per-format records (cold time,
+    algorithmic GB/s and fraction of HBM peak, partition / prepare time,
+    launch shape, per-kernel breakdown, largest error relative to (|A||x|)_i)
+    and the roofline record of the dominant kernel, priced at its format's
+    algorithmic bytes per SpMV.  ref: the oracle's (y, scale) on the FP64
+    values, computed here when None."""
+    import torch
+
+    import oracle
+    import paper_2209_07552_amd as pk
+    dev = torch.device("cuda:0")
     H = host_formats(A, any_order="coo_any" in fmts)
     vbytes = pk._abi.VALUE_BYTES[vt]
     xbytes = 8 if vt == pk.F64 else 4
-
-    def stored(v):
-        if vt == pk.F64:
-            return v
-        v32 = np.asarray(v, np.float32)
-        return v32 if vt == pk.F32 else synth.bf16_bits(v32)
-
+    vname = pk._abi.VT_NAMES[vt]
     mats = {}
     for f in fmts:
         a, b, v = H[f]
         if f == "csr":
-            mats[f] = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=a, idx=b, val=stored(v))
+            mats[f] = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=a, idx=b, val=stored_values(v, vt))
         elif f == "csc":
-            mats[f] = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=stored(v))
+            mats[f] = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=stored_values(v, vt))
         else:
             kind = pk.COO_ANY if f == "coo_any" else pk.COO
-            mats[f] = pk.Mat(kind, vt, A.m, A.n, idx=a, idx2=b, val=stored(v))
-    if args.split != "rows":
-        del H  # (the equal-rows baseline builds its partitions from it)
+            mats[f] = pk.Mat(kind, vt, A.m, A.n, idx=a, idx2=b, val=stored_values(v, vt))
+    del H
     xs = x64 if vt == pk.F64 else x64.astype(np.float32)
     x = torch.from_numpy(xs).to(dev)
-    ydt = torch.float64 if vt == pk.F64 else torch.float32
+    ydt = pk._abi.vector_dtype(vt)
     ys = {f: torch.zeros(A.m, dtype=ydt, device=dev) for f in fmts}
     # launch shape and partition size per format: explicit flags, else the
     # stored picks for this workload, else (or with --autotune) the tuner
     tunes, parts, part_ms = {}, {}, {}
     for f in fmts:
-        stored_t = DEFAULT_TUNES.get(args.workload, {}).get(f)
+        stored_t = DEFAULT_TUNES.get(wkey, {}).get(f)
         if args.nnz_per_wave:
             tunes[f] = pk.Tune(k_per_lane=args.k, waves_per_wg=args.wpb,
                                nnz_per_wave=args.nnz_per_wave, pipeline=args.pipeline,
@@ -445,7 +362,7 @@ def main():
         torch.cuda.synchronize()
         part_ms[f] = e0.elapsed_time(e1)
         if args.split == "rows" and f != "coo_any":  # the paper's baseline split, same np
-            parts[f] = equal_rows_partition(mats[f], H, f, np_f, dev)
+            parts[f] = pk.msrep_build_partition(mats[f], np_f, split=pk.SPLIT_ROWS)
             torch.cuda.synchronize()
     scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
     ws = {f: torch.zeros(max(256, pk.msrep_spmv_ws_bytes(mats[f], parts[f].np)), dtype=torch.uint8,
@@ -472,15 +389,17 @@ def main():
         else:
             pk.msrep_spmv_prepared(mats[f], parts[f], x, ys[f], ws[f], 1.0, 0.0, tunes[f])
 
+    def fmt_bytes(f):
+        return alg_bytes("coo" if f == "coo_any" else f, A.m, A.n, A.nnz, vbytes, xbytes)
+
     def priced_of(kt):
-        return {fk: v for fk, v in kt.items()
-                if kernel_alg_bytes(fk[1], A.m, A.n, A.nnz, 1, vbytes, xbytes, fk[0]) is not None}
+        return {fk: v for fk, v in kt.items() if fk[1] in PRICED_KERNELS}
 
     def timed_steps(steps, only=None):
         """steps cold steps; each SpMV bracketed by events.  only=None: the
         library times every kernel; only=(fmt, kernel): just that kernel in
         that format's SpMV (one event pair, so the step is barely
-        perturbed); only=False: no kernel timing."""
+        perturbed)."""
         ev = {f: [] for f in fmts}
         kt = {}
         for _ in range(steps):
@@ -514,7 +433,7 @@ def main():
         del src, dst
     torch.cuda.synchronize()
     # the dominant kernel: the largest share of the step's time among the
-    # kernels whose algorithmic bytes are defined (the SpMV kernels proper)
+    # SpMV kernels proper (not the boundary merges)
     dom = None
     if priced_of(kt_warm):
         dom = max(priced_of(kt_warm).items(), key=lambda kv: kv[1][1])[0]
@@ -541,17 +460,38 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         warm_ms[f] = e0.elapsed_time(e1) / args.steps
+    # ---- correctness of this run's results: every format against the FP64
+    # oracle (Dot2) on the original values; for FP32 / BF16 values also
+    # against the oracle on the stored values (the accumulation error alone)
+    errs = {}
+    if not args.no_check:
+        if ref is None:
+            ref = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x64)
+        y_ref, sc = ref
+        ref_st = None
+        if vt != pk.F64:
+            ref_st = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, stored_as_f64(stored_values(A.val, vt), vt),
+                                     x64.astype(np.float32).astype(np.float64))
+        for f in fmts:
+            yg = ys[f].double().cpu().numpy()
+            e = {"max_scaled_error_vs_fp64_oracle":
+                 float(np.max(np.abs(yg - y_ref) / np.where(sc > 0, sc, 1.0)))}
+            if ref_st is not None:
+                e["max_scaled_error_vs_oracle_on_stored_values"] = float(
+                    np.max(np.abs(yg - ref_st[0]) / np.where(ref_st[1] > 0, ref_st[1], 1.0)))
+            errs[f] = e
     step_ms = sum(cold_ms.values())
     flops = 2.0 * A.nnz * len(fmts)
     per_fmt = {}
     for f in fmts:
-        b = alg_bytes(f, A.m, A.n, A.nnz, vbytes, xbytes)
-        each = sorted(a.elapsed_time(b) for a, b in ev[f])
+        b = fmt_bytes(f)
+        each = sorted(a.elapsed_time(b_) for a, b_ in ev[f])
         per_fmt[f] = {"ms_cold": round(cold_ms[f], 4),
                       "ms_cold_median": round(float(np.median(each)), 4),
                       "ms_cold_min": round(each[0], 4),
                       "gflops_cold": round(2.0 * A.nnz / cold_ms[f] / 1e6, 2),
                       "gbs_cold": round(b / cold_ms[f] / 1e6, 1),
+                      "frac_cold": round(b / cold_ms[f] / 1e6 / HBM_PEAK_GBS, 4),
                       "alg_bytes": int(b), "partition_ms": round(part_ms[f], 4),
                       "prepare_ms": round(prep_ms[f], 4),
                       "entry": "msrep_spmv" if args.unprepared else "msrep_spmv_prepared",
@@ -566,43 +506,152 @@ def main():
             per_fmt[f]["gbs_warm"] = round(b / warm_ms[f] / 1e6, 1)
         per_fmt[f]["kernels_us"] = {k: round(t / c * 1e3, 2) for (g, k), (c, t) in kt_all.items()
                                     if g == f}
+        per_fmt[f].update(errs.get(f, {}))
     priced = priced_of(ktime)
     if not priced:  # no warmup: take the dominant kernel from the breakdown
         priced = priced_of(kt_all)
     (dom_f, kname), (kc, kt) = max(priced.items(), key=lambda kv: kv[1][1])
     k_ms = kt / kc
-    k_bytes = kernel_alg_bytes(kname, A.m, A.n, A.nnz, parts[dom_f].np, vbytes, xbytes, dom_f)
+    k_bytes = fmt_bytes(dom_f)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    traffic = load_traffic("%s/%s/%s" % (kname, wl["workload"], args.vtype))
-    out = {
-        "metric": "SpMV GFLOP/s (cold HBM; CSR+CSC+COO per step)",
-        "value": round(flops / (step_ms * 1e-3) / 1e9, 3),
-        "unit": "GFLOP/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(step_ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.vtype, "data": "synthetic",
-        "config": dict(wl, formats=fmts, value_type=args.vtype, split=args.split),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kname, "format": dom_f,
-                     "kernel_avg_us": round(k_ms * 1e3, 2), "alg_bytes_per_launch": int(k_bytes)},
-        "per_format": per_fmt,
-        "wall_s_timed_region": round(wall, 3),
-    }
+    traffic = load_traffic("%s/%s/%s" % (kname, wl["workload"], vname))
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": kname, "format": dom_f,
+            "kernel_avg_us": round(k_ms * 1e3, 2), "alg_bytes_per_launch": int(k_bytes),
+            "alg_bytes_basis": "the %s SpMV's own bytes (values, indices, pointer, x and y, "
+                               "each moved once), whichever kernel of the format moves them"
+                               % dom_f,
+            "path": {"format": dom_f, "ms": round(cold_ms[dom_f], 4),
+                     "achieved": round(k_bytes / cold_ms[dom_f] / 1e6, 1),
+                     "frac": round(k_bytes / cold_ms[dom_f] / 1e6 / HBM_PEAK_GBS, 4)}}
+    out = {"step_ms": step_ms, "gflops": flops / (step_ms * 1e-3) / 1e9,
+           "config": dict(wl, formats=fmts, value_type=vname, split=args.split),
+           "roofline": roof, "per_format": per_fmt, "wall_s_timed_region": round(wall, 3),
+           "ref": ref}
     if args.overheads:
         out["overheads"] = overheads(args, mats, part_ms, prep_ms, cold_ms, kt_all)
+    del mats, ws, scrub, ys, x
+    torch.cuda.empty_cache()
+    return out
+
+
+# kernels whose launch is priced against the SpMV's algorithmic bytes (the
+# per-format SpMV kernels proper; the boundary merges and the structure-only
+# CSC kernels are not)
+PRICED_KERNELS = ("spmv_csr_seg", "spmv_coo_seg", "csc_scatter", "csc_reduce")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stencil256",
+                    choices=["rmat20", "stencil256", "uniform4096", "batched", "serve"])
+    ap.add_argument("--rhs", type=int, default=0,
+                    help="k > 0: time msrep_spmm with k right-hand sides (CSR) instead")
+    ap.add_argument("--count", type=int, default=512, help="batched / serving pool size")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
+    ap.add_argument("--rates", default="0.1,0.5,0.9,1.2", help="serving: fractions of capacity")
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--vtype", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--formats", default="csr,csc,coo")
+    ap.add_argument("--nnz-per-wave", type=int, default=0, help="partition size (0: tuned)")
+    ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--pipeline", type=int, default=0)
+    ap.add_argument("--resident", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle checks")
+    ap.add_argument("--only", action="store_true",
+                    help="the named workload alone (no R-MAT or precision blocks)")
+    ap.add_argument("--autotune", action="store_true", help="tune every format first")
+    ap.add_argument("--overheads", action="store_true",
+                    help="also time conversion, partition build and merge against the SpMV")
+    ap.add_argument("--split", default="nnz", choices=["nnz", "rows"],
+                    help="rows: the paper's equal-rows baseline partitions (same np)")
+    ap.add_argument("--unprepared", action="store_true",
+                    help="time msrep_spmv (structure work in every call) instead of "
+                         "msrep_spmv_prepare once + msrep_spmv_prepared")
+    ap.add_argument("--warm", action="store_true",
+                    help="also time back-to-back (cache-warm) SpMVs of each format")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB copy (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "KEY"))
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"))
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--bench-json", default=None, help="the traced run's output (trace summary)")
+    args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, command=args.command)
+        return 0
+    if args.trace_summary:
+        trace_summary(*args.trace_summary, command=args.command, bench_json=args.bench_json)
+        return 0
+    if args.gpus != 1:
+        print("bench.py: one GPU only; --gpus %d is not supported (how the path would "
+              "shard across GPUs is a design note, not code)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2209_07552_amd as pk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    vt = {"f64": pk.F64, "f32": pk.F32, "bf16": pk.BF16}[args.vtype]
+    if args.rhs > 0:
+        return bench_spmm(args, vt)
+    if args.workload == "batched":
+        return bench_batched(args, vt)
+    if args.workload == "serve":
+        return bench_serve(args, vt)
+    fmts = [f for f in args.formats.split(",") if f]
+    A, x64, wl = gen_workload(args.workload)
+    r = measure_matrix(args, A, x64, wl, args.workload, vt, fmts)
+    out = {
+        "metric": "SpMV GFLOP/s (cold HBM; CSR+CSC+COO per step)",
+        "value": round(r["gflops"], 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r["step_ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.vtype, "data": "synthetic",
+        "config": r["config"],
+        "roofline": r["roofline"],
+        "per_format": r["per_format"],
+        "wall_s_timed_region": r["wall_s_timed_region"],
+    }
+    if "overheads" in r:
+        out["overheads"] = r["overheads"]
+    errs = [v["max_scaled_error_vs_fp64_oracle"] for v in r["per_format"].values()
+            if "max_scaled_error_vs_fp64_oracle" in v]
+    if errs:
+        key = "max_scaled_error_vs_oracle" if vt == pk.F64 else "max_scaled_error_vs_fp64_oracle"
+        out[key] = max(errs)
+    if not args.only and args.workload == "stencil256" and vt == pk.F64:
+        # pattern (1), precision: the same stencil with FP32 and BF16 stored
+        # values (FP32 x, y and accumulation), same launch shapes
+        prec = {}
+        for pv in (pk.F32, pk.BF16):
+            rp = measure_matrix(args, A, x64, wl, args.workload, pv, fmts, ref=r["ref"])
+            prec[pk._abi.VT_NAMES[pv]] = {
+                "ms_per_step": round(rp["step_ms"], 4), "gflops": round(rp["gflops"], 3),
+                "speedup_vs_f64": round(r["step_ms"] / rp["step_ms"], 3),
+                "roofline": rp["roofline"], "per_format": rp["per_format"]}
+        out["precision"] = prec
     if not args.no_cpu:
-        f0 = "csr" if "csr" in fmts else fmts[0]
-        yg = ys[f0].double().cpu().numpy()
-        if vt == pk.F64:
-            cb, err = cpu_baseline(A, x64, yg, args.cpu_budget)
-            out["cpu_baseline"] = cb
-            out["max_scaled_error_vs_oracle"] = err
-        else:
-            cb, err = cpu_baseline(A, x64, yg, args.cpu_budget)
-            out["cpu_baseline"] = cb
-            out["max_scaled_error_vs_fp64_oracle"] = err
+        out["cpu_baseline"] = cpu_baseline(A, x64)
+    if not args.only and args.workload == "stencil256" and vt == pk.F64:
+        # the power-law matrix: the same step on R-MAT scale 20
+        del A, x64
+        B, xb, wlb = gen_workload("rmat20")
+        rb = measure_matrix(args, B, xb, wlb, "rmat20", vt, fmts)
+        out["rmat20"] = {"config": rb["config"], "ms_per_step": round(rb["step_ms"], 4),
+                         "gflops": round(rb["gflops"], 3), "roofline": rb["roofline"],
+                         "per_format": rb["per_format"]}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -766,9 +815,11 @@ def bench_spmm(args, vt):
 def bench_batched(args, vt):
     """512 uneven matrices (log-uniform rows in [1e3, 2e5], half uniform 4-64
     nnz/row, half R-MAT-like) in one persistent hipGraph launch, against the
-    plain path (one msrep_spmv launch per matrix, same partitions)."""
+    plain path (one msrep_spmv launch per matrix, same partitions).  Every
+    matrix's y of the batched run is then checked against the FP64 oracle."""
     import torch
 
+    import oracle
     import paper_2209_07552_amd as pk
     import synth
     dev = torch.device("cuda:0")
@@ -797,6 +848,7 @@ def bench_batched(args, vt):
     for _ in range(args.warmup):
         pk.msrep_spmv_batched(plan, xs, ys)
     ms_b = _timed(lambda: pk.msrep_spmv_batched(plan, xs, ys), args.steps)
+    yb = [y.double().cpu().numpy() for y in ys]
     # plain path: one launch (plus merge) per matrix
     parts = [pk.msrep_build_partition(M, max(1, -(-M.nnz // t.nnz_per_wave))) for M, t in zip(Ms, tunes)]
     ws = torch.zeros(1 << 26, dtype=torch.uint8, device=dev)
@@ -807,6 +859,19 @@ def bench_batched(args, vt):
     for _ in range(args.warmup):
         plain()
     ms_p = _timed(plain, max(1, args.steps // 4))
+    # every matrix's batched result against the FP64 oracle on the original
+    # (FP64) values; for FP32 values also against the oracle on the stored
+    # values and FP32-rounded x
+    err, err_st = 0.0, 0.0
+    if not args.no_check:
+        for (A, x), yg in zip(mats, yb):
+            ref, sc = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
+            err = max(err, float(np.max(np.abs(yg - ref) / np.where(sc > 0, sc, 1.0))))
+            if vt != pk.F64:
+                r2, s2 = oracle.spmv_csr(A.m, A.n, A.ptr, A.col,
+                                         A.val.astype(np.float32).astype(np.float64),
+                                         x.astype(np.float32).astype(np.float64))
+                err_st = max(err_st, float(np.max(np.abs(yg - r2) / np.where(s2 > 0, s2, 1.0))))
     out = {"metric": "batched SpMV/s (%d uneven matrices, one persistent hipGraph launch)" % args.count,
            "value": round(args.count / (ms_b * 1e-3), 1), "unit": "SpMV/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 4),
@@ -815,62 +880,119 @@ def bench_batched(args, vt):
            "config": {"workload": "batched-%d" % args.count, "total_nnz": nnz, "items": plan.items()},
            "gflops": round(2.0 * nnz / (ms_b * 1e-3) / 1e9, 2),
            "alg_gbs": round(byts / (ms_b * 1e-3) / 1e9, 1),
+           "frac": round(byts / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "plain_path": {"ms_per_batch": round(ms_p, 4),
                           "spmv_per_s": round(args.count / (ms_p * 1e-3), 1)},
            "speedup_vs_plain": round(ms_p / ms_b, 3)}
+    if not args.no_check:
+        out["max_scaled_error_vs_fp64_oracle"] = err
+        out["checked"] = "all %d matrices, every row" % args.count
+        if vt != pk.F64:
+            out["max_scaled_error_vs_oracle_on_stored_values"] = err_st
     print(json.dumps(out), flush=True)
     return 0
+
+
+def plain_serve(pool, trace, vt, seed=0, nnz_per_wave=1024):
+    """The plain path on a serving trace: every pool matrix resident with its
+    partitions, requests served one at a time in arrival order (a request
+    waits for its arrival and for the one before it), each step one device x
+    generation (the server's generator) and one msrep_spmv launch.  Latency
+    = arrival to the completion of the request's last step, on the same
+    trace clock as the server's.  Returns the latencies in ms."""
+    import torch
+
+    import paper_2209_07552_amd as pk
+    from paper_2209_07552_amd import serving
+    dev = torch.device("cuda:0")
+    vdt = np.float64 if vt == pk.F64 else np.float32
+    used = sorted({q.matrix for q in trace})
+    Ms, Ps = {}, {}
+    for k in used:
+        A = pool[k]
+        Ms[k] = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val.astype(vdt))
+        Ps[k] = pk.msrep_build_partition(Ms[k], max(1, -(-A.nnz // nnz_per_wave)))
+    mmax = max(pool[k].m for k in used)
+    nmax = max(pool[k].n for k in used)
+    ydt = pk._abi.vector_dtype(vt)
+    xbuf = torch.empty(nmax, dtype=ydt, device=dev)
+    ybuf = torch.empty(mmax, dtype=ydt, device=dev)
+    ws = torch.zeros(1 << 26, dtype=torch.uint8, device=dev)
+    done = torch.cuda.Event()
+    torch.cuda.synchronize()
+    order = sorted(range(len(trace)), key=lambda i: trace[i].t_arrive)
+    lat = [0.0] * len(trace)
+    t0 = time.perf_counter()
+    for i in order:
+        q = trace[i]
+        A = pool[q.matrix]
+        while time.perf_counter() - t0 < q.t_arrive:
+            pass
+        x, y = xbuf[:A.n], ybuf[:A.m]
+        for j in range(q.steps):
+            serving.fill_x(x, seed, q.rid, j)
+            pk.msrep_spmv(Ms[q.matrix], Ps[q.matrix], x, y, ws=ws)
+        done.record()
+        done.synchronize()
+        lat[i] = (time.perf_counter() - t0 - q.t_arrive) * 1e3
+    return lat
 
 
 def bench_serve(args, vt):
     """Poisson request stream over a pool of batched-style matrices; each
     request = one matrix + 10..100 SpMVs with fresh x; arena budget as given.
     Rates are fractions of the measured batched capacity.  Beside it, the
-    plain FP64 path: one request at a time, one msrep_spmv launch per SpMV."""
-    import torch
-
+    plain path on the same traces: one request at a time, one msrep_spmv
+    launch per SpMV, x generated on the device.  A sample of served results
+    is checked against the FP64 oracle."""
+    import oracle
     import paper_2209_07552_amd as pk
     from paper_2209_07552_amd import serving
     import synth
-    dev = torch.device("cuda:0")
     t0 = time.time()
     pool = [A for A, _ in synth.batched_set(args.count, seed=0)]
     log("generated pool of %d in %.1fs" % (len(pool), time.time() - t0))
+    budget = int(args.budget_gb * (1 << 30))
     mean_steps = 55.0
     # capacity estimate from a saturated run: SpMVs per second of the mix
     probe = synth.serving_trace(max(64, args.count // 4), rate=1e9, pool=len(pool), seed=99)
-    _, st = serving.serve(pool, probe, budget_bytes=int(args.budget_gb * (1 << 30)), vtype=vt,
-                          max_slots=256)
+    _, st = serving.serve(pool, probe, budget_bytes=budget, vtype=vt, max_slots=256)
     cap_req = st["spmv_per_s"] / mean_steps
     log("saturated mix: %.0f SpMV/s -> capacity ~%.1f req/s" % (st["spmv_per_s"], cap_req))
     points = []
+    n_plain = max(1, args.requests // 4)
     for f in [float(v) for v in args.rates.split(",")]:
         trace = synth.serving_trace(args.requests, rate=max(f * cap_req, 1e-3), pool=len(pool), seed=1)
-        _, st = serving.serve(pool, trace, budget_bytes=int(args.budget_gb * (1 << 30)), vtype=vt,
-                              max_slots=256)
-        points.append({"load": f, "rate_req_s": round(f * cap_req, 2),
-                       "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                       "req_per_s": round(st["req_per_s"], 2),
-                       "spmv_per_s": round(st["spmv_per_s"], 1), "gflops": round(st["gflops"], 2),
-                       "peak_active": st["peak_active"], "ticks": st["ticks"]})
-        log(json.dumps(points[-1]))
-    # plain FP64 path: requests one after another, one launch per SpMV
-    sample = synth.serving_trace(64, rate=1.0, pool=len(pool), seed=1)
-    ws = torch.zeros(1 << 26, dtype=torch.uint8, device=dev)
-    lat = []
-    for q in sample:
-        A = pool[q.matrix]
-        M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val)
-        P = pk.msrep_build_partition(M, max(1, -(-A.nnz // 1024)))
-        x = torch.empty(A.n, dtype=torch.float64, device=dev)
-        y = torch.empty(A.m, dtype=torch.float64, device=dev)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for j in range(q.steps):
-            x.copy_(torch.from_numpy(synth.serving_x(A.n, 0, q.rid, j)), non_blocking=False)
-            pk.msrep_spmv(M, P, x, y, ws=ws)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t1) * 1e3)
+        _, st = serving.serve(pool, trace, budget_bytes=budget, vtype=vt, max_slots=256)
+        pt = {"load": f, "rate_req_s": round(f * cap_req, 2),
+              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+              "req_per_s": round(st["req_per_s"], 2),
+              "spmv_per_s": round(st["spmv_per_s"], 1), "gflops": round(st["gflops"], 2),
+              "peak_active": st["peak_active"], "ticks": st["ticks"]}
+        if f <= 1.0:  # the plain path on the first requests of the same trace
+            lat = plain_serve(pool, trace[:n_plain], vt)
+            pt["plain"] = {"requests": n_plain,
+                           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                           "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        points.append(pt)
+        log(json.dumps(pt))
+    # accuracy of served results: a separate run that keeps the last y of a
+    # sample of requests, each checked against the FP64 oracle on its matrix
+    # and that step's x (for FP32 pools also on the stored values)
+    chk = synth.serving_trace(64, rate=0.5 * cap_req, pool=len(pool), seed=2)
+    res, _ = serving.serve(pool, chk, budget_bytes=budget, vtype=vt, max_slots=256,
+                           keep_y=range(0, 64, 4))
+    err = err_st = 0.0
+    for i in range(0, 64, 4):
+        q, A = chk[i], pool[chk[i].matrix]
+        x = synth.serving_x(A.n, 0, q.rid, q.steps - 1)
+        ref, sc = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x)
+        yg = np.asarray(res[i].y, np.float64)
+        err = max(err, float(np.max(np.abs(yg - ref) / np.where(sc > 0, sc, 1.0))))
+        if vt != pk.F64:
+            r2, s2 = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val.astype(np.float32).astype(np.float64),
+                                     x.astype(np.float32).astype(np.float64))
+            err_st = max(err_st, float(np.max(np.abs(yg - r2) / np.where(s2 > 0, s2, 1.0))))
     best = max(points, key=lambda p: p["req_per_s"])
     out = {"metric": "served p50/p99 latency and req/s (Poisson, continuous batching)",
            "value": best["req_per_s"], "unit": "req/s", "n_gpus": 1, "steps": args.requests,
@@ -879,11 +1001,13 @@ def bench_serve(args, vt):
            "config": {"workload": "serve-pool%d" % len(pool), "budget_gb": args.budget_gb,
                       "steps_per_request": "U{10..100}"},
            "points": points,
-           "plain_fp64_one_request_at_a_time": {
-               "p50_ms": round(float(np.percentile(lat, 50)), 3),
-               "p99_ms": round(float(np.percentile(lat, 99)), 3),
-               "req_per_s": round(1e3 / float(np.mean(lat)), 2),
-               "note": "service time only (no queueing); x generated on the host per step"}}
+           "plain_path": "the same trace's first %d requests, one at a time in arrival order "
+                         "(queueing included), x generated on the device, one msrep_spmv per "
+                         "step, matrices and partitions resident" % n_plain,
+           "max_scaled_error_vs_fp64_oracle": err,
+           "checked": "last y of 16 of 64 requests served at 0.5x capacity, every row"}
+    if vt != pk.F64:
+        out["max_scaled_error_vs_oracle_on_stored_values"] = err_st
     print(json.dumps(out), flush=True)
     return 0
 

@@ -162,6 +162,24 @@ msrep_status msrep_build_partition(const msrep_mat *A, int32_t np,
                                    int64_t lptr_cap, int64_t *lptr_len_d,
                                    void *stream);
 
+/*
+ * The paper's Baseline split (Sec. 5.3), for comparison with the equal-nnz
+ * partitions: partition i holds the whole rows (CSC: columns)
+ * floor(i*rows/np) .. floor((i+1)*rows/np) - 1, however many nonzeros they
+ * have, so partitions are unequal in work and no row is split.  The records
+ * have the meaning given above (start_idx / end_idx the block's first and
+ * last nonzero, start_row / end_row the rows holding them, both flags 0,
+ * local pointers at start_row + 2*i); a block without nonzeros is an empty
+ * partition.  Same arguments, sizes and errors as msrep_build_partition,
+ * and every SpMV entry point takes the result like an equal-nnz partition.
+ * COO in any order has no row blocks (MSREP_ERR_UNSUPPORTED).  Row-sorted
+ * COO is searched by bisection at 2*np positions.
+ */
+msrep_status msrep_build_partition_rows(const msrep_mat *A, int32_t np,
+                                        msrep_part *parts_d, int32_t *lptr_d,
+                                        int64_t lptr_cap, int64_t *lptr_len_d,
+                                        void *stream);
+
 /* ---------------------------------------------------------- conversion */
 /* Workspace bytes msrep_convert needs to turn src into format dst_fmt. */
 size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt);
@@ -423,6 +441,15 @@ msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
 /* Entry c of x_step for request rid (see msrep_serve), on the host. */
 double msrep_serve_x_value(uint64_t seed, int64_t rid, int32_t step,
                            int64_t c);
+
+/* The same x_step of request rid written on the device: x_d holds n values
+ * (FP64 for MSREP_F64, FP32 for MSREP_F32, which rounds each value once),
+ * launched on stream.  For callers that run a request's SpMVs themselves
+ * (one msrep_spmv per step) with the server's inputs.  MSREP_ERR_ARG for a
+ * NULL x_d with n > 0, n < 0 or another value type. */
+msrep_status msrep_serve_fill_x(uint64_t seed, int64_t rid, int32_t step,
+                                void *x_d, int32_t n, int32_t vtype,
+                                void *stream);
 
 #ifdef __cplusplus
 }

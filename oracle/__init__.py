@@ -45,7 +45,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle into oracle/liboracle.so with gcc and return its path."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
                "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -64,17 +64,21 @@ def _load():
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         vp = ctypes.c_void_p
         _lib.oracle_spmv_csr.argtypes = [i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
+        _lib.oracle_spmv_csr_plain.argtypes = [i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, i32]
         _lib.oracle_spmm_csr.argtypes = [i32, i32, i32, vp, vp, vp, vp, i64, dbl, dbl, vp, i64,
                                          vp, vp]
         _lib.oracle_spmv_csc.argtypes = [i32, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
         _lib.oracle_spmv_coo.argtypes = [i32, i32, i64, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
         _lib.oracle_partition_ptr.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
         _lib.oracle_partition_coo.argtypes = [i32, i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        _lib.oracle_partition_rows_ptr.argtypes = _lib.oracle_partition_ptr.argtypes
+        _lib.oracle_partition_rows_coo.argtypes = _lib.oracle_partition_coo.argtypes
         _lib.oracle_csr_to_coo.argtypes = [i32, vp, vp]
         _lib.oracle_coo_to_csr.argtypes = [i32, i64, vp, vp]
         _lib.oracle_transpose.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
-        for f in ("oracle_spmv_csr", "oracle_spmm_csr", "oracle_spmv_csc", "oracle_spmv_coo",
-                  "oracle_partition_ptr", "oracle_partition_coo", "oracle_csr_to_coo",
+        for f in ("oracle_spmv_csr", "oracle_spmv_csr_plain", "oracle_spmm_csr", "oracle_spmv_csc", "oracle_spmv_coo",
+                  "oracle_partition_ptr", "oracle_partition_coo", "oracle_partition_rows_ptr",
+                  "oracle_partition_rows_coo", "oracle_csr_to_coo",
                   "oracle_coo_to_csr", "oracle_transpose"):
             getattr(_lib, f).restype = ctypes.c_int
     return _lib
@@ -111,6 +115,20 @@ def spmv_csr(m, n, row_ptr, col_idx, val, x, alpha=1.0, beta=0.0, y_in=None):
     _check(lib.oracle_spmv_csr(m, n, _p(row_ptr), _p(col_idx), _p(val), _p(x), alpha, beta,
                                _p(yi), _p(y), _p(s)), "spmv_csr")
     return y, s
+
+
+def spmv_csr_plain(m, n, row_ptr, col_idx, val, x, alpha=1.0, beta=0.0, y_in=None,
+                   threads=1):
+    """The uncompensated CSR row loop (plain FP64 sums) on `threads` OpenMP
+    threads: the CPU baseline's arithmetic.  Returns y."""
+    lib = _load()
+    row_ptr, col_idx = _c(row_ptr, np.int32), _c(col_idx, np.int32)
+    val, x = _c(val, np.float64), _c(x, np.float64)
+    yi = _yin(y_in, m, beta)
+    y = np.empty(m, np.float64)
+    _check(lib.oracle_spmv_csr_plain(m, n, _p(row_ptr), _p(col_idx), _p(val), _p(x), alpha, beta,
+                                     _p(yi), _p(y), int(threads)), "spmv_csr_plain")
+    return y
 
 
 def spmm_csr(m, n, row_ptr, col_idx, val, X, alpha=1.0, beta=0.0, Y_in=None):
@@ -191,16 +209,17 @@ def lptr_bound(rows, np_):
     return int(rows) + 2 * int(np_)
 
 
-def partition_ptr(rows, ptr, np_):
+def partition_ptr(rows, ptr, np_, split="nnz"):
     """pCSR (ptr = CSR row_ptr, Algorithm 2) or pCSC (ptr = CSC col_ptr,
-    Algorithm 4)."""
+    Algorithm 4); split="rows": the Baseline's equal row blocks (Sec. 5.3)."""
     lib = _load()
+    fn = lib.oracle_partition_rows_ptr if split == "rows" else lib.oracle_partition_ptr
     ptr = _c(ptr, np.int32)
     P = Partition(np_)
     cap = lptr_bound(rows, np_)
     P.lptr = np.full(cap, -1, np.int32)
     ln = np.zeros(1, np.int64)
-    _check(lib.oracle_partition_ptr(rows, _p(ptr), np_, _p(P.start_idx), _p(P.end_idx),
+    _check(fn(rows, _p(ptr), np_, _p(P.start_idx), _p(P.end_idx),
                                     _p(P.start_row), _p(P.end_row), _p(P.start_flag),
                                     _p(P.end_flag), _p(P.lptr_off), _p(P.lptr), cap, _p(ln)),
            "partition_ptr")
@@ -208,12 +227,14 @@ def partition_ptr(rows, ptr, np_):
     return P
 
 
-def partition_coo(rows, row_idx, np_):
-    """pCOO on row-sorted COO (Algorithm 6)."""
+def partition_coo(rows, row_idx, np_, split="nnz"):
+    """pCOO on row-sorted COO (Algorithm 6); split="rows": the Baseline's
+    equal row blocks (Sec. 5.3)."""
     lib = _load()
+    fn = lib.oracle_partition_rows_coo if split == "rows" else lib.oracle_partition_coo
     row_idx = _c(row_idx, np.int32)
     P = Partition(np_)
-    _check(lib.oracle_partition_coo(rows, len(row_idx), _p(row_idx), np_, _p(P.start_idx),
+    _check(fn(rows, len(row_idx), _p(row_idx), np_, _p(P.start_idx),
                                     _p(P.end_idx), _p(P.start_row), _p(P.end_row),
                                     _p(P.start_flag), _p(P.end_flag), _p(P.lptr_off)),
            "partition_coo")

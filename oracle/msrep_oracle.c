@@ -8,7 +8,8 @@
  * calls this file; only the test suite, the smoke check and the benchmark's
  * CPU-baseline leg do.  It shares no source with the GPU path.
  *
- * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math (see build.py).
+ * Build: gcc -O2 -fPIC -shared -fopenmp -ffp-contract=off -fno-fast-math
+ * (see __init__.py).
  * Contraction is off so that every a*b and a+b below rounds exactly once, as
  * the error-free transformations require; fma() is called explicitly.
  *
@@ -17,10 +18,14 @@
  *     Algorithm 1; CSC swaps the roles of x and y; COO is a single loop over
  *     the nonzeros), every row's dot product accumulated with Dot2 so the
  *     oracle's own error is negligible next to any tolerance.
+ *   - The same CSR product in plain FP64 (no compensation) over OpenMP
+ *     threads: the row loop a CPU timing baseline runs.
  *   - The same product for k right-hand sides (a row-major block X), every
  *     column as Algorithm 1.
  *   - The partition metadata of pCSR / pCSC / pCOO (Sec. 3.2.1-3.2.3,
- *     Algorithms 2, 4 and 6) including each partition's local row pointer.
+ *     Algorithms 2, 4 and 6) including each partition's local row pointer,
+ *     and of the paper's equal-rows Baseline split (Sec. 5.3) in the same
+ *     records.
  *   - Format conversions between CSR, CSC and row-sorted COO (Sec. 2.1).
  *
  * Readings of the paper that this file commits to (the paper is silent,
@@ -145,6 +150,35 @@ int oracle_spmv_csr(int32_t m, int32_t n, const int32_t *row_ptr,
     if (scale_out) scale_out[i] = row_scale(abs_dot, alpha, beta, yi);
   }
   return ORACLE_OK;
+}
+
+/* The same CSR product without compensation: every row's dot product is
+ * summed left to right in plain FP64, y_i = alpha * s_i + beta * y_i, rows
+ * split over nthreads OpenMP threads in contiguous static blocks (rows are
+ * independent, so the result does not depend on nthreads).  This is the
+ * plain row loop of Algorithm 1, the CPU baseline a timing is compared with;
+ * its rounding error is that of ordinary recursive summation, so it is
+ * checked against the Dot2 result above by tolerance only. */
+int oracle_spmv_csr_plain(int32_t m, int32_t n, const int32_t *row_ptr,
+                          const int32_t *col_idx, const double *val,
+                          const double *x, double alpha, double beta,
+                          const double *y_in, double *y_out, int32_t nthreads) {
+  if (m < 0 || n < 0 || !row_ptr || !y_out || nthreads < 1) return ORACLE_ERR_ARG;
+  int bad = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(| : bad)
+  for (int64_t i = 0; i < m; ++i) {
+    double s = 0.0;
+    for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
+      int32_t c = col_idx[j];
+      if (c < 0 || c >= n) {
+        bad = 1;
+        break;
+      }
+      s += val[j] * x[c];
+    }
+    y_out[i] = (beta != 0.0) ? alpha * s + beta * y_in[i] : alpha * s;
+  }
+  return bad ? ORACLE_ERR_FORMAT : ORACLE_OK;
 }
 
 /* Several right-hand sides (the sparse matrix times several dense vectors
@@ -362,6 +396,85 @@ int oracle_partition_coo(int32_t rows, int64_t nnz, const int32_t *row_idx,
     end_row[i] = row_idx[e];
     start_flag[i] = (s > 0 && row_idx[s - 1] == row_idx[s]) ? 1 : 0;
     end_flag[i] = (e + 1 < nnz && row_idx[e + 1] == row_idx[e]) ? 1 : 0;
+  }
+  return ORACLE_OK;
+}
+
+/*
+ * The paper's Baseline split (Sec. 5.3), the comparison point of the
+ * equal-nnz partitions: partition i takes the whole rows (CSC: columns)
+ * floor(i*rows/np) .. floor((i+1)*rows/np) - 1 whatever their nonzeros, so
+ * no row is split (both flags 0).  The records keep the equal-nnz meaning
+ * of every field: start_idx / end_idx are the first and last nonzero of the
+ * block, start_row / end_row the rows holding them (R3), the local pointer
+ * follows R5 at start_row + 2*i, and a block without nonzeros is an empty
+ * partition in the sense of R7.
+ */
+int oracle_partition_rows_ptr(int32_t rows, const int32_t *ptr, int32_t np,
+                              int64_t *start_idx, int64_t *end_idx,
+                              int32_t *start_row, int32_t *end_row,
+                              int32_t *start_flag, int32_t *end_flag,
+                              int64_t *lptr_off, int32_t *lptr, int64_t lptr_cap,
+                              int64_t *lptr_len) {
+  if (rows < 0 || np <= 0 || !ptr) return ORACLE_ERR_ARG;
+  int64_t nnz = ptr[rows];
+  int64_t len = 0;
+  for (int32_t i = 0; i < np; ++i) {
+    int64_t r_lo = ((int64_t)i * rows) / np;
+    int64_t r_hi = ((int64_t)(i + 1) * rows) / np; /* one past the block */
+    int64_t s = ptr[r_lo];
+    int64_t e = (int64_t)ptr[r_hi] - 1;
+    int32_t sr = (s < nnz) ? row_containing(ptr, rows, s) : rows;
+    int32_t er = (s <= e) ? row_containing(ptr, rows, e) : sr - 1;
+    start_idx[i] = s;
+    end_idx[i] = e;
+    start_row[i] = sr;
+    end_row[i] = er;
+    start_flag[i] = 0;
+    end_flag[i] = 0;
+    int64_t off = (int64_t)sr + 2 * (int64_t)i;
+    int64_t R = (int64_t)er - sr + 1; /* 0 for an empty block */
+    if (off + R + 1 > lptr_cap) return ORACLE_ERR_SIZE;
+    if (R == 0) {
+      lptr[off] = 0;
+    } else {
+      for (int64_t j = 0; j <= R; ++j) { /* R5 */
+        int64_t p = ptr[sr + j];
+        if (p < s) p = s;
+        if (p > e + 1) p = e + 1;
+        lptr[off + j] = (int32_t)(p - s);
+      }
+    }
+    lptr_off[i] = off;
+    if (off + R + 1 > len) len = off + R + 1;
+  }
+  if (lptr_len) *lptr_len = len;
+  return ORACLE_OK;
+}
+
+/* The Baseline split of row-sorted COO: the same row blocks, their first
+ * and last positions found by scanning row_idx. */
+int oracle_partition_rows_coo(int32_t rows, int64_t nnz, const int32_t *row_idx,
+                              int32_t np, int64_t *start_idx, int64_t *end_idx,
+                              int32_t *start_row, int32_t *end_row,
+                              int32_t *start_flag, int32_t *end_flag,
+                              int64_t *lptr_off) {
+  if (rows < 0 || nnz < 0 || np <= 0) return ORACLE_ERR_ARG;
+  for (int64_t k = 1; k < nnz; ++k)
+    if (row_idx[k] < row_idx[k - 1]) return ORACLE_ERR_FORMAT;
+  for (int32_t i = 0; i < np; ++i) {
+    int64_t r_lo = ((int64_t)i * rows) / np;
+    int64_t r_hi = ((int64_t)(i + 1) * rows) / np;
+    int64_t s = 0, e1 = 0; /* positions of the first row >= r_lo, >= r_hi */
+    while (s < nnz && row_idx[s] < r_lo) ++s;
+    while (e1 < nnz && row_idx[e1] < r_hi) ++e1;
+    start_idx[i] = s;
+    end_idx[i] = e1 - 1;
+    start_row[i] = (s < nnz) ? row_idx[s] : rows;
+    end_row[i] = (s <= e1 - 1) ? row_idx[e1 - 1] : start_row[i] - 1;
+    start_flag[i] = 0;
+    end_flag[i] = 0;
+    lptr_off[i] = 0;
   }
   return ORACLE_OK;
 }

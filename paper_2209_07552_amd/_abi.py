@@ -98,6 +98,7 @@ def load_library():
         "msrep_validate": (c_i32, [P(_Mat), c_vp]),
         "msrep_lptr_bound": (c_i64, [c_i32, c_i32]),
         "msrep_build_partition": (c_i32, [P(_Mat), c_i32, c_vp, c_vp, c_i64, c_vp, c_vp]),
+        "msrep_build_partition_rows": (c_i32, [P(_Mat), c_i32, c_vp, c_vp, c_i64, c_vp, c_vp]),
         "msrep_convert_ws_bytes": (c_sz, [P(_Mat), c_i32]),
         "msrep_convert": (c_i32, [P(_Mat), P(_Mat), c_vp, c_sz, c_vp]),
         "msrep_spmv_ws_bytes": (c_sz, [P(_Mat), c_i32]),
@@ -293,7 +294,12 @@ def msrep_validate(A: Mat, stream=None):
     _check(load_library().msrep_validate(ctypes.byref(d), _stream(stream)), "validate")
 
 
-def msrep_build_partition(A: Mat, np_: int, stream=None) -> Partition:
+SPLIT_NNZ, SPLIT_ROWS = 0, 1  # equal-nnz partitions / the paper's equal-rows Baseline
+
+
+def msrep_build_partition(A: Mat, np_: int, stream=None, split: int = SPLIT_NNZ) -> Partition:
+    """np_ equal-nnz partitions of A (split=SPLIT_ROWS: the Baseline's equal
+    row blocks, msrep_build_partition_rows)."""
     torch = _require_gpu()
     L = load_library()
     dev = A.idx.device if A.idx is not None else A.ptr.device
@@ -307,8 +313,9 @@ def msrep_build_partition(A: Mat, np_: int, stream=None) -> Partition:
         lptr = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     ln = torch.zeros(1, dtype=torch.int64, device=dev)
     d = A.desc()
-    _check(L.msrep_build_partition(ctypes.byref(d), np_, _ptr(parts), _ptr(lptr), cap, _ptr(ln),
-                                   _stream(stream)), "build_partition")
+    fn = L.msrep_build_partition_rows if split == SPLIT_ROWS else L.msrep_build_partition
+    _check(fn(ctypes.byref(d), np_, _ptr(parts), _ptr(lptr), cap, _ptr(ln), _stream(stream)),
+           "build_partition")
     return Partition(A, np_, parts, lptr, ln)
 
 

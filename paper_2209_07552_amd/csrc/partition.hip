@@ -3,7 +3,9 @@
 // the start/end rows by bisection (O(np log m)), then the local pointers are
 // written by a second kernel (O(m)), the offload the paper's optimised variant
 // applies (Sec. 4.1).  Every partition depends on nothing but A and its own
-// index, so both kernels are embarrassingly parallel.
+// index, so both kernels are embarrassingly parallel.  The paper's Baseline
+// split (equal rows or columns per partition, Sec. 5.3) is built the same way
+// into the same records, for comparison runs.
 #include "common.hpp"
 
 namespace msrep {
@@ -128,6 +130,68 @@ __global__ __launch_bounds__(256) void part_meta_any(int64_t nnz, int32_t np,
   parts[i] = P;
 }
 
+// The paper's Baseline split (Sec. 5.3): partition i takes the whole rows
+// (CSC: columns) floor(i*rows/np) .. floor((i+1)*rows/np) - 1, whatever
+// their nonzeros; no row is split, so both flags are 0.  The record fields
+// keep their equal-nnz meaning: start_row / end_row are the rows holding the
+// block's first and last nonzero, and a block without nonzeros is an empty
+// partition (end_idx = start_idx - 1, start_row = the row of start_idx).
+__global__ __launch_bounds__(256) void part_meta_rows_ptr(const int32_t *__restrict__ ptr,
+                                                          int32_t rows, int64_t nnz, int32_t np,
+                                                          msrep_part *__restrict__ parts) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int32_t r_lo = static_cast<int32_t>((static_cast<int64_t>(i) * rows) / np);
+  const int32_t r_hi = static_cast<int32_t>((static_cast<int64_t>(i + 1) * rows) / np);
+  const int64_t s = ptr[r_lo];
+  const int64_t e = static_cast<int64_t>(ptr[r_hi]) - 1;
+  msrep_part P;
+  P.start_idx = s;
+  P.end_idx = e;
+  P.start_flag = 0;
+  P.end_flag = 0;
+  const int32_t sr = s < nnz ? row_containing(ptr, rows, s) : rows;
+  P.start_row = sr;
+  P.end_row = s > e ? sr - 1 : row_containing(ptr, rows, e);
+  P.lptr_off = static_cast<int64_t>(sr) + 2 * static_cast<int64_t>(i);
+  parts[i] = P;
+}
+
+// First position of a row-sorted row index array holding a row >= r (nnz
+// if none).
+__device__ int64_t first_row_at_least(const int32_t *__restrict__ row_idx, int64_t nnz,
+                                      int32_t r) {
+  int64_t lo = 0, hi = nnz;  // answer in [lo, hi]
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (row_idx[mid] < r)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void part_meta_rows_coo(const int32_t *__restrict__ row_idx,
+                                                          int32_t rows, int64_t nnz, int32_t np,
+                                                          msrep_part *__restrict__ parts) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int32_t r_lo = static_cast<int32_t>((static_cast<int64_t>(i) * rows) / np);
+  const int32_t r_hi = static_cast<int32_t>((static_cast<int64_t>(i + 1) * rows) / np);
+  const int64_t s = first_row_at_least(row_idx, nnz, r_lo);
+  const int64_t e = first_row_at_least(row_idx, nnz, r_hi) - 1;
+  msrep_part P;
+  P.start_idx = s;
+  P.end_idx = e;
+  P.start_flag = 0;
+  P.end_flag = 0;
+  P.lptr_off = 0;
+  P.start_row = s < nnz ? row_idx[s] : rows;
+  P.end_row = s > e ? P.start_row - 1 : row_idx[e];
+  parts[i] = P;
+}
+
 __global__ void store_i64(int64_t *p, int64_t v) { *p = v; }
 
 }  // namespace
@@ -140,16 +204,26 @@ extern "C" int64_t msrep_lptr_bound(int32_t rows, int32_t np) {
   return static_cast<int64_t>(rows) + 2 * static_cast<int64_t>(np);
 }
 
-extern "C" msrep_status msrep_build_partition(const msrep_mat *A, int32_t np, msrep_part *parts_d,
-                                              int32_t *lptr_d, int64_t lptr_cap,
-                                              int64_t *lptr_len_d, void *stream) {
-  if (msrep_status st = check_mat(A, "msrep_build_partition")) return st;
-  if (np <= 0) return fail(MSREP_ERR_ARG, "msrep_build_partition: np must be positive (got %d)", np);
-  if (!parts_d) return fail(MSREP_ERR_ARG, "msrep_build_partition: parts_d is NULL");
+namespace {
+
+enum Split { kSplitNnz, kSplitRows };
+
+msrep_status build_partition(const msrep_mat *A, int32_t np, msrep_part *parts_d, int32_t *lptr_d,
+                             int64_t lptr_cap, int64_t *lptr_len_d, void *stream, Split split,
+                             const char *who) {
+  if (msrep_status st = check_mat(A, who)) return st;
+  if (np <= 0) return fail(MSREP_ERR_ARG, "%s: np must be positive (got %d)", who, np);
+  if (!parts_d) return fail(MSREP_ERR_ARG, "%s: parts_d is NULL", who);
+  if (split == kSplitRows && A->fmt == MSREP_COO_ANY)
+    return fail(MSREP_ERR_UNSUPPORTED, "%s: COO in any order has no row blocks", who);
   hipStream_t s = as_stream(stream);
   const int grid = (np + 255) / 256;
   if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY) {
-    if (A->fmt == MSREP_COO) {
+    if (split == kSplitRows) {
+      hipLaunchKernelGGL(part_meta_rows_coo, dim3(grid), dim3(256), 0, s, A->idx, A->m, A->nnz,
+                         np, parts_d);
+      MSREP_LAUNCHED("part_meta_rows_coo");
+    } else if (A->fmt == MSREP_COO) {
       hipLaunchKernelGGL(part_meta_coo, dim3(grid), dim3(256), 0, s, A->idx, A->m, A->nnz, np,
                          parts_d);
       MSREP_LAUNCHED("part_meta_coo");
@@ -165,16 +239,40 @@ extern "C" msrep_status msrep_build_partition(const msrep_mat *A, int32_t np, ms
   }
   const int32_t rows = major_dim(A);
   const int64_t need = msrep_lptr_bound(rows, np);
-  if (!lptr_d) return fail(MSREP_ERR_ARG, "msrep_build_partition: lptr_d is NULL");
+  if (!lptr_d) return fail(MSREP_ERR_ARG, "%s: lptr_d is NULL", who);
   if (lptr_cap < need)
-    return fail(MSREP_ERR_SIZE, "msrep_build_partition: lptr_cap %lld < rows + 2*np = %lld",
+    return fail(MSREP_ERR_SIZE, "%s: lptr_cap %lld < rows + 2*np = %lld", who,
                 static_cast<long long>(lptr_cap), static_cast<long long>(need));
-  hipLaunchKernelGGL(part_meta_ptr, dim3(grid), dim3(256), 0, s, A->ptr, rows, A->nnz, np, parts_d);
-  MSREP_LAUNCHED("part_meta_ptr");
+  if (split == kSplitRows) {
+    hipLaunchKernelGGL(part_meta_rows_ptr, dim3(grid), dim3(256), 0, s, A->ptr, rows, A->nnz, np,
+                       parts_d);
+    MSREP_LAUNCHED("part_meta_rows_ptr");
+  } else {
+    hipLaunchKernelGGL(part_meta_ptr, dim3(grid), dim3(256), 0, s, A->ptr, rows, A->nnz, np,
+                       parts_d);
+    MSREP_LAUNCHED("part_meta_ptr");
+  }
   // enough blocks to cover the device even when np is small
   const int32_t bpp = np >= 2048 ? 1 : (2048 + np - 1) / np;
   hipLaunchKernelGGL(part_lptr, dim3(static_cast<unsigned>(np) * bpp), dim3(256), 0, s, A->ptr, np,
                      parts_d, lptr_d, lptr_cap, bpp, lptr_len_d);
   MSREP_LAUNCHED("part_lptr");
   return ok();
+}
+
+}  // namespace
+
+extern "C" msrep_status msrep_build_partition(const msrep_mat *A, int32_t np, msrep_part *parts_d,
+                                              int32_t *lptr_d, int64_t lptr_cap,
+                                              int64_t *lptr_len_d, void *stream) {
+  return build_partition(A, np, parts_d, lptr_d, lptr_cap, lptr_len_d, stream, kSplitNnz,
+                         "msrep_build_partition");
+}
+
+extern "C" msrep_status msrep_build_partition_rows(const msrep_mat *A, int32_t np,
+                                                   msrep_part *parts_d, int32_t *lptr_d,
+                                                   int64_t lptr_cap, int64_t *lptr_len_d,
+                                                   void *stream) {
+  return build_partition(A, np, parts_d, lptr_d, lptr_cap, lptr_len_d, stream, kSplitRows,
+                         "msrep_build_partition_rows");
 }

@@ -707,3 +707,30 @@ extern "C" msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
 extern "C" double msrep_serve_x_value(uint64_t seed, int64_t rid, int32_t step, int64_t c) {
   return x_value(seed, rid, step, c);
 }
+
+namespace msrep {
+namespace {
+template <typename T>
+__global__ void fill_x_one(T *__restrict__ x, int32_t n, uint64_t seed, int64_t rid, int32_t step) {
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    x[c] = static_cast<T>(x_value(seed, rid, step, c));
+}
+}  // namespace
+}  // namespace msrep
+
+extern "C" msrep_status msrep_serve_fill_x(uint64_t seed, int64_t rid, int32_t step, void *x_d,
+                                           int32_t n, int32_t vtype, void *stream) {
+  if (n < 0 || (n > 0 && !x_d) || (vtype != MSREP_F64 && vtype != MSREP_F32))
+    return fail(MSREP_ERR_ARG, "msrep_serve_fill_x: bad vector, size or value type");
+  if (n == 0) return ok();
+  const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 1024));
+  if (vtype == MSREP_F64)
+    hipLaunchKernelGGL(fill_x_one<double>, dim3(grid), dim3(256), 0, as_stream(stream),
+                       static_cast<double *>(x_d), n, seed, rid, step);
+  else
+    hipLaunchKernelGGL(fill_x_one<float>, dim3(grid), dim3(256), 0, as_stream(stream),
+                       static_cast<float *>(x_d), n, seed, rid, step);
+  MSREP_LAUNCHED("fill_x_one");
+  return ok();
+}

@@ -36,6 +36,21 @@ def _bind(L):
     g = L.msrep_serve_x_value
     g.restype = ctypes.c_double
     g.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64]
+    h = L.msrep_serve_fill_x
+    h.restype = ctypes.c_int32
+    h.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_void_p]
+
+
+def fill_x(x, seed, rid, step, stream=None):
+    """Write x_step of request rid (the server's generator) into the device
+    tensor x (FP64 or FP32) on the stream."""
+    L = load_library()
+    _bind(L)
+    vt = F64 if x.dtype == _abi._torch().float64 else F32
+    _check(L.msrep_serve_fill_x(int(seed), int(rid), int(step), x.data_ptr(), int(x.numel()), vt,
+                                _abi._stream(stream)), "serve_fill_x")
+    return x
 
 
 def x_value(seed, rid, step, c):
@@ -48,7 +63,9 @@ def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 2
           nnz_per_wave: int = 1024, vtype: int = F64, seed: int = 0, time_scale: float = 1.0,
           keep_y: bool = False, simulate: bool = False, sim=(0.0, 0.0, -1.0), nps=None):
     """Run a request trace.  pool: list of synth.Csr (or objects with m, n,
-    ptr, col, val); trace: list of synth.Request.  Returns (results, stats)."""
+    ptr, col, val); trace: list of synth.Request.  keep_y: True to return
+    every request's last y, or a collection of trace indices to return only
+    theirs.  Returns (results, stats)."""
     L = load_library()
     _bind(L)
     keep = []
@@ -79,17 +96,17 @@ def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 2
     for i, r in enumerate(trace):
         tr[i] = _Request(r.rid, r.t_arrive, r.matrix, r.steps)
     res = (_Result * max(n, 1))()
-    ybufs = []
+    ybufs = [None] * n
     if keep_y:
-        for i, r in enumerate(trace):
-            y = np.zeros(pool[r.matrix].m, xdt)
-            ybufs.append(y)
-            res[i].y_host = y.ctypes.data
+        want = range(n) if keep_y is True else sorted(set(int(i) for i in keep_y))
+        for i in want:
+            ybufs[i] = np.zeros(pool[trace[i].matrix].m, xdt)
+            res[i].y_host = ybufs[i].ctypes.data
     arena = None
     if not simulate:
         arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
     cfg = _ServeCfg(None if arena is None else arena.data_ptr(), int(budget_bytes), int(max_slots),
-                    int(nnz_per_wave), int(seed), float(time_scale), int(keep_y), 0)
+                    int(nnz_per_wave), int(seed), float(time_scale), int(bool(keep_y)), 0)
     st = _ServeStats()
     if simulate:
         rc = L.msrep_serve_simulate(ctypes.byref(cfg), hm, len(pool), tr, n, res,
@@ -100,7 +117,7 @@ def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 2
     out: List[ServeResult] = []
     for i in range(n):
         out.append(ServeResult(res[i].t_arrive, res[i].t_admit, res[i].t_done, res[i].status,
-                               ybufs[i] if keep_y else None))
+                               ybufs[i]))
     stats = {f: getattr(st, f) for f, _ in _ServeStats._fields_ if not f.startswith("_")}
     del keep
     return out, stats

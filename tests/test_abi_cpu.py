@@ -67,6 +67,29 @@ def test_build_partition_argument_errors(kw, np_, code):
     assert L.msrep_last_error()  # a message is set
 
 
+@pytest.mark.parametrize("kw,np_,code", [
+    (dict(fmt=3, idx2=0x6000), 4, -7),  # COO in any order has no row blocks
+    ({}, 0, -1),
+    (dict(ptr=None), 4, -1),
+])
+def test_build_partition_rows_argument_errors(kw, np_, code):
+    L = _lib()
+    d = _desc(**kw)
+    st = L.msrep_build_partition_rows(ctypes.byref(d), np_, 0x4000, 0x5000, 1 << 20, None, None)
+    assert st == code
+    assert L.msrep_last_error()
+
+
+def test_serve_fill_x_argument_errors():
+    from paper_2209_07552_amd import serving
+    L = _lib()
+    serving._bind(L)
+    assert L.msrep_serve_fill_x(0, 1, 0, None, 10, 0, None) == -1   # NULL x with n > 0
+    assert L.msrep_serve_fill_x(0, 1, 0, 0x1000, -1, 0, None) == -1  # negative n
+    assert L.msrep_serve_fill_x(0, 1, 0, 0x1000, 10, 2, None) == -1  # BF16 vectors do not exist
+    assert L.msrep_serve_fill_x(0, 1, 0, None, 0, 0, None) == 0     # empty: nothing launched
+
+
 def test_spmv_argument_errors():
     L = _lib()
     d = _desc()

@@ -66,3 +66,19 @@ def test_small_budget_queues():
     ok = [r.status == 0 for r in res]
     assert any(ok)
     _check_last_y(pool, [q for q, o in zip(trace, ok) if o], [r for r, o in zip(res, ok) if o], 0)
+
+
+@pytest.mark.parametrize("vt", [0, 1])
+def test_fill_x_matches_published_generator(vt):
+    """The device x generator (msrep_serve_fill_x, also the server's) equals
+    the host's SplitMix64 values, rounded once to FP32 for F32."""
+    n = 100_003
+    dt = torch.float64 if vt == pk.F64 else torch.float32
+    for rid, step in ((0, 0), (7, 3), ((1 << 24) - 1, 65535)):
+        x = torch.full((n,), float("nan"), dtype=dt, device="cuda")
+        serving.fill_x(x, SEED, rid, step)
+        torch.cuda.synchronize()
+        want = synth.serving_x(n, SEED, rid, step)
+        if vt == pk.F32:
+            want = want.astype(np.float32)
+        assert np.array_equal(x.cpu().numpy(), want), (rid, step)

@@ -56,17 +56,17 @@ def _tiny_set():
 
 
 # --------------------------------------------------------------- partitions
-def _part_compare(A, fmt, np_):
+def _part_compare(A, fmt, np_, split="nnz"):
     M, _ = device_mat(A, fmt, pk.F64)
-    P = pk.msrep_build_partition(M, np_)
+    P = pk.msrep_build_partition(M, np_, split=pk.SPLIT_ROWS if split == "rows" else pk.SPLIT_NNZ)
     torch.cuda.synchronize()
     rec, lp = P.host()
     H = host_formats(A)
     if fmt == "coo":
-        R = oracle.partition_coo(A.m, H["coo"][0], np_)
+        R = oracle.partition_coo(A.m, H["coo"][0], np_, split)
     else:
         rows = A.m if fmt == "csr" else A.n
-        R = oracle.partition_ptr(rows, H[fmt][0], np_)
+        R = oracle.partition_ptr(rows, H[fmt][0], np_, split)
     for f in ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag",
               "lptr_off"):
         assert np.array_equal(rec[f], getattr(R, f)), (A.name, fmt, np_, f)
@@ -279,17 +279,19 @@ def test_prepared_spmv_repeats_with_fresh_x(fmt, vt):
 
 @pytest.mark.parametrize("fmt", FMTS)
 def test_equal_rows_baseline_partitions(fmt):
-    """The kernels take any consistent partition records: the paper's
-    equal-rows baseline split (unequal nonzeros, no split rows) built on the
-    host gives the oracle's result too."""
-    import bench
+    """The paper's Baseline split (msrep_build_partition_rows: equal row or
+    column blocks, unequal nonzeros, no split rows) is bit-exact against the
+    oracle's, and the SpMV kernels take its records like equal-nnz ones."""
     rng = np.random.default_rng(17)
+    for A, _ in _tiny_set():
+        for np_ in sorted({1, 2, 3, 7, A.m + 2, 64}):
+            _part_compare(A, fmt, np_, "rows")
     for A, x in (synth.rmat_csr(scale=14, edge_factor=16, seed=8), synth.stencil7_csr(48)):
-        H = host_formats(A)
         M, v64 = device_mat(A, fmt, pk.F64)
         y_in = rng.uniform(-1, 1, A.m)
         for np_ in (1, 7, 300):
-            P = bench.equal_rows_partition(M, H, fmt, np_, _dev())
+            _part_compare(A, fmt, np_, "rows")
+            P = pk.msrep_build_partition(M, np_, split=pk.SPLIT_ROWS)
             xd = torch.from_numpy(x).to(_dev())
             yd = torch.from_numpy(y_in.copy()).to(_dev())
             ws = pk.msrep_spmv_prepare(M, P)

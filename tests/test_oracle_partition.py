@@ -31,12 +31,13 @@ def _check_against(P, recs):
 def test_golden_partitions(oracle_lib):
     m, n, g, parts = _golden_arrays()
     for (fmt, np_), recs in parts.items():
-        if fmt == "pcsr":
-            P = oracle.partition_ptr(m, g["row_ptr"], np_)
-        elif fmt == "pcsc":
-            P = oracle.partition_ptr(n, g["csc_col_ptr"], np_)
+        split = "rows" if fmt.startswith("r") else "nnz"  # rcsr/rcsc/rcoo: the Baseline split
+        if fmt[1:] == "csr":
+            P = oracle.partition_ptr(m, g["row_ptr"], np_, split)
+        elif fmt[1:] == "csc":
+            P = oracle.partition_ptr(n, g["csc_col_ptr"], np_, split)
         else:
-            P = oracle.partition_coo(m, g["coo_row_idx"], np_)
+            P = oracle.partition_coo(m, g["coo_row_idx"], np_, split)
         assert len(recs) == np_
         _check_against(P, recs)
     P = oracle.partition_ptr(m, g["row_ptr"], 12)
@@ -227,3 +228,66 @@ def test_partitioned_product_equals_spmv(oracle_lib, np_):
     y, s = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, x, 1.5, -0.5, y_in)
     for r in range(A.m):
         assert abs(Fraction(y[r]) - ex[r]) <= Fraction(2.3e-16) * abs(ex[r]) + Fraction(1e-30)
+
+
+def _rows_brute(ptr, np_):
+    """The Baseline split by a scan: every nonzero's row found by walking the
+    rows, each partition's nonzeros collected from the rows of its block."""
+    rows = len(ptr) - 1
+    row_of = []
+    for r in range(rows):
+        row_of += [r] * int(ptr[r + 1] - ptr[r])
+    out = []
+    for i in range(np_):
+        block = set(range(i * rows // np_, (i + 1) * rows // np_))
+        ks = [k for k, r in enumerate(row_of) if r in block]
+        out.append(ks)
+    return row_of, out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rows_split_brute_force(oracle_lib, seed):
+    """Equal-rows (Baseline) records against a scan on tiny matrices with
+    empty leading, trailing and interior rows, for every np from 1 to rows+2:
+    each partition holds exactly the nonzeros of its row block, no flags, and
+    its local pointer reassembles those rows."""
+    rng = np.random.default_rng(seed)
+    rows = int(rng.integers(1, 12))
+    deg = rng.integers(0, 4, rows) * (rng.random(rows) < 0.7)
+    ptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    for np_ in range(1, rows + 3):
+        row_of, parts = _rows_brute(ptr, np_)
+        P = oracle.partition_ptr(rows, ptr, np_, "rows")
+        coo = np.array(row_of, np.int32)
+        Q = oracle.partition_coo(rows, coo, np_, "rows")
+        for i, ks in enumerate(parts):
+            assert P.start_flag[i] == 0 and P.end_flag[i] == 0
+            if ks:
+                assert (P.start_idx[i], P.end_idx[i]) == (ks[0], ks[-1])
+                assert ks == list(range(ks[0], ks[-1] + 1))
+                assert (P.start_row[i], P.end_row[i]) == (row_of[ks[0]], row_of[ks[-1]])
+                lp = P.local_ptr(i)
+                for j, r in enumerate(range(P.start_row[i], P.end_row[i] + 1)):
+                    assert lp[j + 1] - lp[j] == ptr[r + 1] - ptr[r]
+            else:
+                assert P.end_idx[i] == P.start_idx[i] - 1
+                assert P.end_row[i] == P.start_row[i] - 1
+                assert list(P.local_ptr(i)) == [0]
+            for f in ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag"):
+                assert getattr(Q, f)[i] == getattr(P, f)[i], (f, i)
+
+
+def test_rows_split_equals_nnz_split_when_rows_are_equal(oracle_lib):
+    """With the same number of nonzeros in every row and np dividing the row
+    count, equal row blocks are equal-nnz partitions: both splits agree."""
+    A, _ = synth.uniform_csr(96, 80, 5, seed=4)
+    for np_ in (1, 2, 3, 8, 12, 32, 96):
+        P = oracle.partition_ptr(A.m, A.ptr, np_, "rows")
+        Q = oracle.partition_ptr(A.m, A.ptr, np_)
+        for f in Partition_FIELDS:
+            assert np.array_equal(getattr(P, f), getattr(Q, f)), (np_, f)
+        assert np.array_equal(P.lptr[:P.lptr_len], Q.lptr[:Q.lptr_len])
+
+
+Partition_FIELDS = ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag",
+                    "lptr_off")
