@@ -352,7 +352,10 @@ msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
                                double beta, void *ws_d, size_t ws_bytes,
                                void *stream, msrep_plan *out);
 /* x_ptrs / y_ptrs: host arrays of count device pointers (x_k: n_k values, y_k:
- * m_k values).  Stream-ordered; the pointer arrays are copied before return. */
+ * m_k values).  Stream-ordered; the pointer arrays are copied before return.
+ * A plan holds one pointer table and one set of boundary carries, so calls
+ * on one plan run one after another on the device even when issued on
+ * different streams (each call's work waits for the previous call's). */
 msrep_status msrep_spmv_batched(msrep_plan plan, const void *const *x_ptrs,
                                 void *const *y_ptrs, void *stream);
 /* Work items in the plan (partitions over all matrices). */

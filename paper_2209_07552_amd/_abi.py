@@ -322,14 +322,82 @@ def msrep_build_partition(A: Mat, np_: int, stream=None, split: int = SPLIT_NNZ)
 _ws_cache = {}
 
 
-def _workspace(nbytes, device):
+def _workspace(nbytes, device, stream=None):
+    """A cached scratch tensor per (device, stream): calls on one stream are
+    ordered, so they may share it; another stream gets its own."""
     torch = _torch()
-    key = str(device)
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (str(device), int(s.cuda_stream))
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        if stream is not None:
+            buf.record_stream(stream)
         _ws_cache[key] = buf
     return buf
+
+
+def _scratch(nbytes, device, stream=None):
+    """A workspace for one call: torch's caching allocator may reuse it once
+    the call's work on `stream` (if given) has finished."""
+    torch = _torch()
+    buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if stream is not None:
+        buf.record_stream(stream)
+    return buf
+
+
+def _span(t, rows, ld, k):
+    """Byte range [lo, hi) that rows x k elements of t at row stride ld cover."""
+    if rows == 0 or k == 0:
+        return (t.data_ptr(), t.data_ptr())
+    lo = t.data_ptr()
+    return (lo, lo + ((rows - 1) * ld + k) * t.element_size())
+
+
+def _check_operand_shape(A: Mat, t, name, rows):
+    """t is a torch tensor of A's vector dtype with at least `rows` rows."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor on the GPU" % name)
+    want = vector_dtype(A.vtype)
+    if t.dtype != want:
+        raise ValueError("%s has dtype %s; a %s matrix needs %s" % (name, t.dtype,
+                                                                    VT_NAMES[A.vtype], want))
+    have = t.shape[0] if t.dim() > 0 else 0
+    if have < rows:
+        raise ValueError("%s has %d rows; the matrix needs %d" % (name, have, rows))
+
+
+def _check_operand_device(A: Mat, t, name):
+    """t is on the GPU that holds A."""
+    ref = A.idx if A.idx is not None else A.ptr
+    if ref is not None and t.device != ref.device:
+        raise ValueError("%s is on %s, the matrix on %s" % (name, t.device, ref.device))
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU" % name)
+
+
+def _check_operands(A: Mat, X, Y, rows_x, rows_y, ldx, ldy, k, what):
+    """Shapes and dtypes first, then overlap of the spans the kernels touch,
+    then devices."""
+    _check_operand_shape(A, X, what[0], rows_x)
+    _check_operand_shape(A, Y, what[1], rows_y)
+    xs, ys = _span(X, rows_x, ldx, k), _span(Y, rows_y, ldy, k)
+    if xs[0] < ys[1] and ys[0] < xs[1]:
+        raise ValueError("%s and %s overlap" % what)
+    _check_operand_device(A, X, what[0])
+    _check_operand_device(A, Y, what[1])
+
+
+def _check_vectors(A: Mat, x, y):
+    """x (n values) and y (m values) match A: type, dtype, length, unit
+    stride, no overlap, device."""
+    torch = _torch()
+    for t, name in ((x, "x"), (y, "y")):
+        if isinstance(t, torch.Tensor) and (t.dim() != 1 or (t.numel() > 1 and t.stride(0) != 1)):
+            raise ValueError("%s must be a contiguous 1-D tensor" % name)
+    _check_operands(A, x, y, A.n, A.m, 1, 1, 1, ("x", "y"))
 
 
 def msrep_timing(enable: bool) -> None:
@@ -362,12 +430,13 @@ def msrep_spmv_ws_bytes(A: Mat, np_: int) -> int:
 def msrep_spmv(A: Mat, P: Partition, x, y, alpha=1.0, beta=0.0, tune: Optional[Tune] = None,
                ws=None, stream=None):
     """y <- alpha*A*x + beta*y (in place on the device tensor y); returns y."""
+    _check_vectors(A, x, y)
     _require_gpu()
     L = load_library()
     d = A.desc()
     need = L.msrep_spmv_ws_bytes(ctypes.byref(d), P.np)
     if ws is None:
-        ws = _workspace(need, y.device)
+        ws = _workspace(need, y.device, stream)
     t = tune.c() if tune is not None else None
     _check(L.msrep_spmv(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(x), _ptr(y),
                         float(alpha), float(beta), ctypes.byref(t) if t is not None else None,
@@ -385,7 +454,7 @@ def msrep_spmv_prepare(A: Mat, P: Partition, ws=None, stream=None):
     d = A.desc()
     need = L.msrep_spmv_ws_bytes(ctypes.byref(d), P.np)
     if ws is None:
-        ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=P.parts.device)
+        ws = _scratch(need, P.parts.device, stream)
     _check(L.msrep_spmv_prepare(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(ws),
                                 ws.numel(), _stream(stream)), "spmv_prepare")
     return ws
@@ -394,6 +463,7 @@ def msrep_spmv_prepare(A: Mat, P: Partition, ws=None, stream=None):
 def msrep_spmv_prepared(A: Mat, P: Partition, x, y, ws, alpha=1.0, beta=0.0,
                         tune: Optional[Tune] = None, stream=None):
     """msrep_spmv with ws prepared by msrep_spmv_prepare(A, P); returns y."""
+    _check_vectors(A, x, y)
     _require_gpu()
     L = load_library()
     d = A.desc()
@@ -414,17 +484,19 @@ def msrep_spmm(A: Mat, P: Partition, X, Y, alpha=1.0, beta=0.0, ws=None, stream=
     """Y <- alpha*A*X + beta*Y for the k columns of the row-major device
     tensors X (n x k) and Y (m x k, updated in place; both may be column
     slices of wider tensors, rows strided by their stride(0)); returns Y."""
-    torch = _require_gpu()
-    L = load_library()
+    torch = _torch()
     d = A.desc()
     if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
         raise ValueError("X and Y must be 2-D with the same number of columns")
     if X.stride(1) != 1 or Y.stride(1) != 1:
         raise ValueError("X and Y must have unit column stride (row-major)")
     k = int(X.shape[1])
+    _check_operands(A, X, Y, A.n, A.m, int(X.stride(0)), int(Y.stride(0)), k, ("X", "Y"))
+    _require_gpu()
+    L = load_library()
     need = L.msrep_spmm_ws_bytes(ctypes.byref(d), P.np, k)
     if ws is None:
-        ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=Y.device)
+        ws = _scratch(need, Y.device, stream)
     _check(L.msrep_spmm(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, k, _ptr(X),
                         int(X.stride(0)), _ptr(Y), int(Y.stride(0)), float(alpha), float(beta),
                         _ptr(ws), ws.numel(), _stream(stream)), "spmm")
@@ -438,7 +510,7 @@ def msrep_convert(A: Mat, dst_fmt: int, stream=None) -> Mat:
     B = Mat.empty(dst_fmt, A.vtype, A.m, A.n, A.nnz, device=dev)
     ds, dd = A.desc(), B.desc()
     need = L.msrep_convert_ws_bytes(ctypes.byref(ds), dst_fmt)
-    ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=dev)
+    ws = _scratch(need, dev, stream)
     _check(L.msrep_convert(ctypes.byref(ds), ctypes.byref(dd), _ptr(ws), ws.numel(),
                            _stream(stream)), "convert")
     return B
@@ -449,7 +521,7 @@ def msrep_autotune(A: Mat, x, stream=None) -> Tune:
     L = load_library()
     d = A.desc()
     need = L.msrep_autotune_ws_bytes(ctypes.byref(d))
-    ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=x.device)
+    ws = _scratch(need, x.device, stream)
     out = _Tune()
     _check(L.msrep_autotune(ctypes.byref(d), _ptr(x), _ptr(ws), ws.numel(), ctypes.byref(out),
                             _stream(stream)), "autotune")
@@ -496,6 +568,14 @@ def msrep_plan_create(mats: Sequence[Mat], tunes=None, alpha=1.0, beta=0.0, stre
 def msrep_spmv_batched(plan: Plan, xs, ys, stream=None):
     _require_gpu()
     L = load_library()
+    if len(xs) != plan.count or len(ys) != plan.count:
+        raise ValueError("plan has %d matrices; got %d x and %d y tensors"
+                         % (plan.count, len(xs), len(ys)))
+    for i, (M, x, y) in enumerate(zip(plan.mats, xs, ys)):
+        try:
+            _check_vectors(M, x, y)
+        except (TypeError, ValueError) as e:
+            raise type(e)("matrix %d: %s" % (i, e)) from None
     xa = (c_vp * plan.count)(*[x.data_ptr() for x in xs])
     ya = (c_vp * plan.count)(*[y.data_ptr() for y in ys])
     _check(L.msrep_spmv_batched(plan.handle, xa, ya, _stream(stream)), "spmv_batched")

@@ -78,6 +78,7 @@ struct msrep_plan_s {
   BatchXY *xy_d = nullptr;
   BatchXY *staging = nullptr;  // pinned host copy of the x/y table
   hipEvent_t staged{};
+  hipEvent_t done{};  // after the last graph launch (it reads xy_d and the carries)
   hipStream_t cap{};
   hipGraph_t graph{};
   hipGraphExec_t exec{};
@@ -98,6 +99,7 @@ extern "C" msrep_status msrep_plan_destroy(msrep_plan plan) {
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   if (plan->cap) (void)hipStreamDestroy(plan->cap);
   if (plan->staged) (void)hipEventDestroy(plan->staged);
+  if (plan->done) (void)hipEventDestroy(plan->done);
   if (plan->staging) (void)hipHostFree(plan->staging);
   delete plan;
   return ok();
@@ -235,7 +237,9 @@ extern "C" msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
     return bail(fail(MSREP_ERR_HIP, "msrep_plan_create: hipHostMalloc failed"));
   std::memset(P->staging, 0, sizeof(BatchXY) * count);
   if (hipEventCreateWithFlags(&P->staged, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(P->staged, s) != hipSuccess)
+      hipEventRecord(P->staged, s) != hipSuccess ||
+      hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(P->done, s) != hipSuccess)
     return bail(fail(MSREP_ERR_HIP, "msrep_plan_create: event setup failed"));
   // capture the two launches once
   if (hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)
@@ -273,9 +277,13 @@ extern "C" msrep_status msrep_spmv_batched(msrep_plan plan, const void *const *x
     plan->staging[k].x = x_ptrs[k];
     plan->staging[k].y = y_ptrs[k];
   }
+  // the previous launch, on whatever stream, still reads xy_d and the
+  // carries: the rewrite waits for it on the device
+  MSREP_HIP(hipStreamWaitEvent(s, plan->done, 0));
   MSREP_HIP(hipMemcpyAsync(plan->xy_d, plan->staging, sizeof(BatchXY) * plan->count,
                            hipMemcpyHostToDevice, s));
   MSREP_HIP(hipEventRecord(plan->staged, s));
   MSREP_HIP(hipGraphLaunch(plan->exec, s));
+  MSREP_HIP(hipEventRecord(plan->done, s));
   return ok();
 }

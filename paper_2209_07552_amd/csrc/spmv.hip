@@ -429,3 +429,4 @@ extern "C" msrep_status msrep_spmv_prepared(const msrep_mat *A, const msrep_part
   return spmv_entry(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, tune, ws_d, ws_bytes, stream,
                     kPhaseNumeric, "msrep_spmv_prepared");
 }
+

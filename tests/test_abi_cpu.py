@@ -210,3 +210,49 @@ def test_spmm_argument_errors():
     st = L.msrep_spmm(ctypes.byref(wide), 0x4000, 0x5000, 8, 8, 0x6000, 8, 0x7000, 8, 1.0, 0.0,
                       0x8000, 1 << 30, None)
     assert st == -7 and b"4 GiB" in L.msrep_last_error()
+
+
+def _cpu_mat(vt=0, m=5, n=4):
+    import torch
+    ptr = np.zeros(m + 1, np.int32)
+    return pk.Mat(pk.CSR, vt, m, n, ptr=ptr, idx=np.zeros(0, np.int32),
+                  val=np.zeros(0, np.float64 if vt == 0 else np.float32), device="cpu")
+
+
+def test_wrappers_reject_bad_vectors():
+    """The Python wrappers check x / y / X / Y against the matrix before any
+    call reaches the library (the kernels size their buffers from A)."""
+    import torch
+    A = _cpu_mat()
+    P = pk.Partition(A, 1, None, None, None)
+    x, y = torch.zeros(4, dtype=torch.float64), torch.zeros(5, dtype=torch.float64)
+    bad = [
+        (torch.zeros(4, dtype=torch.float32), y, "dtype"),      # FP32 x for F64 values
+        (x, torch.zeros(4, dtype=torch.float64), "rows"),       # y shorter than m
+        (torch.zeros(3, dtype=torch.float64), y, "rows"),       # x shorter than n
+        (torch.zeros(8, dtype=torch.float64)[::2], y, "contiguous"),
+        (x, "not a tensor", "tensor"),
+    ]
+    for fn in (pk.msrep_spmv, pk.msrep_spmv_prepared):
+        for xx, yy, what in bad:
+            with pytest.raises((ValueError, TypeError)) as e:
+                if fn is pk.msrep_spmv_prepared:
+                    fn(A, P, xx, yy, None)
+                else:
+                    fn(A, P, xx, yy)
+            assert what in str(e.value), (fn.__name__, what, str(e.value))
+    buf = torch.zeros(9, dtype=torch.float64)
+    with pytest.raises(ValueError, match="overlap"):
+        pk.msrep_spmv(A, P, buf[:4], buf[3:8])
+    # a CPU tensor that is otherwise right is refused as not on the GPU
+    with pytest.raises(ValueError, match="GPU"):
+        pk.msrep_spmv(A, P, x, y)
+    # several right-hand sides
+    X, Y = torch.zeros(4, 3, dtype=torch.float64), torch.zeros(5, 3, dtype=torch.float64)
+    with pytest.raises(ValueError, match="rows"):
+        pk.msrep_spmm(A, P, X, Y[:4])
+    with pytest.raises(ValueError, match="dtype"):
+        pk.msrep_spmm(A, P, X.float(), Y)
+    Z = torch.zeros(9, 3, dtype=torch.float64)
+    with pytest.raises(ValueError, match="overlap"):
+        pk.msrep_spmm(A, P, Z[:4], Z[2:7])
