@@ -287,6 +287,28 @@ msrep_status msrep_spmv_prepared(const msrep_mat *A, const msrep_part *parts_d,
                                  const msrep_tune *tune, void *ws_d, size_t ws_bytes,
                                  void *stream);
 
+/*
+ * msrep_spmv without a workspace argument, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  CSR and row-sorted COO only (others:
+ * MSREP_ERR_UNSUPPORTED).  The two FP64 boundary carries per partition live
+ * in a static device array of msrep_spmv_noalloc_max_parts() partitions
+ * (2^19, 8 MiB), which each GPU the library runs on holds until the process
+ * ends; np above that is MSREP_ERR_SIZE.  No allocation, free or memset is
+ * made: the carries need no clearing, since a slot's value is used only after the
+ * same call's SpMV kernel has written it.  Arguments, kernels, results and
+ * other errors are those of msrep_spmv with the same tune (bit-identical y).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (concurrent streams or host threads) race and must be ordered by the
+ * caller.  The first call on a device looks up its copy's address
+ * (MSREP_ERR_HIP if that fails).
+ */
+int32_t msrep_spmv_noalloc_max_parts(void);
+msrep_status msrep_spmv_noalloc(const msrep_mat *A, const msrep_part *parts_d,
+                                const int32_t *lptr_d, int32_t np, const void *x_d,
+                                void *y_d, double alpha, double beta,
+                                const msrep_tune *tune, void *stream);
+
 /* Launch shape and partition size for A, picked by timing every candidate on
  * the stream and keeping the fastest median of three runs:
  *   nnz_per_wave in {256, 512, 1024, 2048, 4096} (the equal-nnz np follows),

@@ -104,6 +104,9 @@ def load_library():
         "msrep_spmv_ws_bytes": (c_sz, [P(_Mat), c_i32]),
         "msrep_spmv": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_vp, c_dbl, c_dbl, P(_Tune),
                                c_vp, c_sz, c_vp]),
+        "msrep_spmv_noalloc_max_parts": (c_i32, []),
+        "msrep_spmv_noalloc": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_vp, c_dbl, c_dbl,
+                                       P(_Tune), c_vp]),
         "msrep_spmv_prepare": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
         "msrep_spmv_prepared": (c_i32, [P(_Mat), c_vp, c_vp, c_i32, c_vp, c_vp, c_dbl, c_dbl,
                                         P(_Tune), c_vp, c_sz, c_vp]),
@@ -441,6 +444,27 @@ def msrep_spmv(A: Mat, P: Partition, x, y, alpha=1.0, beta=0.0, tune: Optional[T
     _check(L.msrep_spmv(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(x), _ptr(y),
                         float(alpha), float(beta), ctypes.byref(t) if t is not None else None,
                         _ptr(ws), ws.numel(), _stream(stream)), "spmv")
+    return y
+
+
+def msrep_spmv_noalloc_max_parts() -> int:
+    """Most partitions msrep_spmv_noalloc takes (its static scratch)."""
+    return int(load_library().msrep_spmv_noalloc_max_parts())
+
+
+def msrep_spmv_noalloc(A: Mat, P: Partition, x, y, alpha=1.0, beta=0.0,
+                       tune: Optional[Tune] = None, stream=None):
+    """msrep_spmv for CSR / row-sorted COO with the boundary carries in the
+    library's static device scratch (no workspace); returns y."""
+    _check_vectors(A, x, y)
+    _require_gpu()
+    L = load_library()
+    d = A.desc()
+    t = tune.c() if tune is not None else None
+    _check(L.msrep_spmv_noalloc(ctypes.byref(d), _ptr(P.parts), _ptr(P.lptr), P.np, _ptr(x),
+                                _ptr(y), float(alpha), float(beta),
+                                ctypes.byref(t) if t is not None else None, _stream(stream)),
+           "spmv_noalloc")
     return y
 
 

@@ -430,3 +430,61 @@ extern "C" msrep_status msrep_spmv_prepared(const msrep_mat *A, const msrep_part
                     kPhaseNumeric, "msrep_spmv_prepared");
 }
 
+// ------------------------------------------------ no-allocation variant
+// The boundary-merge carries of msrep_spmv (two FP64 slots per partition)
+// taken from a file-scope device array instead of a caller workspace, for
+// callers that cannot allocate.  In host code `scratch` names a host-side
+// stand-in; its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is ever passed to a kernel.
+namespace {
+
+constexpr int32_t kNoAllocMaxParts = 1 << 19;  // 8 MiB of carries per device
+__device__ __align__(256) double scratch[2 * static_cast<size_t>(kNoAllocMaxParts)];
+
+std::mutex scratch_mu;
+std::map<int, double *> scratch_addr;  // device ordinal -> address of its copy
+
+// The calling thread's current device's copy of `scratch`.
+msrep_status scratch_on_current_device(double **out, const char *who) {
+  int dev = 0;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess)
+    return fail(MSREP_ERR_HIP, "%s: hipGetDevice failed: %s", who, hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  auto it = scratch_addr.find(dev);
+  if (it == scratch_addr.end()) {
+    void *p = nullptr;
+    const hipError_t g = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g != hipSuccess || !p)
+      return fail(MSREP_ERR_HIP, "%s: hipGetSymbolAddress(scratch) failed on device %d: %s", who,
+                  dev, hipGetErrorString(g));
+    it = scratch_addr.emplace(dev, static_cast<double *>(p)).first;
+  }
+  *out = it->second;
+  return MSREP_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t msrep_spmv_noalloc_max_parts(void) { return kNoAllocMaxParts; }
+
+extern "C" msrep_status msrep_spmv_noalloc(const msrep_mat *A, const msrep_part *parts_d,
+                                           const int32_t *lptr_d, int32_t np, const void *x_d,
+                                           void *y_d, double alpha, double beta,
+                                           const msrep_tune *tune, void *stream) {
+  const char *who = "msrep_spmv_noalloc";
+  if (msrep_status st = check_mat(A, who)) return st;
+  if (A->fmt != MSREP_CSR && A->fmt != MSREP_COO)
+    return fail(MSREP_ERR_UNSUPPORTED, "%s: CSR and row-sorted COO only (format %d)", who,
+                A->fmt);
+  if (np <= 0) return fail(MSREP_ERR_ARG, "%s: np must be positive (got %d)", who, np);
+  if (np > kNoAllocMaxParts)
+    return fail(MSREP_ERR_SIZE, "%s: np=%d exceeds the %d partitions of the static scratch", who,
+                np, kNoAllocMaxParts);
+  double *carry = nullptr;
+  if (msrep_status st = scratch_on_current_device(&carry, who)) return st;
+  // the same checks and kernels as msrep_spmv, on the scratch's carries
+  return spmv_entry(A, parts_d, lptr_d, np, x_d, y_d, alpha, beta, tune, carry,
+                    2 * sizeof(double) * static_cast<size_t>(kNoAllocMaxParts), stream,
+                    kPhaseAll, who);
+}

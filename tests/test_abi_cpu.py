@@ -212,6 +212,22 @@ def test_spmm_argument_errors():
     assert st == -7 and b"4 GiB" in L.msrep_last_error()
 
 
+@pytest.mark.parametrize("kw,np_,code", [
+    (dict(fmt=1), 4, -7),                 # CSC: bucketed path, needs a workspace
+    (dict(fmt=3, idx2=0x6000), 4, -7),    # COO in any order likewise
+    ({}, 0, -1),
+    ({}, (1 << 19) + 1, -3),              # beyond the static scratch
+])
+def test_spmv_noalloc_argument_errors(kw, np_, code):
+    L = _lib()
+    d = _desc(**kw)
+    assert L.msrep_spmv_noalloc_max_parts() == 1 << 19
+    st = L.msrep_spmv_noalloc(ctypes.byref(d), 0x4000, 0x5000, np_, 0x7000, 0x8000, 1.0, 0.0,
+                              None, None)
+    assert st == code
+    assert L.msrep_last_error()
+
+
 def _cpu_mat(vt=0, m=5, n=4):
     import torch
     ptr = np.zeros(m + 1, np.int32)
@@ -233,7 +249,7 @@ def test_wrappers_reject_bad_vectors():
         (torch.zeros(8, dtype=torch.float64)[::2], y, "contiguous"),
         (x, "not a tensor", "tensor"),
     ]
-    for fn in (pk.msrep_spmv, pk.msrep_spmv_prepared):
+    for fn in (pk.msrep_spmv, pk.msrep_spmv_noalloc, pk.msrep_spmv_prepared):
         for xx, yy, what in bad:
             with pytest.raises((ValueError, TypeError)) as e:
                 if fn is pk.msrep_spmv_prepared:
