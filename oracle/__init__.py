@@ -73,12 +73,15 @@ def _load():
         _lib.oracle_partition_coo.argtypes = [i32, i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         _lib.oracle_partition_rows_ptr.argtypes = _lib.oracle_partition_ptr.argtypes
         _lib.oracle_partition_rows_coo.argtypes = _lib.oracle_partition_coo.argtypes
+        _lib.oracle_partition_coo_col.argtypes = _lib.oracle_partition_coo.argtypes
+        _lib.oracle_partition_cols_coo_col.argtypes = _lib.oracle_partition_coo.argtypes
         _lib.oracle_csr_to_coo.argtypes = [i32, vp, vp]
         _lib.oracle_coo_to_csr.argtypes = [i32, i64, vp, vp]
         _lib.oracle_transpose.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         for f in ("oracle_spmv_csr", "oracle_spmv_csr_plain", "oracle_spmm_csr", "oracle_spmv_csc", "oracle_spmv_coo",
                   "oracle_partition_ptr", "oracle_partition_coo", "oracle_partition_rows_ptr",
-                  "oracle_partition_rows_coo", "oracle_csr_to_coo",
+                  "oracle_partition_rows_coo", "oracle_partition_coo_col",
+                  "oracle_partition_cols_coo_col", "oracle_csr_to_coo",
                   "oracle_coo_to_csr", "oracle_transpose"):
             getattr(_lib, f).restype = ctypes.c_int
     return _lib
@@ -238,6 +241,21 @@ def partition_coo(rows, row_idx, np_, split="nnz"):
                                     _p(P.end_idx), _p(P.start_row), _p(P.end_row),
                                     _p(P.start_flag), _p(P.end_flag), _p(P.lptr_off)),
            "partition_coo")
+    return P
+
+
+def partition_coo_col(cols, col_idx, np_, split="nnz"):
+    """pCOO on column-sorted COO (Sec. 3.2.3, Algorithm 6 on the column
+    index; start_row / end_row hold columns); split="rows": the Baseline's
+    equal column blocks (Sec. 5.3)."""
+    lib = _load()
+    fn = (lib.oracle_partition_cols_coo_col if split == "rows"
+          else lib.oracle_partition_coo_col)
+    col_idx = _c(col_idx, np.int32)
+    P = Partition(np_)
+    _check(fn(cols, len(col_idx), _p(col_idx), np_, _p(P.start_idx), _p(P.end_idx),
+              _p(P.start_row), _p(P.end_row), _p(P.start_flag), _p(P.end_flag),
+              _p(P.lptr_off)), "partition_coo_col")
     return P
 
 

@@ -23,7 +23,8 @@
  *   - The same product for k right-hand sides (a row-major block X), every
  *     column as Algorithm 1.
  *   - The partition metadata of pCSR / pCSC / pCOO (Sec. 3.2.1-3.2.3,
- *     Algorithms 2, 4 and 6) including each partition's local row pointer,
+ *     Algorithms 2, 4 and 6; pCOO on row-sorted and on column-sorted COO)
+ *     including each partition's local row pointer,
  *     and of the paper's equal-rows Baseline split (Sec. 5.3) in the same
  *     records.
  *   - Format conversions between CSR, CSC and row-sorted COO (Sec. 2.1).
@@ -477,6 +478,38 @@ int oracle_partition_rows_coo(int32_t rows, int64_t nnz, const int32_t *row_idx,
     lptr_off[i] = 0;
   }
   return ORACLE_OK;
+}
+
+/*
+ * pCOO on column-sorted COO.  Sec. 3.2.3 lets the nonzeros be sorted by
+ * column instead of by row (then the split costs O(np*log(n))), and Sec. 4.3
+ * merges such partitions by columns, like pCSC.  The split is Algorithm 6
+ * with the roles of rows and columns exchanged: the same equal-nnz position
+ * ranges, with start/end *columns* read from col_idx (which must be
+ * non-decreasing), start_flag = the first column began in an earlier
+ * partition, end_flag = the last column continues into a later one.  The
+ * records use the start_row / end_row fields for the columns, as pCSC does.
+ * By construction these records equal the pCSC records of the same matrix
+ * (Algorithm 4), local pointers aside.
+ */
+int oracle_partition_coo_col(int32_t cols, int64_t nnz, const int32_t *col_idx,
+                             int32_t np, int64_t *start_idx, int64_t *end_idx,
+                             int32_t *start_col, int32_t *end_col,
+                             int32_t *start_flag, int32_t *end_flag,
+                             int64_t *lptr_off) {
+  return oracle_partition_coo(cols, nnz, col_idx, np, start_idx, end_idx, start_col,
+                              end_col, start_flag, end_flag, lptr_off);
+}
+
+/* The Baseline split (Sec. 5.3) of column-sorted COO: equal column blocks,
+ * as for CSC. */
+int oracle_partition_cols_coo_col(int32_t cols, int64_t nnz, const int32_t *col_idx,
+                                  int32_t np, int64_t *start_idx, int64_t *end_idx,
+                                  int32_t *start_col, int32_t *end_col,
+                                  int32_t *start_flag, int32_t *end_flag,
+                                  int64_t *lptr_off) {
+  return oracle_partition_rows_coo(cols, nnz, col_idx, np, start_idx, end_idx, start_col,
+                                   end_col, start_flag, end_flag, lptr_off);
 }
 
 /* ------------------------------------------------------------------------ */

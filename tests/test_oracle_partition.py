@@ -14,7 +14,8 @@ from conftest import load_golden
 
 def _golden_arrays():
     kv, parts = load_golden("example_6x6.txt")
-    ints = ("row_ptr", "col_idx", "csc_col_ptr", "csc_row_idx", "coo_row_idx")
+    ints = ("row_ptr", "col_idx", "csc_col_ptr", "csc_row_idx", "coo_row_idx", "coocol_col_idx",
+            "coocol_row_idx")
     g = {k: np.array(kv[k], dtype=np.int64) for k in ints}
     return int(kv["m"][0]), int(kv["n"][0]), g, parts
 
@@ -36,6 +37,8 @@ def test_golden_partitions(oracle_lib):
             P = oracle.partition_ptr(m, g["row_ptr"], np_, split)
         elif fmt[1:] == "csc":
             P = oracle.partition_ptr(n, g["csc_col_ptr"], np_, split)
+        elif fmt[1:] == "coocol":
+            P = oracle.partition_coo_col(n, g["coocol_col_idx"], np_, split)
         else:
             P = oracle.partition_coo(m, g["coo_row_idx"], np_, split)
         assert len(recs) == np_
@@ -291,3 +294,52 @@ def test_rows_split_equals_nnz_split_when_rows_are_equal(oracle_lib):
 
 Partition_FIELDS = ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag",
                     "lptr_off")
+
+
+def test_golden_column_sorted_coo_arrays_and_product(oracle_lib):
+    """The column-sorted COO of the hand-worked example is the CSC expanded
+    (columns repeated by col_ptr), and the COO product over it gives the
+    hand-worked y exactly."""
+    kv, _ = load_golden("example_6x6.txt")
+    m, n, g, _ = _golden_arrays()
+    assert np.array_equal(oracle.csr_to_coo(n, g["csc_col_ptr"]), g["coocol_col_idx"])
+    assert np.array_equal(g["coocol_row_idx"], g["csc_row_idx"])
+    val = np.array(kv["csc_val"], np.float64)
+    x = np.array(kv["x"], np.float64)
+    y, _ = oracle.spmv_coo(m, n, g["coocol_row_idx"], g["coocol_col_idx"], val, x)
+    assert np.array_equal(y, np.array(kv["y_a1_b0"], np.float64))
+
+
+def test_column_sorted_coo_brute_force_tiny(oracle_lib):
+    """pCOO on column-sorted COO against the linear-scan brute force, reading
+    each tiny pointer as a column pointer: every np from 1 to nnz+2."""
+    rng = np.random.default_rng(11)
+    for cptr in _tiny_ptrs(rng, 60):
+        cols = len(cptr) - 1
+        nnz = int(cptr[-1])
+        col_of = np.repeat(np.arange(cols), np.diff(cptr)).astype(np.int32)
+        for np_ in range(1, nnz + 3):
+            P = oracle.partition_coo_col(cols, col_of, np_)
+            for i, (s, e, sc, ec, sf, ef, _) in enumerate(_brute(cptr, np_)):
+                assert (P.start_idx[i], P.end_idx[i], P.start_row[i], P.end_row[i],
+                        P.start_flag[i], P.end_flag[i], P.lptr_off[i]) == \
+                    (s, e, sc, ec, sf, ef, 0), (cptr, np_, i)
+
+
+def test_column_sorted_coo_matches_pcsc(oracle_lib):
+    """The column-sorted split equals pCSC's records (Algorithm 4) of the
+    same matrix, flags included, and its Baseline equals pCSC's Baseline."""
+    A, _ = synth.rmat_csr(scale=9, edge_factor=8, seed=4)
+    cptr, _, _, _ = oracle.transpose(A.m, A.n, A.ptr, A.col)
+    col_of = oracle.csr_to_coo(A.n, cptr)
+    for split in ("nnz", "rows"):
+        for np_ in (1, 5, 64, 333, A.nnz + 3):
+            P = oracle.partition_ptr(A.n, cptr, np_, split)
+            Q = oracle.partition_coo_col(A.n, col_of, np_, split)
+            for f in ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag"):
+                assert np.array_equal(getattr(P, f), getattr(Q, f)), (split, np_, f)
+
+
+def test_rejects_column_unsorted_coo(oracle_lib):
+    with pytest.raises(ValueError):
+        oracle.partition_coo_col(3, np.array([0, 2, 1], np.int32), 2)
