@@ -38,9 +38,10 @@ HBM_PEAK_GBS = 8000.0
 # on MI355X (nnz_per_wave, k_per_lane, waves_per_wg, pipeline, resident).
 DEFAULT_TUNES = {
     "rmat20": {"csr": (512, 4, 8, 2, 1), "coo": (512, 4, 8, 2, 1), "csc": (1024, 4, 2, 1, 0),
-               "coo_any": (1024, 4, 2, 1, 0)},
+               "coo_any": (1024, 4, 2, 1, 0), "coo_col": (1024, 4, 2, 1, 0)},
     "stencil256": {"csr": (2048, 4, 4, 2, 0), "coo": (1024, 4, 2, 2, 0),
-                   "csc": (1024, 4, 2, 2, 0), "coo_any": (1024, 4, 2, 2, 0)},
+                   "csc": (1024, 4, 2, 2, 0), "coo_any": (1024, 4, 2, 2, 0),
+                   "coo_col": (1024, 4, 2, 2, 0)},
 }
 SCRUB_BYTES = 512 << 20
 
@@ -50,16 +51,17 @@ def log(*a):
 
 
 def host_formats(A, any_order=False):
-    """CSC and row-sorted COO arrays of a CSR matrix (plain numpy input
-    preparation: stable sort by column), and with any_order the COO in a
-    seeded random order."""
+    """CSC, row-sorted COO and column-sorted COO arrays of a CSR matrix
+    (plain numpy input preparation: stable sort by column), and with
+    any_order the COO in a seeded random order."""
     rows = np.repeat(np.arange(A.m, dtype=np.int32), np.diff(A.ptr))
     perm = np.argsort(A.col, kind="stable")
     cptr = np.zeros(A.n + 1, np.int64)
     np.cumsum(np.bincount(A.col, minlength=A.n), out=cptr[1:])
     out = {"csr": (A.ptr, A.col, A.val),
            "csc": (cptr.astype(np.int32), rows[perm], A.val[perm]),
-           "coo": (rows, A.col, A.val)}
+           "coo": (rows, A.col, A.val),
+           "coo_col": (rows[perm], A.col[perm], A.val[perm])}
     if any_order:  # COO in a seeded random order
         shuf = np.random.default_rng(0).permutation(A.nnz)
         out["coo_any"] = (rows[shuf], A.col[shuf], A.val[shuf])
@@ -329,7 +331,7 @@ def measure_matrix(args, A, x64, wl, wkey, vt, fmts, ref=None):
         elif f == "csc":
             mats[f] = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=stored_values(v, vt))
         else:
-            kind = pk.COO_ANY if f == "coo_any" else pk.COO
+            kind = {"coo_any": pk.COO_ANY, "coo_col": pk.COO_COL}.get(f, pk.COO)
             mats[f] = pk.Mat(kind, vt, A.m, A.n, idx=a, idx2=b, val=stored_values(v, vt))
     del H
     xs = x64 if vt == pk.F64 else x64.astype(np.float32)
@@ -390,7 +392,8 @@ def measure_matrix(args, A, x64, wl, wkey, vt, fmts, ref=None):
             pk.msrep_spmv_prepared(mats[f], parts[f], x, ys[f], ws[f], 1.0, 0.0, tunes[f])
 
     def fmt_bytes(f):
-        return alg_bytes("coo" if f == "coo_any" else f, A.m, A.n, A.nnz, vbytes, xbytes)
+        return alg_bytes("coo" if f in ("coo_any", "coo_col") else f, A.m, A.n, A.nnz, vbytes,
+                         xbytes)
 
     def priced_of(kt):
         return {fk: v for fk, v in kt.items() if fk[1] in PRICED_KERNELS}

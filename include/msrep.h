@@ -78,10 +78,12 @@ int32_t msrep_timing_read(msrep_kernel_time *out, int32_t cap);
 
 /* ------------------------------------------------------------ matrices */
 /* Storage formats of Sec. 2.1: CSR, CSC (the CSR of the transpose), COO
- * sorted by row (the order Sec. 3.2.3 assumes for pCOO) and COO in any order
+ * sorted by row (the order Sec. 3.2.3 assumes for pCOO), COO in any order
  * (MSREP_COO_ANY, the variant Sec. 3.2.3 mentions whose partitions need the
- * column-style merge of partial vectors). */
-enum { MSREP_CSR = 0, MSREP_CSC = 1, MSREP_COO = 2, MSREP_COO_ANY = 3 };
+ * column-style merge of partial vectors) and COO sorted by column
+ * (MSREP_COO_COL: Sec. 3.2.3's other sorted order, split in O(np log n) and
+ * merged by columns like pCSC, Sec. 4.3). */
+enum { MSREP_CSR = 0, MSREP_CSC = 1, MSREP_COO = 2, MSREP_COO_ANY = 3, MSREP_COO_COL = 4 };
 
 /* Stored value type.  F64 values use FP64 x and y and FP64 arithmetic.  F32
  * and BF16 values use FP32 x and y, FP32 products and in-chunk sums, and FP64
@@ -89,14 +91,16 @@ enum { MSREP_CSR = 0, MSREP_CSC = 1, MSREP_COO = 2, MSREP_COO_ANY = 3 };
 enum { MSREP_F64 = 0, MSREP_F32 = 1, MSREP_BF16 = 2 };
 
 typedef struct msrep_mat {
-  int32_t fmt;   /* MSREP_CSR / MSREP_CSC / MSREP_COO / MSREP_COO_ANY          */
+  int32_t fmt;   /* MSREP_CSR / MSREP_CSC / MSREP_COO / MSREP_COO_ANY /        */
+                 /* MSREP_COO_COL                                               */
   int32_t vtype; /* MSREP_F64 / MSREP_F32 / MSREP_BF16                          */
   int32_t m, n;  /* rows, columns                                               */
   int64_t nnz;   /* number of stored nonzeros                                   */
   const int32_t *ptr;  /* CSR row_ptr[m+1] | CSC col_ptr[n+1] | COO*: NULL     */
   const int32_t *idx;  /* CSR col_idx | CSC row_idx | COO row_idx (sorted) |   */
-                       /* COO_ANY row_idx (any order)                          */
-  const int32_t *idx2; /* COO, COO_ANY col_idx | otherwise NULL                 */
+                       /* COO_ANY row_idx (any order) | COO_COL row_idx       */
+  const int32_t *idx2; /* COO, COO_ANY col_idx | COO_COL col_idx (sorted) |     */
+                       /* otherwise NULL                                        */
   const void *val;     /* nnz values of vtype (BF16: raw 16-bit patterns)       */
 } msrep_mat;
 
@@ -104,8 +108,8 @@ typedef struct msrep_mat {
 int32_t msrep_vtype_bytes(int32_t vtype);
 
 /* O(nnz) structure check on the GPU: pointer starts at 0, is non-decreasing
- * and ends at nnz; indices in range; COO row indices non-decreasing (not
- * required for COO_ANY).
+ * and ends at nnz; indices in range; COO row indices non-decreasing, COO_COL
+ * column indices non-decreasing (no order required for COO_ANY).
  * Returns MSREP_OK or MSREP_ERR_FORMAT (with the first offence described).
  * Synchronises the stream. */
 msrep_status msrep_validate(const msrep_mat *A, void *stream);
@@ -130,7 +134,11 @@ msrep_status msrep_validate(const msrep_mat *A, void *stream);
  * (the paper's local row_ptr with both ends made explicit).  An empty
  * partition (np > nnz) has end_idx = start_idx - 1, start_row = the row of
  * start_idx (or m if start_idx == nnz), end_row = start_row - 1, both flags 0
- * and the single entry lptr[lptr_off] = 0.  COO_ANY: only start_idx and
+ * and the single entry lptr[lptr_off] = 0.  COO_COL: the same records with
+ * columns in place of rows (start_row / end_row hold the columns of
+ * start_idx / end_idx, the flags mark split columns; Algorithm 6 applied to
+ * the column index, equal to pCSC's records of the same matrix), no local
+ * pointer, lptr_off 0.  COO_ANY: only start_idx and
  * end_idx are defined (equal-nnz position ranges; rows are not grouped):
  * start_row 0, end_row -1, flags 0, lptr_off 0.
  */
@@ -155,6 +163,8 @@ int64_t msrep_lptr_bound(int32_t rows, int32_t np);
  *               lptr_cap 0 for COO.  lptr_cap must be >= msrep_lptr_bound.
  *   lptr_len_d: optional (device int64), receives one past the last entry.
  * COO must be sorted by row; row indices are read at 2*np positions only.
+ * COO_COL must be sorted by column; column indices are read at 2*np
+ * positions only.
  * COO_ANY reads no indices.
  */
 msrep_status msrep_build_partition(const msrep_mat *A, int32_t np,
@@ -185,10 +195,10 @@ msrep_status msrep_build_partition_rows(const msrep_mat *A, int32_t np,
 size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt);
 
 /*
- * Convert between CSR, CSC and row-sorted COO (Sec. 2.1; CSC(A) = CSR(A^T)).
- * dst->fmt selects the target; dst->m, n, nnz, vtype must equal src's and its
- * arrays must be allocated (CSR: ptr m+1, idx nnz; CSC: ptr n+1, idx nnz; COO:
- * idx nnz, idx2 nnz; val nnz).  Values are moved, never rounded.  Conversions
+ * Convert between CSR, CSC, row-sorted COO and column-sorted COO (Sec. 2.1;
+ * CSC(A) = CSR(A^T)).  dst->fmt selects the target; dst->m, n, nnz, vtype
+ * must equal src's and its arrays must be allocated (CSR: ptr m+1, idx nnz;
+ * CSC: ptr n+1, idx nnz; COO, COO_COL: idx nnz, idx2 nnz; val nnz).  Values are moved, never rounded.  Conversions
  * are stable: entries that tie on the new major index keep their storage
  * order, so canonical input (sorted minor indices, no duplicates) gives the
  * unique canonical output.  ws_d: msrep_convert_ws_bytes bytes of device
@@ -221,13 +231,13 @@ typedef struct msrep_tune {
 /* Workspace bytes msrep_spmv needs for A split into np partitions.
  *   CSR, COO: two FP64 partial sums per partition for the boundary merge
  *     (16*np, rounded up to 256).
- *   CSC, COO_ANY: bucket counters (buckets x producers int32), per-bucket piece
+ *   CSC, COO_ANY, COO_COL: bucket counters (buckets x producers int32), per-bucket piece
  *     tables, one product per nonzero (8 bytes for F64 values, 4 otherwise)
  *     with its row offset (room for either product layout, see
  *     msrep_tune.pipeline), and the partial row arrays of buckets cut into
  *     several pieces: about (s_p + 4)*nnz bytes.
- * Returns 0 when A is not supported (CSC or COO_ANY with more than 2^26
- * rows). */
+ * Returns 0 when A is not supported (CSC or COO_ANY / COO_COL with more
+ * than 2^26 rows). */
 size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
 
 /*
@@ -242,8 +252,10 @@ size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
  *     merge) are kept sparse: every product is written once, grouped by row
  *     bucket, and each bucket is summed in LDS; no atomics on y.  The order
  *     of the sums within a bucket varies between runs.
- *   COO_ANY: the same bucketed path, each nonzero's column read from idx2
- *     (lptr_d is not read and may be NULL).
+ *   COO_ANY, COO_COL: the same bucketed path, each nonzero's column read
+ *     from idx2 (lptr_d is not read and may be NULL).  For COO_COL this is
+ *     the column-based merge of Sec. 4.3: each partition's partial vector
+ *     over y, kept sparse as for CSC.
  *   x_d: n values, y_d: m values (FP64 for F64 matrices, FP32 otherwise).
  *   beta == 0: y is not read.
  *   ws_d: msrep_spmv_ws_bytes(A, np) bytes, caller-owned, contents free.

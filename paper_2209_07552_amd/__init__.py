@@ -11,7 +11,7 @@ or without the built library raises.
 from __future__ import annotations
 
 from ._abi import (  # noqa: F401
-    BF16, COO, COO_ANY, CSC, CSR, F32, F64, PART_DTYPE, Mat, MsrepError, Partition, Tune, lib_path,
+    BF16, COO, COO_ANY, COO_COL, CSC, CSR, F32, F64, PART_DTYPE, Mat, MsrepError, Partition, Tune, lib_path,
     load_library, msrep_autotune, msrep_build_partition, msrep_convert, msrep_last_error,
     msrep_lptr_bound, msrep_plan_create, SPLIT_NNZ, SPLIT_ROWS, msrep_serve, msrep_spmm, msrep_spmm_ws_bytes,
     msrep_spmv, msrep_spmv_batched, msrep_spmv_noalloc, msrep_spmv_noalloc_max_parts,

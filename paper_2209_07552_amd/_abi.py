@@ -15,9 +15,10 @@ ROOT = os.path.dirname(HERE)
 _LIB_PATH = os.path.join(HERE, "libmsrep.so")
 HEADER = os.path.join(ROOT, "include", "msrep.h")
 
-CSR, CSC, COO, COO_ANY = 0, 1, 2, 3  # COO_ANY: COO in any order
+CSR, CSC, COO, COO_ANY, COO_COL = 0, 1, 2, 3, 4  # COO_ANY: any order; COO_COL: by column
+COO_FORMATS = (COO, COO_ANY, COO_COL)
 F64, F32, BF16 = 0, 1, 2
-FMT_NAMES = {CSR: "csr", CSC: "csc", COO: "coo", COO_ANY: "coo_any"}
+FMT_NAMES = {CSR: "csr", CSC: "csc", COO: "coo", COO_ANY: "coo_any", COO_COL: "coo_col"}
 VT_NAMES = {F64: "f64", F32: "f32", BF16: "bf16"}
 VALUE_BYTES = {F64: 8, F32: 4, BF16: 2}
 
@@ -240,10 +241,10 @@ class Mat:
         M = cls.__new__(cls)
         M.fmt, M.vtype, M.m, M.n, M.nnz = int(fmt), int(vtype), int(m), int(n), int(nnz)
         major = n if fmt == CSC else m
-        M.ptr = None if fmt in (COO, COO_ANY) else torch.empty(major + 1, dtype=torch.int32,
-                                                               device=device)
+        M.ptr = None if fmt in COO_FORMATS else torch.empty(major + 1, dtype=torch.int32,
+                                                            device=device)
         M.idx = torch.empty(nnz, dtype=torch.int32, device=device)
-        M.idx2 = (torch.empty(nnz, dtype=torch.int32, device=device) if fmt in (COO, COO_ANY)
+        M.idx2 = (torch.empty(nnz, dtype=torch.int32, device=device) if fmt in COO_FORMATS
                   else None)
         M.val = torch.empty(nnz, dtype=value_dtype(vtype), device=device)
         return M
@@ -254,7 +255,7 @@ class Mat:
 
     @property
     def major(self):
-        return self.n if self.fmt == CSC else self.m
+        return self.n if self.fmt in (CSC, COO_COL) else self.m
 
     def nbytes(self):
         return sum(t.numel() * t.element_size() for t in (self.ptr, self.idx, self.idx2, self.val)
@@ -307,7 +308,7 @@ def msrep_build_partition(A: Mat, np_: int, stream=None, split: int = SPLIT_NNZ)
     L = load_library()
     dev = A.idx.device if A.idx is not None else A.ptr.device
     parts = torch.empty(max(np_, 1) * PART_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    if A.fmt in (COO, COO_ANY):
+    if A.fmt in COO_FORMATS:
         lptr, cap = None, 0
     else:
         cap = L.msrep_lptr_bound(A.major, np_)

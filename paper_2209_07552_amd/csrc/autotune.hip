@@ -91,7 +91,7 @@ extern "C" msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void
           for (int res : kResident) {
             if (err) break;
             // CSC has neither choice (its producer shapes are fixed)
-            const bool bucketed = A->fmt == MSREP_CSC || A->fmt == MSREP_COO_ANY;
+            const bool bucketed = bucketed_fmt(A->fmt);
             if (bucketed && (res == 1 || wpb != kWpb[0])) continue;
             if (A->fmt == MSREP_COO && pf == 1) continue;  // CSR pipelines, CSC layouts
             if ((err = spmv_launch(A, parts, lptr, np, x_d, y, 1.0, 0.0, K, wpb, pf, res, carry, s)))

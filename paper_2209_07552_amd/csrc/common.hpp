@@ -59,8 +59,15 @@ msrep_status launch_merge_rows(const msrep_mat *A, const msrep_part *parts, int3
 int value_bytes(int32_t vtype);
 // x / y element size for a matrix of this value type.
 inline int vec_bytes(int32_t vtype) { return vtype == MSREP_F64 ? 8 : 4; }
-// Rows of the compressed dimension (CSR: m, CSC: n) and of the result (m).
-inline int32_t major_dim(const msrep_mat *A) { return A->fmt == MSREP_CSC ? A->n : A->m; }
+// Rows of the compressed or sorted dimension (CSR, COO: m; CSC, COO_COL: n).
+inline int32_t major_dim(const msrep_mat *A) {
+  return A->fmt == MSREP_CSC || A->fmt == MSREP_COO_COL ? A->n : A->m;
+}
+// Formats whose SpMV runs the bucketed column-merge path (partial vectors
+// kept sparse) rather than the row-split path.
+inline bool bucketed_fmt(int32_t fmt) {
+  return fmt == MSREP_CSC || fmt == MSREP_COO_ANY || fmt == MSREP_COO_COL;
+}
 
 __host__ __device__ constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

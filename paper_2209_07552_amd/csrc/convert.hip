@@ -1,5 +1,5 @@
-// msrep_convert: CSR <-> CSC <-> row-sorted COO on the GPU (msRep Sec. 2.1;
-// CSC(A) = CSR(A^T)).  All conversions are stable and deterministic:
+// msrep_convert: CSR, CSC, row-sorted and column-sorted COO into one another
+// on the GPU (msRep Sec. 2.1; CSC(A) = CSR(A^T)).  All conversions are stable and deterministic:
 //   * expand:  the major index of every nonzero from a compressed pointer
 //              (mark each non-empty row's first position, inclusive max-scan);
 //   * compress: a pointer from sorted major indices (counting + scan);
@@ -268,11 +268,50 @@ extern "C" size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt) 
   return plan_ws(nullptr, src->nnz, minor).bytes;
 }
 
+namespace {
+
+// Row-major formats (CSR, row-sorted COO) keep their nonzeros grouped by
+// row, column-major ones (CSC, column-sorted COO) by column.
+bool row_major(int32_t fmt) { return fmt == MSREP_CSR || fmt == MSREP_COO; }
+bool compressed(int32_t fmt) { return fmt == MSREP_CSR || fmt == MSREP_CSC; }
+
+// A format's index arrays in terms of its own order: the major index (the
+// one it is grouped by: row for CSR / COO, column for CSC / COO_COL), either
+// compressed (ptr) or one per nonzero (exp), and the minor index.
+struct Sides {
+  const int32_t *ptr, *exp, *minor;
+  int32_t major_extent, minor_extent;
+};
+
+Sides sides_of(const msrep_mat *A) {
+  const bool rm = row_major(A->fmt);
+  Sides d{};
+  d.major_extent = rm ? A->m : A->n;
+  d.minor_extent = rm ? A->n : A->m;
+  switch (A->fmt) {
+    case MSREP_CSR:
+    case MSREP_CSC: d.ptr = A->ptr; d.minor = A->idx; break;
+    case MSREP_COO: d.exp = A->idx; d.minor = A->idx2; break;
+    default: d.exp = A->idx2; d.minor = A->idx; break;  // MSREP_COO_COL
+  }
+  return d;
+}
+
+// Where the destination's major (expanded) and minor indices go.
+int32_t *dst_exp(msrep_mat *D) {
+  return const_cast<int32_t *>(D->fmt == MSREP_COO ? D->idx : D->idx2);
+}
+int32_t *dst_minor(msrep_mat *D) {
+  return const_cast<int32_t *>(D->fmt == MSREP_COO ? D->idx2 : D->idx);
+}
+
+}  // namespace
+
 extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,
                                       size_t ws_bytes, void *stream) {
   if (msrep_status st = check_mat(src, "msrep_convert")) return st;
   if (!dst) return fail(MSREP_ERR_ARG, "msrep_convert: dst is NULL");
-  if (dst->fmt < MSREP_CSR || dst->fmt > MSREP_COO_ANY)
+  if (dst->fmt < MSREP_CSR || dst->fmt > MSREP_COO_COL)
     return fail(MSREP_ERR_ARG, "msrep_convert: unknown target format %d", dst->fmt);
   if (src->fmt == MSREP_COO_ANY || dst->fmt == MSREP_COO_ANY)
     return fail(MSREP_ERR_UNSUPPORTED,
@@ -280,12 +319,11 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
   if (dst->m != src->m || dst->n != src->n || dst->nnz != src->nnz || dst->vtype != src->vtype)
     return fail(MSREP_ERR_ARG, "msrep_convert: dst shape/nnz/vtype differ from src");
   const int64_t nnz = src->nnz;
+  const bool dcomp = compressed(dst->fmt);
   int32_t *dptr = const_cast<int32_t *>(dst->ptr);
-  int32_t *didx = const_cast<int32_t *>(dst->idx);
-  int32_t *didx2 = const_cast<int32_t *>(dst->idx2);
   void *dval = const_cast<void *>(dst->val);
-  if (dst->fmt != MSREP_COO && !dptr) return fail(MSREP_ERR_ARG, "msrep_convert: dst ptr is NULL");
-  if (nnz > 0 && (!didx || !dval || (dst->fmt == MSREP_COO && !didx2)))
+  if (dcomp && !dptr) return fail(MSREP_ERR_ARG, "msrep_convert: dst ptr is NULL");
+  if (nnz > 0 && (!dst->idx || !dval || (!dcomp && !dst->idx2)))
     return fail(MSREP_ERR_ARG, "msrep_convert: dst arrays are NULL");
   const size_t need = msrep_convert_ws_bytes(src, dst->fmt);
   if (!ws_d || ws_bytes < need)
@@ -294,70 +332,56 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
   hipStream_t s = as_stream(stream);
   Ws w = plan_ws(ws_d, nnz, std::max(src->m, src->n));
   const size_t vb = static_cast<size_t>(value_bytes(src->vtype)) * nnz;
-  const int sf = src->fmt, df = dst->fmt;
+  const Sides S = sides_of(src);
+  int32_t *dminor = dst_minor(dst);
 
-  if (sf == df) {  // same format: a copy
-    const int32_t major = major_dim(src);
-    if (sf != MSREP_COO)
-      MSREP_HIP(hipMemcpyAsync(dptr, src->ptr, 4 * (static_cast<size_t>(major) + 1),
-                               hipMemcpyDeviceToDevice, s));
+  if (row_major(src->fmt) == row_major(dst->fmt)) {
+    // same grouping: the major index is compressed or expanded, the minor
+    // index and the values are copied
+    if (dcomp) {
+      if (S.ptr)
+        MSREP_HIP(hipMemcpyAsync(dptr, S.ptr, 4 * (static_cast<size_t>(S.major_extent) + 1),
+                                 hipMemcpyDeviceToDevice, s));
+      else {
+        hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for(nnz + 1)), dim3(256), 0, s, S.exp, nnz,
+                           S.major_extent, dptr);
+        MSREP_LAUNCHED("rows_to_ptr");
+      }
+    } else if (nnz > 0) {
+      if (S.ptr) {
+        if (msrep_status st = expand(S.ptr, S.major_extent, nnz, dst_exp(dst), w.agg, s))
+          return st;
+      } else {
+        MSREP_HIP(hipMemcpyAsync(dst_exp(dst), S.exp, 4 * nnz, hipMemcpyDeviceToDevice, s));
+      }
+    }
     if (nnz > 0) {
-      MSREP_HIP(hipMemcpyAsync(didx, src->idx, 4 * nnz, hipMemcpyDeviceToDevice, s));
-      if (sf == MSREP_COO)
-        MSREP_HIP(hipMemcpyAsync(didx2, src->idx2, 4 * nnz, hipMemcpyDeviceToDevice, s));
+      MSREP_HIP(hipMemcpyAsync(dminor, S.minor, 4 * nnz, hipMemcpyDeviceToDevice, s));
       MSREP_HIP(hipMemcpyAsync(dval, src->val, vb, hipMemcpyDeviceToDevice, s));
     }
     return ok();
   }
-  if (sf == MSREP_CSR && df == MSREP_COO) {
-    if (msrep_status st = expand(src->ptr, src->m, nnz, didx, w.agg, s)) return st;
-    if (nnz > 0) {
-      MSREP_HIP(hipMemcpyAsync(didx2, src->idx, 4 * nnz, hipMemcpyDeviceToDevice, s));
-      MSREP_HIP(hipMemcpyAsync(dval, src->val, vb, hipMemcpyDeviceToDevice, s));
-    }
-    return ok();
-  }
-  if (sf == MSREP_COO && df == MSREP_CSR) {
-    hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for(nnz + 1)), dim3(256), 0, s, src->idx, nnz,
-                       src->m, dptr);
-    MSREP_LAUNCHED("rows_to_ptr");
-    if (nnz > 0) {
-      MSREP_HIP(hipMemcpyAsync(didx, src->idx2, 4 * nnz, hipMemcpyDeviceToDevice, s));
-      MSREP_HIP(hipMemcpyAsync(dval, src->val, vb, hipMemcpyDeviceToDevice, s));
-    }
-    return ok();
-  }
-  // the transposing conversions: sort positions by the new major index
-  //   CSR -> CSC: key = column (idx), other index = row (expanded ptr)
-  //   COO -> CSC: key = column (idx2), other = row (idx)
-  //   CSC -> CSR / COO: key = row (idx), other = column (expanded ptr)
-  const int32_t *key = nullptr;
-  const int32_t *other = nullptr;
-  int32_t key_range = 0;
-  if (sf == MSREP_CSR || sf == MSREP_CSC) {
-    if (msrep_status st = expand(src->ptr, major_dim(src), nnz, w.major, w.agg, s)) return st;
+  // the transposing conversions: a stable sort of the positions by the
+  // source's minor index (the destination's major one); the source's major
+  // index becomes the destination's minor one
+  const int32_t *key = S.minor;
+  const int32_t key_range = S.minor_extent;
+  const int32_t *other = S.exp;
+  if (S.ptr) {
+    if (msrep_status st = expand(S.ptr, S.major_extent, nnz, w.major, w.agg, s)) return st;
     other = w.major;
-    key = src->idx;
-    key_range = sf == MSREP_CSR ? src->n : src->m;
-  } else {  // COO -> CSC
-    other = src->idx;
-    key = src->idx2;
-    key_range = src->n;
   }
-  if (df == MSREP_CSC || df == MSREP_CSR) {
+  if (dcomp) {
     if (msrep_status st = compress_counts(key, nnz, key_range, dptr, w.agg, s)) return st;
   }
   if (nnz == 0) return ok();
   int32_t *perm = nullptr;
   uint32_t *sorted = nullptr;
   if (msrep_status st = stable_sort(key, nnz, key_bits(key_range), w, s, &perm, &sorted)) return st;
-  const int g = grid_for(nnz);
-  if (df == MSREP_COO) {  // CSC -> COO: rows are the sorted keys, columns gathered
-    MSREP_HIP(hipMemcpyAsync(didx, sorted, 4 * nnz, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(gather<int32_t>, dim3(g), dim3(256), 0, s, other, perm, nnz, didx2);
-  } else {
-    hipLaunchKernelGGL(gather<int32_t>, dim3(g), dim3(256), 0, s, other, perm, nnz, didx);
-  }
+  if (!dcomp)
+    MSREP_HIP(hipMemcpyAsync(dst_exp(dst), sorted, 4 * nnz, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(gather<int32_t>, dim3(grid_for(nnz)), dim3(256), 0, s, other, perm, nnz,
+                     dminor);
   MSREP_LAUNCHED("gather");
   if (msrep_status st = gather_values(src->val, perm, nnz, src->vtype, dval, s)) return st;
   return ok();

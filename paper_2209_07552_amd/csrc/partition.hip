@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void part_lptr(const int32_t *__restrict__ ptr
   if (lptr_len && i == np - 1 && sub == 0 && threadIdx.x == 0) *lptr_len = P.lptr_off + n_ent;
 }
 
-// pCOO on row-sorted COO: rows come straight from row_idx.
+// pCOO on row-sorted COO: rows come straight from row_idx.  Called with the
+// column index of column-sorted COO it gives that format's records (columns
+// in the row fields).
 __global__ __launch_bounds__(256) void part_meta_coo(const int32_t *__restrict__ row_idx,
                                                      int32_t rows, int64_t nnz, int32_t np,
                                                      msrep_part *__restrict__ parts) {
@@ -218,13 +220,18 @@ msrep_status build_partition(const msrep_mat *A, int32_t np, msrep_part *parts_d
     return fail(MSREP_ERR_UNSUPPORTED, "%s: COO in any order has no row blocks", who);
   hipStream_t s = as_stream(stream);
   const int grid = (np + 255) / 256;
-  if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY) {
+  if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY || A->fmt == MSREP_COO_COL) {
+    // the sorted index: rows of row-sorted COO, columns of column-sorted COO
+    // (Algorithm 6 applied to that index; the records then hold columns)
+    const bool by_col = A->fmt == MSREP_COO_COL;
+    const int32_t *key = by_col ? A->idx2 : A->idx;
+    const int32_t extent = by_col ? A->n : A->m;
     if (split == kSplitRows) {
-      hipLaunchKernelGGL(part_meta_rows_coo, dim3(grid), dim3(256), 0, s, A->idx, A->m, A->nnz,
+      hipLaunchKernelGGL(part_meta_rows_coo, dim3(grid), dim3(256), 0, s, key, extent, A->nnz,
                          np, parts_d);
       MSREP_LAUNCHED("part_meta_rows_coo");
-    } else if (A->fmt == MSREP_COO) {
-      hipLaunchKernelGGL(part_meta_coo, dim3(grid), dim3(256), 0, s, A->idx, A->m, A->nnz, np,
+    } else if (A->fmt != MSREP_COO_ANY) {
+      hipLaunchKernelGGL(part_meta_coo, dim3(grid), dim3(256), 0, s, key, extent, A->nnz, np,
                          parts_d);
       MSREP_LAUNCHED("part_meta_coo");
     } else {

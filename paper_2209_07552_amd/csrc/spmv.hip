@@ -37,7 +37,7 @@ int value_bytes(int32_t vtype) {
 
 msrep_status check_mat(const msrep_mat *A, const char *who) {
   if (!A) return fail(MSREP_ERR_ARG, "%s: matrix descriptor is NULL", who);
-  if (A->fmt < MSREP_CSR || A->fmt > MSREP_COO_ANY)
+  if (A->fmt < MSREP_CSR || A->fmt > MSREP_COO_COL)
     return fail(MSREP_ERR_ARG, "%s: unknown format %d", who, A->fmt);
   if (!value_bytes(A->vtype)) return fail(MSREP_ERR_ARG, "%s: unknown value type %d", who, A->vtype);
   if (A->m < 0 || A->n < 0 || A->nnz < 0)
@@ -48,7 +48,7 @@ msrep_status check_mat(const msrep_mat *A, const char *who) {
                 static_cast<long long>(A->nnz));
   if (A->nnz > 0 && (A->m == 0 || A->n == 0))
     return fail(MSREP_ERR_ARG, "%s: nonzeros in a matrix with no rows or columns", who);
-  const bool coo = A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY;
+  const bool coo = A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY || A->fmt == MSREP_COO_COL;
   if (!coo && !A->ptr) return fail(MSREP_ERR_ARG, "%s: ptr is NULL", who);
   if (A->nnz > 0 && (!A->idx || !A->val)) return fail(MSREP_ERR_ARG, "%s: idx/val is NULL", who);
   if (coo && A->nnz > 0 && !A->idx2)
@@ -194,7 +194,7 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   double *part = reinterpret_cast<double *>(b + L.part);
   (void)wpb;  // the scatter always runs 16-wavefront producers
   timing_begin("csc_scatter", s);
-  if (A->fmt == MSREP_COO_ANY)  // columns read from col_idx
+  if (A->fmt == MSREP_COO_ANY || A->fmt == MSREP_COO_COL)  // columns read from col_idx
     hipLaunchKernelGGL((coo_any_scatter<VT, K, PACK>), dim3(L.P), dim3(kCscScatterWaves * kWave),
                        align_up((static_cast<size_t>(L.nb) + kWave) * 4, 16), s, A->idx, A->idx2,
                        static_cast<const typename Tr::V *>(A->val), A->nnz, parts, np, L.P,
@@ -244,7 +244,7 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
-  if (A->fmt == MSREP_CSC || A->fmt == MSREP_COO_ANY) {  // carry is the whole workspace here
+  if (bucketed_fmt(A->fmt)) {  // carry is the whole workspace here
     if (pf == 1)
       return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s)
                     : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s);
@@ -346,7 +346,7 @@ namespace msrep {
 
 
 size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t np) {
-  if (fmt == MSREP_CSC || fmt == MSREP_COO_ANY) {
+  if (bucketed_fmt(fmt)) {
     CscLayout L;
     const int pb = vtype == MSREP_F64 ? 8 : 4;
     return csc_layout(m, nnz, np, pb, L) ? L.total : 0;
@@ -386,7 +386,7 @@ msrep_status spmv_entry(const msrep_mat *A, const msrep_part *parts_d, const int
   if (xb >= (uint64_t(1) << 32) || yb >= (uint64_t(1) << 32) ||
       (static_cast<uint64_t>(major_dim(A)) + 1) * 4 >= (uint64_t(1) << 32))
     return fail(MSREP_ERR_UNSUPPORTED, "%s: x or y larger than 4 GiB", who);
-  if (A->fmt == MSREP_CSC || A->fmt == MSREP_COO_ANY) {
+  if (bucketed_fmt(A->fmt)) {
     CscLayout L;
     if (!csc_layout(A->m, A->nnz, np, 8, L))
       return fail(MSREP_ERR_UNSUPPORTED, "%s: CSC and unsorted COO support at most %d rows",

@@ -15,6 +15,7 @@ enum : int64_t {
   kIdxRange = 4,  // minor index out of range
   kRowOrder = 5,  // COO row indices decrease
   kRowRange = 6,  // COO row index out of range
+  kColOrder = 7,  // column-sorted COO column indices decrease
 };
 
 __device__ __forceinline__ void report(unsigned long long *first, int64_t pos, int64_t code) {
@@ -34,13 +35,15 @@ __global__ void check_compressed(const int32_t *__restrict__ ptr, int32_t rows,
     if (static_cast<uint32_t>(idx[k]) >= static_cast<uint32_t>(minor)) report(first, k, kIdxRange);
 }
 
+// order: 0 any, 1 rows non-decreasing, 2 columns non-decreasing
 __global__ void check_coo(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
-                          int64_t nnz, int32_t m, int32_t n, bool sorted,
+                          int64_t nnz, int32_t m, int32_t n, int order,
                           unsigned long long *first) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < nnz; k += stride) {
     if (static_cast<uint32_t>(row[k]) >= static_cast<uint32_t>(m)) report(first, k, kRowRange);
-    if (sorted && k > 0 && row[k - 1] > row[k]) report(first, k, kRowOrder);
+    if (order == 1 && k > 0 && row[k - 1] > row[k]) report(first, k, kRowOrder);
+    if (order == 2 && k > 0 && col[k - 1] > col[k]) report(first, k, kColOrder);
     if (static_cast<uint32_t>(col[k]) >= static_cast<uint32_t>(n)) report(first, k, kIdxRange);
   }
 }
@@ -78,10 +81,11 @@ extern "C" msrep_status msrep_validate(const msrep_mat *A, void *stream) {
   MSREP_LAUNCHED("set_u64");
   const int64_t work = (A->nnz > A->m ? A->nnz : A->m) + 1;
   const int grid = static_cast<int>((work + 255) / 256 < 8192 ? (work + 255) / 256 : 8192);
-  if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY) {
+  if (A->fmt == MSREP_COO || A->fmt == MSREP_COO_ANY || A->fmt == MSREP_COO_COL) {
     if (A->nnz > 0) {
+      const int order = A->fmt == MSREP_COO ? 1 : A->fmt == MSREP_COO_COL ? 2 : 0;
       hipLaunchKernelGGL(check_coo, dim3(grid), dim3(256), 0, s, A->idx, A->idx2, A->nnz, A->m,
-                         A->n, A->fmt == MSREP_COO, word);
+                         A->n, order, word);
       MSREP_LAUNCHED("check_coo");
     }
   } else {
@@ -95,12 +99,13 @@ extern "C" msrep_status msrep_validate(const msrep_mat *A, void *stream) {
   MSREP_HIP(hipStreamSynchronize(s));
   if (host == none) return ok();
   const long long pos = static_cast<long long>(host / 8);
-  static const char *what[] = {"",
+  static const char *what[8] = {"",
                                "pointer does not start at 0",
                                "pointer decreases",
                                "pointer does not end at nnz",
                                "index out of range",
                                "COO row indices are not sorted",
-                               "COO row index out of range"};
+                               "COO row index out of range",
+                               "COO column indices are not sorted"};
   return fail(MSREP_ERR_FORMAT, "msrep_validate: %s at position %lld", what[host % 8], pos);
 }

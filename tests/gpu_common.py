@@ -14,12 +14,15 @@ F32_TOL = 1e-5
 
 
 def host_formats(A):
-    """(csr, csc, coo) host arrays of a synth.Csr."""
+    """(csr, csc, coo, coo_col) host arrays of a synth.Csr: CSR (ptr, col,
+    val), CSC (ptr, row, val), row-sorted COO (row, col, val) and
+    column-sorted COO (row, col, val in the CSC's order)."""
     cptr, crow, _, perm = oracle.transpose(A.m, A.n, A.ptr, A.col)
     rows = oracle.csr_to_coo(A.m, A.ptr)
     return {"csr": (A.ptr, A.col, A.val),
             "csc": (cptr, crow, A.val[perm]),
-            "coo": (rows, A.col, A.val)}
+            "coo": (rows, A.col, A.val),
+            "coo_col": (crow, oracle.csr_to_coo(A.n, cptr), A.val[perm])}
 
 
 def stored_values(val64, vt):
@@ -35,7 +38,7 @@ def stored_values(val64, vt):
 
 
 def device_mat(A, fmt, vt):
-    """Device Mat of A in format fmt ('csr'|'csc'|'coo') and value type vt,
+    """Device Mat of A in format fmt ('csr'|'csc'|'coo'|'coo_col') and value type vt,
     plus the FP64 image of the stored values in that format's order."""
     import paper_2209_07552_amd as pk
     H = host_formats(A)
@@ -45,6 +48,8 @@ def device_mat(A, fmt, vt):
         M = pk.Mat(pk.CSR, vt, A.m, A.n, ptr=a, idx=b, val=sv)
     elif fmt == "csc":
         M = pk.Mat(pk.CSC, vt, A.m, A.n, ptr=a, idx=b, val=sv)
+    elif fmt == "coo_col":
+        M = pk.Mat(pk.COO_COL, vt, A.m, A.n, idx=a, idx2=b, val=sv)
     else:
         M = pk.Mat(pk.COO, vt, A.m, A.n, idx=a, idx2=b, val=sv)
     return M, v64

@@ -1,5 +1,5 @@
-"""GPU parity of msrep_convert: every direction between CSR, CSC and
-row-sorted COO, bit-exact against the oracle's stable conversions (indices
+"""GPU parity of msrep_convert: every direction between CSR, CSC,
+row-sorted COO and column-sorted COO, bit-exact against the oracle's stable conversions (indices
 and values), on adversarial small matrices and at full R-MAT scale."""
 import numpy as np
 import pytest
@@ -13,15 +13,16 @@ pk = pytest.importorskip("paper_2209_07552_amd")
 
 pytestmark = pytest.mark.gpu
 
-FMT = {"csr": 0, "csc": 1, "coo": 2}
+FMT = {"csr": 0, "csc": 1, "coo": 2, "coo_col": 4}
+COO_LIKE = ("coo", "coo_col")  # idx and idx2, no pointer
 
 
 def _mk(A, fmt, vt):
     H = host_formats(A)
     a, b, v = H[fmt]
     sv, _ = stored_values(v, vt)
-    if fmt == "coo":
-        return pk.Mat(pk.COO, vt, A.m, A.n, idx=a, idx2=b, val=sv), H
+    if fmt in COO_LIKE:
+        return pk.Mat(FMT[fmt], vt, A.m, A.n, idx=a, idx2=b, val=sv), H
     return pk.Mat(FMT[fmt], vt, A.m, A.n, ptr=a, idx=b, val=sv), H
 
 
@@ -38,7 +39,7 @@ def _check(A, src, dst, vt):
     a, b, v = H[dst]
     want_v, _ = stored_values(v, vt)
     want_v = np.asarray(want_v)
-    if dst == "coo":
+    if dst in COO_LIKE:
         assert np.array_equal(idx, a) and np.array_equal(idx2, b), (A.name, src, dst)
     else:
         assert np.array_equal(ptr, a) and np.array_equal(idx, b), (A.name, src, dst)
@@ -61,8 +62,8 @@ def _small_set():
     return out
 
 
-@pytest.mark.parametrize("src", ["csr", "csc", "coo"])
-@pytest.mark.parametrize("dst", ["csr", "csc", "coo"])
+@pytest.mark.parametrize("src", ["csr", "csc", "coo", "coo_col"])
+@pytest.mark.parametrize("dst", ["csr", "csc", "coo", "coo_col"])
 def test_convert_small(src, dst):
     for A in _small_set():
         for vt in (0, 1, 2):
@@ -70,7 +71,9 @@ def test_convert_small(src, dst):
 
 
 @pytest.mark.parametrize("src,dst", [("csr", "csc"), ("csc", "csr"), ("csr", "coo"),
-                                     ("coo", "csr"), ("coo", "csc"), ("csc", "coo")])
+                                     ("coo", "csr"), ("coo", "csc"), ("csc", "coo"),
+                                     ("csr", "coo_col"), ("coo_col", "csr"), ("csc", "coo_col"),
+                                     ("coo_col", "csc"), ("coo", "coo_col"), ("coo_col", "coo")])
 def test_convert_rmat(src, dst):
     A, _ = synth.rmat_csr(scale=16, edge_factor=16, seed=7)
     _check(A, src, dst, pk.F64)
@@ -98,3 +101,18 @@ def test_duplicates_keep_storage_order():
     p, i, _, v = _host(pk.msrep_convert(M, pk.CSC))
     cptr, crow, cval, _ = oracle.transpose(2, 2, ptr, col, val)
     assert np.array_equal(p, cptr) and np.array_equal(i, crow) and np.array_equal(v, cval)
+
+
+def test_round_trip_column_sorted_rmat20():
+    """CSR -> column-sorted COO -> CSC -> row-sorted COO -> CSR returns the
+    input bit for bit at R-MAT scale 20; the column-sorted arrays equal the
+    oracle's (the CSC expanded)."""
+    A, _ = synth.rmat_csr(scale=20, edge_factor=16, seed=0)
+    M, H = _mk(A, "csr", pk.F64)
+    K = pk.msrep_convert(M, pk.COO_COL)
+    _, kr, kc, kv = _host(K)
+    a, b, v = H["coo_col"]
+    assert np.array_equal(kr, a) and np.array_equal(kc, b) and np.array_equal(kv, v)
+    R = pk.msrep_convert(pk.msrep_convert(pk.msrep_convert(K, pk.CSC), pk.COO), pk.CSR)
+    ptr, idx, _, val = _host(R)
+    assert np.array_equal(ptr, A.ptr) and np.array_equal(idx, A.col) and np.array_equal(val, A.val)

@@ -31,15 +31,15 @@ def _workload(name):
 
 
 @pytest.mark.parametrize("workload", ["rmat20", "stencil256"])
-@pytest.mark.parametrize("fmt", ["csr", "csc", "coo"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "coo", "coo_col"])
 def test_full_size_bench_configuration(workload, fmt):
     import bench
     A, x, H = _workload(workload)
     npw, k, wpb, pf, res = bench.DEFAULT_TUNES[workload][fmt]
     np_ = -(-A.nnz // npw)
     a, b, v = H[fmt]
-    kind = {"csr": pk.CSR, "csc": pk.CSC, "coo": pk.COO}[fmt]
-    if fmt == "coo":
+    kind = {"csr": pk.CSR, "csc": pk.CSC, "coo": pk.COO, "coo_col": pk.COO_COL}[fmt]
+    if fmt in ("coo", "coo_col"):
         M = pk.Mat(kind, pk.F64, A.m, A.n, idx=a, idx2=b, val=v)
     else:
         M = pk.Mat(kind, pk.F64, A.m, A.n, ptr=a, idx=b, val=v)
@@ -67,8 +67,8 @@ def _mat(A, H, fmt, vt, val=None):
     if val is not None:
         v = val
     sv, v64 = stored_values(v, vt)
-    kind = {"csr": pk.CSR, "csc": pk.CSC, "coo": pk.COO}[fmt]
-    if fmt == "coo":
+    kind = {"csr": pk.CSR, "csc": pk.CSC, "coo": pk.COO, "coo_col": pk.COO_COL}[fmt]
+    if fmt in ("coo", "coo_col"):
         return pk.Mat(kind, vt, A.m, A.n, idx=a, idx2=b, val=sv), v64
     return pk.Mat(kind, vt, A.m, A.n, ptr=a, idx=b, val=sv), v64
 
@@ -90,7 +90,7 @@ def _spmv_bench_config(workload, fmt, M, nnz, x, vt):
 
 
 @pytest.mark.parametrize("vt", [0, 1, 2])
-@pytest.mark.parametrize("fmt", ["csr", "csc", "coo"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "coo", "coo_col"])
 def test_full_size_stencil_times_ones_exact(fmt, vt):
     """256^3 stencil times ones: y_i = 6 - (in-grid neighbours of i), a small
     integer, exact in every value type at the full 16.7M rows."""
@@ -109,7 +109,7 @@ def test_full_size_stencil_times_ones_exact(fmt, vt):
 
 
 @pytest.mark.parametrize("workload", ["rmat20", "stencil256"])
-@pytest.mark.parametrize("fmt", ["csr", "csc", "coo"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "coo", "coo_col"])
 def test_full_size_dyadic_bit_exact(workload, fmt):
     """Dyadic values and x (k/256, |k| <= 256): every partial sum is exact in
     FP64, so the full-size result must equal the oracle's bit for bit, which
@@ -122,7 +122,7 @@ def test_full_size_dyadic_bit_exact(workload, fmt):
     if workload == "rmat20":  # the stencil's 6 and -1 are dyadic already
         v_csr = synth.dyadic(rng, A.nnz)
         val = v_csr
-        if fmt == "csc":
+        if fmt in ("csc", "coo_col"):
             import oracle
             _, _, _, p = oracle.transpose(A.m, A.n, A.ptr, A.col)
             val = v_csr[p]

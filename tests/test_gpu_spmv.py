@@ -15,7 +15,8 @@ pk = pytest.importorskip("paper_2209_07552_amd")
 
 pytestmark = pytest.mark.gpu
 
-FMTS = ["csr", "csc", "coo"]
+FMTS = ["csr", "csc", "coo", "coo_col"]
+BUCKETED = ("csc", "coo_col")  # the column-merge path: its tune picks the product layout
 
 
 def _dev():
@@ -64,13 +65,15 @@ def _part_compare(A, fmt, np_, split="nnz"):
     H = host_formats(A)
     if fmt == "coo":
         R = oracle.partition_coo(A.m, H["coo"][0], np_, split)
+    elif fmt == "coo_col":
+        R = oracle.partition_coo_col(A.n, H["coo_col"][1], np_, split)
     else:
         rows = A.m if fmt == "csr" else A.n
         R = oracle.partition_ptr(rows, H[fmt][0], np_, split)
     for f in ("start_idx", "end_idx", "start_row", "end_row", "start_flag", "end_flag",
               "lptr_off"):
         assert np.array_equal(rec[f], getattr(R, f)), (A.name, fmt, np_, f)
-    if fmt != "coo":
+    if fmt in ("csr", "csc"):
         for i in range(np_):
             o = int(R.lptr_off[i])
             k = int(R.end_row[i] - R.start_row[i] + 2)
@@ -173,7 +176,7 @@ def test_dyadic_bit_exact_any_np(fmt):
     M, v64 = device_mat(A, fmt, pk.F64)
     for np_ in (1, 5, 256, 4096, A.nnz + 7):
         for res in (0, 1):  # CSC: the two product layouts
-            t = pk.Tune(pipeline=1 + res) if fmt == "csc" else pk.Tune(resident=res)
+            t = pk.Tune(pipeline=1 + res) if fmt in BUCKETED else pk.Tune(resident=res)
             y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64, tune=t)
             assert np.array_equal(y, ref), (fmt, np_, res)
 
@@ -265,7 +268,7 @@ def test_prepared_spmv_repeats_with_fresh_x(fmt, vt):
             alpha, beta = (1.0, 0.0) if it % 2 == 0 else (-2.0, 0.25)
             xd = torch.from_numpy(x).to(_dev())
             yd = torch.from_numpy(y_in.copy()).to(_dev())
-            tune = pk.Tune(pipeline=1 + it % 2) if fmt == "csc" else None
+            tune = pk.Tune(pipeline=1 + it % 2) if fmt in BUCKETED else None
             pk.msrep_spmv_prepared(M, P, xd, yd, ws, alpha, beta, tune)
             # an unprepared SpMV of another matrix on the shared workspace
             yb = torch.zeros(B.m, dtype=tdt, device=_dev())
@@ -404,6 +407,14 @@ def test_validate():
     M = pk.Mat(pk.COO, pk.F64, A.m, A.n, idx=rows, idx2=A.col, val=A.val)
     with pytest.raises(pk.MsrepError):
         pk.msrep_validate(M)
+    # column-sorted COO whose columns decrease at one position
+    crow, ccol, cval = host_formats(A)["coo_col"]
+    ccol = ccol.copy()
+    ccol[40], ccol[41] = ccol[41] + 1, ccol[40]
+    M = pk.Mat(pk.COO_COL, pk.F64, A.m, A.n, idx=crow, idx2=ccol, val=cval)
+    with pytest.raises(pk.MsrepError) as e:
+        pk.msrep_validate(M)
+    assert "column indices are not sorted" in str(e.value)
 
 
 def test_autotune_returns_a_valid_tune_and_correct_results():
@@ -518,5 +529,5 @@ def test_spmv_replays_under_graph_capture(fmt):
         torch.cuda.synchronize()
         ref, s = oracle_y(A, fmt, v64, xn)
         assert_close(got, ref, s, F64_TOL, "%s replay %d" % (fmt, rep))
-        if fmt != "csc":  # CSC sums in an order that varies between runs
+        if fmt not in BUCKETED:  # the bucketed path sums in an order that varies
             assert np.array_equal(got, y_eager.cpu().numpy()), (fmt, rep)
