@@ -375,7 +375,11 @@ msrep_status msrep_spmm(const msrep_mat *A, const msrep_part *parts_d, const int
  * by one boundary-merge launch.  The plan keeps the partitions, the work list
  * and the descriptors in ws_d (caller memory, msrep_plan_ws_bytes bytes),
  * which must stay allocated until msrep_plan_destroy.  All matrices must
- * share one value type.  tunes may be NULL (defaults per matrix).
+ * share one value type.  tunes may be NULL (defaults per matrix); the launch
+ * shape (k_per_lane, waves_per_wg, and pipeline: 2 loads two chunks ahead,
+ * otherwise one) comes from tunes[0], the partition size from each tune.
+ * The merge of split rows is one segmented sum over the partitions of all
+ * matrices (as in msrep_spmv).
  */
 typedef struct msrep_plan_s *msrep_plan;
 
@@ -403,8 +407,10 @@ msrep_status msrep_plan_destroy(msrep_plan plan);
  * Matrices are uploaded into the caller's arena when the request is admitted
  * (admission is by bytes: matrix + partitions + vectors must fit in what the
  * arena has free) and stay resident while the request runs.  Every tick
- * executes one step of every active request in one batched launch, so
- * requests that arrive while others run join the next tick.
+ * executes one step of every active request (up to 240 of them) in one
+ * batched launch, so requests that arrive while others run join the next
+ * tick.  A request's descriptor is written to the device once, when it is
+ * admitted; a tick only launches kernels.
  *   x_j[c] = 2*u - 1 with u the top 53 bits of splitmix64(key) / 2^53,
  *   key = seed ^ (rid << 40) ^ ((uint64)j << 24) ^ c (rid < 2^24, j < 2^16)
  *   (SplitMix64: Steele, Lea and Flood 2014), rounded to FP32 for F32 pools.
@@ -425,8 +431,10 @@ typedef struct msrep_serve_cfg {
   int32_t nnz_per_wave; /* partition size when a pool matrix has np == 0     */
   uint64_t seed;        /* x generator seed                                   */
   double time_scale;    /* trace seconds per wall second (1 = real time)     */
-  int32_t keep_y;       /* 1: copy every request's last y into results       */
-  int32_t _pad;
+  int32_t keep_y;       /* msrep_serve: 1 copies every request's last y into  */
+                        /* results[i].y_host (where not NULL)                */
+  int32_t max_queue;    /* msrep_server_submit: most requests waiting for    */
+                        /* admission before MSREP_ERR_BUSY (0: 2^20)          */
 } msrep_serve_cfg;
 
 typedef struct msrep_request {
@@ -474,6 +482,45 @@ msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
                                   msrep_serve_stats *stats,
                                   double upload_bytes_per_s, double flops_per_s,
                                   double tick_seconds);
+
+/*
+ * The same server taking requests as they come.  msrep_server_create copies
+ * the configuration and the pool descriptors (the pool's host arrays and the
+ * arena must stay valid until msrep_server_destroy) and starts the
+ * scheduler on a thread of its own, bound to the device current at the call.
+ *   msrep_server_submit: a request arrives now (req->t_arrive is ignored;
+ *     arrival, admission and completion times are seconds on the server's
+ *     clock, which starts at create).  y_host: NULL, or a host buffer of m
+ *     values that receives the last y before the request is reported done.
+ *     MSREP_ERR_BUSY when max_queue requests already wait; MSREP_ERR_ARG for
+ *     a malformed request; the error that stopped the server otherwise.
+ *   msrep_server_poll: up to cap completions (in completion order), waiting
+ *     up to timeout_ms for the first when none is ready; returns how many
+ *     were written, or a negative status when the server stopped on an
+ *     error.  A request that can never fit the budget completes with status
+ *     MSREP_ERR_BUDGET.
+ *   msrep_server_destroy: waits until every submitted request has finished,
+ *     stops the thread, frees the server and fills stats (may be NULL) over
+ *     every completion; returns the error that stopped the server, if any.
+ * Submit and poll may be called from any threads; destroy exactly once.
+ */
+typedef struct msrep_server_s *msrep_server;
+
+typedef struct msrep_completion {
+  int64_t rid;                      /* the request's rid                    */
+  double t_arrive, t_admit, t_done; /* seconds on the server's clock        */
+  int32_t status;                   /* MSREP_OK or MSREP_ERR_BUDGET         */
+  int32_t _pad;
+} msrep_completion;
+
+msrep_status msrep_server_create(const msrep_serve_cfg *cfg,
+                                 const msrep_host_mat *pool, int32_t pool_size,
+                                 msrep_server *out);
+msrep_status msrep_server_submit(msrep_server server, const msrep_request *req,
+                                 void *y_host);
+int64_t msrep_server_poll(msrep_server server, msrep_completion *out,
+                          int64_t cap, int32_t timeout_ms);
+msrep_status msrep_server_destroy(msrep_server server, msrep_serve_stats *stats);
 
 /* Entry c of x_step for request rid (see msrep_serve), on the host. */
 double msrep_serve_x_value(uint64_t seed, int64_t rid, int32_t step,

@@ -49,7 +49,7 @@ class _HostMat(ctypes.Structure):
 class _ServeCfg(ctypes.Structure):
     _fields_ = [("arena_d", c_vp), ("budget_bytes", c_sz), ("max_slots", c_i32),
                 ("nnz_per_wave", c_i32), ("seed", ctypes.c_uint64), ("time_scale", c_dbl),
-                ("keep_y", c_i32), ("_pad", c_i32)]
+                ("keep_y", c_i32), ("max_queue", c_i32)]
 
 
 class _Request(ctypes.Structure):
@@ -59,6 +59,11 @@ class _Request(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("t_arrive", c_dbl), ("t_admit", c_dbl), ("t_done", c_dbl), ("status", c_i32),
                 ("_pad", c_i32), ("y_host", c_vp)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("rid", c_i64), ("t_arrive", c_dbl), ("t_admit", c_dbl), ("t_done", c_dbl),
+                ("status", c_i32), ("_pad", c_i32)]
 
 
 class _ServeStats(ctypes.Structure):
@@ -124,6 +129,10 @@ def load_library():
         "msrep_plan_destroy": (c_i32, [c_vp]),
         "msrep_serve": (c_i32, [P(_ServeCfg), P(_HostMat), c_i32, P(_Request), c_i64, P(_Result),
                                 P(_ServeStats)]),
+        "msrep_server_create": (c_i32, [P(_ServeCfg), P(_HostMat), c_i32, P(c_vp)]),
+        "msrep_server_submit": (c_i32, [c_vp, P(_Request), c_vp]),
+        "msrep_server_poll": (c_i64, [c_vp, P(_Completion), c_i64, c_i32]),
+        "msrep_server_destroy": (c_i32, [c_vp, P(_ServeStats)]),
         "msrep_timing": (c_i32, [c_i32]),
         "msrep_timing_only": (c_i32, [ctypes.c_char_p]),
         "msrep_timing_read": (c_i32, [P(_KernelTime), c_i32]),

@@ -71,7 +71,7 @@ Layout layout(int32_t count, const msrep_mat *mats, const msrep_tune *tunes) {
 using namespace msrep;
 
 struct msrep_plan_s {
-  int32_t count = 0, vtype = 0, K = 4, wpb = 4, n_waves = 0, grid = 0;
+  int32_t count = 0, vtype = 0, K = 4, wpb = 4, pf = 1, n_waves = 0, grid = 0;
   int64_t n_items = 0;
   char *ws = nullptr;
   Layout L;
@@ -107,19 +107,24 @@ extern "C" msrep_status msrep_plan_destroy(msrep_plan plan) {
 
 namespace {
 
-template <int VT, int K, bool B0>
+template <int VT, int K, bool B0, int PF>
 msrep_status capture_kernels(msrep_plan P, double alpha, double beta) {
   using T = typename vt_traits<VT>::T;
-  const BatchMat *mats = reinterpret_cast<const BatchMat *>(P->ws + P->L.mats_off);
-  const int2 *items = reinterpret_cast<const int2 *>(P->ws + P->L.items_off);
-  const int64_t *wb = reinterpret_cast<const int64_t *>(P->ws + P->L.waves_off);
+  PlanSrc src;
+  src.mats = reinterpret_cast<const BatchMat *>(P->ws + P->L.mats_off);
+  src.xy = P->xy_d;
+  src.items = reinterpret_cast<const int2 *>(P->ws + P->L.items_off);
+  src.wave_begin = reinterpret_cast<const int64_t *>(P->ws + P->L.waves_off);
+  src.n_items = P->n_items;
+  src.n_waves = P->n_waves;
+  src._pad = 0;
   const size_t lds = seg_lds_per_wave<VT, K>() * P->wpb;
-  hipLaunchKernelGGL((spmv_batched_persistent<VT, K, B0>), dim3(P->grid), dim3(P->wpb * kWave),
-                     lds, P->cap, mats, P->xy_d, items, wb, P->n_waves, alpha, beta);
+  hipLaunchKernelGGL((spmv_items_persistent<VT, K, B0, PF, PlanSrc>), dim3(P->grid),
+                     dim3(P->wpb * kWave), lds, P->cap, src, alpha, beta);
   MSREP_LAUNCHED("spmv_batched_persistent");
-  const int g = static_cast<int>((P->n_items + 255) / 256);
-  hipLaunchKernelGGL((merge_batched<T, B0>), dim3(g), dim3(256), 0, P->cap, mats, P->xy_d, items,
-                     P->n_items, alpha, beta);
+  const int g = static_cast<int>((P->n_items + kMergeBlock - 1) / kMergeBlock);
+  hipLaunchKernelGGL((merge_items<T, B0, PlanSrc>), dim3(g > 0 ? g : 1), dim3(kMergeBlock), 0,
+                     P->cap, src, alpha, beta);
   MSREP_LAUNCHED("merge_batched");
   return MSREP_OK;
 }
@@ -127,28 +132,41 @@ msrep_status capture_kernels(msrep_plan P, double alpha, double beta) {
 template <int VT>
 msrep_status capture_vt(msrep_plan P, double alpha, double beta) {
   const bool b0 = beta == 0.0;
+  if (P->pf == 2) {
+    if (P->K == 8)
+      return b0 ? capture_kernels<VT, 8, true, 2>(P, alpha, beta)
+                : capture_kernels<VT, 8, false, 2>(P, alpha, beta);
+    return b0 ? capture_kernels<VT, 4, true, 2>(P, alpha, beta)
+              : capture_kernels<VT, 4, false, 2>(P, alpha, beta);
+  }
   if (P->K == 8)
-    return b0 ? capture_kernels<VT, 8, true>(P, alpha, beta)
-              : capture_kernels<VT, 8, false>(P, alpha, beta);
-  return b0 ? capture_kernels<VT, 4, true>(P, alpha, beta)
-            : capture_kernels<VT, 4, false>(P, alpha, beta);
+    return b0 ? capture_kernels<VT, 8, true, 1>(P, alpha, beta)
+              : capture_kernels<VT, 8, false, 1>(P, alpha, beta);
+  return b0 ? capture_kernels<VT, 4, true, 1>(P, alpha, beta)
+            : capture_kernels<VT, 4, false, 1>(P, alpha, beta);
 }
 
-template <int VT, int K>
+template <int VT, int K, int PF>
 int resident_blocks(int wpb) {
   int nb = 0;
   const size_t lds = seg_lds_per_wave<VT, K>() * wpb;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, spmv_batched_persistent<VT, K, true>,
-                                                   wpb * kWave, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, spmv_items_persistent<VT, K, true, PF, PlanSrc>, wpb * kWave, lds) != hipSuccess)
     return 0;
   return nb;
 }
 
-int resident_for(int32_t vtype, int K, int wpb) {
+template <int VT>
+int resident_vt(int K, int pf, int wpb) {
+  if (pf == 2) return K == 8 ? resident_blocks<VT, 8, 2>(wpb) : resident_blocks<VT, 4, 2>(wpb);
+  return K == 8 ? resident_blocks<VT, 8, 1>(wpb) : resident_blocks<VT, 4, 1>(wpb);
+}
+
+int resident_for(int32_t vtype, int K, int pf, int wpb) {
   switch (vtype) {
-    case MSREP_F64: return K == 8 ? resident_blocks<MSREP_F64, 8>(wpb) : resident_blocks<MSREP_F64, 4>(wpb);
-    case MSREP_F32: return K == 8 ? resident_blocks<MSREP_F32, 8>(wpb) : resident_blocks<MSREP_F32, 4>(wpb);
-    default: return K == 8 ? resident_blocks<MSREP_BF16, 8>(wpb) : resident_blocks<MSREP_BF16, 4>(wpb);
+    case MSREP_F64: return resident_vt<MSREP_F64>(K, pf, wpb);
+    case MSREP_F32: return resident_vt<MSREP_F32>(K, pf, wpb);
+    default: return resident_vt<MSREP_BF16>(K, pf, wpb);
   }
 }
 
@@ -183,6 +201,8 @@ extern "C" msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
   P->vtype = mats[0].vtype;
   P->K = K;
   P->wpb = wpb;
+  // loads one chunk ahead unless the tune asks for two (more registers)
+  P->pf = tunes && tunes[0].pipeline == 2 ? 2 : 1;
   P->ws = static_cast<char *>(ws_d);
   P->L = L;
   P->n_items = L.n_items;
@@ -216,7 +236,7 @@ extern "C" msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, P->device) != hipSuccess)
     return bail(fail(MSREP_ERR_HIP, "hipGetDeviceProperties"));
-  int per_cu = resident_for(P->vtype, K, wpb);
+  int per_cu = resident_for(P->vtype, K, P->pf, wpb);
   if (per_cu < 1) per_cu = 1;
   int64_t waves = static_cast<int64_t>(per_cu) * wpb * prop.multiProcessorCount;
   waves = std::min<int64_t>({waves, kMaxWaves, std::max<int64_t>(1, L.n_items)});

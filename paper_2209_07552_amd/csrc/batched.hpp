@@ -2,6 +2,15 @@
 // persistent launch drains a list of (matrix, partition) work items, each
 // processed by the CSR wave routine, and one launch merges the rows split
 // between partitions of every matrix.
+//
+// Both callers describe their work items through a source type with
+//   __device__ void get(int64_t it, BItem &out) const;   // item it (it may
+//                                                        // differ per lane)
+//   __device__ void waves(int32_t w, int64_t &lo, int64_t &hi) const;
+//   int64_t n_items; int32_t n_waves;
+// The batched plan reads a precomputed item list from device memory; a
+// serving tick passes its active requests in the kernel arguments, so a tick
+// needs no table copy from the host.
 #pragma once
 
 #include "spmv_csr.hpp"
@@ -21,56 +30,202 @@ struct BatchXY {
   void *y;
 };
 
-// wave_begin[w] .. wave_begin[w+1]-1 are the work items of wavefront w.
-template <int VT, int K, bool BETA0>
-__global__ __launch_bounds__(512) void spmv_batched_persistent(
-    const BatchMat *__restrict__ mats, const BatchXY *__restrict__ xy,
-    const int2 *__restrict__ items, const int64_t *__restrict__ wave_begin, int32_t n_waves,
-    double alpha, double beta) {
+// One work item resolved: partition p of a matrix and its vectors.
+struct BItem {
+  const int32_t *col;
+  const void *val;
+  const msrep_part *parts;
+  const int32_t *lptr;
+  double *carry;
+  const void *x;
+  void *y;
+  int32_t m, n, np, p;
+};
+
+__device__ __forceinline__ void bitem_from(const BatchMat &M, const BatchXY &xy, int32_t p,
+                                           BItem &o) {
+  o.col = M.col;
+  o.val = M.val;
+  o.parts = M.parts;
+  o.lptr = M.lptr;
+  o.carry = M.carry;
+  o.x = xy.x;
+  o.y = xy.y;
+  o.m = M.m;
+  o.n = M.n;
+  o.np = M.np;
+  o.p = p;
+}
+
+// The batched plan's items: a device list of (matrix, partition) pairs and
+// equal-work runs of it, one per wavefront.
+struct PlanSrc {
+  const BatchMat *mats;
+  const BatchXY *xy;
+  const int2 *items;
+  const int64_t *wave_begin;  // n_waves + 1 entries
+  int64_t n_items;
+  int32_t n_waves, _pad;
+  __device__ void get(int64_t it, BItem &o) const {
+    const int2 wk = items[it];
+    bitem_from(mats[wk.x], xy[wk.x], wk.y, o);
+  }
+  __device__ void waves(int32_t w, int64_t &lo, int64_t &hi) const {
+    lo = uniform(wave_begin[w]);
+    hi = uniform(wave_begin[w + 1]);
+  }
+};
+
+// ------------------------------------------------------------- serving
+// A request slot of the server: its resident matrix, partitions, carries and
+// vectors.  Written once when the request is admitted.
+struct ServeSlot {
+  BatchMat M;
+  BatchXY xy;
+  int64_t rid;
+};
+
+constexpr int kTickMax = 240;  // requests per tick (the arguments stay below 4 KB)
+
+// One serving tick: the active requests' slots, the step each one runs, and
+// the prefix sums of their partition counts (item it belongs to request i
+// with begin[i] <= it < begin[i+1]).  Passed by value as kernel arguments.
+struct TickSrc {
+  const ServeSlot *table;
+  int64_t n_items;
+  int32_t n_waves, count;
+  int32_t slot[kTickMax];
+  int32_t step[kTickMax];
+  int32_t begin[kTickMax + 1];
+  __device__ int32_t request_of(int64_t it) const {
+    int32_t lo = 0, hi = count;  // begin[lo] <= it < begin[hi]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (begin[mid] <= it)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return lo;
+  }
+  __device__ void get(int64_t it, BItem &o) const {
+    const int32_t i = request_of(it);
+    const ServeSlot *S = table + slot[i];
+    bitem_from(S->M, S->xy, static_cast<int32_t>(it - begin[i]), o);
+  }
+  // equal item counts per wavefront (a request's partitions hold equal
+  // nonzeros, so items cost about the same)
+  __device__ void waves(int32_t w, int64_t &lo, int64_t &hi) const {
+    lo = n_items * w / n_waves;
+    hi = n_items * (w + 1) / n_waves;
+  }
+};
+
+// Resident wavefronts, each draining its run of work items.
+template <int VT, int K, bool BETA0, int PF, class Src>
+__global__ __launch_bounds__(512) void spmv_items_persistent(const Src src, double alpha,
+                                                            double beta) {
   using Tr = vt_traits<VT>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int wid = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
   const int w = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
-  if (w >= n_waves) return;
+  if (w >= src.n_waves) return;
   unsigned char *my = lds_raw + wid * seg_lds_per_wave<VT, K>();
-  const int64_t lo = uniform(wave_begin[w]), hi = uniform(wave_begin[w + 1]);
+  int64_t lo, hi;
+  src.waves(w, lo, hi);
   for (int64_t it = lo; it < hi; ++it) {
-    const int2 wk = items[it];
-    const int32_t k = uniform(wk.x), p = uniform(wk.y);
-    const BatchMat *M = mats + k;
-    const int32_t *col = uniform(M->col);
-    const typename Tr::V *val = static_cast<const typename Tr::V *>(uniform(M->val));
-    const msrep_part *parts = uniform(M->parts);
-    const int32_t *lptr = uniform(M->lptr);
-    const int32_t m = uniform(M->m), n = uniform(M->n), np = uniform(M->np);
-    double *carry = uniform(M->carry);
-    const typename Tr::T *x = static_cast<const typename Tr::T *>(uniform(xy[k].x));
-    typename Tr::T *y = static_cast<typename Tr::T *>(uniform(xy[k].y));
-    csr_partition<VT, K, BETA0>(col, val, parts, lptr, np, p, x, y, m, n, alpha, beta, carry, my);
+    BItem b;
+    src.get(it, b);
+    const int32_t m = uniform(b.m), n = uniform(b.n), np = uniform(b.np), p = uniform(b.p);
+    csr_partition<VT, K, BETA0, PF>(
+        uniform(b.col), static_cast<const typename Tr::V *>(uniform(b.val)), uniform(b.parts),
+        uniform(b.lptr), np, p, static_cast<const typename Tr::T *>(uniform(b.x)),
+        static_cast<typename Tr::T *>(uniform(b.y)), m, n, alpha, beta, uniform(b.carry), my);
     wave_lds_sync();
   }
 }
 
-// Boundary merge of every matrix: one thread per work item (see merge_rows).
-template <typename T, bool BETA0>
-__global__ __launch_bounds__(256) void merge_batched(const BatchMat *__restrict__ mats,
-                                                     const BatchXY *__restrict__ xy,
-                                                     const int2 *__restrict__ items,
-                                                     int64_t n_items, double alpha, double beta) {
-  const int64_t it = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (it >= n_items) return;
-  const int2 wk = items[it];
-  const BatchMat M = mats[wk.x];
-  const int32_t p = wk.y;
-  const msrep_part P = M.parts[p];
-  if (P.end_idx < P.start_idx || !P.end_flag) return;
-  if (P.start_flag && P.start_row == P.end_row) return;
-  const int32_t r = P.end_row;
-  const double tot = split_row_total(M.parts, M.np, M.carry, p, r);
-  if (r < 0 || r >= M.m) return;
-  T *y = static_cast<T *>(xy[wk.x].y);
-  y[r] = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(y[r]));
+// Boundary merge of every matrix at once: the segmented sum of merge_rows
+// (spmv_csr.hpp) run over the concatenated work items.  Chains never cross
+// matrices, since the first partition of a matrix has no start flag and so
+// starts a segment.  The thread of the item where a split row ends writes
+// that row of its matrix's y.
+template <class Src>
+__device__ __forceinline__ MSeg item_seg(const Src &src, int64_t q, BItem &b, MPart &P) {
+  src.get(q, b);
+  P = mpart_load(b.parts, b.p);
+  return mpart_seg(P, b.carry[2 * static_cast<int64_t>(b.p)],
+                   b.carry[2 * static_cast<int64_t>(b.p) + 1]);
+}
+
+template <typename T, bool BETA0, class Src>
+__global__ __launch_bounds__(kMergeBlock) void merge_items(const Src src, double alpha,
+                                                           double beta) {
+  __shared__ double sh_s[kMergeWaves], sh_c[kMergeWaves];
+  __shared__ int sh_f[kMergeWaves];
+  const int t = threadIdx.x;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kMergeBlock;
+  const int64_t q = base + t;
+  MPart P{0, -1, 0, 0};
+  BItem b{};
+  MSeg own{0.0, 0.0, 0};
+  double hd = 0.0;
+  if (q < src.n_items) {
+    own = item_seg(src, q, b, P);
+    hd = b.carry[2 * static_cast<int64_t>(b.p)];
+  }
+  // the 64 items just before the block, loaded up front by wave 0
+  const int64_t near = base > kWave ? base - kWave : 0;
+  MSeg look{0.0, 0.0, 0};
+  if (t < kWave && near + t < base) {
+    BItem bb;
+    MPart PP;
+    look = item_seg(src, near + t, bb, PP);
+  }
+  MSeg excl;
+  (void)block_mseg_scan(own, excl, sh_s, sh_c, sh_f);
+  const bool last = P.er >= P.sr && P.sf && !(P.ef && P.sr == P.er);  // a split row ends here
+  MSeg at = mseg_cat(excl, MSeg{hd, 0.0, 0});
+  const bool need = last && !at.f;  // the row began before this block
+  if (__syncthreads_or(need)) {
+    if (t < kWave) {
+      wave_mseg_scan(look);
+      if (t == kWave - 1) {
+        sh_s[0] = look.s;
+        sh_c[0] = look.c;
+        sh_f[0] = look.f;
+      }
+    }
+    __syncthreads();
+    MSeg acc{sh_s[0], sh_c[0], sh_f[0]};
+    __syncthreads();
+    constexpr int64_t kSpan = kMergeBlock * kMergeLook;
+    int64_t hi = near;
+    while (hi > 0 && !acc.f) {
+      const int64_t lo = hi > kSpan ? hi - kSpan : 0;
+      MSeg w{0.0, 0.0, 0};
+#pragma unroll
+      for (int j = 0; j < kMergeLook; ++j) {
+        const int64_t qq = lo + t * kMergeLook + j;
+        if (qq < hi) {
+          BItem bb;
+          MPart PP;
+          w = mseg_cat(w, item_seg(src, qq, bb, PP));
+        }
+      }
+      MSeg wex;
+      acc = mseg_cat(block_mseg_scan(w, wex, sh_s, sh_c, sh_f), acc);
+      hi = lo;
+    }
+    if (need) at = mseg_cat(acc, at);
+  }
+  if (!last) return;
+  const int32_t r = P.sr;
+  if (r < 0 || r >= b.m) return;
+  const double tot = at.s + at.c;
+  T *yr = static_cast<T *>(b.y) + r;
+  *yr = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(*yr));
 }
 
 // Contiguous runs of work items with about equal cost, one per wavefront:

@@ -1,5 +1,6 @@
-// msrep_serve: a continuous-batching server for the iterative-solver pattern
-// (a request = one pool matrix + `steps` SpMVs against fresh x vectors).
+// msrep_serve and the incremental server (msrep_server_*): continuous
+// batching for the iterative-solver pattern (a request = one pool matrix +
+// `steps` SpMVs against fresh x vectors).
 //
 //  * Residency: a pool matrix is uploaded into the caller's arena when a
 //    request needs it and stays resident (shared by every request on it) until
@@ -11,18 +12,27 @@
 //  * Continuous batching: every tick runs one step of every ready request in
 //    one persistent launch over all their equal-nnz partitions (the batched
 //    kernel), so requests that arrive while others run join the next tick.
+//    A request's device descriptor is written once, when it is admitted; a
+//    tick passes only the list of active slots and their steps, in the
+//    kernel arguments, so a tick costs three launches and one event record.
 //    Uploads and partition builds run on a copy stream, overlapping compute.
 //  * Each request's arithmetic depends only on its matrix, its partitions and
 //    its x: its results are the same alone and in any mix.
-// The scheduler is written against an executor interface; the HIP executor
-// drives the GPU, and a simulated executor (msrep_serve_simulate) runs the
-// same admission and batching logic on a virtual clock, for testing on a CPU.
+// One scheduler serves three drivers: msrep_serve replays a trace known in
+// advance on the GPU; msrep_server_* runs the scheduler on a thread of its
+// own and takes requests as they come (submit / poll); msrep_serve_simulate
+// replays a trace against a simulated device on a virtual clock, for testing
+// on a CPU.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -32,10 +42,11 @@
 namespace msrep {
 namespace {
 
-constexpr int kWpb = 4;     // wavefronts per workgroup of the serving kernels
-constexpr int kK = 4;       // nonzeros per lane per chunk
-constexpr int kRing = 4;    // tick tables in rotation (at most 2 ticks in flight)
+constexpr int kWpb = 4;      // wavefronts per workgroup of the serving kernels
+constexpr int kK = 4;        // nonzeros per lane per chunk
+constexpr int kRing = 4;     // tick events in rotation (at most kInflight ticks in flight)
 constexpr int kInflight = 2;
+constexpr int64_t kDefaultQueue = int64_t(1) << 20;  // incremental server's waiting requests
 
 // ------------------------------------------------------------ x generator
 // SplitMix64 output function (Steele, Lea, Flood 2014) applied to a key.
@@ -53,18 +64,16 @@ __host__ __device__ inline double x_value(uint64_t seed, int64_t rid, int32_t st
   return 2.0 * u - 1.0;
 }
 
-struct FillDesc {
-  void *x;
-  int64_t rid;
-  int32_t n, step;
-};
-
+// x of every request of a tick: block row i fills request i's x for its step.
 template <typename T>
-__global__ void fill_x(const FillDesc *__restrict__ d, uint64_t seed) {
-  const FillDesc f = d[blockIdx.y];
-  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < f.n;
+__global__ void fill_x_tick(const TickSrc src, uint64_t seed) {
+  const ServeSlot *S = src.table + src.slot[blockIdx.y];
+  T *x = static_cast<T *>(const_cast<void *>(S->xy.x));
+  const int32_t n = S->M.n, step = src.step[blockIdx.y];
+  const int64_t rid = S->rid;
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n;
        c += int64_t(gridDim.x) * blockDim.x)
-    static_cast<T *>(f.x)[c] = static_cast<T>(x_value(seed, f.rid, f.step, c));
+    x[c] = static_cast<T>(x_value(seed, rid, step, c));
 }
 
 // ------------------------------------------------------------------ arena
@@ -120,7 +129,7 @@ class Arena {
 };
 
 // ------------------------------------------------------ scheduler state
-enum State { kPending, kWaiting, kLoading, kReady, kDraining, kDone };
+enum State { kWaiting, kLoading, kReady, kDraining, kDone };
 
 struct Resident {  // a pool matrix in the arena
   bool present = false;
@@ -132,16 +141,24 @@ struct Resident {  // a pool matrix in the arena
 };
 
 struct Req {
-  int64_t idx = 0;
+  int64_t key = 0;        // trace index (replay) or submission number (server)
   msrep_request r{};
-  State st = kPending;
-  int32_t np = 1;
-  size_t off = 0, bytes = 0;          // x, y, parts, lptr, carry
-  size_t x_off, y_off, parts_off, lptr_off, carry_off;
-  int32_t enq = 0;                    // steps enqueued
+  void *y_host = nullptr; // last y copied here when it finishes (optional)
+  State st = kWaiting;
+  int32_t np = 1, slot = -1;
+  size_t off = 0, bytes = 0;  // x, y, parts, lptr, carry
+  size_t x_off = 0, y_off = 0, parts_off = 0, lptr_off = 0, carry_off = 0;
+  int32_t enq = 0;            // steps enqueued
   int64_t last_tick = -1;
-  double t_admit = 0, t_done = 0, ready_at = 0;
-  hipEvent_t ev{};                    // partitions built
+  double t_arrive = 0, t_admit = 0, t_done = 0, ready_at = 0;
+  hipEvent_t ev{};            // partitions and descriptor in place
+};
+
+struct Completion {
+  int64_t key, rid;
+  double t_arrive, t_admit, t_done;
+  msrep_status status;
+  int32_t matrix, steps;
 };
 
 size_t mat_bytes(const msrep_mat &A) {
@@ -169,8 +186,7 @@ void layout_req(Req &q, const msrep_mat &A) {
 struct Tick {
   int64_t id;
   std::vector<Req *> reqs;
-  double end = 0;          // simulated
-  hipEvent_t ev{};
+  double end = 0;  // simulated
 };
 
 // ------------------------------------------------------- HIP executor
@@ -180,63 +196,80 @@ struct HipExec {
   char *arena;
   hipStream_t copy{}, comp{};
   hipEvent_t t0{};
+  hipEvent_t tick_ev[kRing]{};
+  std::vector<hipEvent_t> ev_free;  // recycled per-request and per-matrix events
   std::chrono::steady_clock::time_point w0;
-  int32_t vtype;
-  // tick tables: device ring (carved from the arena) and pinned staging ring
-  size_t table_off = 0, table_bytes = 0;
-  char *staging = nullptr;
-  int64_t max_items = 0;
-  int32_t max_reqs = 0;
+  int32_t vtype, max_slots = 0;
+  size_t table_off = 0;
+  ServeSlot *slots_h = nullptr;  // pinned staging of the slot table
   int n_waves_max = 0;
 
   HipExec(const msrep_serve_cfg &c, const msrep_host_mat *p, int32_t vt)
       : cfg(c), pool(p), arena(static_cast<char *>(c.arena_d)), vtype(vt) {}
 
-  msrep_status init(Arena &A, int64_t items_cap, int32_t reqs_cap) {
-    max_items = items_cap;
-    max_reqs = reqs_cap;
+  size_t table_bytes() const { return align_up(sizeof(ServeSlot) * max_slots, 256); }
+
+  msrep_status init(Arena &A, int32_t slots) {
+    max_slots = slots;
     MSREP_HIP(hipStreamCreateWithFlags(&copy, hipStreamNonBlocking));
     MSREP_HIP(hipStreamCreateWithFlags(&comp, hipStreamNonBlocking));
     MSREP_HIP(hipEventCreate(&t0));
-    table_bytes = slot_bytes();
-    if (!A.alloc(table_bytes * kRing, &table_off))
-      return fail(MSREP_ERR_BUDGET, "msrep_serve: budget too small for the tick tables");
-    MSREP_HIP(hipHostMalloc(reinterpret_cast<void **>(&staging), table_bytes * kRing));
+    for (auto &e : tick_ev) MSREP_HIP(hipEventCreate(&e));
+    if (!A.alloc(table_bytes(), &table_off))
+      return fail(MSREP_ERR_BUDGET, "msrep_serve: budget too small for the slot table");
+    MSREP_HIP(hipHostMalloc(reinterpret_cast<void **>(&slots_h), table_bytes()));
+    std::memset(slots_h, 0, table_bytes());
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     MSREP_HIP(hipGetDevice(&dev));
     MSREP_HIP(hipGetDeviceProperties(&prop, dev));
-    const size_t lds = (vtype == MSREP_F64 ? seg_lds_per_wave<MSREP_F64, kK>()
-                                           : seg_lds_per_wave<MSREP_F32, kK>()) * kWpb;
     if (vtype == MSREP_F64)
       MSREP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, spmv_batched_persistent<MSREP_F64, kK, true>, kWpb * kWave, lds));
+          &per_cu, spmv_items_persistent<MSREP_F64, kK, true, 1, TickSrc>, kWpb * kWave,
+          seg_lds_per_wave<MSREP_F64, kK>() * kWpb));
     else
       MSREP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, spmv_batched_persistent<MSREP_F32, kK, true>, kWpb * kWave, lds));
+          &per_cu, spmv_items_persistent<MSREP_F32, kK, true, 1, TickSrc>, kWpb * kWave,
+          seg_lds_per_wave<MSREP_F32, kK>() * kWpb));
     n_waves_max = std::max(1, per_cu) * kWpb * prop.multiProcessorCount;
     MSREP_HIP(hipEventRecord(t0, comp));
     MSREP_HIP(hipEventSynchronize(t0));
     w0 = std::chrono::steady_clock::now();
     return MSREP_OK;
   }
-  size_t slot_bytes() const {
-    return align_up(sizeof(BatchMat) * max_reqs, 256) + align_up(sizeof(BatchXY) * max_reqs, 256) +
-           align_up(sizeof(FillDesc) * max_reqs, 256) + align_up(sizeof(int2) * max_items, 256) +
-           align_up(sizeof(int64_t) * (n_waves_cap() + 1), 256);
-  }
-  static int n_waves_cap() { return 16384; }
+  size_t reserved_bytes() const { return table_bytes(); }
   void shutdown() {
     if (copy) (void)hipStreamSynchronize(copy);
     if (comp) (void)hipStreamSynchronize(comp);
-    if (staging) (void)hipHostFree(staging);
+    if (slots_h) (void)hipHostFree(slots_h);
+    slots_h = nullptr;
+    for (auto &e : tick_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+    ev_free.clear();
     if (t0) (void)hipEventDestroy(t0);
     if (copy) (void)hipStreamDestroy(copy);
     if (comp) (void)hipStreamDestroy(comp);
+    t0 = nullptr;
+    copy = comp = nullptr;
   }
   double now() const {
     const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
     return s * cfg.time_scale;
+  }
+  msrep_status take_event(hipEvent_t *e) {
+    if (*e) return MSREP_OK;
+    if (!ev_free.empty()) {
+      *e = ev_free.back();
+      ev_free.pop_back();
+      return MSREP_OK;
+    }
+    MSREP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return MSREP_OK;
+  }
+  void give_event(hipEvent_t *e) {
+    if (*e) ev_free.push_back(*e);
+    *e = nullptr;
   }
   msrep_mat device_mat(int32_t k, const Resident &R) const {
     msrep_mat A = pool[k].A;
@@ -259,10 +292,13 @@ struct HipExec {
                                static_cast<size_t>(value_bytes(H.vtype)) * H.nnz,
                                hipMemcpyHostToDevice, copy));
     }
-    if (!R.ev) MSREP_HIP(hipEventCreateWithFlags(&R.ev, hipEventDisableTiming));
+    if (msrep_status st = take_event(&R.ev)) return st;
     MSREP_HIP(hipEventRecord(R.ev, copy));
     return MSREP_OK;
   }
+  void evicted(Resident &R) { give_event(&R.ev); }
+  // Partitions of the request's matrix and its slot descriptor, on the copy
+  // stream after the matrix upload.
   msrep_status prepare(Req &q, const Resident &R) {
     const msrep_mat D = device_mat(q.r.matrix, R);
     char *b = arena + q.off;
@@ -270,95 +306,79 @@ struct HipExec {
             &D, q.np, reinterpret_cast<msrep_part *>(b + q.parts_off),
             reinterpret_cast<int32_t *>(b + q.lptr_off), msrep_lptr_bound(D.m, q.np), nullptr, copy))
       return st;
-    if (!q.ev) MSREP_HIP(hipEventCreateWithFlags(&q.ev, hipEventDisableTiming));
+    ServeSlot &S = slots_h[q.slot];
+    S.M = BatchMat{D.idx, D.val, reinterpret_cast<const msrep_part *>(b + q.parts_off),
+                   reinterpret_cast<const int32_t *>(b + q.lptr_off), D.m, D.n, q.np, 0,
+                   reinterpret_cast<double *>(b + q.carry_off)};
+    S.xy = BatchXY{b + q.x_off, b + q.y_off};
+    S.rid = q.r.rid;
+    // the slot was last read by ticks that completed before it was freed
+    MSREP_HIP(hipMemcpyAsync(arena + table_off + sizeof(ServeSlot) * q.slot, &S, sizeof(ServeSlot),
+                             hipMemcpyHostToDevice, copy));
+    if (msrep_status st = take_event(&q.ev)) return st;
     MSREP_HIP(hipEventRecord(q.ev, copy));
     return MSREP_OK;
   }
   bool ready(Req &q) { return hipEventQuery(q.ev) == hipSuccess; }
+  void released(Req &q) { give_event(&q.ev); }
 
-  msrep_status launch(Tick &t, const std::vector<Resident> &res) {
-    const int slot = static_cast<int>(t.id % kRing);
-    char *hs = staging + slot * table_bytes;
-    char *ds = arena + table_off + slot * table_bytes;
-    const int32_t cnt = static_cast<int32_t>(t.reqs.size());
-    size_t o = 0;
-    BatchMat *hm = reinterpret_cast<BatchMat *>(hs + o);
-    const size_t om = o;
-    o += align_up(sizeof(BatchMat) * max_reqs, 256);
-    BatchXY *hxy = reinterpret_cast<BatchXY *>(hs + o);
-    const size_t oxy = o;
-    o += align_up(sizeof(BatchXY) * max_reqs, 256);
-    FillDesc *hf = reinterpret_cast<FillDesc *>(hs + o);
-    const size_t of = o;
-    o += align_up(sizeof(FillDesc) * max_reqs, 256);
-    int2 *hi = reinterpret_cast<int2 *>(hs + o);
-    const size_t oi = o;
-    o += align_up(sizeof(int2) * max_items, 256);
-    int64_t *hw = reinterpret_cast<int64_t *>(hs + o);
-    const size_t ow = o;
-    std::vector<int64_t> cost;
-    int64_t n_items = 0;
-    for (int32_t i = 0; i < cnt; ++i) {
-      Req &q = *t.reqs[i];
-      const msrep_mat D = device_mat(q.r.matrix, res[q.r.matrix]);
-      char *b = arena + q.off;
-      hm[i] = BatchMat{D.idx, D.val, reinterpret_cast<const msrep_part *>(b + q.parts_off),
-                       reinterpret_cast<const int32_t *>(b + q.lptr_off), D.m, D.n, q.np, 0,
-                       reinterpret_cast<double *>(b + q.carry_off)};
-      hxy[i] = BatchXY{b + q.x_off, b + q.y_off};
-      hf[i] = FillDesc{b + q.x_off, q.r.rid, D.n, q.enq};
-      for (int32_t p = 0; p < q.np; ++p) {
-        hi[n_items++] = int2{i, p};
-        cost.push_back(item_cost(D.nnz, D.m, q.np, p));
-      }
+  msrep_status launch(Tick &t, const std::vector<Resident> &) {
+    TickSrc src;
+    src.table = reinterpret_cast<const ServeSlot *>(arena + table_off);
+    src.count = static_cast<int32_t>(t.reqs.size());
+    int64_t items = 0;
+    int32_t max_n = 1;
+    for (int32_t i = 0; i < src.count; ++i) {
+      const Req &q = *t.reqs[i];
+      src.slot[i] = q.slot;
+      src.step[i] = q.enq;
+      src.begin[i] = static_cast<int32_t>(items);
+      items += q.np;
+      max_n = std::max(max_n, pool[q.r.matrix].A.n);
     }
-    const int32_t waves = static_cast<int32_t>(
-        std::min<int64_t>({static_cast<int64_t>(n_waves_max), n_waves_cap(), std::max<int64_t>(1, n_items)}));
-    equal_work_runs(cost.data(), n_items, waves, hw);
-    MSREP_HIP(hipMemcpyAsync(ds, hs, ow + sizeof(int64_t) * (waves + 1), hipMemcpyHostToDevice, comp));
-    const BatchMat *dm = reinterpret_cast<const BatchMat *>(ds + om);
-    const BatchXY *dxy = reinterpret_cast<const BatchXY *>(ds + oxy);
-    const FillDesc *df = reinterpret_cast<const FillDesc *>(ds + of);
-    const int2 *di = reinterpret_cast<const int2 *>(ds + oi);
-    const int64_t *dw = reinterpret_cast<const int64_t *>(ds + ow);
-    const int grid = (waves + kWpb - 1) / kWpb;
-    const int gm = static_cast<int>((n_items + 255) / 256);
+    src.begin[src.count] = static_cast<int32_t>(items);
+    src.n_items = items;
+    src.n_waves = static_cast<int32_t>(std::min<int64_t>(n_waves_max, std::max<int64_t>(1, items)));
+    const int grid = (src.n_waves + kWpb - 1) / kWpb;
+    const int gm = static_cast<int>((items + kMergeBlock - 1) / kMergeBlock);
+    const dim3 gf(static_cast<unsigned>(std::min(64, (max_n + 255) / 256)),
+                  static_cast<unsigned>(src.count));
     if (vtype == MSREP_F64) {
-      hipLaunchKernelGGL(fill_x<double>, dim3(16, cnt), dim3(256), 0, comp, df, cfg.seed);
-      hipLaunchKernelGGL((spmv_batched_persistent<MSREP_F64, kK, true>), dim3(grid), dim3(kWpb * kWave),
-                         (seg_lds_per_wave<MSREP_F64, kK>() * kWpb), comp, dm, dxy, di, dw, waves, 1.0, 0.0);
-      hipLaunchKernelGGL((merge_batched<double, true>), dim3(gm), dim3(256), 0, comp, dm, dxy, di,
-                         n_items, 1.0, 0.0);
+      hipLaunchKernelGGL(fill_x_tick<double>, gf, dim3(256), 0, comp, src, cfg.seed);
+      hipLaunchKernelGGL((spmv_items_persistent<MSREP_F64, kK, true, 1, TickSrc>), dim3(grid),
+                         dim3(kWpb * kWave), (seg_lds_per_wave<MSREP_F64, kK>() * kWpb), comp, src,
+                         1.0, 0.0);
+      hipLaunchKernelGGL((merge_items<double, true, TickSrc>), dim3(gm > 0 ? gm : 1),
+                         dim3(kMergeBlock), 0, comp, src, 1.0, 0.0);
     } else {
-      hipLaunchKernelGGL(fill_x<float>, dim3(16, cnt), dim3(256), 0, comp, df, cfg.seed);
-      hipLaunchKernelGGL((spmv_batched_persistent<MSREP_F32, kK, true>), dim3(grid), dim3(kWpb * kWave),
-                         (seg_lds_per_wave<MSREP_F32, kK>() * kWpb), comp, dm, dxy, di, dw, waves, 1.0, 0.0);
-      hipLaunchKernelGGL((merge_batched<float, true>), dim3(gm), dim3(256), 0, comp, dm, dxy, di,
-                         n_items, 1.0, 0.0);
+      hipLaunchKernelGGL(fill_x_tick<float>, gf, dim3(256), 0, comp, src, cfg.seed);
+      hipLaunchKernelGGL((spmv_items_persistent<MSREP_F32, kK, true, 1, TickSrc>), dim3(grid),
+                         dim3(kWpb * kWave), (seg_lds_per_wave<MSREP_F32, kK>() * kWpb), comp, src,
+                         1.0, 0.0);
+      hipLaunchKernelGGL((merge_items<float, true, TickSrc>), dim3(gm > 0 ? gm : 1),
+                         dim3(kMergeBlock), 0, comp, src, 1.0, 0.0);
     }
     MSREP_LAUNCHED("serve tick");
-    if (!t.ev) MSREP_HIP(hipEventCreate(&t.ev));
-    MSREP_HIP(hipEventRecord(t.ev, comp));
+    MSREP_HIP(hipEventRecord(tick_ev[t.id % kRing], comp));
     return MSREP_OK;
   }
   bool done(Tick &t, double *at) {
-    if (hipEventQuery(t.ev) != hipSuccess) return false;
+    hipEvent_t e = tick_ev[t.id % kRing];
+    if (hipEventQuery(e) != hipSuccess) return false;
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, t0, t.ev);
+    (void)hipEventElapsedTime(&ms, t0, e);
     *at = ms * 1e-3 * cfg.time_scale;
     return true;
   }
-  void release_tick(Tick &t) {
-    if (t.ev) (void)hipEventDestroy(t.ev);
-    t.ev = nullptr;
-  }
-  msrep_status keep_y(Req &q, msrep_result &res) {
-    if (!cfg.keep_y || !res.y_host) return MSREP_OK;
+  msrep_status keep_y(Req &q) {
+    if (!q.y_host) return MSREP_OK;
     const msrep_mat &H = pool[q.r.matrix].A;
-    MSREP_HIP(hipMemcpy(res.y_host, arena + q.off + q.y_off, vec_bytes(vtype) * static_cast<size_t>(H.m),
+    MSREP_HIP(hipMemcpy(q.y_host, arena + q.off + q.y_off, vec_bytes(vtype) * static_cast<size_t>(H.m),
                         hipMemcpyDeviceToHost));
     return MSREP_OK;
   }
+  // Nothing to do: spin while the device works, else sleep until the next
+  // arrival (at most 200 us, so that a late event is not missed for long).
   void idle(double until, bool busy) {
     const double wait = until - now();
     if (busy || wait <= 0) {
@@ -368,11 +388,8 @@ struct HipExec {
     const double s = std::min(wait / cfg.time_scale, 2e-4);
     std::this_thread::sleep_for(std::chrono::duration<double>(s));
   }
-  void free_events(std::vector<Resident> &res, std::vector<Req> &reqs) {
-    for (auto &r : res)
-      if (r.ev) (void)hipEventDestroy(r.ev);
-    for (auto &q : reqs)
-      if (q.ev) (void)hipEventDestroy(q.ev);
+  void release_all(std::vector<Resident> &res) {
+    for (auto &r : res) give_event(&r.ev);
   }
 };
 
@@ -386,7 +403,8 @@ struct SimExec {
   double upload_bw = 25e9, flop_rate = 5e11, tick_cost = 2e-5;
   int32_t vtype;
   SimExec(const msrep_host_mat *p, int32_t vt) : pool(p), vtype(vt) {}
-  msrep_status init(Arena &, int64_t, int32_t) { return MSREP_OK; }
+  msrep_status init(Arena &, int32_t) { return MSREP_OK; }
+  size_t reserved_bytes() const { return 0; }
   void shutdown() {}
   double now() const { return clock; }
   msrep_status upload(int32_t k, Resident &R) {
@@ -394,12 +412,14 @@ struct SimExec {
     R.ready_at = copy_free;
     return MSREP_OK;
   }
+  void evicted(Resident &) {}
   msrep_status prepare(Req &q, const Resident &R) {
     copy_free = std::max({copy_free, clock, R.ready_at}) + 5e-6;
     q.ready_at = copy_free;
     return MSREP_OK;
   }
   bool ready(Req &q) { return clock >= q.ready_at; }
+  void released(Req &) {}
   msrep_status launch(Tick &t, const std::vector<Resident> &) {
     double work = tick_cost;
     for (Req *q : t.reqs) work += 2.0 * static_cast<double>(pool[q->r.matrix].A.nnz) / flop_rate;
@@ -412,268 +432,358 @@ struct SimExec {
     *at = t.end;
     return true;
   }
-  void release_tick(Tick &) {}
-  msrep_status keep_y(Req &, msrep_result &) { return MSREP_OK; }
+  msrep_status keep_y(Req &) { return MSREP_OK; }
   // advance the virtual clock to the next thing that can happen
   double next_event = 0;
   void idle(double until, bool) { clock = std::max(clock, std::min(until, next_event)); }
-  void free_events(std::vector<Resident> &, std::vector<Req> &) {}
+  void release_all(std::vector<Resident> &) {}
 };
 
 // ------------------------------------------------------------ scheduler
-size_t ex_table_bytes(const HipExec &e) { return e.table_bytes * kRing; }
-size_t ex_table_bytes(const SimExec &) { return 0; }
-
+// Admission, residency, eviction and tick formation, independent of how
+// requests arrive and how the device is driven.
 template <class Exec>
-msrep_status run_server(Exec &ex, const msrep_serve_cfg &cfg, const msrep_host_mat *pool,
-                        int32_t pool_size, const msrep_request *trace, int64_t n_req,
-                        msrep_result *results, msrep_serve_stats *stats) {
-  Arena arena(cfg.budget_bytes);
-  std::vector<Resident> res(pool_size);
-  std::vector<Req> reqs(n_req);
-  int64_t max_np = 1;
-  for (int32_t k = 0; k < pool_size; ++k) {
-    const int64_t npw = pool[k].np > 0 ? 0 : std::max(1, cfg.nnz_per_wave);
-    const int64_t np = pool[k].np > 0 ? pool[k].np : std::max<int64_t>(1, (pool[k].A.nnz + npw - 1) / npw);
-    max_np = std::max(max_np, np);
-  }
-  const int32_t slots = cfg.max_slots;
-  if (msrep_status st = ex.init(arena, max_np * slots, slots)) return st;
-  for (int64_t i = 0; i < n_req; ++i) {
-    Req &q = reqs[i];
-    q.idx = i;
-    q.r = trace[i];
-    const msrep_host_mat &H = pool[q.r.matrix];
-    const int64_t npw = std::max(1, cfg.nnz_per_wave);
-    q.np = H.np > 0 ? H.np : static_cast<int32_t>(std::max<int64_t>(1, (H.A.nnz + npw - 1) / npw));
-    layout_req(q, H.A);
-  }
-  std::vector<int64_t> order(n_req);
-  for (int64_t i = 0; i < n_req; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int64_t a, int64_t b) { return trace[a].t_arrive < trace[b].t_arrive; });
-  std::deque<Req *> waiting;
-  std::vector<Req *> admitted;  // loading, ready or draining
-  std::deque<Tick> inflight;
-  int64_t next_arrival = 0, n_finished = 0, tick_id = 0, use_clock = 0;
-  int64_t ticks = 0;
-  int32_t peak_active = 0;
-  msrep_status err = MSREP_OK;
+class Scheduler {
+ public:
+  Scheduler(Exec &ex, const msrep_serve_cfg &cfg, const msrep_host_mat *pool, int32_t pool_size)
+      : ex_(ex), cfg_(cfg), pool_(pool), pool_size_(pool_size), arena_(cfg.budget_bytes),
+        res_(pool_size) {}
 
-  auto finish = [&](Req &q, msrep_status st, double t) {
-    q.st = kDone;
-    q.t_done = t;
-    results[q.idx].t_arrive = q.r.t_arrive;
-    results[q.idx].t_admit = q.t_admit;
-    results[q.idx].t_done = t;
-    results[q.idx].status = st;
-    ++n_finished;
-  };
-  while (n_finished < n_req && err == MSREP_OK) {
-    const double now = ex.now();
-    bool progressed = false;
-    // arrivals
-    while (next_arrival < n_req && trace[order[next_arrival]].t_arrive <= now) {
-      Req &q = reqs[order[next_arrival++]];
-      q.st = kWaiting;
-      waiting.push_back(&q);
-      progressed = true;
-    }
-    // admission, first come first served
-    while (!waiting.empty() && static_cast<int32_t>(admitted.size()) < slots) {
-      Req &q = *waiting.front();
-      Resident &R = res[q.r.matrix];
-      const size_t mb = mat_bytes(pool[q.r.matrix].A);
-      const size_t need = q.bytes + (R.present ? 0 : mb) + 512;
-      const size_t table = arena.cap() >= ex_table_bytes(ex) ? ex_table_bytes(ex) : arena.cap();
-      if (q.bytes + mb + 512 > arena.cap() - table) {  // can never fit
-        waiting.pop_front();
-        finish(q, MSREP_ERR_BUDGET, now);
-        progressed = true;
-        continue;
-      }
-      (void)need;
-      // make room: evict idle resident matrices, least recently used first
-      bool got = false;
-      for (;;) {
-        size_t mo = 0, ro = 0;
-        const bool need_mat = !R.present;
-        bool ok_mat = true;
-        if (need_mat) ok_mat = arena.alloc(mb, &mo);
-        bool ok_req = ok_mat && arena.alloc(q.bytes, &ro);
-        if (ok_mat && ok_req) {
-          if (need_mat) {
-            R.present = true;
-            R.off = mo;
-            R.bytes = mb;
-            if (msrep_status st = ex.upload(q.r.matrix, R)) {
-              err = st;
-              break;
-            }
-          }
-          q.off = ro;
-          got = true;
-          break;
-        }
-        if (ok_mat && need_mat) arena.release(mo);
-        int32_t victim = -1;
-        for (int32_t k = 0; k < pool_size; ++k)
-          if (res[k].present && res[k].refs == 0 && k != q.r.matrix &&
-              (victim < 0 || res[k].last_use < res[victim].last_use))
-            victim = k;
-        if (victim < 0) break;
-        arena.release(res[victim].off);
-        res[victim].present = false;
-      }
-      if (err) break;
-      if (!got) break;  // wait for running requests to free memory
-      R.refs++;
-      R.last_use = ++use_clock;
-      if (msrep_status st = ex.prepare(q, R)) {
-        err = st;
-        break;
-      }
-      q.st = kLoading;
-      q.t_admit = now;
-      waiting.pop_front();
-      admitted.push_back(&q);
-      progressed = true;
-    }
-    if (err) break;
-    for (Req *q : admitted)
-      if (q->st == kLoading && ex.ready(*q)) {
+  msrep_status init() {
+    if (msrep_status st = ex_.init(arena_, cfg_.max_slots)) return st;
+    for (int32_t s = cfg_.max_slots - 1; s >= 0; --s) free_slots_.push_back(s);
+    return MSREP_OK;
+  }
+  int32_t np_of(int32_t k) const {
+    const msrep_host_mat &H = pool_[k];
+    const int64_t npw = std::max(1, cfg_.nnz_per_wave);
+    return H.np > 0 ? H.np : static_cast<int32_t>(std::max<int64_t>(1, (H.A.nnz + npw - 1) / npw));
+  }
+  // A request arrives (at q->t_arrive on the scheduler's clock).
+  void arrive(std::unique_ptr<Req> q) {
+    q->np = np_of(q->r.matrix);
+    layout_req(*q, pool_[q->r.matrix].A);
+    q->st = kWaiting;
+    waiting_.push_back(q.get());
+    owned_.push_back(std::move(q));
+  }
+  bool device_busy() const { return !inflight_.empty(); }
+  bool empty() const { return waiting_.empty() && admitted_.empty() && inflight_.empty(); }
+  size_t waiting() const { return waiting_.size(); }
+  // The earliest time something in flight can change (simulated executor).
+  double next_event(double until) const {
+    double nx = until;
+    for (const Tick &t : inflight_) nx = std::min(nx, t.end);
+    for (Req *q : admitted_)
+      if (q->st == kLoading) nx = std::min(nx, q->ready_at);
+    return nx;
+  }
+
+  // One pass: admit, mark loaded requests ready, retire finished ticks,
+  // launch the next tick.  Returns whether anything happened.
+  bool step(msrep_status &err) {
+    const double now = ex_.now();
+    bool progressed = admit(now, err);
+    if (err) return progressed;
+    for (Req *q : admitted_)
+      if (q->st == kLoading && ex_.ready(*q)) {
         q->st = kReady;
         progressed = true;
       }
-    // completed ticks, oldest first
-    while (!inflight.empty()) {
+    while (!inflight_.empty()) {
       double at = 0;
-      if (!ex.done(inflight.front(), &at)) break;
-      Tick &t = inflight.front();
-      for (Req *q : t.reqs) {
+      if (!ex_.done(inflight_.front(), &at)) break;
+      Tick &t = inflight_.front();
+      for (Req *q : t.reqs)
         if (q->last_tick == t.id && q->enq == q->r.steps) {
-          if (msrep_status st = ex.keep_y(*q, results[q->idx])) err = st;
+          if (msrep_status st = ex_.keep_y(*q)) err = st;
           finish(*q, MSREP_OK, at);
-          res[q->r.matrix].refs--;
-          res[q->r.matrix].last_use = ++use_clock;
-          arena.release(q->off);
+          res_[q->r.matrix].refs--;
+          res_[q->r.matrix].last_use = ++use_clock_;
+          arena_.release(q->off);
+          free_slots_.push_back(q->slot);
+          ex_.released(*q);
         }
-      }
-      ex.release_tick(t);
-      inflight.pop_front();
-      admitted.erase(std::remove_if(admitted.begin(), admitted.end(),
-                                    [](Req *q) { return q->st == kDone; }),
-                     admitted.end());
+      inflight_.pop_front();
+      admitted_.erase(std::remove_if(admitted_.begin(), admitted_.end(),
+                                     [](Req *q) { return q->st == kDone; }),
+                      admitted_.end());
       progressed = true;
     }
-    // one step of every ready request
-    if (static_cast<int>(inflight.size()) < kInflight) {
+    if (err) return progressed;
+    if (static_cast<int>(inflight_.size()) < kInflight) {
       Tick t;
-      t.id = tick_id;
-      for (Req *q : admitted)
+      t.id = tick_id_;
+      // ready requests, at most kTickMax, taken round robin over the
+      // admitted list so that none waits more than one tick for a turn
+      const size_t na = admitted_.size();
+      for (size_t j = 0; j < na && static_cast<int>(t.reqs.size()) < kTickMax; ++j) {
+        Req *q = admitted_[(rr_ + j) % na];
         if (q->st == kReady && q->enq < q->r.steps) t.reqs.push_back(q);
+      }
+      if (na) rr_ = (rr_ + t.reqs.size()) % na;
       if (!t.reqs.empty()) {
-        peak_active = std::max(peak_active, static_cast<int32_t>(t.reqs.size()));
-        if (msrep_status st = ex.launch(t, res)) {
+        peak_active_ = std::max(peak_active_, static_cast<int32_t>(t.reqs.size()));
+        if (msrep_status st = ex_.launch(t, res_)) {
           err = st;
-          break;
+          return progressed;
         }
         for (Req *q : t.reqs) {
           q->enq++;
           q->last_tick = t.id;
           if (q->enq == q->r.steps) q->st = kDraining;
         }
-        inflight.push_back(std::move(t));
-        ++tick_id;
-        ++ticks;
+        inflight_.push_back(std::move(t));
+        ++tick_id_;
+        ++ticks_;
         progressed = true;
       }
     }
-    if (!progressed) {
-      const double until = next_arrival < n_req ? trace[order[next_arrival]].t_arrive : now + 1.0;
-      if constexpr (std::is_same_v<Exec, SimExec>) {
-        double nx = until;
-        for (const Tick &t : inflight) nx = std::min(nx, t.end);
-        for (Req *q : admitted)
-          if (q->st == kLoading) nx = std::min(nx, q->ready_at);
-        ex.next_event = nx;
-      }
-      ex.idle(until, !inflight.empty());
-    }
+    return progressed;
   }
-  ex.shutdown();
-  ex.free_events(res, reqs);
-  if (err) return err;
-  // statistics
+
+  // Completions since the last call (their Req records are freed).
+  std::vector<Completion> take_completed() {
+    std::vector<Completion> out;
+    out.swap(done_);
+    owned_.erase(std::remove_if(owned_.begin(), owned_.end(),
+                                [](const std::unique_ptr<Req> &q) { return q->st == kDone; }),
+                 owned_.end());
+    return out;
+  }
+  void shutdown() {
+    ex_.shutdown();
+    ex_.release_all(res_);
+  }
+  int64_t ticks() const { return ticks_; }
+  int32_t peak_active() const { return peak_active_; }
+  size_t peak_bytes() const { return arena_.peak(); }
+
+ private:
+  void finish(Req &q, msrep_status st, double t) {
+    q.st = kDone;
+    q.t_done = t;
+    done_.push_back(Completion{q.key, q.r.rid, q.t_arrive, q.t_admit, t, st, q.r.matrix,
+                               q.r.steps});
+  }
+  // first come, first served
+  bool admit(double now, msrep_status &err) {
+    bool progressed = false;
+    while (!waiting_.empty() && !free_slots_.empty()) {
+      Req &q = *waiting_.front();
+      Resident &R = res_[q.r.matrix];
+      const size_t mb = mat_bytes(pool_[q.r.matrix].A);
+      const size_t table = std::min(arena_.cap(), ex_.reserved_bytes());
+      if (q.bytes + mb + 512 > arena_.cap() - table) {  // can never fit
+        waiting_.pop_front();
+        finish(q, MSREP_ERR_BUDGET, now);
+        progressed = true;
+        continue;
+      }
+      // make room: evict idle resident matrices, least recently used first
+      bool got = false;
+      for (;;) {
+        size_t mo = 0, ro = 0;
+        const bool need_mat = !R.present;
+        bool ok_mat = true;
+        if (need_mat) ok_mat = arena_.alloc(mb, &mo);
+        const bool ok_req = ok_mat && arena_.alloc(q.bytes, &ro);
+        if (ok_mat && ok_req) {
+          if (need_mat) {
+            R.present = true;
+            R.off = mo;
+            R.bytes = mb;
+            if (msrep_status st = ex_.upload(q.r.matrix, R)) {
+              err = st;
+              return progressed;
+            }
+          }
+          q.off = ro;
+          got = true;
+          break;
+        }
+        if (ok_mat && need_mat) arena_.release(mo);
+        int32_t victim = -1;
+        for (int32_t k = 0; k < pool_size_; ++k)
+          if (res_[k].present && res_[k].refs == 0 && k != q.r.matrix &&
+              (victim < 0 || res_[k].last_use < res_[victim].last_use))
+            victim = k;
+        if (victim < 0) break;
+        arena_.release(res_[victim].off);
+        res_[victim].present = false;
+        ex_.evicted(res_[victim]);
+      }
+      if (!got) break;  // wait for running requests to free memory
+      R.refs++;
+      R.last_use = ++use_clock_;
+      q.slot = free_slots_.back();
+      free_slots_.pop_back();
+      if (msrep_status st = ex_.prepare(q, R)) {
+        err = st;
+        return progressed;
+      }
+      q.st = kLoading;
+      q.t_admit = now;
+      waiting_.pop_front();
+      admitted_.push_back(&q);
+      progressed = true;
+    }
+    return progressed;
+  }
+
+  Exec &ex_;
+  const msrep_serve_cfg &cfg_;
+  const msrep_host_mat *pool_;
+  int32_t pool_size_;
+  Arena arena_;
+  std::vector<Resident> res_;
+  std::vector<std::unique_ptr<Req>> owned_;
+  std::deque<Req *> waiting_;
+  std::vector<Req *> admitted_;  // loading, ready or draining
+  std::deque<Tick> inflight_;
+  std::vector<int32_t> free_slots_;
+  std::vector<Completion> done_;
+  int64_t tick_id_ = 0, ticks_ = 0, use_clock_ = 0;
+  size_t rr_ = 0;
+  int32_t peak_active_ = 0;
+};
+
+// Latency statistics over completions.
+void fill_stats(const std::vector<Completion> &all, const msrep_host_mat *pool, int64_t ticks,
+                int32_t peak_active, size_t peak_bytes, msrep_serve_stats *stats) {
+  if (!stats) return;
   std::vector<double> lat;
   double first = 1e300, last = 0, flops = 0;
   int64_t steps = 0, failed = 0;
-  for (int64_t i = 0; i < n_req; ++i) {
-    first = std::min(first, trace[i].t_arrive);
-    if (results[i].status != MSREP_OK) {
+  for (const Completion &c : all) {
+    first = std::min(first, c.t_arrive);
+    if (c.status != MSREP_OK) {
       ++failed;
       continue;
     }
-    lat.push_back((results[i].t_done - results[i].t_arrive) * 1e3);
-    last = std::max(last, results[i].t_done);
-    steps += trace[i].steps;
-    flops += 2.0 * static_cast<double>(pool[trace[i].matrix].A.nnz) * trace[i].steps;
+    lat.push_back((c.t_done - c.t_arrive) * 1e3);
+    last = std::max(last, c.t_done);
+    steps += c.steps;
+    flops += 2.0 * static_cast<double>(pool[c.matrix].A.nnz) * c.steps;
   }
-  if (stats) {
-    std::memset(stats, 0, sizeof *stats);
-    std::sort(lat.begin(), lat.end());
-    auto pct = [&](double p) {
-      if (lat.empty()) return 0.0;
-      const size_t i = static_cast<size_t>(std::ceil(p * lat.size())) - 1;
-      return lat[std::min(i, lat.size() - 1)];
-    };
-    const double span = lat.empty() ? 0.0 : std::max(last - first, 1e-12);
-    stats->p50_ms = pct(0.50);
-    stats->p99_ms = pct(0.99);
-    stats->max_ms = lat.empty() ? 0.0 : lat.back();
-    double sum = 0;
-    for (double v : lat) sum += v;
-    stats->mean_ms = lat.empty() ? 0.0 : sum / lat.size();
-    stats->makespan_s = span;
-    stats->req_per_s = span > 0 ? lat.size() / span : 0.0;
-    stats->spmv_per_s = span > 0 ? steps / span : 0.0;
-    stats->gflops = span > 0 ? flops / span / 1e9 : 0.0;
-    stats->n_done = static_cast<int64_t>(lat.size());
-    stats->n_failed = failed;
-    stats->ticks = ticks;
-    stats->peak_bytes = static_cast<int64_t>(arena.peak());
-    stats->peak_active = peak_active;
+  std::memset(stats, 0, sizeof *stats);
+  std::sort(lat.begin(), lat.end());
+  auto pct = [&](double p) {
+    if (lat.empty()) return 0.0;
+    const size_t i = static_cast<size_t>(std::ceil(p * lat.size())) - 1;
+    return lat[std::min(i, lat.size() - 1)];
+  };
+  const double span = lat.empty() ? 0.0 : std::max(last - first, 1e-12);
+  stats->p50_ms = pct(0.50);
+  stats->p99_ms = pct(0.99);
+  stats->max_ms = lat.empty() ? 0.0 : lat.back();
+  double sum = 0;
+  for (double v : lat) sum += v;
+  stats->mean_ms = lat.empty() ? 0.0 : sum / lat.size();
+  stats->makespan_s = span;
+  stats->req_per_s = span > 0 ? lat.size() / span : 0.0;
+  stats->spmv_per_s = span > 0 ? steps / span : 0.0;
+  stats->gflops = span > 0 ? flops / span / 1e9 : 0.0;
+  stats->n_done = static_cast<int64_t>(lat.size());
+  stats->n_failed = failed;
+  stats->ticks = ticks;
+  stats->peak_bytes = static_cast<int64_t>(peak_bytes);
+  stats->peak_active = peak_active;
+}
+
+// Replay of a trace known in advance: requests arrive at their trace times.
+template <class Exec>
+msrep_status replay(Exec &ex, const msrep_serve_cfg &cfg, const msrep_host_mat *pool,
+                    int32_t pool_size, const msrep_request *trace, int64_t n_req,
+                    msrep_result *results, msrep_serve_stats *stats) {
+  Scheduler<Exec> sch(ex, cfg, pool, pool_size);
+  if (msrep_status st = sch.init()) {
+    sch.shutdown();
+    return st;
   }
+  std::vector<int64_t> order(n_req);
+  for (int64_t i = 0; i < n_req; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return trace[a].t_arrive < trace[b].t_arrive; });
+  std::vector<Completion> all;
+  all.reserve(n_req);
+  int64_t next = 0;
+  msrep_status err = MSREP_OK;
+  while (static_cast<int64_t>(all.size()) < n_req && err == MSREP_OK) {
+    const double now = ex.now();
+    bool progressed = false;
+    while (next < n_req && trace[order[next]].t_arrive <= now) {
+      const int64_t i = order[next++];
+      auto q = std::make_unique<Req>();
+      q->key = i;
+      q->r = trace[i];
+      q->t_arrive = trace[i].t_arrive;
+      q->y_host = cfg.keep_y ? results[i].y_host : nullptr;
+      sch.arrive(std::move(q));
+      progressed = true;
+    }
+    progressed |= sch.step(err);
+    for (const Completion &c : sch.take_completed()) {
+      msrep_result &r = results[c.key];
+      r.t_arrive = c.t_arrive;
+      r.t_admit = c.t_admit;
+      r.t_done = c.t_done;
+      r.status = c.status;
+      all.push_back(c);
+    }
+    if (!progressed && err == MSREP_OK) {
+      const double until = next < n_req ? trace[order[next]].t_arrive : now + 1.0;
+      if constexpr (std::is_same_v<Exec, SimExec>) ex.next_event = sch.next_event(until);
+      ex.idle(until, sch.device_busy());
+    }
+  }
+  sch.shutdown();
+  if (err) return err;
+  fill_stats(all, pool, sch.ticks(), sch.peak_active(), sch.peak_bytes(), stats);
   return ok();
+}
+
+msrep_status check_cfg_pool(const msrep_serve_cfg *cfg, const msrep_host_mat *pool,
+                            int32_t pool_size, bool need_arena, const char *who) {
+  if (!cfg || !pool || pool_size <= 0)
+    return fail(MSREP_ERR_ARG, "%s: missing configuration or pool", who);
+  if (need_arena && !cfg->arena_d) return fail(MSREP_ERR_ARG, "%s: arena_d is NULL", who);
+  if (cfg->max_slots < 1 || cfg->max_slots > 4096)
+    return fail(MSREP_ERR_ARG, "%s: max_slots must be 1..4096", who);
+  if (!(cfg->time_scale > 0)) return fail(MSREP_ERR_ARG, "%s: time_scale must be > 0", who);
+  if (cfg->max_queue < 0) return fail(MSREP_ERR_ARG, "%s: max_queue must be >= 0", who);
+  const int32_t vt = pool[0].A.vtype;
+  if (vt != MSREP_F64 && vt != MSREP_F32)
+    return fail(MSREP_ERR_UNSUPPORTED, "%s: pool matrices must be F64 or F32", who);
+  for (int32_t k = 0; k < pool_size; ++k) {
+    const msrep_mat &A = pool[k].A;
+    if (A.fmt != MSREP_CSR || A.vtype != vt)
+      return fail(MSREP_ERR_ARG, "%s: pool matrix %d must be CSR of the pool's value type", who, k);
+    if (A.m < 0 || A.n < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31) || A.n >= (1 << 24) ||
+        pool[k].np < 0)
+      return fail(MSREP_ERR_ARG, "%s: pool matrix %d has an unsupported shape", who, k);
+    if (need_arena && (!A.ptr || (A.nnz > 0 && (!A.idx || !A.val))))
+      return fail(MSREP_ERR_ARG, "%s: pool matrix %d has NULL arrays", who, k);
+  }
+  return MSREP_OK;
+}
+
+msrep_status check_request(const msrep_request &r, int32_t pool_size, const char *who,
+                           long long i) {
+  if (r.matrix < 0 || r.matrix >= pool_size || r.steps < 1 || r.steps > 65535 || r.rid < 0 ||
+      r.rid >= (int64_t(1) << 24))
+    return fail(MSREP_ERR_ARG, "%s: request %lld is malformed", who, i);
+  return MSREP_OK;
 }
 
 msrep_status check_serve_args(const msrep_serve_cfg *cfg, const msrep_host_mat *pool,
                               int32_t pool_size, const msrep_request *trace, int64_t n_req,
                               msrep_result *results, bool need_arena) {
-  if (!cfg || !pool || pool_size <= 0 || (n_req > 0 && (!trace || !results)) || n_req < 0)
-    return fail(MSREP_ERR_ARG, "msrep_serve: missing configuration, pool, trace or results");
-  if (need_arena && !cfg->arena_d) return fail(MSREP_ERR_ARG, "msrep_serve: arena_d is NULL");
-  if (cfg->max_slots < 1 || cfg->max_slots > 4096)
-    return fail(MSREP_ERR_ARG, "msrep_serve: max_slots must be 1..4096");
-  if (!(cfg->time_scale > 0)) return fail(MSREP_ERR_ARG, "msrep_serve: time_scale must be > 0");
-  const int32_t vt = pool[0].A.vtype;
-  if (vt != MSREP_F64 && vt != MSREP_F32)
-    return fail(MSREP_ERR_UNSUPPORTED, "msrep_serve: pool matrices must be F64 or F32");
-  for (int32_t k = 0; k < pool_size; ++k) {
-    const msrep_mat &A = pool[k].A;
-    if (A.fmt != MSREP_CSR || A.vtype != vt)
-      return fail(MSREP_ERR_ARG, "msrep_serve: pool matrix %d must be CSR of the pool's value type", k);
-    if (A.m < 0 || A.n < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31) || A.n >= (1 << 24))
-      return fail(MSREP_ERR_ARG, "msrep_serve: pool matrix %d has an unsupported shape", k);
-    if (need_arena && (!A.ptr || (A.nnz > 0 && (!A.idx || !A.val))))
-      return fail(MSREP_ERR_ARG, "msrep_serve: pool matrix %d has NULL arrays", k);
-  }
-  for (int64_t i = 0; i < n_req; ++i) {
-    const msrep_request &r = trace[i];
-    if (r.matrix < 0 || r.matrix >= pool_size || r.steps < 1 || r.steps > 65535 || r.rid < 0 ||
-        r.rid >= (int64_t(1) << 24))
-      return fail(MSREP_ERR_ARG, "msrep_serve: request %lld is malformed", static_cast<long long>(i));
-  }
+  if (n_req < 0 || (n_req > 0 && (!trace || !results)))
+    return fail(MSREP_ERR_ARG, "msrep_serve: missing trace or results");
+  if (msrep_status st = check_cfg_pool(cfg, pool, pool_size, need_arena, "msrep_serve")) return st;
+  for (int64_t i = 0; i < n_req; ++i)
+    if (msrep_status st = check_request(trace[i], pool_size, "msrep_serve", i)) return st;
   return MSREP_OK;
 }
 
@@ -687,7 +797,7 @@ extern "C" msrep_status msrep_serve(const msrep_serve_cfg *cfg, const msrep_host
                                     msrep_result *results, msrep_serve_stats *stats) {
   if (msrep_status st = check_serve_args(cfg, pool, pool_size, trace, n_req, results, true)) return st;
   HipExec ex(*cfg, pool, pool[0].A.vtype);
-  return run_server(ex, *cfg, pool, pool_size, trace, n_req, results, stats);
+  return replay(ex, *cfg, pool, pool_size, trace, n_req, results, stats);
 }
 
 extern "C" msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
@@ -701,7 +811,169 @@ extern "C" msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
   if (upload_bytes_per_s > 0) ex.upload_bw = upload_bytes_per_s;
   if (flops_per_s > 0) ex.flop_rate = flops_per_s;
   if (tick_seconds >= 0) ex.tick_cost = tick_seconds;
-  return run_server(ex, *cfg, pool, pool_size, trace, n_req, results, stats);
+  return replay(ex, *cfg, pool, pool_size, trace, n_req, results, stats);
+}
+
+// ------------------------------------------------------ incremental server
+// The scheduler on a thread of its own; submit() hands requests over through
+// an inbox, completions come back through an outbox that poll() drains.
+struct msrep_server_s {
+  msrep_serve_cfg cfg{};
+  std::vector<msrep_host_mat> pool;
+  int device = 0;
+  std::unique_ptr<HipExec> ex;
+  std::unique_ptr<Scheduler<HipExec>> sch;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_in, cv_out;
+  std::deque<std::unique_ptr<Req>> inbox;
+  std::deque<Completion> outbox;
+  std::vector<Completion> all;  // every completion, for the final statistics
+  int64_t submitted = 0, waiting = 0;  // waiting: admission queue (inbox not included)
+  bool stop = false;
+  msrep_status err = MSREP_OK;
+  std::string err_text;
+
+  void run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+      std::vector<std::unique_ptr<Req>> in;
+      bool stopping;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        while (!inbox.empty()) {
+          in.push_back(std::move(inbox.front()));
+          inbox.pop_front();
+        }
+        stopping = stop;
+      }
+      for (auto &q : in) {
+        q->t_arrive = ex->now();
+        sch->arrive(std::move(q));
+      }
+      msrep_status e = MSREP_OK;
+      bool progressed = sch->step(e) || !in.empty();
+      std::vector<Completion> c = sch->take_completed();
+      if (!c.empty() || e) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Completion &x : c) {
+          outbox.push_back(x);
+          all.push_back(x);
+        }
+        waiting = static_cast<int64_t>(sch->waiting());
+        if (e) {
+          err = e;
+          err_text = last_error();
+        }
+      } else {
+        std::lock_guard<std::mutex> lk(mu);
+        waiting = static_cast<int64_t>(sch->waiting());
+      }
+      if (!c.empty() || e) cv_out.notify_all();
+      if (e) break;
+      if (stopping && sch->empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (inbox.empty()) break;
+        continue;
+      }
+      if (!progressed) {
+        if (sch->device_busy()) {
+          std::this_thread::yield();
+        } else {
+          std::unique_lock<std::mutex> lk(mu);
+          cv_in.wait_for(lk, std::chrono::microseconds(200),
+                         [&] { return !inbox.empty() || stop; });
+        }
+      }
+    }
+    cv_out.notify_all();
+  }
+};
+
+extern "C" msrep_status msrep_server_create(const msrep_serve_cfg *cfg, const msrep_host_mat *pool,
+                                            int32_t pool_size, msrep_server *out) {
+  const char *who = "msrep_server_create";
+  if (!out) return fail(MSREP_ERR_ARG, "%s: out is NULL", who);
+  *out = nullptr;
+  if (msrep_status st = check_cfg_pool(cfg, pool, pool_size, true, who)) return st;
+  auto s = std::make_unique<msrep_server_s>();
+  s->cfg = *cfg;
+  s->pool.assign(pool, pool + pool_size);
+  MSREP_HIP(hipGetDevice(&s->device));
+  s->ex = std::make_unique<HipExec>(s->cfg, s->pool.data(), pool[0].A.vtype);
+  s->sch = std::make_unique<Scheduler<HipExec>>(*s->ex, s->cfg, s->pool.data(), pool_size);
+  if (msrep_status st = s->sch->init()) {
+    s->sch->shutdown();
+    return st;
+  }
+  msrep_server_s *raw = s.get();
+  try {
+    s->worker = std::thread([raw] { raw->run(); });
+  } catch (...) {
+    s->sch->shutdown();
+    return fail(MSREP_ERR_ARG, "%s: cannot start the scheduler thread", who);
+  }
+  *out = s.release();
+  return ok();
+}
+
+extern "C" msrep_status msrep_server_submit(msrep_server s, const msrep_request *req,
+                                            void *y_host) {
+  const char *who = "msrep_server_submit";
+  if (!s || !req) return fail(MSREP_ERR_ARG, "%s: server or request is NULL", who);
+  if (msrep_status st = check_request(*req, static_cast<int32_t>(s->pool.size()), who, 0)) return st;
+  auto q = std::make_unique<Req>();
+  q->r = *req;
+  q->y_host = y_host;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->err) return fail(s->err, "%s: the server stopped: %s", who, s->err_text.c_str());
+    if (s->stop) return fail(MSREP_ERR_ARG, "%s: the server is being destroyed", who);
+    const int64_t cap = s->cfg.max_queue > 0 ? s->cfg.max_queue : kDefaultQueue;
+    if (s->waiting + static_cast<int64_t>(s->inbox.size()) >= cap)
+      return fail(MSREP_ERR_BUSY, "%s: %lld requests already wait", who,
+                  static_cast<long long>(cap));
+    q->key = s->submitted++;
+    s->inbox.push_back(std::move(q));
+  }
+  s->cv_in.notify_one();
+  return ok();
+}
+
+extern "C" int64_t msrep_server_poll(msrep_server s, msrep_completion *out, int64_t cap,
+                                     int32_t timeout_ms) {
+  if (!s || (cap > 0 && !out) || cap < 0)
+    return fail(MSREP_ERR_ARG, "msrep_server_poll: server or output is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->outbox.empty() && timeout_ms > 0 && !s->err)
+    s->cv_out.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                       [&] { return !s->outbox.empty() || s->err; });
+  int64_t n = 0;
+  while (n < cap && !s->outbox.empty()) {
+    const Completion &c = s->outbox.front();
+    out[n++] = msrep_completion{c.rid, c.t_arrive, c.t_admit, c.t_done, c.status, 0};
+    s->outbox.pop_front();
+  }
+  if (n == 0 && s->err) return fail(s->err, "msrep_server_poll: %s", s->err_text.c_str());
+  return n;
+}
+
+extern "C" msrep_status msrep_server_destroy(msrep_server s, msrep_serve_stats *stats) {
+  if (!s) return ok();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_in.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  s->sch->shutdown();
+  const msrep_status err = s->err;
+  const std::string text = s->err_text;
+  fill_stats(s->all, s->pool.data(), s->sch->ticks(), s->sch->peak_active(), s->sch->peak_bytes(),
+             stats);
+  delete s;
+  if (err) return fail(err, "msrep_server_destroy: the server had stopped: %s", text.c_str());
+  return ok();
 }
 
 extern "C" double msrep_serve_x_value(uint64_t seed, int64_t rid, int32_t step, int64_t c) {

@@ -472,52 +472,6 @@ __global__ __launch_bounds__(512) void spmv_csr_seg(
                                     lds_raw + wid * seg_lds_per_wave<VT, K>());
 }
 
-// Boundary merge of the batched paths (one thread per work item, see
-// merge_batched).  Total of a row split across partitions, owned by partition p (the one
-// holding the row's first piece): p's tail plus the heads of the following
-// partitions that continue row r, added in partition order with TwoSum.  The
-// chain is read kChain partitions per round (only their row and flag words,
-// 16 bytes each, and their head sums), so a row spanning many partitions
-// costs a few dependent memory rounds, not one per partition.  An empty
-// partition has end_row = start_row - 1.
-constexpr int kChain = 8;
-
-__device__ __forceinline__ double split_row_total(const msrep_part *__restrict__ parts, int32_t np,
-                                                  const double *__restrict__ carry, int32_t p,
-                                                  int32_t r) {
-  double s = carry[2 * static_cast<int64_t>(p) + 1], c = 0.0;
-  bool going = true;
-  for (int32_t q0 = p + 1; going && q0 < np; q0 += kChain) {
-    int4 f[kChain];  // start_row, end_row, start_flag, end_flag
-    double h[kChain];
-#pragma unroll
-    for (int b = 0; b < kChain; ++b) {
-      const int32_t q = q0 + b < np ? q0 + b : np - 1;  // in bounds; unused past np
-      const int32_t *w = &parts[q].start_row;  // 8-byte aligned (40-byte records)
-      f[b] = make_int4(w[0], w[1], w[2], w[3]);
-      h[b] = carry[2 * static_cast<int64_t>(q)];
-    }
-#pragma unroll
-    for (int b = 0; b < kChain; ++b) {
-      if (!going) break;
-      if (q0 + b >= np) {
-        going = false;
-        break;
-      }
-      if (f[b].y < f[b].x) continue;  // empty partition
-      if (!f[b].z || f[b].x != r) {
-        going = false;
-        break;
-      }
-      double e;
-      two_sum(s, h[b], s, e);
-      c += e;
-      if (!(f[b].w && f[b].y == r)) going = false;  // the row's last piece
-    }
-  }
-  return s + c;
-}
-
 // ---- boundary merge for the row-split formats (CSR, COO) ----
 // The partial sums of split rows are combined as a segmented sum over the
 // partitions in partition order (msRep Algorithm 3 merging step, Sec. 4.3).

@@ -1,4 +1,5 @@
-"""Binding of msrep_serve / msrep_serve_simulate (argument marshalling only).
+"""Binding of msrep_serve / msrep_serve_simulate and of the incremental
+server msrep_server_* (argument marshalling only).
 
 A pool entry is a host CSR matrix (ptr, col, val numpy arrays, FP64 or FP32
 values).  For msrep_serve the arrays are copied once into pinned host memory
@@ -14,8 +15,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _abi
-from ._abi import F32, F64, MsrepError, _check, _HostMat, _Mat, _Request, _Result, _ServeCfg, \
-    _ServeStats, load_library
+from ._abi import F32, F64, MsrepError, _check, _Completion, _HostMat, _Mat, _Request, _Result, \
+    _ServeCfg, _ServeStats, load_library
 
 
 @dataclass
@@ -57,6 +58,106 @@ def x_value(seed, rid, step, c):
     L = load_library()
     _bind(L)
     return float(L.msrep_serve_x_value(seed, rid, step, c))
+
+
+def _host_pool(pool, vtype, pinned):
+    """(array of msrep_host_mat, the host arrays it points into)."""
+    keep = []
+    hm = (_HostMat * len(pool))()
+    vdt = np.float64 if vtype == F64 else np.float32
+    for k, A in enumerate(pool):
+        ptr = np.ascontiguousarray(A.ptr, np.int32)
+        col = np.ascontiguousarray(A.col, np.int32)
+        val = np.ascontiguousarray(A.val, vdt)
+        if pinned:  # pinned host copies, so that uploads are asynchronous
+            import torch
+            arrs = [torch.from_numpy(a).pin_memory() for a in (ptr, col, val)]
+            keep.extend(arrs)
+            pp, cp, vp = (a.data_ptr() for a in arrs)
+        else:
+            keep.extend((ptr, col, val))
+            pp, cp, vp = ptr.ctypes.data, col.ctypes.data, val.ctypes.data
+        hm[k].A = _Mat(0, vtype, A.m, A.n, int(ptr[-1]), pp, cp, None, vp)
+        hm[k].np = 0
+    return hm, keep
+
+
+@dataclass
+class Completion:
+    rid: int
+    t_arrive: float
+    t_admit: float
+    t_done: float
+    status: int
+
+
+class Server:
+    """The incremental server (msrep_server_create / submit / poll /
+    destroy) over a pool of host CSR matrices and a device arena of
+    budget_bytes.  Requests are submitted as they come; poll() returns
+    completions; close() waits for everything submitted and returns the
+    latency statistics."""
+
+    def __init__(self, pool: Sequence, budget_bytes: int, max_slots: int = 256,
+                 nnz_per_wave: int = 1024, vtype: int = F64, seed: int = 0, max_queue: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise MsrepError(-4, "msrep_server needs a GPU")
+        self._L = load_library()
+        self.pool = list(pool)
+        self._hm, self._keep = _host_pool(self.pool, vtype, pinned=True)
+        self._arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
+        self._cfg = _ServeCfg(self._arena.data_ptr(), int(budget_bytes), int(max_slots),
+                              int(nnz_per_wave), int(seed), 1.0, 0, int(max_queue))
+        self.vtype = vtype
+        self._ys = {}
+        h = ctypes.c_void_p()
+        _check(self._L.msrep_server_create(ctypes.byref(self._cfg), self._hm, len(self.pool),
+                                           ctypes.byref(h)), "server_create")
+        self._h = h.value
+
+    def submit(self, rid: int, matrix: int, steps: int, keep_y: bool = False):
+        """Submit request rid (steps SpMVs on pool matrix `matrix`); with
+        keep_y its last y is kept (y_of(rid)).  Raises MsrepError with
+        status -6 (busy) when the queue is full."""
+        y = None
+        if keep_y:
+            xdt = np.float64 if self.vtype == F64 else np.float32
+            y = np.zeros(self.pool[matrix].m, xdt)
+            self._ys[int(rid)] = y
+        r = _Request(int(rid), 0.0, int(matrix), int(steps))
+        _check(self._L.msrep_server_submit(self._h, ctypes.byref(r),
+                                           None if y is None else y.ctypes.data), "server_submit")
+
+    def poll(self, cap: int = 1024, timeout_ms: int = 0) -> List[Completion]:
+        buf = (_Completion * max(cap, 1))()
+        n = self._L.msrep_server_poll(self._h, buf, cap, int(timeout_ms))
+        if n < 0:
+            raise MsrepError(int(n), _abi.msrep_last_error())
+        return [Completion(buf[i].rid, buf[i].t_arrive, buf[i].t_admit, buf[i].t_done,
+                           buf[i].status) for i in range(n)]
+
+    def y_of(self, rid: int):
+        return self._ys.get(int(rid))
+
+    def close(self) -> dict:
+        st = _ServeStats()
+        if self._h:
+            h, self._h = self._h, None
+            _check(self._L.msrep_server_destroy(h, ctypes.byref(st)), "server_destroy")
+        return {f: getattr(st, f) for f, _ in _ServeStats._fields_ if not f.startswith("_")}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 256,

@@ -272,3 +272,22 @@ def test_wrappers_reject_bad_vectors():
     Z = torch.zeros(9, 3, dtype=torch.float64)
     with pytest.raises(ValueError, match="overlap"):
         pk.msrep_spmm(A, P, Z[:4], Z[2:7])
+
+
+def test_server_argument_errors():
+    """msrep_server_* refuse NULL handles and bad configurations before any
+    device call."""
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.msrep_server_create(None, None, 0, ctypes.byref(h)) == -1 and not h.value
+    cfg = _abi._ServeCfg(0x1000, 1 << 20, 0, 1024, 0, 1.0, 0, 0)  # max_slots 0
+    pool = (_abi._HostMat * 1)()
+    pool[0].A = _desc()
+    assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
+    cfg = _abi._ServeCfg(0x1000, 1 << 20, 4, 1024, 0, 1.0, 0, -1)  # negative max_queue
+    assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
+    r = _abi._Request(0, 0.0, 0, 1)
+    assert L.msrep_server_submit(None, ctypes.byref(r), None) == -1
+    assert L.msrep_server_poll(None, None, 0, 0) == -1
+    assert L.msrep_server_destroy(None, None) == 0
+    assert ctypes.sizeof(_abi._Completion) == 40

@@ -82,3 +82,91 @@ def test_fill_x_matches_published_generator(vt):
         if vt == pk.F32:
             want = want.astype(np.float32)
         assert np.array_equal(x.cpu().numpy(), want), (rid, step)
+
+
+def _oracle_y(A, rid, steps, vt):
+    x = synth.serving_x(A.n, SEED, rid, steps - 1)
+    val = A.val
+    if vt == pk.F32:
+        x = x.astype(np.float32).astype(np.float64)
+        val = A.val.astype(np.float32).astype(np.float64)
+    return oracle.spmv_csr(A.m, A.n, A.ptr, A.col, val, x)
+
+
+@pytest.mark.parametrize("vt", [0, 1])
+def test_incremental_server_results(vt):
+    """msrep_server_*: requests submitted from two host threads while others
+    run, completions polled as they come; every last y matches the oracle
+    and equals the trace-replay server's y for the same request bit for
+    bit; the statistics count every request."""
+    import threading
+    import time
+    pool = _pool()
+    reqs = [(rid, rid % len(pool), 2 + (rid * 7) % 9) for rid in range(24)]
+    tol = F64_TOL if vt == pk.F64 else F32_TOL
+    got = {}
+    with serving.Server(pool, 2 << 30, vtype=vt, seed=SEED) as S:
+        def feed(part):
+            for rid, k, steps in part:
+                S.submit(rid, k, steps, keep_y=True)
+                time.sleep(0.0005)
+        th = [threading.Thread(target=feed, args=(reqs[i::2],)) for i in range(2)]
+        for t in th:
+            t.start()
+        deadline = time.time() + 60
+        while len(got) < len(reqs) and time.time() < deadline:
+            for c in S.poll(timeout_ms=50):
+                assert c.status == 0, c
+                assert c.t_arrive <= c.t_admit <= c.t_done, c
+                got[c.rid] = c
+        for t in th:
+            t.join()
+        assert len(got) == len(reqs)
+        ys = {rid: S.y_of(rid).copy() for rid, _, _ in reqs}
+        st = S.close()
+    assert st["n_done"] == len(reqs) and st["n_failed"] == 0 and st["ticks"] > 0
+    for rid, k, steps in reqs:
+        ref, s = _oracle_y(pool[k], rid, steps, vt)
+        assert_close(ys[rid], ref, s, tol, "server request %d" % rid)
+    # the same requests replayed by msrep_serve give the same bits
+    trace = [synth.Request(rid, 0.0, k, steps) for rid, k, steps in reqs[:6]]
+    res, _ = serving.serve(pool, trace, budget_bytes=2 << 30, vtype=vt, seed=SEED, keep_y=True)
+    for (rid, _, _), r in zip(reqs[:6], res):
+        assert np.array_equal(r.y, ys[rid]), rid
+
+
+def test_incremental_server_busy_and_budget():
+    """A full queue refuses submissions with MSREP_ERR_BUSY; a request whose
+    matrix can never fit the arena completes with MSREP_ERR_BUDGET while the
+    others finish."""
+    pool = _pool(4, m_hi=20_000)
+    big = max(range(len(pool)), key=lambda k: pool[k].nnz)
+    small = min(range(len(pool)), key=lambda k: pool[k].nnz)
+    # one slot: a long request holds it while others wait in a queue of 2
+    with serving.Server(pool, 2 << 30, max_slots=1, seed=SEED, max_queue=2) as S:
+        S.submit(0, big, 3000)
+        busy = 0
+        for rid in range(1, 8):
+            try:
+                S.submit(rid, small, 2)
+            except pk.MsrepError as e:
+                assert e.status == -6
+                busy += 1
+        assert busy > 0
+        st = S.close()
+    assert st["n_done"] == 8 - busy
+    # a budget too small for the largest matrix
+    A = pool[big]
+    budget = 4 * (A.m + A.nnz) + 8 * A.nnz // 2
+    with serving.Server(pool, budget, seed=SEED) as S:
+        S.submit(100, big, 2)
+        S.submit(101, small, 2, keep_y=True)
+        out = {}
+        for _ in range(400):
+            for c in S.poll(timeout_ms=50):
+                out[c.rid] = c.status
+            if len(out) == 2:
+                break
+        assert out == {100: -5, 101: 0}, out
+        ref, s = _oracle_y(pool[small], 101, 2, pk.F64)
+        assert_close(S.y_of(101), ref, s, F64_TOL, "small request beside a refused one")
