@@ -33,7 +33,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "msrep_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB selects another build (the sanitizer build, build_sanitized()).
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 OK = 0
 ERR_ARG = -1

@@ -12,7 +12,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-_LIB_PATH = os.path.join(HERE, "libmsrep.so")
+# MSREP_LIB selects another build of the library (the sanitizer build of
+# build.py --sanitize); by default the one next to this file.
+_LIB_PATH = os.environ.get("MSREP_LIB") or os.path.join(HERE, "libmsrep.so")
 HEADER = os.path.join(ROOT, "include", "msrep.h")
 
 CSR, CSC, COO, COO_ANY, COO_COL = 0, 1, 2, 3, 4  # COO_ANY: any order; COO_COL: by column
