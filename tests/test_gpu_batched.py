@@ -72,3 +72,45 @@ def test_batched_rejects_mixed_types():
     M1 = pk.Mat(pk.CSR, pk.F32, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val.astype(np.float32))
     with pytest.raises(pk.MsrepError):
         pk.msrep_plan_create([M0, M1])
+
+
+_full = {}
+
+
+def _full_set():
+    """The benchmark's batched set: 512 matrices, rows log-uniform in
+    [1e3, 2e5], half uniform (4-64 per row) and half R-MAT-like."""
+    if "mats" not in _full:
+        _full["mats"] = synth.batched_set(512, seed=0)
+    return _full["mats"]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("vt,pf", [(0, 1), (1, 1), (0, 2)])
+def test_batched_full_set_every_matrix(vt, pf):
+    """All 512 matrices of the benchmark's set (416.7M nonzeros) in one plan,
+    with the benchmark's launch shape and both load depths: every entry of
+    every y against the oracle (FP32 values: on the stored values and
+    FP32-rounded x)."""
+    dev = torch.device("cuda:0")
+    mats = _full_set()
+    xdt = np.float64 if vt == 0 else np.float32
+    Ms, xs, ys = [], [], []
+    for A, x in mats:
+        sv, _ = stored_values(A.val, vt)
+        Ms.append(pk.Mat(pk.CSR, vt, A.m, A.n, ptr=A.ptr, idx=A.col, val=sv))
+        xs.append(torch.from_numpy(x.astype(xdt)).to(dev))
+        ys.append(torch.full((A.m,), float("nan"), dtype=xs[-1].dtype, device=dev))
+    tunes = [pk.Tune(k_per_lane=4, waves_per_wg=4, nnz_per_wave=1024, pipeline=pf)] * len(Ms)
+    plan = pk.msrep_plan_create(Ms, tunes)
+    pk.msrep_spmv_batched(plan, xs, ys)
+    torch.cuda.synchronize()
+    tol = F64_TOL if vt == 0 else F32_TOL
+    for k, (A, x) in enumerate(mats):
+        v = A.val if vt == 0 else A.val.astype(np.float32).astype(np.float64)
+        xo = x if vt == 0 else x.astype(np.float32).astype(np.float64)
+        ref, s = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, v, xo)
+        assert_close(ys[k].cpu().numpy(), ref, s, tol, "full set vt%d pf%d matrix %d" % (vt, pf, k))
+    plan.destroy()
+    del Ms, xs, ys
+    torch.cuda.empty_cache()
