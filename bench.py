@@ -40,8 +40,8 @@ DEFAULT_TUNES = {
     "rmat20": {"csr": (512, 4, 8, 2, 1), "coo": (512, 4, 8, 2, 1), "csc": (1024, 4, 2, 1, 0),
                "coo_any": (1024, 4, 2, 1, 0), "coo_col": (1024, 4, 2, 1, 0)},
     "stencil256": {"csr": (2048, 4, 4, 2, 0), "coo": (1024, 4, 2, 2, 0),
-                   "csc": (1024, 4, 2, 2, 0), "coo_any": (1024, 4, 2, 2, 0),
-                   "coo_col": (1024, 4, 2, 2, 0)},
+                   "csc": (1024, 4, 2, 3, 0), "coo_any": (1024, 4, 2, 2, 0),
+                   "coo_col": (1024, 4, 2, 3, 0)},
 }
 SCRUB_BYTES = 512 << 20
 
@@ -542,7 +542,7 @@ def measure_matrix(args, A, x64, wl, wkey, vt, fmts, ref=None):
 # kernels whose launch is priced against the SpMV's algorithmic bytes (the
 # per-format SpMV kernels proper; the boundary merges and the structure-only
 # CSC kernels are not)
-PRICED_KERNELS = ("spmv_csr_seg", "spmv_coo_seg", "csc_scatter", "csc_reduce")
+PRICED_KERNELS = ("spmv_csr_seg", "spmv_coo_seg", "csc_scatter", "csc_reduce", "cscw_tile", "cscw_merge")
 
 
 def main():

@@ -221,10 +221,14 @@ typedef struct msrep_tune {
                         /* np = ceil(nnz / nnz_per_wave); not read by msrep_spmv */
   int32_t pipeline;     /* CSR: chunks of indices/values loaded ahead, 1 or 2  */
                         /* (2 also gathers x one chunk ahead); 0 = default 2.  */
-                        /* CSC: product layout, 1 = one record per product     */
-                        /* (value and 32-bit row offset: one store each, for   */
-                        /* rows that scatter widely), 2 (default) = values and */
-                        /* 16-bit row offsets in two arrays (2 bytes less).    */
+                        /* CSC, COO_COL, COO_ANY (column merge): 1 = one       */
+                        /* record per product (value and 32-bit row offset:    */
+                        /* one store each, for rows that scatter widely), 2    */
+                        /* (default) = values and 16-bit row offsets in two    */
+                        /* arrays (2 bytes less), 3 = row windows: each run of */
+                        /* partitions sums its products in LDS over the 256-   */
+                        /* row windows its rows touch (for banded matrices;    */
+                        /* rows outside 30 windows take device atomics).       */
   int32_t _pad;
 } msrep_tune;
 
@@ -235,7 +239,9 @@ typedef struct msrep_tune {
  *     tables, one product per nonzero (8 bytes for F64 values, 4 otherwise)
  *     with its row offset (room for either product layout, see
  *     msrep_tune.pipeline), and the partial row arrays of buckets cut into
- *     several pieces: about (s_p + 4)*nnz bytes.
+ *     several pieces: about (s_p + 4)*nnz bytes; the row-window layout's
+ *     window lists, contributor lists, window sums and spill sums (8*m
+ *     bytes), its sums sharing the products' space.
  * Returns 0 when A is not supported (CSC or COO_ANY / COO_COL with more
  * than 2^26 rows). */
 size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
@@ -325,7 +331,8 @@ msrep_status msrep_spmv_noalloc(const msrep_mat *A, const msrep_part *parts_d,
  * the stream and keeping the fastest median of three runs:
  *   nnz_per_wave in {256, 512, 1024, 2048, 4096} (the equal-nnz np follows),
  *   k_per_lane in {4, 8}, waves_per_wg in {2, 4, 8} (CSR, COO),
- *   pipeline in {1, 2} (CSR, CSC), resident in {0, 1} (CSR, COO).
+ *   pipeline in {1, 2} (CSR), {1, 2, 3} (CSC, COO_COL, COO_ANY),
+ *   resident in {0, 1} (CSR, COO).
  * x_d holds n values for the timed SpMVs.  Synchronises the stream.
  * ws_d: at least msrep_autotune_ws_bytes(A) bytes (partitions, local
  * pointers, a y and the SpMV workspace of the largest np). */

@@ -18,7 +18,7 @@ namespace {
 constexpr int kNpw[] = {256, 512, 1024, 2048, 4096};
 constexpr int kK[] = {4, 8};
 constexpr int kWpb[] = {2, 4, 8};
-constexpr int kPf[] = {1, 2};
+constexpr int kPf[] = {1, 2, 3};  // CSR load depth; column merge: layouts, 3 = row windows
 constexpr int kResident[] = {0, 1};
 constexpr int kReps = 3;
 
@@ -94,6 +94,7 @@ extern "C" msrep_status msrep_autotune(const msrep_mat *A, const void *x_d, void
             const bool bucketed = bucketed_fmt(A->fmt);
             if (bucketed && (res == 1 || wpb != kWpb[0])) continue;
             if (A->fmt == MSREP_COO && pf == 1) continue;  // CSR pipelines, CSC layouts
+            if (pf == 3 && !bucketed) continue;            // row windows: column merge only
             if ((err = spmv_launch(A, parts, lptr, np, x_d, y, 1.0, 0.0, K, wpb, pf, res, carry, s)))
               break;
             std::vector<float> t;

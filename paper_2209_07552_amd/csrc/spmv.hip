@@ -7,6 +7,7 @@
 #include "common.hpp"
 #include "spmv_coo.hpp"
 #include "spmv_csc.hpp"
+#include "spmv_cscw.hpp"
 #include "spmv_csr.hpp"
 
 namespace msrep {
@@ -227,6 +228,121 @@ msrep_status launch_csc(const msrep_mat *A, const msrep_part *parts, const int32
   return MSREP_OK;
 }
 
+// The windowed CSC path (spmv_cscw.hpp): its numeric regions overlap the
+// bucketed products, its structure regions follow both (cscw_layout).
+void cscw_place(const msrep_mat *A, int32_t np, const CscLayout &L, CscwLayout &W) {
+  cscw_layout(A->m, A->nnz, np, L, W);
+}
+
+msrep_status cscw_structure(const msrep_mat *A, const msrep_part *parts, int32_t np,
+                            const CscwLayout &W, char *b, hipStream_t s) {
+  int32_t *wlist = reinterpret_cast<int32_t *>(b + W.wlist);
+  int32_t *wcnt = reinterpret_cast<int32_t *>(b + W.wcnt);
+  int32_t *flags = reinterpret_cast<int32_t *>(b + W.flags);
+  int32_t *inv_cnt = reinterpret_cast<int32_t *>(b + W.inv_cnt);
+  int32_t *inv_off = reinterpret_cast<int32_t *>(b + W.inv_off);
+  int32_t *inv_agg = reinterpret_cast<int32_t *>(b + W.inv_agg);
+  int32_t *inv_list = reinterpret_cast<int32_t *>(b + W.inv_list);
+  timing_begin("cscw_windows", s);
+  hipLaunchKernelGGL(cscw_fill_i32, dim3(static_cast<unsigned>(std::min<int64_t>((W.nwin + 256) / 256, 4096))),
+                     dim3(256), 0, s, inv_cnt, W.nwin + 1, int32_t(0));
+  hipLaunchKernelGGL(cscw_fill_i32, dim3(1), dim3(64), 0, s, flags, int64_t(4), int32_t(0));
+  hipLaunchKernelGGL(cscw_windows, dim3(W.P), dim3(1024), 0, s, A->idx, A->nnz, parts, np, W.P,
+                     A->m, wlist, wcnt, flags, inv_cnt);
+  MSREP_LAUNCHED("cscw_windows");
+  timing_end("cscw_windows", s);
+  if (msrep_status st = scan::device_scan<int32_t, scan::SumOp>(inv_cnt, inv_off, W.nwin + 1,
+                                                                inv_agg, false, s))
+    return st;
+  const int64_t pairs = static_cast<int64_t>(W.P) * kWinMax;
+  hipLaunchKernelGGL(cscw_inv_fill, dim3(static_cast<unsigned>((pairs + 255) / 256)), dim3(256), 0,
+                     s, wlist, wcnt, W.P, inv_off, inv_cnt, inv_list);
+  MSREP_LAUNCHED("cscw_inv_fill");
+  return MSREP_OK;
+}
+
+template <int VT>
+msrep_status cscw_numeric(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                          int32_t np, const void *x, void *y, double alpha, double beta,
+                          const CscLayout &L, const CscwLayout &W, char *b, hipStream_t s) {
+  using Tr = vt_traits<VT>;
+  using T = typename Tr::T;
+  const int32_t *wlist = reinterpret_cast<const int32_t *>(b + W.wlist);
+  const int32_t *wcnt = reinterpret_cast<const int32_t *>(b + W.wcnt);
+  const int32_t *flags = reinterpret_cast<const int32_t *>(b + W.flags);
+  const int32_t *inv_off = reinterpret_cast<const int32_t *>(b + W.inv_off);
+  const int32_t *inv_list = reinterpret_cast<const int32_t *>(b + W.inv_list);
+  double *part = reinterpret_cast<double *>(b + L.prod + W.part);
+  double *yacc = reinterpret_cast<double *>(b + L.prod + W.yacc);
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return fail(MSREP_ERR_HIP, "msrep_spmv: cannot query the LDS size");
+    if (static_cast<size_t>(lds) < cscw_lds<4>())
+      return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: row windows need %zu bytes of LDS per block "
+                  "(the device offers %d)", cscw_lds<4>(), lds);
+  }
+  hipLaunchKernelGGL(cscw_zero, dim3(static_cast<unsigned>(std::min<int64_t>((A->m + 255) / 256, 8192))),
+                     dim3(256), 0, s, flags, yacc, static_cast<int64_t>(A->m));
+  MSREP_LAUNCHED("cscw_zero");
+  timing_begin("cscw_tile", s);
+  if (A->fmt == MSREP_CSC)
+    hipLaunchKernelGGL((cscw_tile<VT, 4, false>), dim3(W.P), dim3(kWinWaves * kWave), cscw_lds<4>(),
+                       s, A->idx, A->idx2, static_cast<const typename Tr::V *>(A->val), parts, lptr,
+                       np, W.P, static_cast<const T *>(x), A->m, A->n, wlist, wcnt, part, yacc);
+  else
+    hipLaunchKernelGGL((cscw_tile<VT, 4, true>), dim3(W.P), dim3(kWinWaves * kWave), cscw_lds<4>(),
+                       s, A->idx, A->idx2, static_cast<const typename Tr::V *>(A->val), parts, lptr,
+                       np, W.P, static_cast<const T *>(x), A->m, A->n, wlist, wcnt, part, yacc);
+  MSREP_LAUNCHED("cscw_tile");
+  timing_end("cscw_tile", s);
+  timing_begin("cscw_merge", s);
+  if (beta == 0.0)
+    hipLaunchKernelGGL((cscw_merge<T, true>), dim3(static_cast<unsigned>(W.nwin)), dim3(kWinMergeBlock),
+                       0, s, inv_off, inv_list, flags, part, yacc, A->m, static_cast<T *>(y), alpha,
+                       beta);
+  else
+    hipLaunchKernelGGL((cscw_merge<T, false>), dim3(static_cast<unsigned>(W.nwin)), dim3(kWinMergeBlock),
+                       0, s, inv_off, inv_list, flags, part, yacc, A->m, static_cast<T *>(y), alpha,
+                       beta);
+  MSREP_LAUNCHED("cscw_merge");
+  timing_end("cscw_merge", s);
+  return MSREP_OK;
+}
+
+// CSC, COO_COL, COO_ANY.  pf == 3: the windowed path; otherwise the bucketed
+// path with product layout pf.  The structure phase (msrep_spmv_prepare,
+// which has no tune) builds the structure of both paths.
+template <int VT>
+msrep_status launch_csc_any(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
+                            int32_t np, const void *x, void *y, double alpha, double beta, int K,
+                            int wpb, int pf, void *ws, int phase, hipStream_t s) {
+  if (pf == 3 || phase == kPhaseStructure) {
+    using Acc = typename vt_traits<VT>::A;
+    CscLayout L;
+    if (!csc_layout(A->m, A->nnz, np, sizeof(Acc), L))
+      return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: CSC supports at most %d rows",
+                  kCscMaxBuckets << kCscMaxShift);
+    CscwLayout W;
+    cscw_place(A, np, L, W);
+    char *b = static_cast<char *>(ws);
+    if (phase != kPhaseNumeric)
+      if (msrep_status st = cscw_structure(A, parts, np, W, b, s)) return st;
+    if (phase == kPhaseStructure) {
+      // and the bucketed path's structure, for calls with either layout
+      return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s)
+                    : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s);
+    }
+    return cscw_numeric<VT>(A, parts, lptr, np, x, y, alpha, beta, L, W, b, s);
+  }
+  if (pf == 1)
+    return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s)
+                  : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s);
+  return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s)
+                : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s);
+}
+
 template <int VT, int K, bool B0>
 msrep_status dispatch_rows(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                            int32_t np, const void *x, void *y, double alpha, double beta,
@@ -244,13 +360,8 @@ msrep_status dispatch_vt(const msrep_mat *A, const msrep_part *parts, const int3
   using T = typename vt_traits<VT>::T;
   const bool b0 = beta == 0.0;
   msrep_status st;
-  if (bucketed_fmt(A->fmt)) {  // carry is the whole workspace here
-    if (pf == 1)
-      return K == 8 ? launch_csc<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s)
-                    : launch_csc<VT, 4, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s);
-    return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s)
-                  : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, carry, phase, s);
-  }
+  if (bucketed_fmt(A->fmt))  // carry is the whole workspace here
+    return launch_csc_any<VT>(A, parts, lptr, np, x, y, alpha, beta, K, wpb, pf, carry, phase, s);
   if (phase == kPhaseStructure) return MSREP_OK;  // CSR, COO: no structure-only work
   if (K == 8)
     st = b0 ? dispatch_rows<VT, 8, true>(A, parts, lptr, np, x, y, alpha, beta, wpb, pf, resident, carry, s)
@@ -298,8 +409,8 @@ msrep_status resolve_tune(const msrep_tune *tune, int *K, int *wpb, int *pf, int
   *pf = 2;
   *resident = 0;
   if (!tune) return MSREP_OK;
-  if (tune->pipeline < 0 || tune->pipeline > 2)
-    return fail(MSREP_ERR_ARG, "%s: pipeline must be 0, 1 or 2 (got %d)", who, tune->pipeline);
+  if (tune->pipeline < 0 || tune->pipeline > 3)
+    return fail(MSREP_ERR_ARG, "%s: pipeline must be 0..3 (got %d)", who, tune->pipeline);
   if (tune->pipeline) *pf = tune->pipeline;
   if (tune->k_per_lane != 0 && tune->k_per_lane != 4 && tune->k_per_lane != 8)
     return fail(MSREP_ERR_ARG, "%s: k_per_lane must be 4 or 8 (got %d)", who, tune->k_per_lane);
@@ -349,7 +460,12 @@ size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t
   if (bucketed_fmt(fmt)) {
     CscLayout L;
     const int pb = vtype == MSREP_F64 ? 8 : 4;
-    return csc_layout(m, nnz, np, pb, L) ? L.total : 0;
+    if (!csc_layout(m, nnz, np, pb, L)) return 0;
+    // the windowed path's numeric regions overlap the bucketed ones, its
+    // structure follows both
+    CscwLayout W;
+    cscw_layout(m, nnz, np, L, W);
+    return W.struct_end;
   }
   return align_up(16 * static_cast<size_t>(np), 256);
 }
@@ -380,6 +496,8 @@ msrep_status spmv_entry(const msrep_mat *A, const msrep_part *parts_d, const int
   }
   int K, wpb, pf, resident;
   if (msrep_status st = resolve_tune(tune, &K, &wpb, &pf, &resident, who)) return st;
+  if (pf == 3 && !bucketed_fmt(A->fmt))
+    return fail(MSREP_ERR_ARG, "%s: pipeline 3 (row windows) is a CSC / column-merge layout", who);
   // x, y and the local pointers are addressed through 32-bit buffer offsets
   const uint64_t xb = static_cast<uint64_t>(A->n) * vec_bytes(A->vtype);
   const uint64_t yb = static_cast<uint64_t>(A->m) * vec_bytes(A->vtype);

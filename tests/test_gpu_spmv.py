@@ -175,7 +175,9 @@ def test_dyadic_bit_exact_any_np(fmt):
     x = synth.dyadic(rng, A.n)
     M, v64 = device_mat(A, fmt, pk.F64)
     for np_ in (1, 5, 256, 4096, A.nnz + 7):
-        for res in (0, 1):  # CSC: the two product layouts
+        for res in (0, 1, 2):  # column merge: the two product layouts and the row windows
+            if res == 2 and fmt not in BUCKETED:
+                continue
             t = pk.Tune(pipeline=1 + res) if fmt in BUCKETED else pk.Tune(resident=res)
             y, ref, _ = _run(A, x, fmt, pk.F64, np_, M=M, v64=v64, tune=t)
             assert np.array_equal(y, ref), (fmt, np_, res)
@@ -262,13 +264,13 @@ def test_prepared_spmv_repeats_with_fresh_x(fmt, vt):
         P = pk.msrep_build_partition(M, np_)
         PB = pk.msrep_build_partition(MB, 33)
         ws = pk.msrep_spmv_prepare(M, P)
-        for it in range(4):
+        for it in range(6):
             x = rng.uniform(-1, 1, A.n).astype(xdt)
             y_in = rng.uniform(-1, 1, A.m).astype(xdt)
             alpha, beta = (1.0, 0.0) if it % 2 == 0 else (-2.0, 0.25)
             xd = torch.from_numpy(x).to(_dev())
             yd = torch.from_numpy(y_in.copy()).to(_dev())
-            tune = pk.Tune(pipeline=1 + it % 2) if fmt in BUCKETED else None
+            tune = pk.Tune(pipeline=1 + it % 3) if fmt in BUCKETED else None
             pk.msrep_spmv_prepared(M, P, xd, yd, ws, alpha, beta, tune)
             # an unprepared SpMV of another matrix on the shared workspace
             yb = torch.zeros(B.m, dtype=tdt, device=_dev())
@@ -336,7 +338,7 @@ def test_coo_any_order(vt):
             i = np.arange(np_, dtype=np.int64)
             assert np.array_equal(rec["start_idx"], i * A.nnz // np_)
             assert np.array_equal(rec["end_idx"], (i + 1) * A.nnz // np_ - 1)
-            for pf in (1, 2):
+            for pf in (1, 2, 3):
                 for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
                     y = torch.from_numpy(y_in.copy()).to(_dev())
                     pk.msrep_spmv(M, P, xd, y, alpha, beta, pk.Tune(pipeline=pf))
@@ -365,7 +367,7 @@ def test_coo_any_dyadic_bit_exact_and_prepared():
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), ref), np_
         ws = pk.msrep_spmv_prepare(M, P)
-        for pf in (1, 2):
+        for pf in (1, 2, 3):
             y2 = torch.full((A.m,), float("nan"), dtype=torch.float64, device=_dev())
             pk.msrep_spmv_prepared(M, P, xd, y2, ws, tune=pk.Tune(pipeline=pf))
             torch.cuda.synchronize()
@@ -440,7 +442,7 @@ def test_csc_many_buckets_and_pieces(vt):
         M, v64 = device_mat(A, "csc", vt)
         y_in = rng.uniform(-1, 1, A.m)
         for np_ in (5, 4096, 100_000):
-            for pf in (1, 2):  # product records / value and row-offset arrays
+            for pf in (1, 2, 3):  # product records / value and row-offset arrays / row windows
                 y, ref, s = _run(A, x, "csc", vt, np_, 0.75, -1.5, y_in, M=M, v64=v64,
                                  tune=pk.Tune(pipeline=pf))
                 assert_close(y, ref, s, tol, "%s csc vt%d np%d pf%d" % (A.name, vt, np_, pf))
@@ -494,7 +496,7 @@ def test_csc_tall_matrix_uses_wide_buckets(vt):
     tol = F64_TOL if vt == 0 else F32_TOL
     M, v64 = device_mat(A, "csc", vt)
     for np_ in (3, 1000):
-        for pf in (1, 2):
+        for pf in (1, 2, 3):
             y, ref, s = _run(A, x, "csc", vt, np_, 0.5, 2.0, y_in, M=M, v64=v64,
                              tune=pk.Tune(pipeline=pf))
             assert_close(y, ref, s, tol, "tall csc vt%d np%d pf%d" % (vt, np_, pf))
@@ -531,3 +533,57 @@ def test_spmv_replays_under_graph_capture(fmt):
         assert_close(got, ref, s, F64_TOL, "%s replay %d" % (fmt, rep))
         if fmt not in BUCKETED:  # the bucketed path sums in an order that varies
             assert np.array_equal(got, y_eager.cpu().numpy()), (fmt, rep)
+
+
+@pytest.mark.parametrize("fmt", ["csc", "coo_col", "coo_any"])
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_row_windows_banded_and_spilled(fmt, vt):
+    """The windowed column merge (pipeline 3): on stencils the producers'
+    rows fit their LDS windows; on R-MAT they do not and the rest goes
+    through the spill sums.  Both against the oracle, with alpha and beta,
+    for several np; dyadic stencils bit-exact."""
+    tol = F64_TOL if vt == 0 else F32_TOL
+    rng = np.random.default_rng(41)
+    sets = [synth.stencil7_csr(40), synth.rmat_csr(scale=13, edge_factor=16, seed=12),
+            synth.uniform_csr(2000, 30000, 9, seed=5)]
+    for A, x in sets:
+        if fmt == "coo_any":
+            M, r, c, v64 = _coo_any(A, vt, 3)
+        else:
+            M, v64 = device_mat(A, fmt, vt)
+        y_in = rng.uniform(-1, 1, A.m)
+        for np_ in (1, 37, 2000, A.nnz + 5):
+            for alpha, beta in ((1.0, 0.0), (0.5, -2.0)):
+                if fmt == "coo_any":
+                    xs = np.asarray(x, np.float64 if vt == 0 else np.float32)
+                    P = pk.msrep_build_partition(M, np_)
+                    yd = torch.from_numpy(y_in.astype(xs.dtype)).to(_dev())
+                    pk.msrep_spmv(M, P, torch.from_numpy(xs).to(_dev()), yd, alpha, beta,
+                                  pk.Tune(pipeline=3))
+                    torch.cuda.synchronize()
+                    yi = None if beta == 0.0 else y_in.astype(xs.dtype).astype(np.float64)
+                    ref, s = oracle.spmv_coo(A.m, A.n, r, c, v64, xs.astype(np.float64), alpha,
+                                             beta, yi)
+                    y = yd.cpu().numpy()
+                else:
+                    y, ref, s = _run(A, x, fmt, vt, np_, alpha, beta, y_in, M=M, v64=v64,
+                                     tune=pk.Tune(pipeline=3))
+                assert_close(y, ref, s, tol, "%s %s vt%d np%d b%g windows" % (A.name, fmt, vt,
+                                                                              np_, beta))
+    # dyadic stencil: exact sums in any order
+    A, _ = synth.stencil7_csr(32)
+    x = synth.dyadic(rng, A.n)
+    M, v64 = device_mat(A, "csc" if fmt == "coo_any" else fmt, pk.F64)
+    if fmt != "coo_any":
+        y, ref, _ = _run(A, x, fmt, pk.F64, 500, M=M, v64=v64, tune=pk.Tune(pipeline=3))
+        assert np.array_equal(y, ref)
+
+
+def test_row_windows_rejected_for_row_formats():
+    A, x = synth.uniform_csr(100, 100, 5, seed=1)
+    M, _ = device_mat(A, "csr", pk.F64)
+    P = pk.msrep_build_partition(M, 4)
+    y = torch.zeros(A.m, dtype=torch.float64, device=_dev())
+    with pytest.raises(pk.MsrepError) as e:
+        pk.msrep_spmv(M, P, torch.from_numpy(x).to(_dev()), y, tune=pk.Tune(pipeline=3))
+    assert e.value.status == -1
