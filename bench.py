@@ -842,22 +842,51 @@ def bench_batched(args, vt):
     for k, (A, _) in enumerate(mats):
         key = (k % 2, int(np.log10(max(A.m, 10))))
         classes.setdefault(key, k)
-    tuned = {key: pk.msrep_autotune(Ms[k], xs[k]) for key, k in classes.items()}
-    tunes = [pk.Tune(k_per_lane=4, waves_per_wg=4,
-                     nnz_per_wave=tuned[(k % 2, int(np.log10(max(A.m, 10))))].nnz_per_wave)
-             for k, (A, _) in enumerate(mats)]
+    tuned = ({} if args.nnz_per_wave else
+             {key: pk.msrep_autotune(Ms[k], xs[k]) for key, k in classes.items()})
+    def class_tune(k, A):
+        return tuned[(k % 2, int(np.log10(max(A.m, 10))))]
+
+    def plan_tunes(floor):
+        return [pk.Tune(k_per_lane=args.k or 4, waves_per_wg=args.wpb or 4,
+                        nnz_per_wave=(args.nnz_per_wave or
+                                      max(class_tune(k, A).nnz_per_wave, floor)),
+                        pipeline=args.pipeline)
+                for k, (A, _) in enumerate(mats)]
     log("autotuned %d classes in %.1fs" % (len(classes), time.time() - t0))
+    # the persistent kernel pays a fixed latency per work item (its chain of
+    # descriptor and partition loads), so the plan's items may want more
+    # nonzeros than the single-matrix tuner's partitions: time the plan with
+    # the tuned sizes and with floors of 2048-8192 nonzeros, keep the fastest
+    floors = [0] if args.nnz_per_wave else [0, 2048, 4096, 8192]
+    best = None
+    for floor in floors:
+        tn = plan_tunes(floor)
+        pl = pk.msrep_plan_create(Ms, tn)
+        for _ in range(2):
+            pk.msrep_spmv_batched(pl, xs, ys)
+        t = _timed(lambda: pk.msrep_spmv_batched(pl, xs, ys), 3)
+        log("plan item floor %d: %.3f ms (%d items)" % (floor, t, pl.items()))
+        if best is None or t < best[0]:
+            best = (t, floor, tn)
+        pl.destroy()
+    _, floor, tunes = best
     plan = pk.msrep_plan_create(Ms, tunes)
     for _ in range(args.warmup):
         pk.msrep_spmv_batched(plan, xs, ys)
     ms_b = _timed(lambda: pk.msrep_spmv_batched(plan, xs, ys), args.steps)
     yb = [y.double().cpu().numpy() for y in ys]
-    # plain path: one launch (plus merge) per matrix
-    parts = [pk.msrep_build_partition(M, max(1, -(-M.nnz // t.nnz_per_wave))) for M, t in zip(Ms, tunes)]
+    # plain path: one launch (plus merge) per matrix, each with its class's
+    # tuned launch shape and partition size
+    ptunes = ([pk.Tune(k_per_lane=args.k or 4, waves_per_wg=args.wpb or 4,
+                       nnz_per_wave=args.nnz_per_wave, pipeline=args.pipeline)] * len(mats)
+              if args.nnz_per_wave else [class_tune(k, A) for k, (A, _) in enumerate(mats)])
+    parts = [pk.msrep_build_partition(M, max(1, -(-M.nnz // t.nnz_per_wave)))
+             for M, t in zip(Ms, ptunes)]
     ws = torch.zeros(1 << 26, dtype=torch.uint8, device=dev)
 
     def plain():
-        for M, P, x, y, t in zip(Ms, parts, xs, ys, tunes):
+        for M, P, x, y, t in zip(Ms, parts, xs, ys, ptunes):
             pk.msrep_spmv(M, P, x, y, 1.0, 0.0, t, ws=ws)
     for _ in range(args.warmup):
         plain()
@@ -880,7 +909,8 @@ def bench_batched(args, vt):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.vtype,
            "data": "synthetic",
-           "config": {"workload": "batched-%d" % args.count, "total_nnz": nnz, "items": plan.items()},
+           "config": {"workload": "batched-%d" % args.count, "total_nnz": nnz, "items": plan.items(),
+                      "item_floor_nnz": floor},
            "gflops": round(2.0 * nnz / (ms_b * 1e-3) / 1e9, 2),
            "alg_gbs": round(byts / (ms_b * 1e-3) / 1e9, 1),
            "frac": round(byts / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -1,12 +1,19 @@
 // msrep_convert: CSR, CSC, row-sorted and column-sorted COO into one another
 // on the GPU (msRep Sec. 2.1; CSC(A) = CSR(A^T)).  All conversions are stable and deterministic:
 //   * expand:  the major index of every nonzero from a compressed pointer
-//              (mark each non-empty row's first position, inclusive max-scan);
-//   * compress: a pointer from sorted major indices (counting + scan);
+//              (per tile of positions: the row holding its first position by
+//              binary search, the rows starting inside it marked in LDS, a
+//              block max-scan carrying each mark forward);
+//   * compress: a pointer from sorted major indices (each position writes the
+//              pointers of the indices it starts);
 //   * transpose: a stable LSD radix sort of (new major index, position)
 //              pairs, 8-bit digits, ranks formed with wavefront ballots, so
-//              entries that tie keep their storage order;
-//   * gathers move indices and values (2, 4 or 8 bytes) by the permutation.
+//              entries that tie keep their storage order; the first pass
+//              reads the source's index array and takes positions as values,
+//              and each XCD sorts a contiguous run of tiles, so the short
+//              per-digit runs of neighbouring tiles meet in one L2;
+//   * gathers move the minor indices and the values (2, 4 or 8 bytes) by
+//              the permutation.
 #include <algorithm>
 
 #include "common.hpp"
@@ -26,24 +33,71 @@ __global__ void fill(T *__restrict__ a, int64_t n, T v) {
     a[i] = v;
 }
 
-// major index r at the first position of every non-empty major slice
-__global__ void mark_starts(const int32_t *__restrict__ ptr, int32_t rows, int64_t nnz,
-                            int32_t *__restrict__ out) {
-  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < rows;
-       r += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t a = ptr[r], b = ptr[r + 1];
-    if (a < b && a >= 0 && a < nnz) out[a] = static_cast<int32_t>(r);
+// The last row r in [0, rows) with ptr[r] <= key, found by one wavefront:
+// each step probes 64 evenly spaced rows of the interval left.
+__device__ int32_t wave_row_of(const int32_t *__restrict__ ptr, int32_t rows, int64_t key) {
+  const int lane = threadIdx.x & 63;
+  int64_t lo = 0, hi = rows;
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t r = lo + lane * step;
+    const uint64_t le = __ballot(r < hi && ptr[r] <= key);
+    const int j = le ? 63 - __clzll(static_cast<long long>(le)) : 0;
+    lo += j * step;
+    hi = lo + step < hi ? lo + step : hi;
   }
+  return static_cast<int32_t>(lo);
 }
 
-// counts[i + 1] += 1 for every index i (counts has minor + 1 entries)
-__global__ void histogram(const int32_t *__restrict__ idx, int64_t nnz, int32_t minor,
-                          int32_t *__restrict__ counts) {
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < nnz;
-       k += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t i = idx[k];
-    if (static_cast<uint32_t>(i) < static_cast<uint32_t>(minor)) atomicAdd(counts + i + 1, 1);
+// Expanded major indices of one tile of kTile positions.  ptr must be
+// non-decreasing from ptr[0] = 0 to ptr[rows] = nnz (a malformed pointer gives
+// wrong indices but no access outside ptr, out or LDS).
+__global__ __launch_bounds__(kBlock) void expand_tile(const int32_t *__restrict__ ptr,
+                                                      int32_t rows, int64_t nnz,
+                                                      int32_t *__restrict__ out) {
+  constexpr int kPad = kTile + kTile / 32;  // one pad word per 32: conflict-free strided reads
+  __shared__ int32_t mark[kPad];
+  __shared__ int32_t ends[2];
+  __shared__ int32_t sh[kBlock / 64];
+  const int tid = threadIdx.x;
+  const int64_t base = blockIdx.x * int64_t(kTile);
+  const int64_t last = (base + kTile < nnz ? base + kTile : nnz) - 1;
+  if (tid < 128) {  // wavefronts 0 and 1: the rows of the first and last positions
+    const int32_t r = wave_row_of(ptr, rows, tid < 64 ? base : last);
+    if ((tid & 63) == 0) ends[tid >> 6] = r;
   }
+  for (int i = tid; i < kPad; i += kBlock) mark[i] = -1;
+  __syncthreads();
+  const int32_t r0 = ends[0], r1 = ends[1];
+  if (tid == 0) mark[0] = r0;
+  // rows starting inside the tile; of several rows starting at one position
+  // (empty rows before it) the last one marks it
+  for (int32_t r = r0 + 1 + tid; r <= r1; r += kBlock) {
+    const int64_t a = ptr[r];
+    if (a > base && a <= last && ptr[r + 1] != a) {
+      const int i = static_cast<int>(a - base);
+      mark[i + i / 32] = r;
+    }
+  }
+  __syncthreads();
+  int32_t run = -1;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int i = tid * kItems + j;
+    run = max(run, mark[i + i / 32]);
+  }
+  int32_t before;
+  block_exscan<int32_t, MaxOp>(run, before, sh);
+  run = before;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int i = tid * kItems + j;
+    run = max(run, mark[i + i / 32]);
+    mark[i + i / 32] = run;
+  }
+  __syncthreads();
+  for (int i = tid; i < kTile; i += kBlock)
+    if (base + i <= last) out[base + i] = mark[i + i / 32];
 }
 
 // ptr of a row-sorted COO: ptr[r] = first position whose row is >= r
@@ -60,12 +114,6 @@ __global__ void rows_to_ptr(const int32_t *__restrict__ row, int64_t nnz, int32_
 }
 
 // --------------------------------------------------- LSD radix sort
-__global__ void iota(int32_t *__restrict__ a, int64_t n) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    a[i] = static_cast<int32_t>(i);
-}
-
 // hist[d * nb + b] = number of keys of tile b whose digit is d
 __global__ __launch_bounds__(kBlock) void radix_hist(const uint32_t *__restrict__ keys, int64_t n,
                                                      int shift, int64_t nb,
@@ -73,38 +121,49 @@ __global__ __launch_bounds__(kBlock) void radix_hist(const uint32_t *__restrict_
   __shared__ int32_t cnt[kRadix];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = blockIdx.x * int64_t(kTile);
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = tile * int64_t(kTile);
   for (int i = 0; i < kItems; ++i) {
     const int64_t k = base + i * kBlock + threadIdx.x;
     if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & (kRadix - 1)], 1);
   }
   __syncthreads();
-  hist[threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+  hist[threadIdx.x * nb + tile] = cnt[threadIdx.x];
 }
 
-// Stable scatter: tile items are taken in storage order (round i holds items
-// i*256 + tid); an item's rank is the number of earlier tile items with its
-// digit, found with ballots inside a wavefront and LDS counts across them.
+// Stable scatter of one tile.  Wavefront w takes the w-th quarter of the
+// tile, in rounds of 64 items in storage order.  Every item is ranked among
+// the earlier items of its quarter with the same digit (ballots within a
+// round, per-wavefront LDS counts across rounds); the quarters' counts are
+// then combined per digit, and each item goes to the tile's offset for its
+// digit + the earlier quarters' counts + its rank.
+// kIota: the values are the positions themselves (vin is not read).
+template <bool kIota>
 __global__ __launch_bounds__(kBlock) void radix_scatter(
     const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n, int shift,
     int64_t nb, const int32_t *__restrict__ off, uint32_t *__restrict__ kout,
     int32_t *__restrict__ vout) {
-  __shared__ int32_t run[kRadix];
-  __shared__ int32_t wcnt[kBlock / 64][kRadix];
-  __shared__ int32_t base_off[kRadix];
+  constexpr int kWaves = kBlock / 64, kQuarter = kTile / kWaves, kRounds = kQuarter / 64;
+  __shared__ int32_t wcnt[kWaves][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  run[tid] = 0;
-  base_off[tid] = off[tid * nb + blockIdx.x];
-  for (int i = 0; i < kBlock / 64; ++i) wcnt[i][tid] = 0;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  for (int v = 0; v < kWaves; ++v) wcnt[v][tid] = 0;
+  const int64_t base = tile * int64_t(kTile) + w * int64_t(kQuarter) + lane;
+  uint32_t key[kRounds];
+  int32_t val[kRounds], rank[kRounds];
+#pragma unroll
+  for (int i = 0; i < kRounds; ++i) {
+    const int64_t k = base + i * 64;
+    const bool valid = k < n;
+    key[i] = valid ? kin[k] : 0u;
+    val[i] = kIota ? static_cast<int32_t>(k) : (valid ? vin[k] : 0);
+  }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = blockIdx.x * int64_t(kTile);
-  for (int i = 0; i < kItems; ++i) {
-    const int64_t k = base + i * kBlock + tid;
-    const bool valid = k < n;
-    const uint32_t key = valid ? kin[k] : 0u;
-    const int32_t val = valid ? vin[k] : 0;
-    const int d = static_cast<int>((key >> shift) & (kRadix - 1));
+#pragma unroll
+  for (int i = 0; i < kRounds; ++i) {
+    const bool valid = base + i * 64 < n;
+    const int d = static_cast<int>((key[i] >> shift) & (kRadix - 1));
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -112,27 +171,36 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(
       peers &= ((d >> b) & 1) ? bal : ~bal;
     }
     const int wrank = __popcll(peers & lt);
-    if (valid && wrank == 0) wcnt[w][d] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      int32_t r = run[d] + wrank;
-      for (int v = 0; v < w; ++v) r += wcnt[v][d];
-      const int64_t dst = static_cast<int64_t>(base_off[d]) + r;
-      kout[dst] = key;
-      vout[dst] = val;
+    const int32_t c = wcnt[w][d];
+    rank[i] = c + wrank;
+    wave_lds_sync();
+    if (valid && wrank == 0) wcnt[w][d] = c + __popcll(peers);
+    wave_lds_sync();
+  }
+  __syncthreads();
+  {  // digit tid: where each quarter's items of this digit start
+    int32_t o = off[tid * nb + tile];
+    for (int v = 0; v < kWaves; ++v) {
+      const int32_t c = wcnt[v][tid];
+      wcnt[v][tid] = o;
+      o += c;
     }
-    __syncthreads();
-    int32_t add = 0;
-    for (int v = 0; v < kBlock / 64; ++v) {
-      add += wcnt[v][tid];
-      wcnt[v][tid] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kRounds; ++i) {
+    if (base + i * 64 < n) {
+      const int d = static_cast<int>((key[i] >> shift) & (kRadix - 1));
+      const int64_t dst = static_cast<int64_t>(wcnt[w][d]) + rank[i];
+      kout[dst] = key[i];
+      vout[dst] = val[i];
     }
-    run[tid] += add;
-    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------- gathers
+// dst[i] = src[perm[i]].  The minor indices and the values are gathered by
+// two launches: one pass over two arrays of random reads was slower.
 template <typename E>
 __global__ void gather(const E *__restrict__ src, const int32_t *__restrict__ perm, int64_t n,
                        E *__restrict__ dst) {
@@ -152,7 +220,7 @@ struct Ws {
   uint32_t *ka, *kb;       // nnz: radix keys
   int32_t *va, *vb;        // nnz: radix values (positions)
   int32_t *hist;           // 256 * tiles(nnz)
-  int32_t *agg;            // tiles(max(nnz, 256*tiles, minor+1)) scan aggregates
+  int32_t *agg;            // tiles(256 * tiles(nnz)) scan aggregates of the histograms
   int64_t *agg64;
   size_t bytes;
 };
@@ -167,7 +235,7 @@ Ws plan_ws(void *base, int64_t nnz, int64_t minor) {
   };
   const int64_t nt = tiles(nnz);
   const int64_t hist_n = kRadix * nt;
-  const int64_t scan_n = std::max<int64_t>({nnz, hist_n, minor + 1, 1});
+  const int64_t scan_n = std::max<int64_t>(hist_n, 1);
   w.major = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz)));
   w.ka = reinterpret_cast<uint32_t *>(take(4 * static_cast<size_t>(nnz)));
   w.kb = reinterpret_cast<uint32_t *>(take(4 * static_cast<size_t>(nnz)));
@@ -181,52 +249,42 @@ Ws plan_ws(void *base, int64_t nnz, int64_t minor) {
 }
 
 // Major index (row of CSR, column of CSC) of every entry.
-msrep_status expand(const int32_t *ptr, int32_t rows, int64_t nnz, int32_t *out, int32_t *agg,
-                    hipStream_t s) {
+msrep_status expand(const int32_t *ptr, int32_t rows, int64_t nnz, int32_t *out, hipStream_t s) {
   if (nnz == 0) return MSREP_OK;
-  hipLaunchKernelGGL(fill<int32_t>, dim3(grid_for(nnz)), dim3(256), 0, s, out, nnz, int32_t(-1));
-  MSREP_LAUNCHED("fill");
-  hipLaunchKernelGGL(mark_starts, dim3(grid_for(rows)), dim3(256), 0, s, ptr, rows, nnz, out);
-  MSREP_LAUNCHED("mark_starts");
-  return device_scan<int32_t, MaxOp>(out, out, nnz, agg, true, s);
-}
-
-// Pointer of minor+1 entries from unsorted indices: counts, then a scan.
-msrep_status compress_counts(const int32_t *idx, int64_t nnz, int32_t minor, int32_t *ptr,
-                             int32_t *agg, hipStream_t s) {
-  hipLaunchKernelGGL(fill<int32_t>, dim3(grid_for(minor + 1)), dim3(256), 0, s, ptr,
-                     int64_t(minor) + 1, int32_t(0));
-  MSREP_LAUNCHED("fill");
-  if (nnz > 0) {
-    hipLaunchKernelGGL(histogram, dim3(grid_for(nnz)), dim3(256), 0, s, idx, nnz, minor, ptr);
-    MSREP_LAUNCHED("histogram");
-  }
-  return device_scan<int32_t, SumOp>(ptr, ptr, int64_t(minor) + 1, agg, true, s);
+  hipLaunchKernelGGL(expand_tile, dim3(tiles(nnz)), dim3(kBlock), 0, s, ptr, rows, nnz, out);
+  MSREP_LAUNCHED("expand_tile");
+  return MSREP_OK;
 }
 
 // Stable sort of positions 0..nnz-1 by key (keys < 2^bits); returns the
 // buffer holding the permutation and the sorted keys.
 msrep_status stable_sort(const int32_t *keys, int64_t nnz, int bits, Ws &w, hipStream_t s,
                          int32_t **perm, uint32_t **sorted) {
-  uint32_t *kin = w.ka, *kout = w.kb;
-  int32_t *vin = w.va, *vout = w.vb;
-  MSREP_HIP(hipMemcpyAsync(kin, keys, 4 * static_cast<size_t>(nnz), hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(iota, dim3(grid_for(nnz)), dim3(256), 0, s, vin, nnz);
-  MSREP_LAUNCHED("iota");
+  // the first pass reads the source keys and positions 0..nnz-1 implicitly
+  const uint32_t *kin = reinterpret_cast<const uint32_t *>(keys);
+  const int32_t *vin = nullptr;
+  uint32_t *kout = w.ka, *kspare = w.kb;
+  int32_t *vout = w.va, *vspare = w.vb;
   const int64_t nt = tiles(nnz);
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(radix_hist, dim3(nt), dim3(kBlock), 0, s, kin, nnz, shift, nt, w.hist);
     MSREP_LAUNCHED("radix_hist");
     if (msrep_status st = device_scan<int32_t, SumOp>(w.hist, w.hist, kRadix * nt, w.agg, false, s))
       return st;
-    hipLaunchKernelGGL(radix_scatter, dim3(nt), dim3(kBlock), 0, s, kin, vin, nnz, shift, nt,
-                       w.hist, kout, vout);
+    if (vin)
+      hipLaunchKernelGGL(radix_scatter<false>, dim3(nt), dim3(kBlock), 0, s, kin, vin, nnz, shift,
+                         nt, w.hist, kout, vout);
+    else
+      hipLaunchKernelGGL(radix_scatter<true>, dim3(nt), dim3(kBlock), 0, s, kin, vin, nnz, shift,
+                         nt, w.hist, kout, vout);
     MSREP_LAUNCHED("radix_scatter");
-    std::swap(kin, kout);
-    std::swap(vin, vout);
+    kin = kout;
+    vin = vout;
+    std::swap(kout, kspare);
+    std::swap(vout, vspare);
   }
-  *perm = vin;
-  *sorted = kin;
+  *perm = const_cast<int32_t *>(vin);
+  *sorted = const_cast<uint32_t *>(kin);
   return MSREP_OK;
 }
 
@@ -236,21 +294,23 @@ int key_bits(int64_t range) {
   return b;
 }
 
-msrep_status gather_values(const void *src, const int32_t *perm, int64_t nnz, int32_t vtype,
-                           void *dst, hipStream_t s) {
+msrep_status gather_entries_by(const int32_t *minor, const void *val, const int32_t *perm,
+                               int64_t nnz, int32_t vtype, int32_t *dminor, void *dval,
+                               hipStream_t s) {
   const int g = grid_for(nnz);
+  hipLaunchKernelGGL(gather<int32_t>, dim3(g), dim3(256), 0, s, minor, perm, nnz, dminor);
   switch (value_bytes(vtype)) {
     case 8:
       hipLaunchKernelGGL(gather<uint64_t>, dim3(g), dim3(256), 0, s,
-                         static_cast<const uint64_t *>(src), perm, nnz, static_cast<uint64_t *>(dst));
+                         static_cast<const uint64_t *>(val), perm, nnz, static_cast<uint64_t *>(dval));
       break;
     case 4:
       hipLaunchKernelGGL(gather<uint32_t>, dim3(g), dim3(256), 0, s,
-                         static_cast<const uint32_t *>(src), perm, nnz, static_cast<uint32_t *>(dst));
+                         static_cast<const uint32_t *>(val), perm, nnz, static_cast<uint32_t *>(dval));
       break;
     default:
       hipLaunchKernelGGL(gather<uint16_t>, dim3(g), dim3(256), 0, s,
-                         static_cast<const uint16_t *>(src), perm, nnz, static_cast<uint16_t *>(dst));
+                         static_cast<const uint16_t *>(val), perm, nnz, static_cast<uint16_t *>(dval));
   }
   MSREP_LAUNCHED("gather");
   return MSREP_OK;
@@ -349,7 +409,7 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
       }
     } else if (nnz > 0) {
       if (S.ptr) {
-        if (msrep_status st = expand(S.ptr, S.major_extent, nnz, dst_exp(dst), w.agg, s))
+        if (msrep_status st = expand(S.ptr, S.major_extent, nnz, dst_exp(dst), s))
           return st;
       } else {
         MSREP_HIP(hipMemcpyAsync(dst_exp(dst), S.exp, 4 * nnz, hipMemcpyDeviceToDevice, s));
@@ -368,21 +428,32 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
   const int32_t key_range = S.minor_extent;
   const int32_t *other = S.exp;
   if (S.ptr) {
-    if (msrep_status st = expand(S.ptr, S.major_extent, nnz, w.major, w.agg, s)) return st;
+    if (msrep_status st = expand(S.ptr, S.major_extent, nnz, w.major, s)) return st;
     other = w.major;
   }
-  if (dcomp) {
-    if (msrep_status st = compress_counts(key, nnz, key_range, dptr, w.agg, s)) return st;
+  if (nnz == 0) {
+    if (dcomp) {  // an empty pointer
+      hipLaunchKernelGGL(fill<int32_t>, dim3(grid_for(int64_t(key_range) + 1)), dim3(256), 0, s,
+                         dptr, int64_t(key_range) + 1, int32_t(0));
+      MSREP_LAUNCHED("fill");
+    }
+    return ok();
   }
-  if (nnz == 0) return ok();
   int32_t *perm = nullptr;
   uint32_t *sorted = nullptr;
   if (msrep_status st = stable_sort(key, nnz, key_bits(key_range), w, s, &perm, &sorted)) return st;
-  if (!dcomp)
+  if (dcomp) {
+    // the pointer from the sorted keys: ptr[c] = the first position whose key
+    // is >= c (each position writes the pointers of the keys it starts; no
+    // atomics, so heavy columns cost nothing extra)
+    hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for(nnz + 1)), dim3(256), 0, s,
+                       reinterpret_cast<const int32_t *>(sorted), nnz, key_range, dptr);
+    MSREP_LAUNCHED("rows_to_ptr");
+  } else {
     MSREP_HIP(hipMemcpyAsync(dst_exp(dst), sorted, 4 * nnz, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(gather<int32_t>, dim3(grid_for(nnz)), dim3(256), 0, s, other, perm, nnz,
-                     dminor);
-  MSREP_LAUNCHED("gather");
-  if (msrep_status st = gather_values(src->val, perm, nnz, src->vtype, dval, s)) return st;
+  }
+  if (msrep_status st =
+          gather_entries_by(other, src->val, perm, nnz, src->vtype, dminor, dval, s))
+    return st;
   return ok();
 }

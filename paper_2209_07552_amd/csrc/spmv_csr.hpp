@@ -268,12 +268,22 @@ __device__ __forceinline__ void csr_partition(
     gather(c_cur, xv_cur);
     load_items<V, K>(col, val, s0, -lead + CH, nloc, c_nxt, v_nxt);
   }
+  // PF == 2: a window of the local row pointer kept in registers: lw0 =
+  // lp[j0 + lane] and lw1 = lp[j0 + 64 + lane]; each chunk loads the 64
+  // words after it, and the window slides by the rows the chunk finished, so
+  // a chunk needs no dependent pointer load unless 64 or more rows start
+  // inside it.  (The register-lean PF == 1 loads lp[j0 + lane] per chunk.)
+  int32_t lw0 = buf_load<int32_t>(rl, static_cast<uint32_t>(lane) * 4u);
+  int32_t lw1 = PF == 2 ? buf_load<int32_t>(rl, static_cast<uint32_t>(kWave + lane) * 4u) : 0;
   for (int32_t cb = -lead; cb < nloc; cb += CH) {
     const int32_t cs = cb > 0 ? cb : 0;                 // first valid local position
     const int32_t ce = cb + CH < nloc ? cb + CH : nloc;  // one past the last
-    // ---- 1. issue: the first batch of local row pointers, then the loads of
+    // ---- 1. issue: the pointer words after the window, then the loads of
     //         later chunks, while this chunk's products are formed
-    const int32_t lpv0 = buf_load<int32_t>(rl, static_cast<uint32_t>(j0 + lane) * 4u);
+    if constexpr (PF != 2) lw0 = buf_load<int32_t>(rl, static_cast<uint32_t>(j0 + lane) * 4u);
+    const int32_t lpv0 = lw0;
+    const int32_t lw2 =
+        PF == 2 ? buf_load<int32_t>(rl, static_cast<uint32_t>(j0 + 2 * kWave + lane) * 4u) : 0;
     int32_t c_nn[K];
     V v_nn[K];
     if constexpr (PF == 2) {
@@ -435,7 +445,26 @@ __device__ __forceinline__ void csr_partition(
     }
     carry_v = next_carry;
     carry_on = cont;
-    j0 = cont ? j1 : j1 + 1;
+    {
+      const int32_t j0n = cont ? j1 : j1 + 1;
+      const int32_t d = j0n - j0;  // wave-uniform
+      if constexpr (PF != 2) {
+        // (reloaded at the next chunk's start)
+      } else if (one_batch && d <= kWave) {
+        // slide the window: lane L takes word j0n + L from lw0 / lw1 / lw2
+        const int32_t src = lane + d;  // 0 .. 127
+        const int addr = (src & (kWave - 1)) << 2;
+        const int32_t a = __builtin_amdgcn_ds_bpermute(addr, lw0);
+        const int32_t b = __builtin_amdgcn_ds_bpermute(addr, lw1);
+        const int32_t c = __builtin_amdgcn_ds_bpermute(addr, lw2);
+        lw0 = src < kWave ? a : b;
+        lw1 = src < kWave ? b : c;
+      } else {
+        lw0 = buf_load<int32_t>(rl, static_cast<uint32_t>(j0n + lane) * 4u);
+        lw1 = buf_load<int32_t>(rl, static_cast<uint32_t>(j0n + kWave + lane) * 4u);
+      }
+      j0 = j0n;
+    }
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       c_cur[t] = c_nxt[t];
