@@ -558,6 +558,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     ap.add_argument("--rates", default="0.1,0.5,0.9,1.2", help="serving: fractions of capacity")
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--steps-per-tick", type=int, default=0,
+                    help="serving: most steps of one request per tick (0: library default)")
     ap.add_argument("--vtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--formats", default="csr,csc,coo")
     ap.add_argument("--nnz-per-wave", type=int, default=0, help="partition size (0: tuned)")
@@ -579,6 +581,8 @@ def main():
                          "msrep_spmv_prepare once + msrep_spmv_prepared")
     ap.add_argument("--warm", action="store_true",
                     help="also time back-to-back (cache-warm) SpMVs of each format")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="also measure the plain-stream HBM ceiling with --only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "KEY"))
@@ -647,6 +651,13 @@ def main():
         out["precision"] = prec
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, x64)
+    if not args.only or args.ceiling:
+        # what plain streams reach here, beside the roofline's 8 TB/s peak
+        ceil = stream_ceiling()
+        out["stream_ceiling"] = ceil
+        if out["roofline"].get("unit") == "GB/s":
+            out["roofline"]["frac_of_stream_read"] = round(
+                out["roofline"]["achieved"] / ceil["read_gbs"], 4)
     if not args.only and args.workload == "stencil256" and vt == pk.F64:
         # the power-law matrix: the same step on R-MAT scale 20
         del A, x64
@@ -657,6 +668,43 @@ def main():
                          "per_format": rb["per_format"]}
     print(json.dumps(out), flush=True)
     return 0
+
+
+def stream_ceiling(reps=5):
+    """The HBM rate plain streams reach on this GPU (msrep_probe_stream):
+    one pass of 16-byte loads over 2 GiB, and a 2 GiB copy, each cold
+    (scrubbed before), median of reps.  The practical ceiling beside the
+    8 TB/s peak for kernels that stream their operands."""
+    import torch
+
+    import paper_2209_07552_amd as pk
+    dev = torch.device("cuda:0")
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device=dev)
+    out = {"bytes": nbytes, "kind": "msrep_probe_stream"}
+    for mode, key, mult in ((0, "read_gbs", 1), (1, "copy_gbs", 2)):
+        best = None
+        for blocks in (2048, 65536):
+            ts = []
+            for _ in range(reps):
+                scrub.fill_(1)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pk.msrep_probe_stream(src, dst, mode, blocks)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            if best is None or ms < best[0]:
+                best = (ms, blocks)
+        out[key] = round(mult * nbytes / best[0] / 1e6, 1)
+        out[key.replace("_gbs", "_blocks")] = best[1]
+    out["copy_counts"] = "read + write bytes"
+    del src, dst, scrub
+    torch.cuda.empty_cache()
+    return out
 
 
 def _timed(fn, reps):
@@ -989,14 +1037,17 @@ def bench_serve(args, vt):
     mean_steps = 55.0
     # capacity estimate from a saturated run: SpMVs per second of the mix
     probe = synth.serving_trace(max(64, args.count // 4), rate=1e9, pool=len(pool), seed=99)
-    _, st = serving.serve(pool, probe, budget_bytes=budget, vtype=vt, max_slots=256)
+    spt = args.steps_per_tick
+    _, st = serving.serve(pool, probe, budget_bytes=budget, vtype=vt, max_slots=256,
+                          steps_per_tick=spt)
     cap_req = st["spmv_per_s"] / mean_steps
     log("saturated mix: %.0f SpMV/s -> capacity ~%.1f req/s" % (st["spmv_per_s"], cap_req))
     points = []
     n_plain = max(1, args.requests // 4)
     for f in [float(v) for v in args.rates.split(",")]:
         trace = synth.serving_trace(args.requests, rate=max(f * cap_req, 1e-3), pool=len(pool), seed=1)
-        _, st = serving.serve(pool, trace, budget_bytes=budget, vtype=vt, max_slots=256)
+        _, st = serving.serve(pool, trace, budget_bytes=budget, vtype=vt, max_slots=256,
+                              steps_per_tick=spt)
         pt = {"load": f, "rate_req_s": round(f * cap_req, 2),
               "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
               "req_per_s": round(st["req_per_s"], 2),
@@ -1014,7 +1065,7 @@ def bench_serve(args, vt):
     # and that step's x (for FP32 pools also on the stored values)
     chk = synth.serving_trace(64, rate=0.5 * cap_req, pool=len(pool), seed=2)
     res, _ = serving.serve(pool, chk, budget_bytes=budget, vtype=vt, max_slots=256,
-                           keep_y=range(0, 64, 4))
+                           keep_y=range(0, 64, 4), steps_per_tick=spt)
     err = err_st = 0.0
     for i in range(0, 64, 4):
         q, A = chk[i], pool[chk[i].matrix]
@@ -1032,7 +1083,8 @@ def bench_serve(args, vt):
            "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": args.vtype, "data": "synthetic",
            "config": {"workload": "serve-pool%d" % len(pool), "budget_gb": args.budget_gb,
-                      "steps_per_request": "U{10..100}"},
+                      "steps_per_request": "U{10..100}",
+                      "steps_per_tick": spt or 8},
            "points": points,
            "plain_path": "the same trace's first %d requests, one at a time in arrival order "
                          "(queueing included), x generated on the device, one msrep_spmv per "

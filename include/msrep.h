@@ -76,6 +76,18 @@ msrep_status msrep_timing_only(const char *kernel);
  * MSREP_ERR_HIP when an event cannot be read). */
 int32_t msrep_timing_read(msrep_kernel_time *out, int32_t cap);
 
+/* A calibration aid, not part of the method: the HBM rate this GPU reaches
+ * on plain streams, as the practical ceiling beside the 8 TB/s peak for the
+ * SpMV kernels, which stream their index and value arrays.  mode 0 reads
+ * `bytes` from src (16-byte loads, one pass; dst receives at most 16 bytes,
+ * only if the data hashes to a fixed value), mode 1 copies src to dst.
+ * Both buffers are device memory, 16-byte aligned, bytes a multiple of 16
+ * (dst at least 16 bytes in mode 0, `bytes` in mode 1, not overlapping src).
+ * blocks = workgroups of 256 lanes (0: 65536).  Asynchronous on `stream`.
+ * MSREP_ERR_ARG for NULL or misaligned buffers, a bad size or mode. */
+msrep_status msrep_probe_stream(const void *src, void *dst, size_t bytes, int32_t mode,
+                                int32_t blocks, void *stream);
+
 /* ------------------------------------------------------------ matrices */
 /* Storage formats of Sec. 2.1: CSR, CSC (the CSR of the transpose), COO
  * sorted by row (the order Sec. 3.2.3 assumes for pCOO), COO in any order
@@ -414,10 +426,14 @@ msrep_status msrep_plan_destroy(msrep_plan plan);
  * Matrices are uploaded into the caller's arena when the request is admitted
  * (admission is by bytes: matrix + partitions + vectors must fit in what the
  * arena has free) and stay resident while the request runs.  Every tick
- * executes one step of every active request (up to 240 of them) in one
- * batched launch, so requests that arrive while others run join the next
- * tick.  A request's descriptor is written to the device once, when it is
- * admitted; a tick only launches kernels.
+ * executes the next steps of every active request, up to steps_per_tick of
+ * each (240 steps per tick in all), in one batched launch, so requests that
+ * arrive while others run join the next tick.  A request's steps are
+ * independent SpMVs, each on an x/y pair of its own (a request reserves
+ * min(steps, steps_per_tick) pairs), so a tick that runs several of them
+ * gives the same results as ticks of one step each.  A request's descriptor
+ * is written to the device once, when it is admitted; a tick only launches
+ * kernels.
  *   x_j[c] = 2*u - 1 with u the top 53 bits of splitmix64(key) / 2^53,
  *   key = seed ^ (rid << 40) ^ ((uint64)j << 24) ^ c (rid < 2^24, j < 2^16)
  *   (SplitMix64: Steele, Lea and Flood 2014), rounded to FP32 for F32 pools.
@@ -442,6 +458,9 @@ typedef struct msrep_serve_cfg {
                         /* results[i].y_host (where not NULL)                */
   int32_t max_queue;    /* msrep_server_submit: most requests waiting for    */
                         /* admission before MSREP_ERR_BUSY (0: 2^20)          */
+  int32_t steps_per_tick; /* most steps of one request in a tick (1..16;   */
+                          /* 0: 8)                                           */
+  int32_t _pad;
 } msrep_serve_cfg;
 
 typedef struct msrep_request {

@@ -16,6 +16,6 @@ from ._abi import (  # noqa: F401
     msrep_lptr_bound, msrep_plan_create, SPLIT_NNZ, SPLIT_ROWS, msrep_serve, msrep_spmm, msrep_spmm_ws_bytes,
     msrep_spmv, msrep_spmv_batched, msrep_spmv_noalloc, msrep_spmv_noalloc_max_parts,
     msrep_spmv_prepare, msrep_spmv_prepared, msrep_spmv_ws_bytes, msrep_timing,
-    msrep_timing_only, msrep_timing_read,
+    msrep_timing_only, msrep_timing_read, msrep_probe_stream,
     msrep_validate, mat_from_csr, exported_symbols,
 )

@@ -51,7 +51,8 @@ class _HostMat(ctypes.Structure):
 class _ServeCfg(ctypes.Structure):
     _fields_ = [("arena_d", c_vp), ("budget_bytes", c_sz), ("max_slots", c_i32),
                 ("nnz_per_wave", c_i32), ("seed", ctypes.c_uint64), ("time_scale", c_dbl),
-                ("keep_y", c_i32), ("max_queue", c_i32)]
+                ("keep_y", c_i32), ("max_queue", c_i32), ("steps_per_tick", c_i32),
+                ("_pad", c_i32)]
 
 
 class _Request(ctypes.Structure):
@@ -138,6 +139,7 @@ def load_library():
         "msrep_timing": (c_i32, [c_i32]),
         "msrep_timing_only": (c_i32, [ctypes.c_char_p]),
         "msrep_timing_read": (c_i32, [P(_KernelTime), c_i32]),
+        "msrep_probe_stream": (c_i32, [c_vp, c_vp, c_sz, c_i32, c_i32, c_vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -435,6 +437,14 @@ def msrep_timing_read() -> dict:
         raise MsrepError(n, msrep_last_error() or "timing read")
     return {buf[i].name.decode(): (int(buf[i].calls), float(buf[i].total_ms))
             for i in range(min(n, 64))}
+
+
+def msrep_probe_stream(src, dst, mode: int, blocks: int = 0, stream=None) -> None:
+    """Launch the plain stream probe over all of src (mode 0: read, with dst
+    a 16-byte sink; mode 1: copy into dst of the same size)."""
+    nbytes = src.numel() * src.element_size()
+    _check(load_library().msrep_probe_stream(_ptr(src), _ptr(dst), nbytes, int(mode), int(blocks),
+                                             _stream(stream)), "probe_stream")
 
 
 def msrep_spmv_ws_bytes(A: Mat, np_: int) -> int:

@@ -77,27 +77,33 @@ struct PlanSrc {
 };
 
 // ------------------------------------------------------------- serving
-// A request slot of the server: its resident matrix, partitions, carries and
-// vectors.  Written once when the request is admitted.
+// A request slot of the server: its resident matrix, partitions, and its
+// copies of the x, y and carry vectors (copy c at x + c*x_stride bytes,
+// y + c*y_stride bytes, carry + c*2*np), one per step a tick may run.
+// Written once when the request is admitted.
 struct ServeSlot {
   BatchMat M;
   BatchXY xy;
   int64_t rid;
+  int64_t x_stride, y_stride;
 };
 
-constexpr int kTickMax = 240;  // requests per tick (the arguments stay below 4 KB)
+constexpr int kTickMax = 240;  // steps per tick (the arguments stay below 4 KB)
 
-// One serving tick: the active requests' slots, the step each one runs, and
-// the prefix sums of their partition counts (item it belongs to request i
-// with begin[i] <= it < begin[i+1]).  Passed by value as kernel arguments.
+// One serving tick: an entry per step it runs (the request's slot, the step
+// index j in the low 16 bits and the copy it uses above them), and the
+// prefix sums of their partition counts (item it belongs to entry i with
+// begin[i] <= it < begin[i+1]).  Passed by value as kernel arguments.
 struct TickSrc {
   const ServeSlot *table;
   int64_t n_items;
   int32_t n_waves, count;
   int32_t slot[kTickMax];
-  int32_t step[kTickMax];
+  int32_t step[kTickMax];  // j | copy << 16
   int32_t begin[kTickMax + 1];
-  __device__ int32_t request_of(int64_t it) const {
+  __device__ static int32_t step_of(int32_t v) { return v & 0xffff; }
+  __device__ static int32_t copy_of(int32_t v) { return v >> 16; }
+  __device__ int32_t entry_of(int64_t it) const {
     int32_t lo = 0, hi = count;  // begin[lo] <= it < begin[hi]
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
@@ -109,9 +115,13 @@ struct TickSrc {
     return lo;
   }
   __device__ void get(int64_t it, BItem &o) const {
-    const int32_t i = request_of(it);
+    const int32_t i = entry_of(it);
     const ServeSlot *S = table + slot[i];
     bitem_from(S->M, S->xy, static_cast<int32_t>(it - begin[i]), o);
+    const int64_t c = copy_of(step[i]);
+    o.x = static_cast<const char *>(o.x) + c * S->x_stride;
+    o.y = static_cast<char *>(o.y) + c * S->y_stride;
+    o.carry += c * 2 * static_cast<int64_t>(S->M.np);
   }
   // equal item counts per wavefront (a request's partitions hold equal
   // nonzeros, so items cost about the same)

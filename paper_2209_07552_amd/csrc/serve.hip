@@ -9,12 +9,14 @@
 //    served) when its matrix (if not resident), its partitions and its x/y/
 //    merge buffers fit in the free arena; one that can never fit fails with
 //    MSREP_ERR_BUDGET.  At most max_slots requests are admitted at once.
-//  * Continuous batching: every tick runs one step of every ready request in
-//    one persistent launch over all their equal-nnz partitions (the batched
+//  * Continuous batching: every tick runs the next steps of every ready
+//    request (up to steps_per_tick of each; a request's steps are
+//    independent SpMVs, each on an x/y/carry copy of its own) in one
+//    persistent launch over all their equal-nnz partitions (the batched
 //    kernel), so requests that arrive while others run join the next tick.
 //    A request's device descriptor is written once, when it is admitted; a
-//    tick passes only the list of active slots and their steps, in the
-//    kernel arguments, so a tick costs three launches and one event record.
+//    tick passes only its entries (slot, step, copy), in the kernel
+//    arguments, so a tick costs three launches and one event record.
 //    Uploads and partition builds run on a copy stream, overlapping compute.
 //  * Each request's arithmetic depends only on its matrix, its partitions and
 //    its x: its results are the same alone and in any mix.
@@ -47,6 +49,8 @@ constexpr int kK = 4;        // nonzeros per lane per chunk
 constexpr int kRing = 4;     // tick events in rotation (at most kInflight ticks in flight)
 constexpr int kInflight = 2;
 constexpr int64_t kDefaultQueue = int64_t(1) << 20;  // incremental server's waiting requests
+constexpr int32_t kDefaultStepsPerTick = 8;
+constexpr int32_t kMaxStepsPerTick = 16;
 
 // ------------------------------------------------------------ x generator
 // SplitMix64 output function (Steele, Lea, Flood 2014) applied to a key.
@@ -64,12 +68,14 @@ __host__ __device__ inline double x_value(uint64_t seed, int64_t rid, int32_t st
   return 2.0 * u - 1.0;
 }
 
-// x of every request of a tick: block row i fills request i's x for its step.
+// x of every step of a tick: block row i fills entry i's x copy for its step.
 template <typename T>
 __global__ void fill_x_tick(const TickSrc src, uint64_t seed) {
   const ServeSlot *S = src.table + src.slot[blockIdx.y];
-  T *x = static_cast<T *>(const_cast<void *>(S->xy.x));
-  const int32_t n = S->M.n, step = src.step[blockIdx.y];
+  const int32_t sc = src.step[blockIdx.y];
+  T *x = reinterpret_cast<T *>(static_cast<char *>(const_cast<void *>(S->xy.x)) +
+                               TickSrc::copy_of(sc) * S->x_stride);
+  const int32_t n = S->M.n, step = TickSrc::step_of(sc);
   const int64_t rid = S->rid;
   for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n;
        c += int64_t(gridDim.x) * blockDim.x)
@@ -146,8 +152,11 @@ struct Req {
   void *y_host = nullptr; // last y copied here when it finishes (optional)
   State st = kWaiting;
   int32_t np = 1, slot = -1;
-  size_t off = 0, bytes = 0;  // x, y, parts, lptr, carry
+  int32_t copies = 1;         // x/y/carry copies: steps one tick may run
+  int32_t last_copy = 0;      // the copy the last step ran on
+  size_t off = 0, bytes = 0;  // x, y, parts, lptr, carry (copies of x, y, carry)
   size_t x_off = 0, y_off = 0, parts_off = 0, lptr_off = 0, carry_off = 0;
+  size_t x_stride = 0, y_stride = 0;
   int32_t enq = 0;            // steps enqueued
   int64_t last_tick = -1;
   double t_arrive = 0, t_admit = 0, t_done = 0, ready_at = 0;
@@ -175,17 +184,27 @@ void layout_req(Req &q, const msrep_mat &A) {
     o += align_up(b ? b : 1, 256);
     return at;
   };
-  q.x_off = take(xb * A.n);
-  q.y_off = take(xb * A.m);
+  const size_t c = static_cast<size_t>(q.copies);
+  q.x_stride = align_up(xb * static_cast<size_t>(A.n) ? xb * A.n : 1, 256);
+  q.y_stride = align_up(xb * static_cast<size_t>(A.m) ? xb * A.m : 1, 256);
+  q.x_off = take(q.x_stride * c);
+  q.y_off = take(q.y_stride * c);
   q.parts_off = take(sizeof(msrep_part) * q.np);
   q.lptr_off = take(4 * static_cast<size_t>(msrep_lptr_bound(A.m, q.np)));
-  q.carry_off = take(16 * static_cast<size_t>(q.np));
+  q.carry_off = take(16 * static_cast<size_t>(q.np) * c);
   q.bytes = o;
 }
 
+// One step of one request in a tick, on copy `copy` of its vectors.
+struct Entry {
+  Req *q;
+  int32_t step, copy;
+};
+
 struct Tick {
   int64_t id;
-  std::vector<Req *> reqs;
+  std::vector<Entry> ent;
+  int32_t requests = 0;
   double end = 0;  // simulated
 };
 
@@ -312,6 +331,8 @@ struct HipExec {
                    reinterpret_cast<double *>(b + q.carry_off)};
     S.xy = BatchXY{b + q.x_off, b + q.y_off};
     S.rid = q.r.rid;
+    S.x_stride = static_cast<int64_t>(q.x_stride);
+    S.y_stride = static_cast<int64_t>(q.y_stride);
     // the slot was last read by ticks that completed before it was freed
     MSREP_HIP(hipMemcpyAsync(arena + table_off + sizeof(ServeSlot) * q.slot, &S, sizeof(ServeSlot),
                              hipMemcpyHostToDevice, copy));
@@ -325,13 +346,14 @@ struct HipExec {
   msrep_status launch(Tick &t, const std::vector<Resident> &) {
     TickSrc src;
     src.table = reinterpret_cast<const ServeSlot *>(arena + table_off);
-    src.count = static_cast<int32_t>(t.reqs.size());
+    src.count = static_cast<int32_t>(t.ent.size());
     int64_t items = 0;
     int32_t max_n = 1;
     for (int32_t i = 0; i < src.count; ++i) {
-      const Req &q = *t.reqs[i];
+      const Entry &e = t.ent[i];
+      const Req &q = *e.q;
       src.slot[i] = q.slot;
-      src.step[i] = q.enq;
+      src.step[i] = e.step | (e.copy << 16);
       src.begin[i] = static_cast<int32_t>(items);
       items += q.np;
       max_n = std::max(max_n, pool[q.r.matrix].A.n);
@@ -373,8 +395,8 @@ struct HipExec {
   msrep_status keep_y(Req &q) {
     if (!q.y_host) return MSREP_OK;
     const msrep_mat &H = pool[q.r.matrix].A;
-    MSREP_HIP(hipMemcpy(q.y_host, arena + q.off + q.y_off, vec_bytes(vtype) * static_cast<size_t>(H.m),
-                        hipMemcpyDeviceToHost));
+    MSREP_HIP(hipMemcpy(q.y_host, arena + q.off + q.y_off + q.y_stride * q.last_copy,
+                        vec_bytes(vtype) * static_cast<size_t>(H.m), hipMemcpyDeviceToHost));
     return MSREP_OK;
   }
   // Nothing to do: spin while the device works, else sleep until the next
@@ -422,7 +444,8 @@ struct SimExec {
   void released(Req &) {}
   msrep_status launch(Tick &t, const std::vector<Resident> &) {
     double work = tick_cost;
-    for (Req *q : t.reqs) work += 2.0 * static_cast<double>(pool[q->r.matrix].A.nnz) / flop_rate;
+    for (const Entry &e : t.ent)
+      work += 2.0 * static_cast<double>(pool[e.q->r.matrix].A.nnz) / flop_rate;
     dev_free = std::max(dev_free, clock) + work;
     t.end = dev_free;
     return MSREP_OK;
@@ -459,9 +482,13 @@ class Scheduler {
     const int64_t npw = std::max(1, cfg_.nnz_per_wave);
     return H.np > 0 ? H.np : static_cast<int32_t>(std::max<int64_t>(1, (H.A.nnz + npw - 1) / npw));
   }
+  int32_t steps_per_tick() const {
+    return cfg_.steps_per_tick > 0 ? cfg_.steps_per_tick : kDefaultStepsPerTick;
+  }
   // A request arrives (at q->t_arrive on the scheduler's clock).
   void arrive(std::unique_ptr<Req> q) {
     q->np = np_of(q->r.matrix);
+    q->copies = std::max(1, std::min(steps_per_tick(), q->r.steps));
     layout_req(*q, pool_[q->r.matrix].A);
     q->st = kWaiting;
     waiting_.push_back(q.get());
@@ -494,8 +521,9 @@ class Scheduler {
       double at = 0;
       if (!ex_.done(inflight_.front(), &at)) break;
       Tick &t = inflight_.front();
-      for (Req *q : t.reqs)
-        if (q->last_tick == t.id && q->enq == q->r.steps) {
+      for (const Entry &e : t.ent) {
+        Req *q = e.q;
+        if (e.step == q->r.steps - 1) {  // the request's last step: once per request
           if (msrep_status st = ex_.keep_y(*q)) err = st;
           finish(*q, MSREP_OK, at);
           res_[q->r.matrix].refs--;
@@ -504,6 +532,7 @@ class Scheduler {
           free_slots_.push_back(q->slot);
           ex_.released(*q);
         }
+      }
       inflight_.pop_front();
       admitted_.erase(std::remove_if(admitted_.begin(), admitted_.end(),
                                      [](Req *q) { return q->st == kDone; }),
@@ -514,23 +543,32 @@ class Scheduler {
     if (static_cast<int>(inflight_.size()) < kInflight) {
       Tick t;
       t.id = tick_id_;
-      // ready requests, at most kTickMax, taken round robin over the
-      // admitted list so that none waits more than one tick for a turn
+      // ready requests taken round robin over the admitted list, so that
+      // none waits more than one tick for a turn; each runs its next steps,
+      // up to its copies, while the tick has room (kTickMax steps)
       const size_t na = admitted_.size();
-      for (size_t j = 0; j < na && static_cast<int>(t.reqs.size()) < kTickMax; ++j) {
+      std::vector<Req *> took;
+      for (size_t j = 0; j < na && static_cast<int>(t.ent.size()) < kTickMax; ++j) {
         Req *q = admitted_[(rr_ + j) % na];
-        if (q->st == kReady && q->enq < q->r.steps) t.reqs.push_back(q);
+        if (q->st != kReady || q->enq >= q->r.steps) continue;
+        const int32_t room = kTickMax - static_cast<int32_t>(t.ent.size());
+        const int32_t k = std::min({q->copies, q->r.steps - q->enq, room});
+        for (int32_t c = 0; c < k; ++c) t.ent.push_back(Entry{q, q->enq + c, c});
+        took.push_back(q);
       }
-      if (na) rr_ = (rr_ + t.reqs.size()) % na;
-      if (!t.reqs.empty()) {
-        peak_active_ = std::max(peak_active_, static_cast<int32_t>(t.reqs.size()));
+      if (na) rr_ = (rr_ + took.size()) % na;
+      if (!t.ent.empty()) {
+        t.requests = static_cast<int32_t>(took.size());
+        peak_active_ = std::max(peak_active_, t.requests);
         if (msrep_status st = ex_.launch(t, res_)) {
           err = st;
           return progressed;
         }
-        for (Req *q : t.reqs) {
-          q->enq++;
+        for (const Entry &e : t.ent) {
+          Req *q = e.q;
+          q->enq = e.step + 1;
           q->last_tick = t.id;
+          q->last_copy = e.copy;
           if (q->enq == q->r.steps) q->st = kDraining;
         }
         inflight_.push_back(std::move(t));
@@ -752,6 +790,8 @@ msrep_status check_cfg_pool(const msrep_serve_cfg *cfg, const msrep_host_mat *po
     return fail(MSREP_ERR_ARG, "%s: max_slots must be 1..4096", who);
   if (!(cfg->time_scale > 0)) return fail(MSREP_ERR_ARG, "%s: time_scale must be > 0", who);
   if (cfg->max_queue < 0) return fail(MSREP_ERR_ARG, "%s: max_queue must be >= 0", who);
+  if (cfg->steps_per_tick < 0 || cfg->steps_per_tick > kMaxStepsPerTick)
+    return fail(MSREP_ERR_ARG, "%s: steps_per_tick must be 0..%d", who, kMaxStepsPerTick);
   const int32_t vt = pool[0].A.vtype;
   if (vt != MSREP_F64 && vt != MSREP_F32)
     return fail(MSREP_ERR_UNSUPPORTED, "%s: pool matrices must be F64 or F32", who);

@@ -4,6 +4,10 @@
 // waits for them and totals the elapsed times by kernel name.  Off by
 // default, so the SpMV path records nothing.  Every event record adds a gap
 // of a few microseconds between kernels, hence the filter.
+//
+// msrep_probe_stream: plain 16-byte streams (a read and a copy) that give
+// the HBM rate reachable on this GPU, the practical ceiling for the SpMV
+// kernels' streams.
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -133,4 +137,57 @@ extern "C" int32_t msrep_timing_read(msrep_kernel_time *out, int32_t cap) {
   for (size_t i = 0; i < agg.size() && static_cast<int32_t>(i) < cap; ++i) out[i] = agg[i];
   ok();
   return static_cast<int32_t>(agg.size());
+}
+
+namespace msrep {
+namespace {
+
+// One pass over n 16-byte words; the xor of everything read decides a store
+// that never happens for real data, so the loads cannot be dropped.
+__global__ __launch_bounds__(256) void probe_read(const u32x4 *__restrict__ a, size_t n,
+                                                  u32x4 *__restrict__ sink) {
+  u32x4 acc = {0u, 0u, 0u, 0u};
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
+    const u32x4 v = __builtin_nontemporal_load(a + i);
+    acc.x ^= v.x;
+    acc.y ^= v.y;
+    acc.z ^= v.z;
+    acc.w ^= v.w;
+  }
+  if ((acc.x & acc.y & acc.z & acc.w) == 0xffffffffu) sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void probe_copy(const u32x4 *__restrict__ a, size_t n,
+                                                  u32x4 *__restrict__ b) {
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    b[i] = __builtin_nontemporal_load(a + i);
+}
+
+}  // namespace
+}  // namespace msrep
+
+extern "C" msrep_status msrep_probe_stream(const void *src, void *dst, size_t bytes, int32_t mode,
+                                           int32_t blocks, void *stream) {
+  if (!src || !dst || (reinterpret_cast<uintptr_t>(src) & 15) ||
+      (reinterpret_cast<uintptr_t>(dst) & 15))
+    return fail(MSREP_ERR_ARG, "msrep_probe_stream: NULL or misaligned buffer");
+  if (bytes == 0 || (bytes & 15) || (mode != 0 && mode != 1) || blocks < 0)
+    return fail(MSREP_ERR_ARG, "msrep_probe_stream: bad size, mode or block count");
+  if (mode == 1) {
+    const char *a = static_cast<const char *>(src);
+    const char *b = static_cast<const char *>(dst);
+    if (a < b + bytes && b < a + bytes)
+      return fail(MSREP_ERR_ARG, "msrep_probe_stream: copy buffers overlap");
+  }
+  const int g = blocks ? blocks : 65536;
+  hipStream_t s = as_stream(stream);
+  const size_t n = bytes / 16;
+  if (mode == 0)
+    hipLaunchKernelGGL(probe_read, dim3(g), dim3(256), 0, s, static_cast<const u32x4 *>(src), n,
+                       static_cast<u32x4 *>(dst));
+  else
+    hipLaunchKernelGGL(probe_copy, dim3(g), dim3(256), 0, s, static_cast<const u32x4 *>(src), n,
+                       static_cast<u32x4 *>(dst));
+  MSREP_LAUNCHED(mode == 0 ? "probe_read" : "probe_copy");
+  return ok();
 }

@@ -99,7 +99,8 @@ class Server:
     latency statistics."""
 
     def __init__(self, pool: Sequence, budget_bytes: int, max_slots: int = 256,
-                 nnz_per_wave: int = 1024, vtype: int = F64, seed: int = 0, max_queue: int = 0):
+                 nnz_per_wave: int = 1024, vtype: int = F64, seed: int = 0, max_queue: int = 0,
+                 steps_per_tick: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise MsrepError(-4, "msrep_server needs a GPU")
@@ -108,7 +109,8 @@ class Server:
         self._hm, self._keep = _host_pool(self.pool, vtype, pinned=True)
         self._arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
         self._cfg = _ServeCfg(self._arena.data_ptr(), int(budget_bytes), int(max_slots),
-                              int(nnz_per_wave), int(seed), 1.0, 0, int(max_queue))
+                              int(nnz_per_wave), int(seed), 1.0, 0, int(max_queue),
+                              int(steps_per_tick))
         self.vtype = vtype
         self._ys = {}
         h = ctypes.c_void_p()
@@ -162,11 +164,13 @@ class Server:
 
 def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 256,
           nnz_per_wave: int = 1024, vtype: int = F64, seed: int = 0, time_scale: float = 1.0,
-          keep_y: bool = False, simulate: bool = False, sim=(0.0, 0.0, -1.0), nps=None):
+          keep_y: bool = False, simulate: bool = False, sim=(0.0, 0.0, -1.0), nps=None,
+          steps_per_tick: int = 0):
     """Run a request trace.  pool: list of synth.Csr (or objects with m, n,
     ptr, col, val); trace: list of synth.Request.  keep_y: True to return
     every request's last y, or a collection of trace indices to return only
-    theirs.  Returns (results, stats)."""
+    theirs.  steps_per_tick: most steps of one request per tick (0: the
+    library's default).  Returns (results, stats)."""
     L = load_library()
     _bind(L)
     keep = []
@@ -207,7 +211,8 @@ def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 2
     if not simulate:
         arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
     cfg = _ServeCfg(None if arena is None else arena.data_ptr(), int(budget_bytes), int(max_slots),
-                    int(nnz_per_wave), int(seed), float(time_scale), int(bool(keep_y)), 0)
+                    int(nnz_per_wave), int(seed), float(time_scale), int(bool(keep_y)), 0,
+                    int(steps_per_tick))
     st = _ServeStats()
     if simulate:
         rc = L.msrep_serve_simulate(ctypes.byref(cfg), hm, len(pool), tr, n, res,

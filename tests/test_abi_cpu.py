@@ -175,6 +175,21 @@ def test_timing_toggle_and_empty_read():
     assert L.msrep_timing_read(None, -1) == -1
 
 
+def test_probe_stream_argument_errors():
+    """The stream probe refuses NULL or misaligned buffers, sizes that are
+    not whole 16-byte words, unknown modes and overlapping copies, before
+    any launch."""
+    L = _lib()
+    assert L.msrep_probe_stream(None, 0x1000, 4096, 0, 0, None) == -1
+    assert L.msrep_probe_stream(0x1008, 0x2000, 4096, 0, 0, None) == -1
+    assert L.msrep_probe_stream(0x1000, 0x2000, 4095, 0, 0, None) == -1
+    assert L.msrep_probe_stream(0x1000, 0x2000, 0, 1, 0, None) == -1
+    assert L.msrep_probe_stream(0x1000, 0x2000, 4096, 2, 0, None) == -1
+    assert L.msrep_probe_stream(0x1000, 0x2000, 4096, 0, -1, None) == -1
+    assert L.msrep_probe_stream(0x1000, 0x1800, 4096, 1, 0, None) == -1
+    assert b"overlap" in L.msrep_last_error()
+
+
 def test_spmm_argument_errors():
     """msrep_spmm: CSR only, ld >= k, k >= 0, workspace per pass width, all
     checked before any launch."""
@@ -286,6 +301,11 @@ def test_server_argument_errors():
     assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
     cfg = _abi._ServeCfg(0x1000, 1 << 20, 4, 1024, 0, 1.0, 0, -1)  # negative max_queue
     assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
+    for spt in (-1, 17):  # steps_per_tick outside 0..16
+        cfg = _abi._ServeCfg(0x1000, 1 << 20, 4, 1024, 0, 1.0, 0, 0, spt)
+        assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
+        assert b"steps_per_tick" in L.msrep_last_error()
+    assert ctypes.sizeof(_abi._ServeCfg) == 56
     r = _abi._Request(0, 0.0, 0, 1)
     assert L.msrep_server_submit(None, ctypes.byref(r), None) == -1
     assert L.msrep_server_poll(None, None, 0, 0) == -1

@@ -56,6 +56,27 @@ def test_alone_equals_mix():
         assert np.array_equal(alone[0].y, r.y), q.rid
 
 
+@pytest.mark.parametrize("vt", [0, 1])
+def test_steps_per_tick_same_results(vt):
+    """A request's steps run several to a tick, each on a vector copy of its
+    own: the last y is bit-identical with one step per tick, eight or
+    sixteen, and matches the oracle; 1..40 steps per request leave partial
+    groups of every size."""
+    pool = _pool()
+    trace = synth.serving_trace(20, rate=5e4, pool=len(pool), seed=9, k_lo=1, k_hi=40)
+    outs = {}
+    for spt in (1, 8, 16):
+        res, st = serving.serve(pool, trace, budget_bytes=2 << 30, vtype=vt, seed=SEED,
+                                keep_y=True, steps_per_tick=spt)
+        assert st["n_done"] == len(trace) and st["n_failed"] == 0
+        outs[spt] = (res, st)
+    assert outs[8][1]["ticks"] < outs[1][1]["ticks"]
+    _check_last_y(pool, trace, outs[8][0], vt)
+    for spt in (8, 16):
+        for q, a, b in zip(trace, outs[1][0], outs[spt][0]):
+            assert np.array_equal(a.y, b.y), (spt, q.rid)
+
+
 def test_small_budget_queues():
     pool = _pool(4, m_hi=20_000)
     trace = synth.serving_trace(12, rate=1e6, pool=len(pool), seed=7, k_lo=2, k_hi=4)

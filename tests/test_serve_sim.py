@@ -19,16 +19,25 @@ def _pool(count=6, m_hi=20_000):
     return [A for A, _ in synth.batched_set(count, seed=3, m_lo=500, m_hi=m_hi)]
 
 
-def _bytes(A, np_, xb=8):
+SPT = 8  # the library's default steps per tick: a request holds min(steps, SPT) vector copies
+
+
+def _bytes(A, np_, xb=8, steps=1):
     r = lambda b: (b + 255) // 256 * 256
+    c = max(1, min(steps, SPT))
     mat = r(4 * (A.m + 1)) + r(4 * A.nnz) + r(xb * A.nnz)
-    req = r(xb * A.n) + r(xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) + r(16 * np_)
+    req = (c * r(xb * A.n) + c * r(xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) +
+           r(16 * np_ * c))
     return mat, req
+
+
+def _np(A):
+    return max(1, -(-A.nnz // 1024))
 
 
 def test_all_complete_with_a_large_budget():
     pool = _pool()
-    trace = synth.serving_trace(40, rate=2000.0, pool=len(pool), seed=1, k_lo=3, k_hi=12)
+    trace = synth.serving_trace(40, rate=20000.0, pool=len(pool), seed=1, k_lo=3, k_hi=12)
     res, st = serving.serve(pool, trace, budget_bytes=1 << 34, simulate=True)
     assert all(r.status == 0 for r in res)
     for r, q in zip(res, trace):
@@ -43,9 +52,10 @@ def test_all_complete_with_a_large_budget():
 def test_request_that_can_never_fit_fails_alone():
     pool = _pool()
     big = max(range(len(pool)), key=lambda k: pool[k].nnz)
-    mat, req = _bytes(pool[big], max(1, -(-pool[big].nnz // 1024)))
+    mat, req = _bytes(pool[big], _np(pool[big]), steps=5)
     budget = mat + req - 4096  # too small for the largest matrix only
-    others = [k for k in range(len(pool)) if sum(_bytes(pool[k], max(1, -(-pool[k].nnz // 1024)))) + 512 <= budget]
+    others = [k for k in range(len(pool))
+              if sum(_bytes(pool[k], _np(pool[k]), steps=4)) + 512 <= budget]
     trace = [synth.Request(0, 0.0, big, 5)] + [synth.Request(i + 1, 1e-4 * i, k, 4)
                                                for i, k in enumerate(others)]
     res, st = serving.serve(pool, trace, budget_bytes=budget, simulate=True)
@@ -56,17 +66,39 @@ def test_request_that_can_never_fit_fails_alone():
 
 def test_budget_bounds_residency_and_queues():
     pool = _pool()
-    sizes = [sum(_bytes(A, max(1, -(-A.nnz // 1024)))) for A in pool]
-    budget = max(sizes) + 1024  # room for one request of any matrix at a time
+    # room for one request of any matrix (at the most steps) at a time
+    budget = max(sum(_bytes(A, _np(A), steps=6)) for A in pool) + 1024
     trace = synth.serving_trace(30, rate=1e6, pool=len(pool), seed=2, k_lo=2, k_hi=6)
     res, st = serving.serve(pool, trace, budget_bytes=budget, simulate=True)
     assert all(r.status == 0 for r in res)
     assert st["peak_bytes"] <= budget
-    # requests on different matrices never overlapped: each waited its turn
-    iv = sorted((r.t_admit, r.t_done, q.matrix) for r, q in zip(res, trace))
-    for (a0, d0, m0), (a1, d1, m1) in zip(iv, iv[1:]):
-        if m0 != m1 and sizes[m0] + sizes[m1] - 0 > budget:
+    # requests on different matrices that cannot both fit never overlapped
+    size = [sum(_bytes(pool[q.matrix], _np(pool[q.matrix]), steps=q.steps)) for q in trace]
+    iv = sorted((r.t_admit, r.t_done, q.matrix, size[i])
+                for i, (r, q) in enumerate(zip(res, trace)))
+    for (a0, d0, m0, s0), (a1, d1, m1, s1) in zip(iv, iv[1:]):
+        if m0 != m1 and s0 + s1 > budget:
             assert a1 >= d0 - 1e-12
+
+
+def test_steps_per_tick_batches_a_requests_steps():
+    """A tick runs up to steps_per_tick steps of each request: one step per
+    tick needs at least as many ticks as the longest request has steps;
+    eight per tick need far fewer, and every request still completes."""
+    pool = _pool()
+    trace = synth.serving_trace(20, rate=200.0, pool=len(pool), seed=6, k_lo=10, k_hi=40)
+    one = serving.serve(pool, trace, budget_bytes=1 << 34, simulate=True, steps_per_tick=1)
+    eight = serving.serve(pool, trace, budget_bytes=1 << 34, simulate=True, steps_per_tick=8)
+    assert all(r.status == 0 for r in one[0]) and all(r.status == 0 for r in eight[0])
+    assert one[1]["ticks"] >= max(q.steps for q in trace)
+    assert eight[1]["ticks"] * 4 <= one[1]["ticks"]
+    assert eight[1]["p50_ms"] < one[1]["p50_ms"]
+    # a tick never holds more than 240 steps: 300 requests of 16 steps arriving
+    # at once take at least 300*16/240 ticks
+    burst = [synth.Request(i, 0.0, i % len(pool), 16) for i in range(300)]
+    res, st = serving.serve(pool, burst, budget_bytes=1 << 36, max_slots=300, simulate=True,
+                            steps_per_tick=16)
+    assert all(r.status == 0 for r in res) and st["ticks"] >= 300 * 16 // 240
 
 
 def test_max_slots_one_serialises():
