@@ -37,7 +37,7 @@ int32_t parts_of(const msrep_mat &A, int64_t npw) {
 
 struct Layout {
   std::vector<size_t> parts_off, lptr_off;
-  size_t items_off, waves_off, mats_off, xy_off, carry_off, total;
+  size_t items_off, groups_off, mats_off, xy_off, carry_off, total;
   int64_t n_items;
 };
 
@@ -57,7 +57,7 @@ Layout layout(int32_t count, const msrep_mat *mats, const msrep_tune *tunes) {
     L.n_items += np;
   }
   L.items_off = take(sizeof(int2) * static_cast<size_t>(L.n_items));
-  L.waves_off = take(sizeof(int64_t) * (kMaxWaves + 1));
+  L.groups_off = take(sizeof(int64_t) * (kXcds + 1));
   L.mats_off = take(sizeof(BatchMat) * static_cast<size_t>(count));
   L.xy_off = take(sizeof(BatchXY) * static_cast<size_t>(count));
   L.carry_off = take(16 * static_cast<size_t>(L.n_items));
@@ -114,7 +114,7 @@ msrep_status capture_kernels(msrep_plan P, double alpha, double beta) {
   src.mats = reinterpret_cast<const BatchMat *>(P->ws + P->L.mats_off);
   src.xy = P->xy_d;
   src.items = reinterpret_cast<const int2 *>(P->ws + P->L.items_off);
-  src.wave_begin = reinterpret_cast<const int64_t *>(P->ws + P->L.waves_off);
+  src.group_begin = reinterpret_cast<const int64_t *>(P->ws + P->L.groups_off);
   src.n_items = P->n_items;
   src.n_waves = P->n_waves;
   src._pad = 0;
@@ -232,7 +232,7 @@ extern "C" msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
       item_nnz.push_back(item_cost(A.nnz, A.m, np, p));
     }
   }
-  // resident wavefronts and their equal-work runs of consecutive items
+  // resident wavefronts; the items in equal-work groups, one per XCD
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, P->device) != hipSuccess)
     return bail(fail(MSREP_ERR_HIP, "hipGetDeviceProperties"));
@@ -242,12 +242,13 @@ extern "C" msrep_status msrep_plan_create(int32_t count, const msrep_mat *mats,
   waves = std::min<int64_t>({waves, kMaxWaves, std::max<int64_t>(1, L.n_items)});
   P->grid = static_cast<int>((waves + wpb - 1) / wpb);
   P->n_waves = static_cast<int32_t>(waves);
-  std::vector<int64_t> wb(P->n_waves + 1, L.n_items);
-  equal_work_runs(item_nnz.data(), L.n_items, P->n_waves, wb.data());
+  const int32_t groups = std::min<int32_t>(kXcds, P->grid);
+  std::vector<int64_t> wb(groups + 1, L.n_items);
+  equal_work_runs(item_nnz.data(), L.n_items, groups, wb.data());
   P->xy_d = reinterpret_cast<BatchXY *>(P->ws + L.xy_off);
   if (hipMemcpyAsync(P->ws + L.items_off, items.data(), sizeof(int2) * items.size(),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(P->ws + L.waves_off, wb.data(), sizeof(int64_t) * wb.size(),
+      hipMemcpyAsync(P->ws + L.groups_off, wb.data(), sizeof(int64_t) * wb.size(),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(P->ws + L.mats_off, bm.data(), sizeof(BatchMat) * bm.size(),
                      hipMemcpyHostToDevice, s) != hipSuccess ||

@@ -6,8 +6,13 @@
 // Both callers describe their work items through a source type with
 //   __device__ void get(int64_t it, BItem &out) const;   // item it (it may
 //                                                        // differ per lane)
-//   __device__ void waves(int32_t w, int64_t &lo, int64_t &hi) const;
+//   __device__ void group(int32_t g, int32_t G, int64_t &lo, int64_t &hi) const;
+//                                  // items [lo, hi) of group g of G
 //   int64_t n_items; int32_t n_waves;
+// The items are split into one contiguous group per XCD; the wavefronts of
+// an XCD sweep its group together (wavefront j of the XCD's W takes items
+// lo + j, lo + j + W, ...), so at any moment an XCD works on a window of
+// consecutive items, i.e. on a few matrices, whose x vectors its L2 holds.
 // The batched plan reads a precomputed item list from device memory; a
 // serving tick passes its active requests in the kernel arguments, so a tick
 // needs no table copy from the host.
@@ -58,21 +63,21 @@ __device__ __forceinline__ void bitem_from(const BatchMat &M, const BatchXY &xy,
 }
 
 // The batched plan's items: a device list of (matrix, partition) pairs and
-// equal-work runs of it, one per wavefront.
+// its split into equal-work groups, one per XCD.
 struct PlanSrc {
   const BatchMat *mats;
   const BatchXY *xy;
   const int2 *items;
-  const int64_t *wave_begin;  // n_waves + 1 entries
+  const int64_t *group_begin;  // G + 1 entries, G = min(8, grid)
   int64_t n_items;
   int32_t n_waves, _pad;
   __device__ void get(int64_t it, BItem &o) const {
     const int2 wk = items[it];
     bitem_from(mats[wk.x], xy[wk.x], wk.y, o);
   }
-  __device__ void waves(int32_t w, int64_t &lo, int64_t &hi) const {
-    lo = uniform(wave_begin[w]);
-    hi = uniform(wave_begin[w + 1]);
+  __device__ void group(int32_t g, int32_t, int64_t &lo, int64_t &hi) const {
+    lo = uniform(group_begin[g]);
+    hi = uniform(group_begin[g + 1]);
   }
 };
 
@@ -123,15 +128,16 @@ struct TickSrc {
     o.y = static_cast<char *>(o.y) + c * S->y_stride;
     o.carry += c * 2 * static_cast<int64_t>(S->M.np);
   }
-  // equal item counts per wavefront (a request's partitions hold equal
+  // equal item counts per group (a request's partitions hold equal
   // nonzeros, so items cost about the same)
-  __device__ void waves(int32_t w, int64_t &lo, int64_t &hi) const {
-    lo = n_items * w / n_waves;
-    hi = n_items * (w + 1) / n_waves;
+  __device__ void group(int32_t g, int32_t G, int64_t &lo, int64_t &hi) const {
+    lo = n_items * g / G;
+    hi = n_items * (g + 1) / G;
   }
 };
 
-// Resident wavefronts, each draining its run of work items.
+// Resident wavefronts; those of one XCD (blocks are dealt to the XCDs round
+// robin by id) sweep that XCD's group of items together.
 template <int VT, int K, bool BETA0, int PF, class Src>
 __global__ __launch_bounds__(512) void spmv_items_persistent(const Src src, double alpha,
                                                             double beta) {
@@ -139,12 +145,15 @@ __global__ __launch_bounds__(512) void spmv_items_persistent(const Src src, doub
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int wid = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
-  const int w = xcd_block(blockIdx.x, gridDim.x) * wpb + wid;
-  if (w >= src.n_waves) return;
+  const int nb = static_cast<int>(gridDim.x);
+  const int G = nb < kXcds ? nb : kXcds;
+  const int g = static_cast<int>(blockIdx.x) % G;
+  const int j = (static_cast<int>(blockIdx.x) / G) * wpb + wid;  // wavefront within the group
+  const int wg = (nb / G + (g < nb % G ? 1 : 0)) * wpb;             // wavefronts of the group
   unsigned char *my = lds_raw + wid * seg_lds_per_wave<VT, K>();
   int64_t lo, hi;
-  src.waves(w, lo, hi);
-  for (int64_t it = lo; it < hi; ++it) {
+  src.group(g, G, lo, hi);
+  for (int64_t it = lo + j; it < hi; it += wg) {
     BItem b;
     src.get(it, b);
     const int32_t m = uniform(b.m), n = uniform(b.n), np = uniform(b.np), p = uniform(b.p);
