@@ -141,11 +141,13 @@ def pmc_summary(fetch_dir, write_dir, kernel, key, command):
     for d, ctr in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         c = _read_counters(d)
         kv = [v for (k, n), vs in c.items() if n == ctr and kernel in k for v in vs]
+        # the calibration copy is the largest copy of the run (the matrix
+        # uploads are many small staged copies)
         cv = [v for (k, n), vs in c.items() if n == ctr and "copy" in k.lower() for v in vs]
         if not kv or not cv:
             raise SystemExit("no %s readings for %s / the copy kernel in %s" % (ctr, kernel, d))
-        scale = COPY_CAL_BYTES / (float(np.median(cv)) * 1024.0)
-        out[ctr] = (float(np.median(kv)), float(np.median(cv)), scale)
+        scale = COPY_CAL_BYTES / (float(max(cv)) * 1024.0)
+        out[ctr] = (float(np.median(kv)), float(max(cv)), scale)
     fetch = out["FETCH_SIZE"][0] * 1024.0 * out["FETCH_SIZE"][2]
     write = out["WRITE_SIZE"][0] * 1024.0 * out["WRITE_SIZE"][2]
     rec = {"key": key, "kernel": kernel, "bytes_per_launch": int(fetch + write),
@@ -184,6 +186,23 @@ def trace_summary(trace_dir, out_name, command, bench_json=None):
         lines.append("%-72s %8s %12.2f %12.2f %7.2f" % (
             short, r.get("Calls"), float(r.get("AverageNs", 0)) / 1e3,
             float(r.get("TotalDurationNs", 0)) / 1e3, float(r.get("Percentage", 0))))
+    # one kernel runs on several matrices in one command: the per-launch
+    # trace split by launch grid (the grid tells the matrices apart)
+    traces = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if traces:
+        by = {}
+        for r in csv.DictReader(open(traces[0])):
+            name = r.get("Kernel_Name", "").replace("(anonymous namespace)::", "")
+            if "msrep::" not in name:
+                continue
+            grid = r.get("Grid_Size_X", r.get("Grid_Size", "?"))
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            by.setdefault((name.split("(")[0][:60], grid), []).append(d)
+        lines += ["", "# per launch grid (msrep kernels): calls, average and median us",
+                  "%-60s %10s %8s %12s %12s" % ("kernel", "grid", "calls", "avg_us", "median_us")]
+        for (name, grid), ds in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("%-60s %10s %8d %12.2f %12.2f" % (name, grid, len(ds), sum(ds) / len(ds),
+                                                         float(np.median(ds))))
     if bench_json:
         rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
         rf = rec.get("roofline", {})

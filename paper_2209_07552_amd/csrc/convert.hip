@@ -100,17 +100,33 @@ __global__ __launch_bounds__(kBlock) void expand_tile(const int32_t *__restrict_
     if (base + i <= last) out[base + i] = mark[i + i / 32];
 }
 
-// ptr of a row-sorted COO: ptr[r] = first position whose row is >= r
+// ptr of a row-sorted COO: ptr[r] = first position whose row is >= r.
+// Thread t takes positions 4t .. 4t+3 (and nnz itself, for the rows after
+// the last entry): position k writes the pointers of the rows from the one
+// after row[k-1] up to row[k].
 __global__ void rows_to_ptr(const int32_t *__restrict__ row, int64_t nnz, int32_t m,
                             int32_t *__restrict__ ptr) {
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k <= nnz;
-       k += int64_t(gridDim.x) * blockDim.x) {
-    int64_t lo = k == 0 ? 0 : static_cast<int64_t>(row[k - 1]) + 1;
-    int64_t hi = k == nnz ? m : static_cast<int64_t>(row[k]);
-    lo = lo < 0 ? 0 : lo;
-    hi = hi > m ? m : hi;
-    for (int64_t r = lo; r <= hi; ++r) ptr[r] = static_cast<int32_t>(k);
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; 4 * t <= nnz;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t k0 = 4 * t;
+    int64_t prev = k0 == 0 ? -1 : static_cast<int64_t>(row[k0 - 1]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t k = k0 + i;
+      if (k > nnz) break;
+      const int64_t cur = k == nnz ? m : static_cast<int64_t>(row[k]);
+      const int64_t lo = prev + 1 < 0 ? 0 : prev + 1;
+      const int64_t hi = cur > m ? m : cur;
+      for (int64_t r = lo; r <= hi; ++r) ptr[r] = static_cast<int32_t>(k);
+      prev = cur;
+    }
   }
+}
+
+// Threads of rows_to_ptr for nnz positions.
+int grid_for_ptr(int64_t nnz) {
+  const int64_t g = (nnz / 4 + 1 + 255) / 256;
+  return static_cast<int>(g < 1 ? 1 : (g > 65536 ? 65536 : g));
 }
 
 // --------------------------------------------------- LSD radix sort
@@ -403,7 +419,7 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
         MSREP_HIP(hipMemcpyAsync(dptr, S.ptr, 4 * (static_cast<size_t>(S.major_extent) + 1),
                                  hipMemcpyDeviceToDevice, s));
       else {
-        hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for(nnz + 1)), dim3(256), 0, s, S.exp, nnz,
+        hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for_ptr(nnz)), dim3(256), 0, s, S.exp, nnz,
                            S.major_extent, dptr);
         MSREP_LAUNCHED("rows_to_ptr");
       }
@@ -446,7 +462,7 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
     // the pointer from the sorted keys: ptr[c] = the first position whose key
     // is >= c (each position writes the pointers of the keys it starts; no
     // atomics, so heavy columns cost nothing extra)
-    hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for(nnz + 1)), dim3(256), 0, s,
+    hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for_ptr(nnz)), dim3(256), 0, s,
                        reinterpret_cast<const int32_t *>(sorted), nnz, key_range, dptr);
     MSREP_LAUNCHED("rows_to_ptr");
   } else {
