@@ -168,6 +168,27 @@ def pmc_summary(fetch_dir, write_dir, kernel, key, command):
     print(json.dumps(rec))
 
 
+def counter_summary(dirs, out_name, kernels, command):
+    """Mean per dispatch of every counter of rocprofv3 --pmc runs (one
+    directory per pass) for the kernels whose names contain one of
+    `kernels`, as a short text table under profiles/."""
+    rows = {}
+    for d in dirs:
+        for (k, ctr), vs in _read_counters(d).items():
+            name = k.replace("(anonymous namespace)::", "").split("(")[0]
+            if not any(x in name for x in kernels):
+                continue
+            rows.setdefault(name[:70], {})[ctr] = (float(np.mean(vs)), len(vs))
+    lines = ["# rocprofv3 counters, mean per dispatch", "# command: " + command, ""]
+    for name, ctrs in sorted(rows.items()):
+        lines.append(name)
+        for ctr, (v, c) in sorted(ctrs.items()):
+            lines.append("    %-40s %18.1f   (%d dispatches)" % (ctr, v, c))
+    path = os.path.join(ROOT, "profiles", out_name)
+    open(path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def trace_summary(trace_dir, out_name, command, bench_json=None):
     """Kernel-trace statistics (rocprofv3 --kernel-trace --stats, csv) as a
     short text table under profiles/; with the traced run's own JSON line,
@@ -606,6 +627,8 @@ def main():
                     help="also run one plain 256 MiB copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "KEY"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"))
+    ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
+                    help="OUT_NAME KERNELS(comma-separated) PMC_DIR...: counter means per kernel")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--bench-json", default=None, help="the traced run's output (trace summary)")
     args = ap.parse_args()
@@ -614,6 +637,10 @@ def main():
         return 0
     if args.trace_summary:
         trace_summary(*args.trace_summary, command=args.command, bench_json=args.bench_json)
+        return 0
+    if args.counter_summary:
+        out_name, kernels, *dirs = args.counter_summary
+        counter_summary(dirs, out_name, kernels.split(","), command=args.command)
         return 0
     if args.gpus != 1:
         print("bench.py: one GPU only; --gpus %d is not supported (how the path would "
