@@ -1,6 +1,7 @@
 """GPU parity of msrep_convert: every direction between CSR, CSC,
 row-sorted COO and column-sorted COO, bit-exact against the oracle's stable conversions (indices
-and values), on adversarial small matrices and at full R-MAT scale."""
+and values), on adversarial small matrices, at full R-MAT scale and on the
+full-size stencil."""
 import numpy as np
 import pytest
 
@@ -116,3 +117,25 @@ def test_round_trip_column_sorted_rmat20():
     R = pk.msrep_convert(pk.msrep_convert(pk.msrep_convert(K, pk.CSC), pk.COO), pk.CSR)
     ptr, idx, _, val = _host(R)
     assert np.array_equal(ptr, A.ptr) and np.array_equal(idx, A.col) and np.array_equal(val, A.val)
+
+
+def test_convert_stencil_full_size():
+    """The benchmark's 256^3 stencil (117M nonzeros, 2^24 rows): CSR -> CSC and
+    CSR -> row-sorted COO bit-exact against the oracle's conversions (the
+    stencil is symmetric, so its CSC arrays also equal its CSR arrays)."""
+    A, _ = synth.stencil7_csr(256, seed=0)
+    M = pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val)
+    C = pk.msrep_convert(M, pk.CSC)
+    cptr, crow, _, cval = _host(C)
+    del C
+    optr, orow, _, perm = oracle.transpose(A.m, A.n, A.ptr, A.col)
+    assert np.array_equal(cptr, optr) and np.array_equal(crow, orow)
+    assert np.array_equal(cval, A.val[perm])
+    assert np.array_equal(cptr, A.ptr) and np.array_equal(crow, A.col)
+    del cptr, crow, cval, optr, orow, perm
+    O = pk.msrep_convert(M, pk.COO)
+    _, r, c, v = _host(O)
+    assert np.array_equal(r, oracle.csr_to_coo(A.m, A.ptr))
+    assert np.array_equal(c, A.col) and np.array_equal(v, A.val)
+    del O, M
+    torch.cuda.empty_cache()
