@@ -16,7 +16,7 @@ Infinity Cache, and HIP events on the library's stream bracket each SpMV, so
 the reported throughput is the SpMV time alone.  A warm (back-to-back) figure
 is reported beside it.
 
-Prints one JSON line (rank 0, N = 1).  --gpus N > 1 exits: this build runs on
+Prints one JSON line (rank 0, N = 1).  --gpus N > 1 exits: the benchmark runs on
 one GPU.
 """
 from __future__ import annotations
