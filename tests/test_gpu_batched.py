@@ -114,3 +114,27 @@ def test_batched_full_set_every_matrix(vt, pf):
     plan.destroy()
     del Ms, xs, ys
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("count", [1, 3, 9, 40])
+def test_batched_tiny_plans(count):
+    """Plans whose grid has fewer workgroups than the GPU has XCDs (one item
+    group per workgroup) and just above: every matrix against the oracle."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(count)
+    mats = []
+    for _ in range(count):
+        m, n = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        mats.append(synth.uniform_csr(m, n, min(3, n), seed=int(rng.integers(1 << 30)))[0])
+    Ms = [pk.Mat(pk.CSR, pk.F64, A.m, A.n, ptr=A.ptr, idx=A.col, val=A.val) for A in mats]
+    plan = pk.msrep_plan_create(Ms, [pk.Tune(nnz_per_wave=1 << 20, waves_per_wg=4)] * count, 2.0)
+    assert plan.items() == count
+    xs = [rng.uniform(-1, 1, A.n) for A in mats]
+    xd = [torch.from_numpy(x).to(dev) for x in xs]
+    yd = [torch.full((A.m,), float("nan"), dtype=torch.float64, device=dev) for A in mats]
+    pk.msrep_spmv_batched(plan, xd, yd)
+    torch.cuda.synchronize()
+    for k, A in enumerate(mats):
+        ref, s = oracle.spmv_csr(A.m, A.n, A.ptr, A.col, A.val, xs[k], 2.0)
+        assert_close(yd[k].cpu().numpy(), ref, s, F64_TOL, "tiny plan %d matrix %d" % (count, k))
+    plan.destroy()
