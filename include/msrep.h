@@ -520,6 +520,11 @@ msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
  *     values that receives the last y before the request is reported done.
  *     MSREP_ERR_BUSY when max_queue requests already wait; MSREP_ERR_ARG for
  *     a malformed request; the error that stopped the server otherwise.
+ *   msrep_server_register: adds *mat (CSR of the pool's value type, host
+ *     arrays the caller keeps valid until destroy, as for the pool) to the
+ *     running server's pool and returns its index in *index, which requests
+ *     may name from then on; the same checks as the pool at create
+ *     (MSREP_ERR_ARG), the error that stopped the server otherwise.
  *   msrep_server_poll: up to cap completions (in completion order), waiting
  *     up to timeout_ms for the first when none is ready; returns how many
  *     were written, or a negative status when the server stopped on an
@@ -528,7 +533,8 @@ msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
  *   msrep_server_destroy: waits until every submitted request has finished,
  *     stops the thread, frees the server and fills stats (may be NULL) over
  *     every completion; returns the error that stopped the server, if any.
- * Submit and poll may be called from any threads; destroy exactly once.
+ * Register, submit and poll may be called from any threads; destroy exactly
+ * once.
  */
 typedef struct msrep_server_s *msrep_server;
 
@@ -544,6 +550,8 @@ msrep_status msrep_server_create(const msrep_serve_cfg *cfg,
                                  msrep_server *out);
 msrep_status msrep_server_submit(msrep_server server, const msrep_request *req,
                                  void *y_host);
+msrep_status msrep_server_register(msrep_server server, const msrep_host_mat *mat,
+                                   int32_t *index);
 int64_t msrep_server_poll(msrep_server server, msrep_completion *out,
                           int64_t cap, int32_t timeout_ms);
 msrep_status msrep_server_destroy(msrep_server server, msrep_serve_stats *stats);

@@ -134,6 +134,7 @@ def load_library():
                                 P(_ServeStats)]),
         "msrep_server_create": (c_i32, [P(_ServeCfg), P(_HostMat), c_i32, P(c_vp)]),
         "msrep_server_submit": (c_i32, [c_vp, P(_Request), c_vp]),
+        "msrep_server_register": (c_i32, [c_vp, P(_HostMat), P(c_i32)]),
         "msrep_server_poll": (c_i64, [c_vp, P(_Completion), c_i64, c_i32]),
         "msrep_server_destroy": (c_i32, [c_vp, P(_ServeStats)]),
         "msrep_timing": (c_i32, [c_i32]),

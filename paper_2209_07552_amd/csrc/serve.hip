@@ -482,6 +482,13 @@ class Scheduler {
     const int64_t npw = std::max(1, cfg_.nnz_per_wave);
     return H.np > 0 ? H.np : static_cast<int32_t>(std::max<int64_t>(1, (H.A.nnz + npw - 1) / npw));
   }
+  // More pool matrices (the incremental server's registrations): pool
+  // points at the whole pool, the first pool_size_ entries unchanged.
+  void grow_pool(const msrep_host_mat *pool, int32_t pool_size) {
+    pool_ = pool;
+    pool_size_ = pool_size;
+    res_.resize(static_cast<size_t>(pool_size));
+  }
   int32_t steps_per_tick() const {
     return cfg_.steps_per_tick > 0 ? cfg_.steps_per_tick : kDefaultStepsPerTick;
   }
@@ -781,6 +788,21 @@ msrep_status replay(Exec &ex, const msrep_serve_cfg &cfg, const msrep_host_mat *
   return ok();
 }
 
+// One pool matrix: CSR of the pool's value type, a supported shape, and
+// host arrays (when it will be uploaded).
+msrep_status check_pool_mat(const msrep_host_mat &H, int32_t vt, bool need_arrays,
+                            const char *who, int32_t k) {
+  const msrep_mat &A = H.A;
+  if (A.fmt != MSREP_CSR || A.vtype != vt)
+    return fail(MSREP_ERR_ARG, "%s: pool matrix %d must be CSR of the pool's value type", who, k);
+  if (A.m < 0 || A.n < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31) || A.n >= (1 << 24) ||
+      H.np < 0)
+    return fail(MSREP_ERR_ARG, "%s: pool matrix %d has an unsupported shape", who, k);
+  if (need_arrays && (!A.ptr || (A.nnz > 0 && (!A.idx || !A.val))))
+    return fail(MSREP_ERR_ARG, "%s: pool matrix %d has NULL arrays", who, k);
+  return MSREP_OK;
+}
+
 msrep_status check_cfg_pool(const msrep_serve_cfg *cfg, const msrep_host_mat *pool,
                             int32_t pool_size, bool need_arena, const char *who) {
   if (!cfg || !pool || pool_size <= 0)
@@ -795,16 +817,8 @@ msrep_status check_cfg_pool(const msrep_serve_cfg *cfg, const msrep_host_mat *po
   const int32_t vt = pool[0].A.vtype;
   if (vt != MSREP_F64 && vt != MSREP_F32)
     return fail(MSREP_ERR_UNSUPPORTED, "%s: pool matrices must be F64 or F32", who);
-  for (int32_t k = 0; k < pool_size; ++k) {
-    const msrep_mat &A = pool[k].A;
-    if (A.fmt != MSREP_CSR || A.vtype != vt)
-      return fail(MSREP_ERR_ARG, "%s: pool matrix %d must be CSR of the pool's value type", who, k);
-    if (A.m < 0 || A.n < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31) || A.n >= (1 << 24) ||
-        pool[k].np < 0)
-      return fail(MSREP_ERR_ARG, "%s: pool matrix %d has an unsupported shape", who, k);
-    if (need_arena && (!A.ptr || (A.nnz > 0 && (!A.idx || !A.val))))
-      return fail(MSREP_ERR_ARG, "%s: pool matrix %d has NULL arrays", who, k);
-  }
+  for (int32_t k = 0; k < pool_size; ++k)
+    if (msrep_status st = check_pool_mat(pool[k], vt, need_arena, who, k)) return st;
   return MSREP_OK;
 }
 
@@ -859,7 +873,10 @@ extern "C" msrep_status msrep_serve_simulate(const msrep_serve_cfg *cfg,
 // an inbox, completions come back through an outbox that poll() drains.
 struct msrep_server_s {
   msrep_serve_cfg cfg{};
-  std::vector<msrep_host_mat> pool;
+  std::vector<msrep_host_mat> pool;     // the worker's pool (registrations applied)
+  std::vector<msrep_host_mat> pending;  // registered, not yet applied (under mu)
+  int32_t pool_count = 0;               // pool + pending: valid matrix indices (under mu)
+  int32_t vtype = 0;                    // the pool's value type (fixed at creation)
   int device = 0;
   std::unique_ptr<HipExec> ex;
   std::unique_ptr<Scheduler<HipExec>> sch;
@@ -878,6 +895,7 @@ struct msrep_server_s {
     (void)hipSetDevice(device);
     for (;;) {
       std::vector<std::unique_ptr<Req>> in;
+      std::vector<msrep_host_mat> reg;
       bool stopping;
       {
         std::lock_guard<std::mutex> lk(mu);
@@ -885,7 +903,13 @@ struct msrep_server_s {
           in.push_back(std::move(inbox.front()));
           inbox.pop_front();
         }
+        reg.swap(pending);
         stopping = stop;
+      }
+      if (!reg.empty()) {  // before the requests, which may name the new matrices
+        pool.insert(pool.end(), reg.begin(), reg.end());
+        ex->pool = pool.data();
+        sch->grow_pool(pool.data(), static_cast<int32_t>(pool.size()));
       }
       for (auto &q : in) {
         q->t_arrive = ex->now();
@@ -939,6 +963,8 @@ extern "C" msrep_status msrep_server_create(const msrep_serve_cfg *cfg, const ms
   auto s = std::make_unique<msrep_server_s>();
   s->cfg = *cfg;
   s->pool.assign(pool, pool + pool_size);
+  s->pool_count = pool_size;
+  s->vtype = pool[0].A.vtype;
   MSREP_HIP(hipGetDevice(&s->device));
   s->ex = std::make_unique<HipExec>(s->cfg, s->pool.data(), pool[0].A.vtype);
   s->sch = std::make_unique<Scheduler<HipExec>>(*s->ex, s->cfg, s->pool.data(), pool_size);
@@ -961,12 +987,12 @@ extern "C" msrep_status msrep_server_submit(msrep_server s, const msrep_request 
                                             void *y_host) {
   const char *who = "msrep_server_submit";
   if (!s || !req) return fail(MSREP_ERR_ARG, "%s: server or request is NULL", who);
-  if (msrep_status st = check_request(*req, static_cast<int32_t>(s->pool.size()), who, 0)) return st;
   auto q = std::make_unique<Req>();
   q->r = *req;
   q->y_host = y_host;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (msrep_status st = check_request(*req, s->pool_count, who, 0)) return st;
     if (s->err) return fail(s->err, "%s: the server stopped: %s", who, s->err_text.c_str());
     if (s->stop) return fail(MSREP_ERR_ARG, "%s: the server is being destroyed", who);
     const int64_t cap = s->cfg.max_queue > 0 ? s->cfg.max_queue : kDefaultQueue;
@@ -975,6 +1001,25 @@ extern "C" msrep_status msrep_server_submit(msrep_server s, const msrep_request 
                   static_cast<long long>(cap));
     q->key = s->submitted++;
     s->inbox.push_back(std::move(q));
+  }
+  s->cv_in.notify_one();
+  return ok();
+}
+
+extern "C" msrep_status msrep_server_register(msrep_server s, const msrep_host_mat *mat,
+                                              int32_t *index) {
+  const char *who = "msrep_server_register";
+  if (!s || !mat || !index) return fail(MSREP_ERR_ARG, "%s: server, matrix or index is NULL", who);
+  *index = -1;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (msrep_status st = check_pool_mat(*mat, s->vtype, true, who, s->pool_count))
+      return st;
+    if (s->err) return fail(s->err, "%s: the server stopped: %s", who, s->err_text.c_str());
+    if (s->stop) return fail(MSREP_ERR_ARG, "%s: the server is being destroyed", who);
+    if (s->pool_count == INT32_MAX) return fail(MSREP_ERR_SIZE, "%s: the pool is full", who);
+    s->pending.push_back(*mat);
+    *index = s->pool_count++;
   }
   s->cv_in.notify_one();
   return ok();

@@ -131,6 +131,16 @@ class Server:
         _check(self._L.msrep_server_submit(self._h, ctypes.byref(r),
                                            None if y is None else y.ctypes.data), "server_submit")
 
+    def register(self, A) -> int:
+        """Add matrix A (synth.Csr or alike) to the running server's pool;
+        returns the index requests name it by."""
+        hm, keep = _host_pool([A], self.vtype, pinned=True)
+        idx = ctypes.c_int32(-1)
+        _check(self._L.msrep_server_register(self._h, hm, ctypes.byref(idx)), "server_register")
+        self._keep.extend(keep)  # the host arrays stay valid until close()
+        self.pool.append(A)
+        return int(idx.value)
+
     def poll(self, cap: int = 1024, timeout_ms: int = 0) -> List[Completion]:
         buf = (_Completion * max(cap, 1))()
         n = self._L.msrep_server_poll(self._h, buf, cap, int(timeout_ms))

@@ -308,6 +308,9 @@ def test_server_argument_errors():
     assert ctypes.sizeof(_abi._ServeCfg) == 56
     r = _abi._Request(0, 0.0, 0, 1)
     assert L.msrep_server_submit(None, ctypes.byref(r), None) == -1
+    idx = ctypes.c_int32(7)
+    assert L.msrep_server_register(None, pool, ctypes.byref(idx)) == -1
+    assert b"NULL" in L.msrep_last_error()
     assert L.msrep_server_poll(None, None, 0, 0) == -1
     assert L.msrep_server_destroy(None, None) == 0
     assert ctypes.sizeof(_abi._Completion) == 40

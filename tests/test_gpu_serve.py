@@ -77,6 +77,48 @@ def test_steps_per_tick_same_results(vt):
             assert np.array_equal(a.y, b.y), (spt, q.rid)
 
 
+def test_incremental_server_register():
+    """msrep_server_register: matrices added to a running server's pool (from
+    another host thread while requests run) get the next indices, and
+    requests on them complete with the oracle's last y; a bad matrix is
+    refused."""
+    import ctypes
+    import threading
+    import time
+    pool = _pool(3)
+    extra = [A for A, _ in synth.batched_set(3, seed=21, m_lo=400, m_hi=12_000)]
+    got, idx = {}, []
+    with serving.Server(pool, 2 << 30, seed=SEED) as S:
+        for rid in range(6):
+            S.submit(rid, rid % 3, 4, keep_y=True)
+        th = threading.Thread(target=lambda: idx.extend(S.register(A) for A in extra))
+        th.start()
+        th.join()
+        assert idx == [3, 4, 5]
+        reqs = [(rid, k, 3 + rid % 5) for rid, k in zip(range(6, 15), [3, 4, 5] * 3)]
+        for rid, k, steps in reqs:
+            S.submit(rid, k, steps, keep_y=True)
+        with pytest.raises(pk.MsrepError):
+            S.submit(99, 6, 2)  # no matrix 6 yet
+        bad = synth.uniform_csr(10, 10, 2, seed=1)[0]
+        hm, keep = serving._host_pool([bad], pk.F32, pinned=False)  # wrong value type
+        i = ctypes.c_int32(-1)
+        assert S._L.msrep_server_register(S._h, hm, ctypes.byref(i)) == -1 and i.value == -1
+        deadline = time.time() + 60
+        while len(got) < 15 and time.time() < deadline:
+            for c in S.poll(timeout_ms=50):
+                assert c.status == 0, c
+                got[c.rid] = c
+        assert len(got) == 15
+        ys = {rid: S.y_of(rid).copy() for rid, _, _ in reqs}
+        st = S.close()
+    assert st["n_done"] == 15
+    full = pool + extra
+    for rid, k, steps in reqs:
+        ref, sc = _oracle_y(full[k], rid, steps, pk.F64)
+        assert_close(ys[rid], ref, sc, F64_TOL, "registered matrix %d, request %d" % (k, rid))
+
+
 def test_small_budget_queues():
     pool = _pool(4, m_hi=20_000)
     trace = synth.serving_trace(12, rate=1e6, pool=len(pool), seed=7, k_lo=2, k_hi=4)
