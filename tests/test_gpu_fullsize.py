@@ -132,3 +132,21 @@ def test_full_size_dyadic_bit_exact(workload, fmt):
     assert np.array_equal(y, ref), (workload, fmt, int(np.sum(y != ref)))
     del M
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("vt", [1, 2])
+@pytest.mark.parametrize("workload", ["rmat20", "stencil256"])
+@pytest.mark.parametrize("fmt", ["csr", "csc", "coo", "coo_col"])
+def test_full_size_low_precision_random_x(workload, fmt, vt):
+    """FP32 and BF16 stored values with the benchmark's random x (rounded to
+    FP32), at full size and in the benchmark's configuration: every row
+    within 1e-5 of (|A||x|)_i against the FP64 oracle on the stored values."""
+    from gpu_common import F32_TOL
+    A, x, H = _workload(workload)
+    M, v64 = _mat(A, H, fmt, vt)
+    x32 = x.astype(np.float32)
+    y = _spmv_bench_config(workload, fmt, M, A.nnz, x32, vt)
+    ref, s = oracle_y(A, fmt, v64, x32.astype(np.float64))
+    assert_close(y, ref, s, F32_TOL, "%s %s vt%d" % (workload, fmt, vt))
+    del M
+    torch.cuda.empty_cache()
