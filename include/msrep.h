@@ -254,8 +254,9 @@ typedef struct msrep_tune {
  *     several pieces: about (s_p + 4)*nnz bytes; the row-window layout's
  *     window lists, contributor lists, window sums and spill sums (8*m
  *     bytes), its sums sharing the products' space.
- * Returns 0 when A is not supported (CSC or COO_ANY / COO_COL with more
- * than 2^26 rows). */
+ *   Matrices of these formats with more than 2^26 rows (more than the
+ *   buckets cover) need only the row-window layout.
+ * Returns 0 for a malformed descriptor. */
 size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
 
 /*
@@ -274,6 +275,10 @@ size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
  *     from idx2 (lptr_d is not read and may be NULL).  For COO_COL this is
  *     the column-based merge of Sec. 4.3: each partition's partial vector
  *     over y, kept sparse as for CSC.
+ *   These three formats take the row-window path (msrep_tune.pipeline 3)
+ *   when the tune asks for it, and always when A has more than 2^26 rows
+ *   (the bucketed path's limit): its window sums cover the rows each run of
+ *   partitions touches most, device atomics the rest, so any row count runs.
  *   x_d: n values, y_d: m values (FP64 for F64 matrices, FP32 otherwise).
  *   beta == 0: y is not read.
  *   ws_d: msrep_spmv_ws_bytes(A, np) bytes, caller-owned, contents free.
@@ -283,7 +288,7 @@ size_t msrep_spmv_ws_bytes(const msrep_mat *A, int32_t np);
  * one uncaptured call with the same launch shape, which fills host-side
  * caches.  Errors: MSREP_ERR_ARG (NULL arrays, np <= 0, bad tune),
  * MSREP_ERR_SIZE (workspace too small), MSREP_ERR_UNSUPPORTED (x or y over
- * 4 GiB, CSC with more than 2^26 rows), MSREP_ERR_HIP (a launch failed).
+ * 4 GiB), MSREP_ERR_HIP (a launch failed).
  */
 msrep_status msrep_spmv(const msrep_mat *A, const msrep_part *parts_d,
                         const int32_t *lptr_d, int32_t np, const void *x_d,

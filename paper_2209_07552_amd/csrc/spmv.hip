@@ -313,23 +313,25 @@ msrep_status cscw_numeric(const msrep_mat *A, const msrep_part *parts, const int
 
 // CSC, COO_COL, COO_ANY.  pf == 3: the windowed path; otherwise the bucketed
 // path with product layout pf.  The structure phase (msrep_spmv_prepare,
-// which has no tune) builds the structure of both paths.
+// which has no tune) builds the structure of both paths.  Matrices with more
+// rows than the buckets cover (2^26) take the windowed path whatever pf is:
+// its spill vector takes any row, so it has no row limit.
 template <int VT>
 msrep_status launch_csc_any(const msrep_mat *A, const msrep_part *parts, const int32_t *lptr,
                             int32_t np, const void *x, void *y, double alpha, double beta, int K,
                             int wpb, int pf, void *ws, int phase, hipStream_t s) {
-  if (pf == 3 || phase == kPhaseStructure) {
-    using Acc = typename vt_traits<VT>::A;
-    CscLayout L;
-    if (!csc_layout(A->m, A->nnz, np, sizeof(Acc), L))
-      return fail(MSREP_ERR_UNSUPPORTED, "msrep_spmv: CSC supports at most %d rows",
-                  kCscMaxBuckets << kCscMaxShift);
+  using Acc = typename vt_traits<VT>::A;
+  CscLayout L;
+  const bool bucketed_ok = csc_layout(A->m, A->nnz, np, sizeof(Acc), L);
+  if (!bucketed_ok) L = CscLayout{};  // windowed only: its regions from the workspace's start
+  if (pf == 3 || phase == kPhaseStructure || !bucketed_ok) {
     CscwLayout W;
     cscw_place(A, np, L, W);
     char *b = static_cast<char *>(ws);
     if (phase != kPhaseNumeric)
       if (msrep_status st = cscw_structure(A, parts, np, W, b, s)) return st;
     if (phase == kPhaseStructure) {
+      if (!bucketed_ok) return MSREP_OK;
       // and the bucketed path's structure, for calls with either layout
       return K == 8 ? launch_csc<VT, 8, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s)
                     : launch_csc<VT, 4, false>(A, parts, lptr, np, x, y, alpha, beta, wpb, ws, phase, s);
@@ -460,7 +462,7 @@ size_t spmv_ws_bytes(int32_t fmt, int32_t vtype, int32_t m, int64_t nnz, int32_t
   if (bucketed_fmt(fmt)) {
     CscLayout L;
     const int pb = vtype == MSREP_F64 ? 8 : 4;
-    if (!csc_layout(m, nnz, np, pb, L)) return 0;
+    if (!csc_layout(m, nnz, np, pb, L)) L = CscLayout{};  // windowed only (over 2^26 rows)
     // the windowed path's numeric regions overlap the bucketed ones, its
     // structure follows both
     CscwLayout W;
@@ -504,12 +506,6 @@ msrep_status spmv_entry(const msrep_mat *A, const msrep_part *parts_d, const int
   if (xb >= (uint64_t(1) << 32) || yb >= (uint64_t(1) << 32) ||
       (static_cast<uint64_t>(major_dim(A)) + 1) * 4 >= (uint64_t(1) << 32))
     return fail(MSREP_ERR_UNSUPPORTED, "%s: x or y larger than 4 GiB", who);
-  if (bucketed_fmt(A->fmt)) {
-    CscLayout L;
-    if (!csc_layout(A->m, A->nnz, np, 8, L))
-      return fail(MSREP_ERR_UNSUPPORTED, "%s: CSC and unsorted COO support at most %d rows",
-                  who, kCscMaxBuckets << kCscMaxShift);
-  }
   const size_t need = msrep_spmv_ws_bytes(A, np);
   if (!ws_d || ws_bytes < need)
     return fail(MSREP_ERR_SIZE, "%s: workspace of %zu bytes needed (got %zu)", who, need,

@@ -502,6 +502,53 @@ def test_csc_tall_matrix_uses_wide_buckets(vt):
             assert_close(y, ref, s, tol, "tall csc vt%d np%d pf%d" % (vt, np_, pf))
 
 
+@pytest.mark.parametrize("vt", [0, 1])
+def test_column_merge_taller_than_the_buckets(vt):
+    """More than 2^26 rows, beyond the bucketed path's reach: CSC, COO sorted
+    by column and COO in any order run the row-window path whatever the
+    tune's pipeline (rows spread over the whole height spill to device
+    atomics), checked against the oracle with beta != 0; the workspace query
+    sizes it, and a prepared call gives the same y."""
+    rng = np.random.default_rng(17)
+    m, n, nnz = (1 << 26) + 4097, 2000, 40_000
+    rows = np.concatenate([rng.integers(0, 30_000, nnz // 2), rng.integers(0, m, nnz - nnz // 2)])
+    cols = rng.integers(0, n, nnz)
+    key = np.unique(rows.astype(np.int64) * n + cols)
+    rows, cols = (key // n).astype(np.int64), (key % n).astype(np.int32)
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=m))]).astype(np.int32)
+    A = synth.Csr(m, n, ptr, cols, rng.uniform(-1, 1, len(cols)), name="taller")
+    x = rng.uniform(-1, 1, n)
+    y_in = rng.uniform(-1, 1, m)
+    tol = F64_TOL if vt == 0 else F32_TOL
+    for fmt in ("csc", "coo_col"):
+        M, v64 = device_mat(A, fmt, vt)
+        assert pk.msrep_spmv_ws_bytes(M, 7) >= 8 * m
+        for pf in (1, 3):
+            y, ref, s = _run(A, x, fmt, vt, 7, 0.5, 2.0, y_in, M=M, v64=v64,
+                             tune=pk.Tune(pipeline=pf))
+            assert_close(y, ref, s, tol, "taller %s vt%d pf%d" % (fmt, vt, pf))
+        del M
+    # COO in any order: the row-sorted COO shuffled
+    from gpu_common import stored_values
+    H = host_formats(A)
+    r, c, v = H["coo"]
+    perm = rng.permutation(len(c))
+    sv, v64 = stored_values(v[perm], vt)
+    M = pk.Mat(pk.COO_ANY, vt, A.m, A.n, idx=r[perm], idx2=c[perm], val=sv)
+    P = pk.msrep_build_partition(M, 5)
+    xdt = np.float64 if vt == 0 else np.float32
+    xs = torch.from_numpy(x.astype(xdt)).to(_dev())
+    y = torch.from_numpy(y_in.astype(xdt)).to(_dev())
+    ws = pk.msrep_spmv_prepare(M, P)
+    pk.msrep_spmv_prepared(M, P, xs, y, ws, 0.5, 2.0)
+    torch.cuda.synchronize()
+    ref, s = oracle.spmv_coo(A.m, A.n, r[perm], c[perm], v64, x.astype(xdt).astype(np.float64),
+                             0.5, 2.0, y_in.astype(xdt).astype(np.float64))
+    assert_close(y.cpu().numpy(), ref, s, tol, "taller coo_any vt%d" % vt)
+    del M, P, ws, xs, y
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("fmt", FMTS)
 def test_spmv_replays_under_graph_capture(fmt):
     """msrep_spmv launches kernels only (no memsets), so a caller can capture
