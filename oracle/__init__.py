@@ -79,11 +79,12 @@ def _load():
         _lib.oracle_csr_to_coo.argtypes = [i32, vp, vp]
         _lib.oracle_coo_to_csr.argtypes = [i32, i64, vp, vp]
         _lib.oracle_transpose.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        _lib.oracle_coo_sort.argtypes = [i32, i32, i64, vp, vp, vp]
         for f in ("oracle_spmv_csr", "oracle_spmv_csr_plain", "oracle_spmm_csr", "oracle_spmv_csc", "oracle_spmv_coo",
                   "oracle_partition_ptr", "oracle_partition_coo", "oracle_partition_rows_ptr",
                   "oracle_partition_rows_coo", "oracle_partition_coo_col",
                   "oracle_partition_cols_coo_col", "oracle_csr_to_coo",
-                  "oracle_coo_to_csr", "oracle_transpose"):
+                  "oracle_coo_to_csr", "oracle_transpose", "oracle_coo_sort"):
             getattr(_lib, f).restype = ctypes.c_int
     return _lib
 
@@ -275,6 +276,17 @@ def coo_to_csr(m, row_idx):
     row_ptr = np.empty(m + 1, np.int32)
     _check(lib.oracle_coo_to_csr(m, len(row_idx), _p(row_idx), _p(row_ptr)), "coo_to_csr")
     return row_ptr
+
+
+def coo_sort(n_major, n_minor, major, minor):
+    """The storage positions of COO entries given in any order, sorted by
+    (major, minor); entries equal on both keep their storage order."""
+    lib = _load()
+    major, minor = _c(major, np.int32), _c(minor, np.int32)
+    perm = np.empty(len(major), np.int64)
+    _check(lib.oracle_coo_sort(int(n_major), int(n_minor), len(major), _p(major), _p(minor),
+                               _p(perm)), "coo_sort")
+    return perm
 
 
 def transpose(m, n, row_ptr, col_idx, val=None):

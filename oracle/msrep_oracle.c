@@ -27,7 +27,9 @@
  *     including each partition's local row pointer,
  *     and of the paper's equal-rows Baseline split (Sec. 5.3) in the same
  *     records.
- *   - Format conversions between CSR, CSC and row-sorted COO (Sec. 2.1).
+ *   - Format conversions between CSR, CSC and row-sorted COO (Sec. 2.1),
+ *     and the order that sorts COO given in any order by (row, column) or
+ *     (column, row) (Sec. 2.1's COO, sorted as Sec. 3.2.3 takes it).
  *
  * Readings of the paper that this file commits to (the paper is silent,
  * garbled or 1-based in these places):
@@ -571,5 +573,45 @@ int oracle_transpose(int32_t m, int32_t n, const int32_t *row_ptr,
     }
   }
   free(next);
+  return ORACLE_OK;
+}
+
+/*
+ * COO in any order -> sorted COO (Sec. 2.1 stores COO as (row, column,
+ * value) triples in any order; Sec. 3.2.3 partitions it sorted by row or by
+ * column).  perm[j] = the storage position of the j-th entry in the order
+ * sorted by (major, minor), entries equal on both keeping their storage
+ * order.  Two stable counting sorts, least significant key first: by minor,
+ * then by major.  major in [0, n_major), minor in [0, n_minor).
+ */
+int oracle_coo_sort(int32_t n_major, int32_t n_minor, int64_t nnz, const int32_t *major,
+                    const int32_t *minor, int64_t *perm) {
+  if (n_major < 0 || n_minor < 0 || nnz < 0 || (nnz > 0 && (!major || !minor || !perm)))
+    return ORACLE_ERR_ARG;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (major[k] < 0 || major[k] >= n_major || minor[k] < 0 || minor[k] >= n_minor)
+      return ORACLE_ERR_FORMAT;
+  int64_t *tmp = (int64_t *)malloc(((size_t)nnz + 1) * sizeof(int64_t));
+  int64_t *cnt = (int64_t *)calloc((size_t)(n_major > n_minor ? n_major : n_minor) + 1,
+                                   sizeof(int64_t));
+  if (!tmp || !cnt) {
+    free(tmp);
+    free(cnt);
+    return ORACLE_ERR_SIZE;
+  }
+  /* pass 1: storage order -> stable by minor (into tmp) */
+  for (int64_t k = 0; k < nnz; ++k) cnt[minor[k] + 1] += 1;
+  for (int64_t c = 0; c < n_minor; ++c) cnt[c + 1] += cnt[c];
+  for (int64_t k = 0; k < nnz; ++k) tmp[cnt[minor[k]]++] = k;
+  /* pass 2: that order -> stable by major (into perm) */
+  for (int64_t c = 0; c <= n_major; ++c) cnt[c] = 0;
+  for (int64_t k = 0; k < nnz; ++k) cnt[major[k] + 1] += 1;
+  for (int64_t r = 0; r < n_major; ++r) cnt[r + 1] += cnt[r];
+  for (int64_t j = 0; j < nnz; ++j) {
+    const int64_t k = tmp[j];
+    perm[cnt[major[k]]++] = k;
+  }
+  free(tmp);
+  free(cnt);
   return ORACLE_OK;
 }

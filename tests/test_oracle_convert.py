@@ -70,3 +70,47 @@ def test_stable_with_duplicates(oracle_lib):
 def test_coo_to_csr_rejects_unsorted(oracle_lib):
     with pytest.raises(ValueError):
         oracle.coo_to_csr(3, np.array([1, 0], np.int32))
+
+
+def test_coo_sort_hand_example(oracle_lib):
+    """COO in any order sorted by (row, column): worked by hand, with a
+    duplicate (row 1, column 2) whose two entries keep their storage order,
+    and the same entries sorted by (column, row)."""
+    row = np.array([2, 1, 0, 1, 2, 1], np.int32)
+    col = np.array([0, 2, 1, 0, 2, 2], np.int32)
+    # by (row, col): (0,1)@2, (1,0)@3, (1,2)@1, (1,2)@5, (2,0)@0, (2,2)@4
+    assert list(oracle.coo_sort(3, 3, row, col)) == [2, 3, 1, 5, 0, 4]
+    # by (col, row): (0,1)@3, (0,2)@0, (1,0)@2, (2,1)@1, (2,1)@5, (2,2)@4
+    assert list(oracle.coo_sort(3, 3, col, row)) == [3, 0, 2, 1, 5, 4]
+    assert len(oracle.coo_sort(4, 4, np.zeros(0, np.int32), np.zeros(0, np.int32))) == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_coo_sort_vs_numpy_lexsort(oracle_lib, seed):
+    """Against numpy's stable lexicographic sort (a library routine with a
+    unique answer for a stable order), on shuffled entries with many
+    duplicates, in both key orders; the sorted triples equal the CSR /
+    CSC the oracle's own conversions give for the deduplicated-free case."""
+    rng = np.random.default_rng(seed)
+    m, n, nnz = 57, 31, 2000
+    row = rng.integers(0, m, nnz).astype(np.int32)
+    col = rng.integers(0, n, nnz).astype(np.int32)
+    p = oracle.coo_sort(m, n, row, col)
+    assert np.array_equal(p, np.lexsort((col, row)))
+    q = oracle.coo_sort(n, m, col, row)
+    assert np.array_equal(q, np.lexsort((row, col)))
+    # a CSR matrix shuffled and sorted back gives its CSR arrays
+    A, _ = synth.uniform_csr(200, 150, 9, seed=seed)
+    rows = oracle.csr_to_coo(A.m, A.ptr)
+    sh = rng.permutation(A.nnz)
+    back = oracle.coo_sort(A.m, A.n, rows[sh], A.col[sh])
+    assert np.array_equal(rows[sh][back], rows) and np.array_equal(A.col[sh][back], A.col)
+    cptr, crow, _, _ = oracle.transpose(A.m, A.n, A.ptr, A.col)
+    bc = oracle.coo_sort(A.n, A.m, A.col[sh], rows[sh])
+    assert np.array_equal(rows[sh][bc], crow)
+    assert np.array_equal(oracle.coo_to_csr(A.n, A.col[sh][bc]), cptr)
+
+
+def test_coo_sort_rejects_out_of_range(oracle_lib):
+    with pytest.raises(ValueError):
+        oracle.coo_sort(2, 2, np.array([0, 2], np.int32), np.array([0, 0], np.int32))
