@@ -213,9 +213,11 @@ size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt);
  * CSC: ptr n+1, idx nnz; COO, COO_COL: idx nnz, idx2 nnz; val nnz).  Values are moved, never rounded.  Conversions
  * are stable: entries that tie on the new major index keep their storage
  * order, so canonical input (sorted minor indices, no duplicates) gives the
- * unique canonical output.  ws_d: msrep_convert_ws_bytes bytes of device
- * memory.  COO_ANY is neither source nor target (MSREP_ERR_UNSUPPORTED):
- * msrep_spmv takes it as it is.
+ * unique canonical output.  COO in any order (COO_ANY) may be the source:
+ * its entries are sorted stably by the target's major index, ties by its
+ * minor index, so equal (row, column) pairs keep their storage order; it is
+ * not a target (MSREP_ERR_UNSUPPORTED; msrep_spmv takes it as it is).
+ * ws_d: msrep_convert_ws_bytes bytes of device memory.
  */
 msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,
                            size_t ws_bytes, void *stream);

@@ -235,13 +235,14 @@ struct Ws {
   int32_t *major;          // nnz: major index of every source entry
   uint32_t *ka, *kb;       // nnz: radix keys
   int32_t *va, *vb;        // nnz: radix values (positions)
+  int32_t *p1;             // nnz (COO in any order): positions sorted by the minor index
   int32_t *hist;           // 256 * tiles(nnz)
   int32_t *agg;            // tiles(256 * tiles(nnz)) scan aggregates of the histograms
   int64_t *agg64;
   size_t bytes;
 };
 
-Ws plan_ws(void *base, int64_t nnz, int64_t minor) {
+Ws plan_ws(void *base, int64_t nnz, int64_t minor, bool any_order) {
   Ws w{};
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -257,6 +258,7 @@ Ws plan_ws(void *base, int64_t nnz, int64_t minor) {
   w.kb = reinterpret_cast<uint32_t *>(take(4 * static_cast<size_t>(nnz)));
   w.va = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz)));
   w.vb = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz)));
+  w.p1 = any_order ? reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(nnz))) : nullptr;
   w.hist = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(hist_n)));
   w.agg = reinterpret_cast<int32_t *>(take(4 * static_cast<size_t>(tiles(scan_n) + 1)));
   w.agg64 = nullptr;
@@ -341,7 +343,7 @@ extern "C" size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt) 
   if (!src || src->nnz < 0 || src->m < 0 || src->n < 0) return 0;
   (void)dst_fmt;
   const int64_t minor = std::max(src->m, src->n);
-  return plan_ws(nullptr, src->nnz, minor).bytes;
+  return plan_ws(nullptr, src->nnz, minor, src->fmt == MSREP_COO_ANY).bytes;
 }
 
 namespace {
@@ -383,15 +385,65 @@ int32_t *dst_minor(msrep_mat *D) {
 
 }  // namespace
 
+namespace {
+
+// COO in any order (idx: rows, idx2: columns) into any sorted format: the
+// positions sorted stably by the target's minor index, then stably by its
+// major index (an LSD sort on the pair), so entries equal on both keep their
+// storage order.
+msrep_status sort_any(const msrep_mat *src, msrep_mat *dst, Ws &w, hipStream_t s) {
+  const int64_t nnz = src->nnz;
+  const bool rm = row_major(dst->fmt);
+  const int32_t *smaj = rm ? src->idx : src->idx2;
+  const int32_t *smin = rm ? src->idx2 : src->idx;
+  const int32_t maj_ext = rm ? src->m : src->n, min_ext = rm ? src->n : src->m;
+  const bool dcomp = compressed(dst->fmt);
+  int32_t *dptr = const_cast<int32_t *>(dst->ptr);
+  if (nnz == 0) {
+    if (dcomp) {
+      hipLaunchKernelGGL(fill<int32_t>, dim3(grid_for(int64_t(maj_ext) + 1)), dim3(256), 0, s,
+                         dptr, int64_t(maj_ext) + 1, int32_t(0));
+      MSREP_LAUNCHED("fill");
+    }
+    return ok();
+  }
+  int32_t *perm = nullptr;
+  uint32_t *sorted = nullptr;
+  if (msrep_status st = stable_sort(smin, nnz, key_bits(min_ext), w, s, &perm, &sorted)) return st;
+  MSREP_HIP(hipMemcpyAsync(w.p1, perm, 4 * static_cast<size_t>(nnz), hipMemcpyDeviceToDevice, s));
+  // the major index in that order, sorted stably
+  hipLaunchKernelGGL(gather<int32_t>, dim3(grid_for(nnz)), dim3(256), 0, s, smaj, w.p1, nnz, w.major);
+  MSREP_LAUNCHED("gather");
+  if (msrep_status st = stable_sort(w.major, nnz, key_bits(maj_ext), w, s, &perm, &sorted))
+    return st;
+  // storage positions in the final order
+  hipLaunchKernelGGL(gather<int32_t>, dim3(grid_for(nnz)), dim3(256), 0, s, w.p1, perm, nnz, w.major);
+  MSREP_LAUNCHED("gather");
+  if (dcomp) {
+    hipLaunchKernelGGL(rows_to_ptr, dim3(grid_for_ptr(nnz)), dim3(256), 0, s,
+                       reinterpret_cast<const int32_t *>(sorted), nnz, maj_ext, dptr);
+    MSREP_LAUNCHED("rows_to_ptr");
+  } else {
+    MSREP_HIP(hipMemcpyAsync(dst_exp(dst), sorted, 4 * static_cast<size_t>(nnz),
+                             hipMemcpyDeviceToDevice, s));
+  }
+  if (msrep_status st = gather_entries_by(smin, src->val, w.major, nnz, src->vtype, dst_minor(dst),
+                                          const_cast<void *>(dst->val), s))
+    return st;
+  return ok();
+}
+
+}  // namespace
+
 extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,
                                       size_t ws_bytes, void *stream) {
   if (msrep_status st = check_mat(src, "msrep_convert")) return st;
   if (!dst) return fail(MSREP_ERR_ARG, "msrep_convert: dst is NULL");
   if (dst->fmt < MSREP_CSR || dst->fmt > MSREP_COO_COL)
     return fail(MSREP_ERR_ARG, "msrep_convert: unknown target format %d", dst->fmt);
-  if (src->fmt == MSREP_COO_ANY || dst->fmt == MSREP_COO_ANY)
+  if (dst->fmt == MSREP_COO_ANY)
     return fail(MSREP_ERR_UNSUPPORTED,
-                "msrep_convert: COO in any order is taken by msrep_spmv as it is, not converted");
+                "msrep_convert: COO in any order is not a target (every other format is one)");
   if (dst->m != src->m || dst->n != src->n || dst->nnz != src->nnz || dst->vtype != src->vtype)
     return fail(MSREP_ERR_ARG, "msrep_convert: dst shape/nnz/vtype differ from src");
   const int64_t nnz = src->nnz;
@@ -406,10 +458,11 @@ extern "C" msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void
     return fail(MSREP_ERR_SIZE, "msrep_convert: workspace of %zu bytes needed (got %zu)", need,
                 ws_d ? ws_bytes : size_t(0));
   hipStream_t s = as_stream(stream);
-  Ws w = plan_ws(ws_d, nnz, std::max(src->m, src->n));
+  Ws w = plan_ws(ws_d, nnz, std::max(src->m, src->n), src->fmt == MSREP_COO_ANY);
   const size_t vb = static_cast<size_t>(value_bytes(src->vtype)) * nnz;
-  const Sides S = sides_of(src);
   int32_t *dminor = dst_minor(dst);
+  if (src->fmt == MSREP_COO_ANY) return sort_any(src, dst, w, s);
+  const Sides S = sides_of(src);
 
   if (row_major(src->fmt) == row_major(dst->fmt)) {
     // same grouping: the major index is compressed or expanded, the minor

@@ -139,3 +139,59 @@ def test_convert_stencil_full_size():
     assert np.array_equal(c, A.col) and np.array_equal(v, A.val)
     del O, M
     torch.cuda.empty_cache()
+
+
+def _any_order(A, rng):
+    """A's entries as COO in a seeded random order: (rows, cols, vals)."""
+    rows = oracle.csr_to_coo(A.m, A.ptr)
+    sh = rng.permutation(A.nnz)
+    return rows[sh], A.col[sh], A.val[sh]
+
+
+def _expect_from_any(m, n, r, c, v, dst):
+    """The oracle's sorted arrays for COO in any order converted to dst."""
+    if dst in ("csr", "coo"):
+        p = oracle.coo_sort(m, n, r, c)
+        if dst == "coo":
+            return r[p], c[p], v[p]
+        return oracle.coo_to_csr(m, r[p]), c[p], v[p]
+    p = oracle.coo_sort(n, m, c, r)
+    if dst == "coo_col":
+        return r[p], c[p], v[p]
+    return oracle.coo_to_csr(n, c[p]), r[p], v[p]
+
+
+@pytest.mark.parametrize("dst", ["csr", "csc", "coo", "coo_col"])
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_convert_from_any_order(dst, vt):
+    """COO in any order into every sorted format, bit-exact against the
+    oracle's sort (ties by the other index, then storage order), on the small
+    adversarial set, duplicates, and R-MAT 16 shuffled."""
+    rng = np.random.default_rng(5)
+    mats = _small_set() + [synth.rmat_csr(scale=16, edge_factor=16, seed=7)[0]]
+    for A in mats:
+        r, c, v = _any_order(A, rng)
+        if A.nnz > 4:  # duplicates: repeat a few entries with other values
+            k = rng.integers(0, A.nnz, 4)
+            r, c = np.concatenate([r, r[k]]), np.concatenate([c, c[k]])
+            v = np.concatenate([v, rng.uniform(-1, 1, 4)])
+        sv, _ = stored_values(v, vt)
+        M = pk.Mat(pk.COO_ANY, vt, A.m, A.n, idx=r, idx2=c, val=sv)
+        B = pk.msrep_convert(M, FMT[dst])
+        ptr, idx, idx2, val = _host(B)
+        a, b, want = _expect_from_any(A.m, A.n, r, c, np.asarray(sv), dst)
+        got_v = val.view(np.uint16) if vt == pk.BF16 else val
+        if dst in COO_LIKE:
+            assert np.array_equal(idx, a) and np.array_equal(idx2, b), (A.name, dst)
+        else:
+            assert np.array_equal(ptr, a) and np.array_equal(idx, b), (A.name, dst)
+        assert np.array_equal(got_v, want), (A.name, dst, vt)
+
+
+def test_convert_from_any_order_rmat20_round_trip():
+    """R-MAT scale 20 shuffled and sorted back: CSR bit for bit."""
+    A, _ = synth.rmat_csr(scale=20, edge_factor=16, seed=0)
+    r, c, v = _any_order(A, np.random.default_rng(3))
+    M = pk.Mat(pk.COO_ANY, pk.F64, A.m, A.n, idx=r, idx2=c, val=v)
+    ptr, idx, _, val = _host(pk.msrep_convert(M, pk.CSR))
+    assert np.array_equal(ptr, A.ptr) and np.array_equal(idx, A.col) and np.array_equal(val, A.val)
