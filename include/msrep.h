@@ -434,13 +434,15 @@ msrep_status msrep_plan_destroy(msrep_plan plan);
  * (admission is by bytes: matrix + partitions + vectors must fit in what the
  * arena has free) and stay resident while the request runs.  Every tick
  * executes the next steps of every active request, up to steps_per_tick of
- * each (240 steps per tick in all), in one batched launch, so requests that
- * arrive while others run join the next tick.  A request's steps are
- * independent SpMVs, each on an x/y pair of its own (a request reserves
- * min(steps, steps_per_tick) pairs), so a tick that runs several of them
- * gives the same results as ticks of one step each.  A request's descriptor
- * is written to the device once, when it is admitted; a tick only launches
- * kernels.
+ * each (240 requests per tick at most), in one batched launch, so requests
+ * that arrive while others run join the next tick.  A request's steps are
+ * independent SpMVs: those that share a tick are the columns of one
+ * multi-vector product Y = A*X (X: n x c, Y: m x c row-major, c =
+ * min(steps, steps_per_tick), reserved with the request), so the matrix is
+ * read once per tick rather than once per step.  A request's descriptor is
+ * written to the device once, when it is admitted; a tick only launches
+ * kernels.  Pool matrices are CSR of one value type with nnz < 2^31,
+ * n < 2^24 and m < 2^26 (else MSREP_ERR_ARG).
  *   x_j[c] = 2*u - 1 with u the top 53 bits of splitmix64(key) / 2^53,
  *   key = seed ^ (rid << 40) ^ ((uint64)j << 24) ^ c (rid < 2^24, j < 2^16)
  *   (SplitMix64: Steele, Lea and Flood 2014), rounded to FP32 for F32 pools.
@@ -465,7 +467,7 @@ typedef struct msrep_serve_cfg {
                         /* results[i].y_host (where not NULL)                */
   int32_t max_queue;    /* msrep_server_submit: most requests waiting for    */
                         /* admission before MSREP_ERR_BUSY (0: 2^20)          */
-  int32_t steps_per_tick; /* most steps of one request in a tick (1..16;   */
+  int32_t steps_per_tick; /* most steps of one request in a tick (1..8;    */
                           /* 0: 8)                                           */
   int32_t _pad;
 } msrep_serve_cfg;
@@ -504,7 +506,7 @@ msrep_status msrep_serve(const msrep_serve_cfg *cfg,
 /* The same scheduler (admission, residency, eviction, continuous batching)
  * driven by a simulated device on a virtual clock instead of the GPU: an
  * upload takes bytes / upload_bytes_per_s, a tick takes tick_seconds plus
- * 2*nnz / flops_per_s for each request in it (values <= 0 keep defaults of
+ * 2*nnz / flops_per_s for each step in it (values <= 0 keep defaults of
  * 25 GB/s, 500 GFLOP/s, 20 us).  No HIP call is made; cfg->arena_d may be
  * NULL and keep_y is ignored.  Results carry virtual times.  For testing the
  * scheduling logic without a GPU. */

@@ -14,11 +14,11 @@
 // lo + j, lo + j + W, ...), so at any moment an XCD works on a window of
 // consecutive items, i.e. on a few matrices, whose x vectors its L2 holds.
 // The batched plan reads a precomputed item list from device memory; a
-// serving tick passes its active requests in the kernel arguments, so a tick
-// needs no table copy from the host.
+// serving tick (serve.hip) passes its active requests in the kernel
+// arguments, so a tick needs no table copy from the host.
 #pragma once
 
-#include "spmv_csr.hpp"
+#include "spmm_csr.hpp"
 
 namespace msrep {
 
@@ -45,6 +45,7 @@ struct BItem {
   const void *x;
   void *y;
   int32_t m, n, np, p;
+  int64_t ldy;  // y's row stride in elements (1: a vector; k: a column of an m x k block)
 };
 
 __device__ __forceinline__ void bitem_from(const BatchMat &M, const BatchXY &xy, int32_t p,
@@ -60,6 +61,7 @@ __device__ __forceinline__ void bitem_from(const BatchMat &M, const BatchXY &xy,
   o.n = M.n;
   o.np = M.np;
   o.p = p;
+  o.ldy = 1;
 }
 
 // The batched plan's items: a device list of (matrix, partition) pairs and
@@ -78,61 +80,6 @@ struct PlanSrc {
   __device__ void group(int32_t g, int32_t, int64_t &lo, int64_t &hi) const {
     lo = uniform(group_begin[g]);
     hi = uniform(group_begin[g + 1]);
-  }
-};
-
-// ------------------------------------------------------------- serving
-// A request slot of the server: its resident matrix, partitions, and its
-// copies of the x, y and carry vectors (copy c at x + c*x_stride bytes,
-// y + c*y_stride bytes, carry + c*2*np), one per step a tick may run.
-// Written once when the request is admitted.
-struct ServeSlot {
-  BatchMat M;
-  BatchXY xy;
-  int64_t rid;
-  int64_t x_stride, y_stride;
-};
-
-constexpr int kTickMax = 240;  // steps per tick (the arguments stay below 4 KB)
-
-// One serving tick: an entry per step it runs (the request's slot, the step
-// index j in the low 16 bits and the copy it uses above them), and the
-// prefix sums of their partition counts (item it belongs to entry i with
-// begin[i] <= it < begin[i+1]).  Passed by value as kernel arguments.
-struct TickSrc {
-  const ServeSlot *table;
-  int64_t n_items;
-  int32_t n_waves, count;
-  int32_t slot[kTickMax];
-  int32_t step[kTickMax];  // j | copy << 16
-  int32_t begin[kTickMax + 1];
-  __device__ static int32_t step_of(int32_t v) { return v & 0xffff; }
-  __device__ static int32_t copy_of(int32_t v) { return v >> 16; }
-  __device__ int32_t entry_of(int64_t it) const {
-    int32_t lo = 0, hi = count;  // begin[lo] <= it < begin[hi]
-    while (hi - lo > 1) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (begin[mid] <= it)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    return lo;
-  }
-  __device__ void get(int64_t it, BItem &o) const {
-    const int32_t i = entry_of(it);
-    const ServeSlot *S = table + slot[i];
-    bitem_from(S->M, S->xy, static_cast<int32_t>(it - begin[i]), o);
-    const int64_t c = copy_of(step[i]);
-    o.x = static_cast<const char *>(o.x) + c * S->x_stride;
-    o.y = static_cast<char *>(o.y) + c * S->y_stride;
-    o.carry += c * 2 * static_cast<int64_t>(S->M.np);
-  }
-  // equal item counts per group (a request's partitions hold equal
-  // nonzeros, so items cost about the same)
-  __device__ void group(int32_t g, int32_t G, int64_t &lo, int64_t &hi) const {
-    lo = n_items * g / G;
-    hi = n_items * (g + 1) / G;
   }
 };
 
@@ -243,7 +190,7 @@ __global__ __launch_bounds__(kMergeBlock) void merge_items(const Src src, double
   const int32_t r = P.sr;
   if (r < 0 || r >= b.m) return;
   const double tot = at.s + at.c;
-  T *yr = static_cast<T *>(b.y) + r;
+  T *yr = static_cast<T *>(b.y) + static_cast<int64_t>(r) * b.ldy;
   *yr = static_cast<T>(BETA0 ? alpha * tot : alpha * tot + beta * static_cast<double>(*yr));
 }
 

@@ -10,13 +10,15 @@
 //    merge buffers fit in the free arena; one that can never fit fails with
 //    MSREP_ERR_BUDGET.  At most max_slots requests are admitted at once.
 //  * Continuous batching: every tick runs the next steps of every ready
-//    request (up to steps_per_tick of each; a request's steps are
-//    independent SpMVs, each on an x/y/carry copy of its own) in one
-//    persistent launch over all their equal-nnz partitions (the batched
-//    kernel), so requests that arrive while others run join the next tick.
-//    A request's device descriptor is written once, when it is admitted; a
-//    tick passes only its entries (slot, step, copy), in the kernel
-//    arguments, so a tick costs three launches and one event record.
+//    request (up to steps_per_tick of each) in one persistent launch over
+//    all their equal-nnz partitions, so requests that arrive while others
+//    run join the next tick.  A request's steps are independent SpMVs: those
+//    of one tick are the columns of a multi-vector product (X and Y of
+//    steps_per_tick columns), so its matrix is read once per tick, not once
+//    per step.  A request's device descriptor is written once, when it is
+//    admitted; a tick passes only its entries (slot, first step, steps), in
+//    the kernel arguments, so a tick costs three launches and one event
+//    record.
 //    Uploads and partition builds run on a copy stream, overlapping compute.
 //  * Each request's arithmetic depends only on its matrix, its partitions and
 //    its x: its results are the same alone and in any mix.
@@ -44,13 +46,132 @@
 namespace msrep {
 namespace {
 
-constexpr int kWpb = 4;      // wavefronts per workgroup of the serving kernels
-constexpr int kK = 4;        // nonzeros per lane per chunk
 constexpr int kRing = 4;     // tick events in rotation (at most kInflight ticks in flight)
 constexpr int kInflight = 2;
 constexpr int64_t kDefaultQueue = int64_t(1) << 20;  // incremental server's waiting requests
 constexpr int32_t kDefaultStepsPerTick = 8;
-constexpr int32_t kMaxStepsPerTick = 16;
+constexpr int32_t kMaxStepsPerTick = kSpmmMaxCols;  // a tick's steps of a request: one pass
+
+// ------------------------------------------------------- tick descriptors
+// A request slot of the server: its resident matrix, partitions, carries and
+// vectors.  A request's steps that share a tick are the columns of one
+// multi-vector pass: X (n x ld) and Y (m x ld) row-major, column c holding
+// step j0 + c of the tick, the head and tail carries of column c at
+// carry + c*2*np.  Written once when the request is admitted.
+struct ServeSlot {
+  BatchMat M;
+  BatchXY xy;
+  int64_t rid;
+  int32_t ld;     // columns of X and Y (the most steps the request runs in a tick)
+  int32_t ebytes; // bytes of an x or y element
+};
+
+constexpr int kTickMax = 240;  // requests per tick (the arguments stay below 4 KB)
+
+// One serving tick: an entry per request it runs (its slot; its first step
+// j0 and its count k of steps, as j0 | k << 16), and the prefix sums of the
+// requests' partition counts (item it belongs to entry i with begin[i] <= it
+// < begin[i+1]).  Passed by value as kernel arguments.
+struct TickSrc {
+  const ServeSlot *table;
+  int64_t n_items;
+  int32_t n_waves, count;
+  int32_t slot[kTickMax];
+  int32_t step[kTickMax];  // j0 | k << 16
+  int32_t begin[kTickMax + 1];
+  __device__ static int32_t first_of(int32_t v) { return v & 0xffff; }
+  __device__ static int32_t count_of(int32_t v) { return v >> 16; }
+  __device__ int32_t entry_of(int64_t it) const {
+    int32_t lo = 0, hi = count;  // begin[lo] <= it < begin[hi]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (begin[mid] <= it)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return lo;
+  }
+  // equal item counts per group (a request's partitions hold equal
+  // nonzeros, so items cost about the same)
+  __device__ void group(int32_t g, int32_t G, int64_t &lo, int64_t &hi) const {
+    lo = n_items * g / G;
+    hi = n_items * (g + 1) / G;
+  }
+};
+
+// The tick's items seen by the boundary merge for column blockIdx.y: a
+// request running fewer steps has no such column (m = 0: nothing written).
+struct TickColSrc : TickSrc {
+  __device__ void get(int64_t it, BItem &o) const {
+    const int32_t i = entry_of(it);
+    const ServeSlot *S = table + slot[i];
+    bitem_from(S->M, S->xy, static_cast<int32_t>(it - begin[i]), o);
+    o.ldy = S->ld;
+    const int32_t c = static_cast<int32_t>(blockIdx.y);
+    if (c < count_of(step[i])) {
+      o.y = static_cast<char *>(o.y) + static_cast<int64_t>(c) * S->ebytes;
+      o.carry += static_cast<int64_t>(c) * 2 * S->M.np;
+    } else {
+      o.m = 0;
+    }
+  }
+};
+
+// The tick's passes: resident wavefronts, those of one XCD sweeping its group
+// of items together; item (request, partition p) runs the request's k steps
+// as passes of 8, 4, 2 and 1 columns of the multi-vector routine.
+template <int VT>
+__global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void
+serve_passes(const TickSrc src) {
+  using Tr = vt_traits<VT>;
+  using T = typename Tr::T;
+  using V = typename Tr::V;
+  __shared__ int32_t s_mark_all[kSpmmWaves][kWave];
+  __shared__ int32_t s_rows_all[kSpmmWaves][kWave];
+  const int wid = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int nb = static_cast<int>(gridDim.x);
+  const int G = nb < kXcds ? nb : kXcds;
+  const int g = static_cast<int>(blockIdx.x) % G;
+  const int j = (static_cast<int>(blockIdx.x) / G) * wpb + wid;
+  const int wg = (nb / G + (g < nb % G ? 1 : 0)) * wpb;
+  int64_t lo, hi;
+  src.group(g, G, lo, hi);
+  for (int64_t it = lo + j; it < hi; it += wg) {
+    const int32_t i = uniform(src.entry_of(it));
+    const ServeSlot *S = src.table + src.slot[i];
+    const int32_t k = TickSrc::count_of(src.step[i]);
+    const int32_t p = static_cast<int32_t>(it - src.begin[i]);
+    const int32_t *col = uniform(S->M.col);
+    const V *val = static_cast<const V *>(uniform(S->M.val));
+    const msrep_part *parts = uniform(S->M.parts);
+    const int32_t *lptr = uniform(S->M.lptr);
+    double *carry = uniform(S->M.carry);
+    const int32_t m = uniform(S->M.m), n = uniform(S->M.n), np = uniform(S->M.np);
+    const int64_t ld = uniform(S->ld);
+    const T *X = static_cast<const T *>(uniform(S->xy.x));
+    T *Y = static_cast<T *>(uniform(S->xy.y));
+    const int64_t cs = 2 * static_cast<int64_t>(np);
+    int32_t c0 = 0;
+    auto pass = [&](auto nr_c, auto cpl_c) {
+      constexpr int NR = decltype(nr_c)::value, CPL = decltype(cpl_c)::value;
+      // bytes from the pass's first column to the end of X and of Y
+      const int64_t xe = static_cast<int64_t>(n) * ld - c0, ye = static_cast<int64_t>(m) * ld - c0;
+      const uint32_t xb = static_cast<uint32_t>((xe > 0 ? xe : 0) * sizeof(T));
+      const uint32_t yb = static_cast<uint32_t>((ye > 0 ? ye : 0) * sizeof(T));
+      spmm_partition<VT, NR, true, CPL>(col, val, parts, lptr, np, p, X + c0, ld, Y + c0, ld, m,
+                                        1.0, 0.0, carry + c0 * cs, cs, xb, yb, s_mark_all[wid],
+                                        s_rows_all[wid]);
+      c0 += NR;
+      wave_lds_sync();
+    };
+    if (k == 8) pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 2>{});
+    if (k - c0 >= 4) pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{});
+    if (k - c0 >= 2) pass(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+    if (k - c0 >= 1) pass(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
+  }
+}
 
 // ------------------------------------------------------------ x generator
 // SplitMix64 output function (Steele, Lea, Flood 2014) applied to a key.
@@ -68,18 +189,18 @@ __host__ __device__ inline double x_value(uint64_t seed, int64_t rid, int32_t st
   return 2.0 * u - 1.0;
 }
 
-// x of every step of a tick: block row i fills entry i's x copy for its step.
+// X of every request of a tick: block row i fills entry i's k columns, column
+// c with x of step j0 + c.
 template <typename T>
 __global__ void fill_x_tick(const TickSrc src, uint64_t seed) {
   const ServeSlot *S = src.table + src.slot[blockIdx.y];
   const int32_t sc = src.step[blockIdx.y];
-  T *x = reinterpret_cast<T *>(static_cast<char *>(const_cast<void *>(S->xy.x)) +
-                               TickSrc::copy_of(sc) * S->x_stride);
-  const int32_t n = S->M.n, step = TickSrc::step_of(sc);
-  const int64_t rid = S->rid;
+  T *X = static_cast<T *>(const_cast<void *>(S->xy.x));
+  const int32_t n = S->M.n, j0 = TickSrc::first_of(sc), k = TickSrc::count_of(sc);
+  const int64_t rid = S->rid, ld = S->ld;
   for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n;
        c += int64_t(gridDim.x) * blockDim.x)
-    x[c] = static_cast<T>(x_value(seed, rid, step, c));
+    for (int32_t s = 0; s < k; ++s) X[c * ld + s] = static_cast<T>(x_value(seed, rid, j0 + s, c));
 }
 
 // ------------------------------------------------------------------ arena
@@ -152,11 +273,10 @@ struct Req {
   void *y_host = nullptr; // last y copied here when it finishes (optional)
   State st = kWaiting;
   int32_t np = 1, slot = -1;
-  int32_t copies = 1;         // x/y/carry copies: steps one tick may run
-  int32_t last_copy = 0;      // the copy the last step ran on
-  size_t off = 0, bytes = 0;  // x, y, parts, lptr, carry (copies of x, y, carry)
+  int32_t copies = 1;         // columns of X and Y: steps one tick may run
+  int32_t last_copy = 0;      // the column the last step ran in
+  size_t off = 0, bytes = 0;  // X, Y, parts, lptr, carries
   size_t x_off = 0, y_off = 0, parts_off = 0, lptr_off = 0, carry_off = 0;
-  size_t x_stride = 0, y_stride = 0;
   int32_t enq = 0;            // steps enqueued
   int64_t last_tick = -1;
   double t_arrive = 0, t_admit = 0, t_done = 0, ready_at = 0;
@@ -185,20 +305,18 @@ void layout_req(Req &q, const msrep_mat &A) {
     return at;
   };
   const size_t c = static_cast<size_t>(q.copies);
-  q.x_stride = align_up(xb * static_cast<size_t>(A.n) ? xb * A.n : 1, 256);
-  q.y_stride = align_up(xb * static_cast<size_t>(A.m) ? xb * A.m : 1, 256);
-  q.x_off = take(q.x_stride * c);
-  q.y_off = take(q.y_stride * c);
+  q.x_off = take(xb * static_cast<size_t>(A.n) * c);
+  q.y_off = take(xb * static_cast<size_t>(A.m) * c);
   q.parts_off = take(sizeof(msrep_part) * q.np);
   q.lptr_off = take(4 * static_cast<size_t>(msrep_lptr_bound(A.m, q.np)));
   q.carry_off = take(16 * static_cast<size_t>(q.np) * c);
   q.bytes = o;
 }
 
-// One step of one request in a tick, on copy `copy` of its vectors.
+// k consecutive steps of one request in a tick, from step j0.
 struct Entry {
   Req *q;
-  int32_t step, copy;
+  int32_t j0, k;
 };
 
 struct Tick {
@@ -244,13 +362,11 @@ struct HipExec {
     MSREP_HIP(hipGetDeviceProperties(&prop, dev));
     if (vtype == MSREP_F64)
       MSREP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, spmv_items_persistent<MSREP_F64, kK, true, 1, TickSrc>, kWpb * kWave,
-          seg_lds_per_wave<MSREP_F64, kK>() * kWpb));
+          &per_cu, serve_passes<MSREP_F64>, kSpmmWaves * kWave, 0));
     else
       MSREP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, spmv_items_persistent<MSREP_F32, kK, true, 1, TickSrc>, kWpb * kWave,
-          seg_lds_per_wave<MSREP_F32, kK>() * kWpb));
-    n_waves_max = std::max(1, per_cu) * kWpb * prop.multiProcessorCount;
+          &per_cu, serve_passes<MSREP_F32>, kSpmmWaves * kWave, 0));
+    n_waves_max = std::max(1, per_cu) * kSpmmWaves * prop.multiProcessorCount;
     MSREP_HIP(hipEventRecord(t0, comp));
     MSREP_HIP(hipEventSynchronize(t0));
     w0 = std::chrono::steady_clock::now();
@@ -331,8 +447,8 @@ struct HipExec {
                    reinterpret_cast<double *>(b + q.carry_off)};
     S.xy = BatchXY{b + q.x_off, b + q.y_off};
     S.rid = q.r.rid;
-    S.x_stride = static_cast<int64_t>(q.x_stride);
-    S.y_stride = static_cast<int64_t>(q.y_stride);
+    S.ld = q.copies;
+    S.ebytes = static_cast<int32_t>(vec_bytes(D.vtype));
     // the slot was last read by ticks that completed before it was freed
     MSREP_HIP(hipMemcpyAsync(arena + table_off + sizeof(ServeSlot) * q.slot, &S, sizeof(ServeSlot),
                              hipMemcpyHostToDevice, copy));
@@ -348,37 +464,39 @@ struct HipExec {
     src.table = reinterpret_cast<const ServeSlot *>(arena + table_off);
     src.count = static_cast<int32_t>(t.ent.size());
     int64_t items = 0;
-    int32_t max_n = 1;
+    int32_t max_n = 1, kmax = 1;
     for (int32_t i = 0; i < src.count; ++i) {
       const Entry &e = t.ent[i];
       const Req &q = *e.q;
       src.slot[i] = q.slot;
-      src.step[i] = e.step | (e.copy << 16);
+      src.step[i] = e.j0 | (e.k << 16);
       src.begin[i] = static_cast<int32_t>(items);
       items += q.np;
       max_n = std::max(max_n, pool[q.r.matrix].A.n);
+      kmax = std::max(kmax, e.k);
     }
     src.begin[src.count] = static_cast<int32_t>(items);
     src.n_items = items;
     src.n_waves = static_cast<int32_t>(std::min<int64_t>(n_waves_max, std::max<int64_t>(1, items)));
-    const int grid = (src.n_waves + kWpb - 1) / kWpb;
+    TickColSrc msrc;
+    static_cast<TickSrc &>(msrc) = src;
+    const int grid = (src.n_waves + kSpmmWaves - 1) / kSpmmWaves;
     const int gm = static_cast<int>((items + kMergeBlock - 1) / kMergeBlock);
     const dim3 gf(static_cast<unsigned>(std::min(64, (max_n + 255) / 256)),
                   static_cast<unsigned>(src.count));
+    const dim3 gmc(static_cast<unsigned>(gm > 0 ? gm : 1), static_cast<unsigned>(kmax));
     if (vtype == MSREP_F64) {
       hipLaunchKernelGGL(fill_x_tick<double>, gf, dim3(256), 0, comp, src, cfg.seed);
-      hipLaunchKernelGGL((spmv_items_persistent<MSREP_F64, kK, true, 1, TickSrc>), dim3(grid),
-                         dim3(kWpb * kWave), (seg_lds_per_wave<MSREP_F64, kK>() * kWpb), comp, src,
-                         1.0, 0.0);
-      hipLaunchKernelGGL((merge_items<double, true, TickSrc>), dim3(gm > 0 ? gm : 1),
-                         dim3(kMergeBlock), 0, comp, src, 1.0, 0.0);
+      hipLaunchKernelGGL(serve_passes<MSREP_F64>, dim3(grid), dim3(kSpmmWaves * kWave), 0, comp,
+                         src);
+      hipLaunchKernelGGL((merge_items<double, true, TickColSrc>), gmc, dim3(kMergeBlock), 0, comp,
+                         msrc, 1.0, 0.0);
     } else {
       hipLaunchKernelGGL(fill_x_tick<float>, gf, dim3(256), 0, comp, src, cfg.seed);
-      hipLaunchKernelGGL((spmv_items_persistent<MSREP_F32, kK, true, 1, TickSrc>), dim3(grid),
-                         dim3(kWpb * kWave), (seg_lds_per_wave<MSREP_F32, kK>() * kWpb), comp, src,
-                         1.0, 0.0);
-      hipLaunchKernelGGL((merge_items<float, true, TickSrc>), dim3(gm > 0 ? gm : 1),
-                         dim3(kMergeBlock), 0, comp, src, 1.0, 0.0);
+      hipLaunchKernelGGL(serve_passes<MSREP_F32>, dim3(grid), dim3(kSpmmWaves * kWave), 0, comp,
+                         src);
+      hipLaunchKernelGGL((merge_items<float, true, TickColSrc>), gmc, dim3(kMergeBlock), 0, comp,
+                         msrc, 1.0, 0.0);
     }
     MSREP_LAUNCHED("serve tick");
     MSREP_HIP(hipEventRecord(tick_ev[t.id % kRing], comp));
@@ -395,8 +513,11 @@ struct HipExec {
   msrep_status keep_y(Req &q) {
     if (!q.y_host) return MSREP_OK;
     const msrep_mat &H = pool[q.r.matrix].A;
-    MSREP_HIP(hipMemcpy(q.y_host, arena + q.off + q.y_off + q.y_stride * q.last_copy,
-                        vec_bytes(vtype) * static_cast<size_t>(H.m), hipMemcpyDeviceToHost));
+    // column last_copy of the request's Y (m rows of `copies` values)
+    const size_t eb = vec_bytes(vtype);
+    MSREP_HIP(hipMemcpy2D(q.y_host, eb, arena + q.off + q.y_off + eb * q.last_copy,
+                          eb * static_cast<size_t>(q.copies), eb, static_cast<size_t>(H.m),
+                          hipMemcpyDeviceToHost));
     return MSREP_OK;
   }
   // Nothing to do: spin while the device works, else sleep until the next
@@ -445,7 +566,7 @@ struct SimExec {
   msrep_status launch(Tick &t, const std::vector<Resident> &) {
     double work = tick_cost;
     for (const Entry &e : t.ent)
-      work += 2.0 * static_cast<double>(pool[e.q->r.matrix].A.nnz) / flop_rate;
+      work += 2.0 * e.k * static_cast<double>(pool[e.q->r.matrix].A.nnz) / flop_rate;
     dev_free = std::max(dev_free, clock) + work;
     t.end = dev_free;
     return MSREP_OK;
@@ -530,7 +651,7 @@ class Scheduler {
       Tick &t = inflight_.front();
       for (const Entry &e : t.ent) {
         Req *q = e.q;
-        if (e.step == q->r.steps - 1) {  // the request's last step: once per request
+        if (e.j0 + e.k == q->r.steps) {  // the request's last steps: once per request
           if (msrep_status st = ex_.keep_y(*q)) err = st;
           finish(*q, MSREP_OK, at);
           res_[q->r.matrix].refs--;
@@ -552,20 +673,16 @@ class Scheduler {
       t.id = tick_id_;
       // ready requests taken round robin over the admitted list, so that
       // none waits more than one tick for a turn; each runs its next steps,
-      // up to its copies, while the tick has room (kTickMax steps)
+      // up to its copies, while the tick has room (kTickMax requests)
       const size_t na = admitted_.size();
-      std::vector<Req *> took;
       for (size_t j = 0; j < na && static_cast<int>(t.ent.size()) < kTickMax; ++j) {
         Req *q = admitted_[(rr_ + j) % na];
         if (q->st != kReady || q->enq >= q->r.steps) continue;
-        const int32_t room = kTickMax - static_cast<int32_t>(t.ent.size());
-        const int32_t k = std::min({q->copies, q->r.steps - q->enq, room});
-        for (int32_t c = 0; c < k; ++c) t.ent.push_back(Entry{q, q->enq + c, c});
-        took.push_back(q);
+        t.ent.push_back(Entry{q, q->enq, std::min(q->copies, q->r.steps - q->enq)});
       }
-      if (na) rr_ = (rr_ + took.size()) % na;
+      if (na) rr_ = (rr_ + t.ent.size()) % na;
       if (!t.ent.empty()) {
-        t.requests = static_cast<int32_t>(took.size());
+        t.requests = static_cast<int32_t>(t.ent.size());
         peak_active_ = std::max(peak_active_, t.requests);
         if (msrep_status st = ex_.launch(t, res_)) {
           err = st;
@@ -573,9 +690,9 @@ class Scheduler {
         }
         for (const Entry &e : t.ent) {
           Req *q = e.q;
-          q->enq = e.step + 1;
+          q->enq = e.j0 + e.k;
           q->last_tick = t.id;
-          q->last_copy = e.copy;
+          q->last_copy = e.k - 1;
           if (q->enq == q->r.steps) q->st = kDraining;
         }
         inflight_.push_back(std::move(t));
@@ -795,8 +912,9 @@ msrep_status check_pool_mat(const msrep_host_mat &H, int32_t vt, bool need_array
   const msrep_mat &A = H.A;
   if (A.fmt != MSREP_CSR || A.vtype != vt)
     return fail(MSREP_ERR_ARG, "%s: pool matrix %d must be CSR of the pool's value type", who, k);
+  // (X and Y of a request, up to kMaxStepsPerTick columns, stay below 4 GiB)
   if (A.m < 0 || A.n < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31) || A.n >= (1 << 24) ||
-      H.np < 0)
+      A.m >= (1 << 26) || H.np < 0)
     return fail(MSREP_ERR_ARG, "%s: pool matrix %d has an unsupported shape", who, k);
   if (need_arrays && (!A.ptr || (A.nnz > 0 && (!A.idx || !A.val))))
     return fail(MSREP_ERR_ARG, "%s: pool matrix %d has NULL arrays", who, k);

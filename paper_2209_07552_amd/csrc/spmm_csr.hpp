@@ -137,13 +137,17 @@ __device__ __forceinline__ void spmm_scale_rows(T *__restrict__ Y, int64_t ldy, 
   }
 }
 
+// Partition p of one pass: NR columns of X (n rows of ldx) into Y (m rows of
+// ldy), head and tail carries of column c at carry + c*cstride + 2p.
+// s_mark and s_rows: 64 ints of LDS each, the wavefront's own.
 template <int VT, int NR, bool BETA0, int CPL>
-__global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void spmm_csr(
+__device__ __forceinline__ void spmm_partition(
     const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
-    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
+    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np, int32_t p,
     const typename vt_traits<VT>::T *__restrict__ X, int64_t ldx,
     typename vt_traits<VT>::T *__restrict__ Y, int64_t ldy, int32_t m, double alpha,
-    double beta, double *__restrict__ carry, int64_t cstride, uint32_t xbytes, uint32_t ybytes) {
+    double beta, double *__restrict__ carry, int64_t cstride, uint32_t xbytes, uint32_t ybytes,
+    int32_t *s_mark, int32_t *s_rows) {
   using Tr = vt_traits<VT>;
   using V = typename Tr::V;
   using T = typename Tr::T;
@@ -153,18 +157,12 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
   constexpr int LPS = NR / CPL;   // lanes per slot
   constexpr int U = LPS;          // positions per slot
   constexpr int G = kWave / LPS;  // slots per chunk
-  __shared__ int32_t s_mark_all[kSpmmWaves][kWave];
-  __shared__ int32_t s_rows_all[kSpmmWaves][kWave];
-  const int wid = threadIdx.x / kWave;
-  int32_t *s_mark = s_mark_all[wid];
-  int32_t *s_rows = s_rows_all[wid];
   const int lane = lane_id();
   const int q = lane / LPS, cl = lane % LPS;  // slot, and the lane's first column / CPL
   // byte offsets of X and Y elements (32-bit)
   const uint32_t xrow = static_cast<uint32_t>(ldx) * sizeof(T), xcol = cl * CPL * sizeof(T);
   const uint32_t yrow = static_cast<uint32_t>(ldy) * sizeof(T);
-  const PartStride ps(np);
-  for (int32_t p = ps.p; p < np; p += ps.step) {
+  {
     const msrep_part *pp = parts + p;
     const int64_t s0 = uniform(pp->start_idx);
     const int64_t e0 = uniform(pp->end_idx);
@@ -436,6 +434,23 @@ __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per
     if (!eflag) spmm_scale_rows<T, NR>(Y, ldy, gap_lo > 0 ? gap_lo : 0, gap_hi, beta, BETA0);
     if (p == 0) spmm_scale_rows<T, NR>(Y, ldy, 0, r0 < m ? r0 : m, beta, BETA0);
   }
+}
+
+template <int VT, int NR, bool BETA0, int CPL>
+__global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void spmm_csr(
+    const int32_t *__restrict__ col, const typename vt_traits<VT>::V *__restrict__ val,
+    const msrep_part *__restrict__ parts, const int32_t *__restrict__ lptr, int32_t np,
+    const typename vt_traits<VT>::T *__restrict__ X, int64_t ldx,
+    typename vt_traits<VT>::T *__restrict__ Y, int64_t ldy, int32_t m, double alpha,
+    double beta, double *__restrict__ carry, int64_t cstride, uint32_t xbytes, uint32_t ybytes) {
+  __shared__ int32_t s_mark_all[kSpmmWaves][kWave];
+  __shared__ int32_t s_rows_all[kSpmmWaves][kWave];
+  const int wid = threadIdx.x / kWave;
+  const PartStride ps(np);
+  for (int32_t p = ps.p; p < np; p += ps.step)
+    spmm_partition<VT, NR, BETA0, CPL>(col, val, parts, lptr, np, p, X, ldx, Y, ldy, m, alpha,
+                                       beta, carry, cstride, xbytes, ybytes, s_mark_all[wid],
+                                       s_rows_all[wid]);
 }
 
 }  // namespace msrep

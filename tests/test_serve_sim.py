@@ -19,14 +19,14 @@ def _pool(count=6, m_hi=20_000):
     return [A for A, _ in synth.batched_set(count, seed=3, m_lo=500, m_hi=m_hi)]
 
 
-SPT = 8  # the library's default steps per tick: a request holds min(steps, SPT) vector copies
+SPT = 8  # the library's default steps per tick: a request's X and Y have min(steps, SPT) columns
 
 
 def _bytes(A, np_, xb=8, steps=1):
     r = lambda b: (b + 255) // 256 * 256
     c = max(1, min(steps, SPT))
     mat = r(4 * (A.m + 1)) + r(4 * A.nnz) + r(xb * A.nnz)
-    req = (c * r(xb * A.n) + c * r(xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) +
+    req = (r(c * xb * A.n) + r(c * xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) +
            r(16 * np_ * c))
     return mat, req
 
@@ -93,12 +93,14 @@ def test_steps_per_tick_batches_a_requests_steps():
     assert one[1]["ticks"] >= max(q.steps for q in trace)
     assert eight[1]["ticks"] * 4 <= one[1]["ticks"]
     assert eight[1]["p50_ms"] < one[1]["p50_ms"]
-    # a tick never holds more than 240 steps: 300 requests of 16 steps arriving
-    # at once take at least 300*16/240 ticks
-    burst = [synth.Request(i, 0.0, i % len(pool), 16) for i in range(300)]
+    # a tick never holds more than 240 requests: 300 requests of 64 steps
+    # arriving at once (eight ticks' worth each) fill ticks to 240 and take
+    # at least 300*8/240 ticks
+    burst = [synth.Request(i, 0.0, i % len(pool), 64) for i in range(300)]
     res, st = serving.serve(pool, burst, budget_bytes=1 << 36, max_slots=300, simulate=True,
-                            steps_per_tick=16)
-    assert all(r.status == 0 for r in res) and st["ticks"] >= 300 * 16 // 240
+                            steps_per_tick=8)
+    assert all(r.status == 0 for r in res)
+    assert st["peak_active"] == 240 and st["ticks"] >= 300 * 8 // 240
 
 
 def test_max_slots_one_serialises():
