@@ -1081,8 +1081,10 @@ def bench_serve(args, vt):
     log("generated pool of %d in %.1fs" % (len(pool), time.time() - t0))
     budget = int(args.budget_gb * (1 << 30))
     mean_steps = 55.0
-    # capacity estimate from a saturated run: SpMVs per second of the mix
-    probe = synth.serving_trace(max(64, args.count // 4), rate=1e9, pool=len(pool), seed=99)
+    # capacity estimate from a saturated run: SpMVs per second of the mix,
+    # with enough requests (four per pool matrix) that the run is mostly
+    # steady state rather than first uploads and a draining tail
+    probe = synth.serving_trace(max(64, 4 * args.count), rate=1e9, pool=len(pool), seed=99)
     spt = args.steps_per_tick
     _, st = serving.serve(pool, probe, budget_bytes=budget, vtype=vt, max_slots=256,
                           steps_per_tick=spt)
