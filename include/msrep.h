@@ -433,15 +433,19 @@ msrep_status msrep_plan_destroy(msrep_plan plan);
  * Matrices are uploaded into the caller's arena when the request is admitted
  * (admission is by bytes: matrix + partitions + vectors must fit in what the
  * arena has free) and stay resident while the request runs.  Every tick
- * executes the next steps of every active request, up to steps_per_tick of
- * each (240 requests per tick at most), in one batched launch, so requests
- * that arrive while others run join the next tick.  A request's steps are
- * independent SpMVs: those that share a tick are the columns of one
- * multi-vector product Y = A*X (X: n x c, Y: m x c row-major, c =
- * min(steps, steps_per_tick), reserved with the request), so the matrix is
- * read once per tick rather than once per step.  A request's descriptor is
- * written to the device once, when it is admitted; a tick only launches
- * kernels.  Pool matrices are CSR of one value type with nnz < 2^31,
+ * executes the next steps of every active request (240 requests per tick at
+ * most) in one batched launch, so requests that arrive while others run
+ * join the next tick.  A request's steps are independent SpMVs: those that
+ * share a tick are the columns of a multi-vector product Y = A*X, run as
+ * passes of up to 8 columns side by side, so the matrix is read once per 8
+ * steps rather than once per step.  A request reserves c = min(steps,
+ * steps_per_tick) columns of X and Y (in blocks of 8, each block row-major).
+ * How many of them a tick runs follows the load: all that are left while
+ * the tick is small against the GPU, else 8 per request.  Every tick but a
+ * request's last runs a multiple of 8 of its steps, so its passes, and its
+ * results, are bit-identical alone and in any mix, at any load and for
+ * every steps_per_tick of 8 or more.  A request's descriptor is written to
+ * the device once, when it is admitted; a tick only launches kernels.  Pool matrices are CSR of one value type with nnz < 2^31,
  * n < 2^24 and m < 2^26 (else MSREP_ERR_ARG).
  *   x_j[c] = 2*u - 1 with u the top 53 bits of splitmix64(key) / 2^53,
  *   key = seed ^ (rid << 40) ^ ((uint64)j << 24) ^ c (rid < 2^24, j < 2^16)
@@ -467,8 +471,8 @@ typedef struct msrep_serve_cfg {
                         /* results[i].y_host (where not NULL)                */
   int32_t max_queue;    /* msrep_server_submit: most requests waiting for    */
                         /* admission before MSREP_ERR_BUSY (0: 2^20)          */
-  int32_t steps_per_tick; /* most steps of one request in a tick (1..8;    */
-                          /* 0: 8)                                           */
+  int32_t steps_per_tick; /* most steps of one request in a tick (1..64;   */
+                          /* 0: 64)                                          */
   int32_t _pad;
 } msrep_serve_cfg;
 

@@ -49,49 +49,59 @@ namespace {
 constexpr int kRing = 4;     // tick events in rotation (at most kInflight ticks in flight)
 constexpr int kInflight = 2;
 constexpr int64_t kDefaultQueue = int64_t(1) << 20;  // incremental server's waiting requests
-constexpr int32_t kDefaultStepsPerTick = 8;
-constexpr int32_t kMaxStepsPerTick = kSpmmMaxCols;  // a tick's steps of a request: one pass
+constexpr int32_t kMaxStepsPerTick = 64;
+constexpr int32_t kDefaultStepsPerTick = kMaxStepsPerTick;
+constexpr int64_t kTickRounds = 1;  // a tick's items: at most this many rounds of resident waves
+// passes (of at most 8 columns) that k steps of a request take in a tick
+constexpr int32_t pass_count(int32_t k) { return (k + kSpmmMaxCols - 1) / kSpmmMaxCols; }
 
 // ------------------------------------------------------- tick descriptors
 // A request slot of the server: its resident matrix, partitions, carries and
-// vectors.  A request's steps that share a tick are the columns of one
-// multi-vector pass: X (n x ld) and Y (m x ld) row-major, column c holding
-// step j0 + c of the tick, the head and tail carries of column c at
-// carry + c*2*np.  Written once when the request is admitted.
+// vectors.  A request's steps that share a tick are the columns of a
+// multi-vector product, stored in blocks of ld = min(8, copies) columns: block
+// b of X is n x ld row-major at X + b*n*ld, of Y m x ld at Y + b*m*ld; column c
+// (step j0 + c of the tick) is column c % ld of block c / ld, and its head and
+// tail carries sit at carry + c*2*np.  Written once when the request is
+// admitted.
 struct ServeSlot {
   BatchMat M;
   BatchXY xy;
   int64_t rid;
-  int32_t ld;     // columns of X and Y (the most steps the request runs in a tick)
+  int32_t ld;     // columns per block of X and Y
   int32_t ebytes; // bytes of an x or y element
 };
 
 constexpr int kTickMax = 240;  // requests per tick (the arguments stay below 4 KB)
 
 // One serving tick: an entry per request it runs (its slot; its first step
-// j0 and its count k of steps, as j0 | k << 16), and the prefix sums of the
-// requests' partition counts (item it belongs to entry i with begin[i] <= it
-// < begin[i+1]).  Passed by value as kernel arguments.
+// j0 and its count k of steps, as j0 | k << 16) and two prefix sums over the
+// entries: of their partition counts (the merge's items: (request,
+// partition)), and of partitions times passes (the product's items:
+// (request, partition, pass), pass b covering columns 8b .. 8b+7).  Passed
+// by value as kernel arguments.
 struct TickSrc {
   const ServeSlot *table;
-  int64_t n_items;
+  int64_t n_items, n_pass_items;
   int32_t n_waves, count;
   int32_t slot[kTickMax];
   int32_t step[kTickMax];  // j0 | k << 16
   int32_t begin[kTickMax + 1];
+  int32_t pbegin[kTickMax + 1];
   __device__ static int32_t first_of(int32_t v) { return v & 0xffff; }
   __device__ static int32_t count_of(int32_t v) { return v >> 16; }
-  __device__ int32_t entry_of(int64_t it) const {
-    int32_t lo = 0, hi = count;  // begin[lo] <= it < begin[hi]
+  // the entry i with b[i] <= it < b[i+1]
+  __device__ int32_t find(const int32_t *b, int64_t it) const {
+    int32_t lo = 0, hi = count;
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
-      if (begin[mid] <= it)
+      if (b[mid] <= it)
         lo = mid;
       else
         hi = mid;
     }
     return lo;
   }
+  __device__ int32_t entry_of(int64_t it) const { return find(begin, it); }
   // equal item counts per group (a request's partitions hold equal
   // nonzeros, so items cost about the same)
   __device__ void group(int32_t g, int32_t G, int64_t &lo, int64_t &hi) const {
@@ -100,17 +110,19 @@ struct TickSrc {
   }
 };
 
-// The tick's items seen by the boundary merge for column blockIdx.y: a
-// request running fewer steps has no such column (m = 0: nothing written).
+// The tick's (request, partition) items seen by the boundary merge for column
+// blockIdx.y: a request running fewer steps has no such column (m = 0:
+// nothing written).
 struct TickColSrc : TickSrc {
   __device__ void get(int64_t it, BItem &o) const {
     const int32_t i = entry_of(it);
     const ServeSlot *S = table + slot[i];
     bitem_from(S->M, S->xy, static_cast<int32_t>(it - begin[i]), o);
-    o.ldy = S->ld;
-    const int32_t c = static_cast<int32_t>(blockIdx.y);
+    const int32_t c = static_cast<int32_t>(blockIdx.y), ld = S->ld;
+    o.ldy = ld;
     if (c < count_of(step[i])) {
-      o.y = static_cast<char *>(o.y) + static_cast<int64_t>(c) * S->ebytes;
+      o.y = static_cast<char *>(o.y) +
+            (static_cast<int64_t>(c / ld) * S->M.m * ld + c % ld) * S->ebytes;
       o.carry += static_cast<int64_t>(c) * 2 * S->M.np;
     } else {
       o.m = 0;
@@ -118,9 +130,13 @@ struct TickColSrc : TickSrc {
   }
 };
 
-// The tick's passes: resident wavefronts, those of one XCD sweeping its group
-// of items together; item (request, partition p) runs the request's k steps
-// as passes of 8, 4, 2 and 1 columns of the multi-vector routine.
+// The tick's products: resident wavefronts, those of one XCD sweeping its
+// group of (request, partition, pass) items together (a partition's passes
+// are neighbours, so they read its slice of A through one L2).  Pass b of a
+// request running k steps covers columns 8b .. min(k, 8b+8) - 1 of block b:
+// one 8-column pass of the multi-vector routine, or passes of 4, 2 and 1.
+// Every request's passes depend only on its own k, so its arithmetic does
+// not depend on the tick's other requests.
 template <int VT>
 __global__ __launch_bounds__(kSpmmWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void
 serve_passes(const TickSrc src) {
@@ -136,27 +152,30 @@ serve_passes(const TickSrc src) {
   const int g = static_cast<int>(blockIdx.x) % G;
   const int j = (static_cast<int>(blockIdx.x) / G) * wpb + wid;
   const int wg = (nb / G + (g < nb % G ? 1 : 0)) * wpb;
-  int64_t lo, hi;
-  src.group(g, G, lo, hi);
+  const int64_t lo = src.n_pass_items * g / G, hi = src.n_pass_items * (g + 1) / G;
   for (int64_t it = lo + j; it < hi; it += wg) {
-    const int32_t i = uniform(src.entry_of(it));
+    const int32_t i = uniform(src.find(src.pbegin, it));
     const ServeSlot *S = src.table + src.slot[i];
     const int32_t k = TickSrc::count_of(src.step[i]);
-    const int32_t p = static_cast<int32_t>(it - src.begin[i]);
+    const int32_t passes = pass_count(k);
+    const int32_t li = static_cast<int32_t>(it - src.pbegin[i]);
+    const int32_t p = li / passes, blk = li % passes;
     const int32_t *col = uniform(S->M.col);
     const V *val = static_cast<const V *>(uniform(S->M.val));
     const msrep_part *parts = uniform(S->M.parts);
     const int32_t *lptr = uniform(S->M.lptr);
-    double *carry = uniform(S->M.carry);
     const int32_t m = uniform(S->M.m), n = uniform(S->M.n), np = uniform(S->M.np);
     const int64_t ld = uniform(S->ld);
-    const T *X = static_cast<const T *>(uniform(S->xy.x));
-    T *Y = static_cast<T *>(uniform(S->xy.y));
     const int64_t cs = 2 * static_cast<int64_t>(np);
+    // the pass's block of X, Y and carries
+    const T *X = static_cast<const T *>(uniform(S->xy.x)) + blk * static_cast<int64_t>(n) * ld;
+    T *Y = static_cast<T *>(uniform(S->xy.y)) + blk * static_cast<int64_t>(m) * ld;
+    double *carry = uniform(S->M.carry) + static_cast<int64_t>(blk) * kSpmmMaxCols * cs;
+    const int32_t w = min(kSpmmMaxCols, k - blk * kSpmmMaxCols);  // columns of this pass
     int32_t c0 = 0;
     auto pass = [&](auto nr_c, auto cpl_c) {
       constexpr int NR = decltype(nr_c)::value, CPL = decltype(cpl_c)::value;
-      // bytes from the pass's first column to the end of X and of Y
+      // bytes from the pass's first column to the end of the block of X and of Y
       const int64_t xe = static_cast<int64_t>(n) * ld - c0, ye = static_cast<int64_t>(m) * ld - c0;
       const uint32_t xb = static_cast<uint32_t>((xe > 0 ? xe : 0) * sizeof(T));
       const uint32_t yb = static_cast<uint32_t>((ye > 0 ? ye : 0) * sizeof(T));
@@ -166,10 +185,10 @@ serve_passes(const TickSrc src) {
       c0 += NR;
       wave_lds_sync();
     };
-    if (k == 8) pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 2>{});
-    if (k - c0 >= 4) pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{});
-    if (k - c0 >= 2) pass(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
-    if (k - c0 >= 1) pass(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
+    if (w == 8) pass(std::integral_constant<int, 8>{}, std::integral_constant<int, 2>{});
+    if (w - c0 >= 4) pass(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{});
+    if (w - c0 >= 2) pass(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+    if (w - c0 >= 1) pass(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
   }
 }
 
@@ -190,7 +209,7 @@ __host__ __device__ inline double x_value(uint64_t seed, int64_t rid, int32_t st
 }
 
 // X of every request of a tick: block row i fills entry i's k columns, column
-// c with x of step j0 + c.
+// c (column c % ld of block c / ld) with x of step j0 + c.
 template <typename T>
 __global__ void fill_x_tick(const TickSrc src, uint64_t seed) {
   const ServeSlot *S = src.table + src.slot[blockIdx.y];
@@ -200,7 +219,8 @@ __global__ void fill_x_tick(const TickSrc src, uint64_t seed) {
   const int64_t rid = S->rid, ld = S->ld;
   for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < n;
        c += int64_t(gridDim.x) * blockDim.x)
-    for (int32_t s = 0; s < k; ++s) X[c * ld + s] = static_cast<T>(x_value(seed, rid, j0 + s, c));
+    for (int32_t s = 0; s < k; ++s)
+      X[(s / ld) * n * ld + c * ld + s % ld] = static_cast<T>(x_value(seed, rid, j0 + s, c));
 }
 
 // ------------------------------------------------------------------ arena
@@ -275,6 +295,9 @@ struct Req {
   int32_t np = 1, slot = -1;
   int32_t copies = 1;         // columns of X and Y: steps one tick may run
   int32_t last_copy = 0;      // the column the last step ran in
+  // columns per block of X and Y, and blocks
+  int32_t ld() const { return copies < kSpmmMaxCols ? copies : kSpmmMaxCols; }
+  int32_t blocks() const { return (copies + ld() - 1) / ld(); }
   size_t off = 0, bytes = 0;  // X, Y, parts, lptr, carries
   size_t x_off = 0, y_off = 0, parts_off = 0, lptr_off = 0, carry_off = 0;
   int32_t enq = 0;            // steps enqueued
@@ -305,8 +328,9 @@ void layout_req(Req &q, const msrep_mat &A) {
     return at;
   };
   const size_t c = static_cast<size_t>(q.copies);
-  q.x_off = take(xb * static_cast<size_t>(A.n) * c);
-  q.y_off = take(xb * static_cast<size_t>(A.m) * c);
+  const size_t cb = static_cast<size_t>(q.ld()) * q.blocks();  // whole blocks
+  q.x_off = take(xb * static_cast<size_t>(A.n) * cb);
+  q.y_off = take(xb * static_cast<size_t>(A.m) * cb);
   q.parts_off = take(sizeof(msrep_part) * q.np);
   q.lptr_off = take(4 * static_cast<size_t>(msrep_lptr_bound(A.m, q.np)));
   q.carry_off = take(16 * static_cast<size_t>(q.np) * c);
@@ -340,6 +364,7 @@ struct HipExec {
   size_t table_off = 0;
   ServeSlot *slots_h = nullptr;  // pinned staging of the slot table
   int n_waves_max = 0;
+  int64_t wave_slots() const { return n_waves_max; }
 
   HipExec(const msrep_serve_cfg &c, const msrep_host_mat *p, int32_t vt)
       : cfg(c), pool(p), arena(static_cast<char *>(c.arena_d)), vtype(vt) {}
@@ -447,7 +472,7 @@ struct HipExec {
                    reinterpret_cast<double *>(b + q.carry_off)};
     S.xy = BatchXY{b + q.x_off, b + q.y_off};
     S.rid = q.r.rid;
-    S.ld = q.copies;
+    S.ld = q.ld();
     S.ebytes = static_cast<int32_t>(vec_bytes(D.vtype));
     // the slot was last read by ticks that completed before it was freed
     MSREP_HIP(hipMemcpyAsync(arena + table_off + sizeof(ServeSlot) * q.slot, &S, sizeof(ServeSlot),
@@ -463,7 +488,7 @@ struct HipExec {
     TickSrc src;
     src.table = reinterpret_cast<const ServeSlot *>(arena + table_off);
     src.count = static_cast<int32_t>(t.ent.size());
-    int64_t items = 0;
+    int64_t items = 0, pitems = 0;
     int32_t max_n = 1, kmax = 1;
     for (int32_t i = 0; i < src.count; ++i) {
       const Entry &e = t.ent[i];
@@ -471,13 +496,17 @@ struct HipExec {
       src.slot[i] = q.slot;
       src.step[i] = e.j0 | (e.k << 16);
       src.begin[i] = static_cast<int32_t>(items);
+      src.pbegin[i] = static_cast<int32_t>(pitems);
       items += q.np;
+      pitems += static_cast<int64_t>(q.np) * pass_count(e.k);
       max_n = std::max(max_n, pool[q.r.matrix].A.n);
       kmax = std::max(kmax, e.k);
     }
     src.begin[src.count] = static_cast<int32_t>(items);
+    src.pbegin[src.count] = static_cast<int32_t>(pitems);
     src.n_items = items;
-    src.n_waves = static_cast<int32_t>(std::min<int64_t>(n_waves_max, std::max<int64_t>(1, items)));
+    src.n_pass_items = pitems;
+    src.n_waves = static_cast<int32_t>(std::min<int64_t>(n_waves_max, std::max<int64_t>(1, pitems)));
     TickColSrc msrc;
     static_cast<TickSrc &>(msrc) = src;
     const int grid = (src.n_waves + kSpmmWaves - 1) / kSpmmWaves;
@@ -513,11 +542,12 @@ struct HipExec {
   msrep_status keep_y(Req &q) {
     if (!q.y_host) return MSREP_OK;
     const msrep_mat &H = pool[q.r.matrix].A;
-    // column last_copy of the request's Y (m rows of `copies` values)
-    const size_t eb = vec_bytes(vtype);
-    MSREP_HIP(hipMemcpy2D(q.y_host, eb, arena + q.off + q.y_off + eb * q.last_copy,
-                          eb * static_cast<size_t>(q.copies), eb, static_cast<size_t>(H.m),
-                          hipMemcpyDeviceToHost));
+    // column last_copy of the request's Y: column last_copy % ld of block
+    // last_copy / ld (m rows of ld values)
+    const size_t eb = vec_bytes(vtype), ld = static_cast<size_t>(q.ld());
+    const size_t at = (q.last_copy / ld) * ld * static_cast<size_t>(H.m) + q.last_copy % ld;
+    MSREP_HIP(hipMemcpy2D(q.y_host, eb, arena + q.off + q.y_off + eb * at, eb * ld, eb,
+                          static_cast<size_t>(H.m), hipMemcpyDeviceToHost));
     return MSREP_OK;
   }
   // Nothing to do: spin while the device works, else sleep until the next
@@ -546,6 +576,7 @@ struct SimExec {
   double upload_bw = 25e9, flop_rate = 5e11, tick_cost = 2e-5;
   int32_t vtype;
   SimExec(const msrep_host_mat *p, int32_t vt) : pool(p), vtype(vt) {}
+  int64_t wave_slots() const { return 4096; }
   msrep_status init(Arena &, int32_t) { return MSREP_OK; }
   size_t reserved_bytes() const { return 0; }
   void shutdown() {}
@@ -613,11 +644,33 @@ class Scheduler {
   int32_t steps_per_tick() const {
     return cfg_.steps_per_tick > 0 ? cfg_.steps_per_tick : kDefaultStepsPerTick;
   }
+  // Steps of request q in a tick whose cap is `cap` (a multiple of 8): all
+  // that are left if they fit, else whole blocks of 8.  Every tick but a
+  // request's last so runs a multiple of 8 of its steps, its passes are the
+  // same whatever the caps were, and so are its results (with fewer than 8
+  // copies, steps_per_tick below 8, a tick runs up to `copies` steps).
+  static int32_t steps_this_tick(const Req &q, int32_t cap) {
+    const int32_t left = q.r.steps - q.enq;
+    if (q.copies < kSpmmMaxCols) return std::min(q.copies, left);
+    const int32_t lim = std::min(q.copies, cap);
+    return left <= lim ? left : lim / kSpmmMaxCols * kSpmmMaxCols;
+  }
   // A request arrives (at q->t_arrive on the scheduler's clock).
   void arrive(std::unique_ptr<Req> q) {
     q->np = np_of(q->r.matrix);
     q->copies = std::max(1, std::min(steps_per_tick(), q->r.steps));
+    // a tick's (partition, pass) items of one request stay below 2^31
+    const int64_t max_pass = ((int64_t(1) << 31) - 1) / q->np;
+    if (pass_count(q->copies) > max_pass)
+      q->copies = static_cast<int32_t>(max_pass * kSpmmMaxCols);
     layout_req(*q, pool_[q->r.matrix].A);
+    // a request whose vectors would hold more than a sixteenth of the arena
+    // reserves 8 columns (what a tick under load runs), so that a small
+    // arena still holds many requests; its results are the same
+    if (q->copies > kSpmmMaxCols && q->bytes > arena_.cap() / 16) {
+      q->copies = kSpmmMaxCols;
+      layout_req(*q, pool_[q->r.matrix].A);
+    }
     q->st = kWaiting;
     waiting_.push_back(q.get());
     owned_.push_back(std::move(q));
@@ -672,13 +725,37 @@ class Scheduler {
       Tick t;
       t.id = tick_id_;
       // ready requests taken round robin over the admitted list, so that
-      // none waits more than one tick for a turn; each runs its next steps,
-      // up to its copies, while the tick has room (kTickMax requests)
+      // none waits more than one tick for a turn (kTickMax requests a tick)
       const size_t na = admitted_.size();
-      for (size_t j = 0; j < na && static_cast<int>(t.ent.size()) < kTickMax; ++j) {
+      take_.clear();
+      for (size_t j = 0; j < na && static_cast<int>(take_.size()) < kTickMax; ++j) {
         Req *q = admitted_[(rr_ + j) % na];
-        if (q->st != kReady || q->enq >= q->r.steps) continue;
-        t.ent.push_back(Entry{q, q->enq, std::min(q->copies, q->r.steps - q->enq)});
+        if (q->st == kReady && q->enq < q->r.steps) take_.push_back(q);
+      }
+      // the most steps of a request in this tick: the largest multiple of 8
+      // that keeps the tick's (partition, pass) items within kTickRounds
+      // rounds of the resident wavefronts.  A lone request then runs all its
+      // steps in a tick or two; a busy server runs 8 of each, so that each
+      // request's matrix is read once per tick and the x blocks the tick
+      // gathers from stay few.
+      const int64_t room = kTickRounds * ex_.wave_slots();
+      int32_t cap = kSpmmMaxCols;
+      for (int32_t c = kMaxStepsPerTick; c > kSpmmMaxCols; c -= kSpmmMaxCols) {
+        int64_t items = 0;
+        for (const Req *q : take_)
+          items += static_cast<int64_t>(q->np) * pass_count(steps_this_tick(*q, c));
+        if (items <= room) {
+          cap = c;
+          break;
+        }
+      }
+      // (partition, pass) items below 2^31 in all
+      int64_t pitems = 0;
+      for (Req *q : take_) {
+        const int32_t k = steps_this_tick(*q, cap);
+        pitems += static_cast<int64_t>(q->np) * pass_count(k);
+        if (pitems >= (int64_t(1) << 31)) break;
+        t.ent.push_back(Entry{q, q->enq, k});
       }
       if (na) rr_ = (rr_ + t.ent.size()) % na;
       if (!t.ent.empty()) {
@@ -794,6 +871,7 @@ class Scheduler {
   }
 
   Exec &ex_;
+  std::vector<Req *> take_;  // the requests a tick takes
   const msrep_serve_cfg &cfg_;
   const msrep_host_mat *pool_;
   int32_t pool_size_;
@@ -912,7 +990,7 @@ msrep_status check_pool_mat(const msrep_host_mat &H, int32_t vt, bool need_array
   const msrep_mat &A = H.A;
   if (A.fmt != MSREP_CSR || A.vtype != vt)
     return fail(MSREP_ERR_ARG, "%s: pool matrix %d must be CSR of the pool's value type", who, k);
-  // (X and Y of a request, up to kMaxStepsPerTick columns, stay below 4 GiB)
+  // (a block of 8 columns of a request's X or Y stays below 4 GiB)
   if (A.m < 0 || A.n < 0 || A.nnz < 0 || A.nnz >= (int64_t(1) << 31) || A.n >= (1 << 24) ||
       A.m >= (1 << 26) || H.np < 0)
     return fail(MSREP_ERR_ARG, "%s: pool matrix %d has an unsupported shape", who, k);

@@ -306,7 +306,7 @@ def test_server_argument_errors():
     assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
     cfg = _abi._ServeCfg(0x1000, 1 << 20, 4, 1024, 0, 1.0, 0, -1)  # negative max_queue
     assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
-    for spt in (-1, 9):  # steps_per_tick outside 0..8
+    for spt in (-1, 65):  # steps_per_tick outside 0..64
         cfg = _abi._ServeCfg(0x1000, 1 << 20, 4, 1024, 0, 1.0, 0, 0, spt)
         assert L.msrep_server_create(ctypes.byref(cfg), pool, 1, ctypes.byref(h)) == -1
         assert b"steps_per_tick" in L.msrep_last_error()

@@ -58,21 +58,28 @@ def test_alone_equals_mix():
 
 @pytest.mark.parametrize("vt", [0, 1])
 def test_steps_per_tick_same_results(vt):
-    """A request's steps run several to a tick, as the columns of one
-    multi-vector pass (passes of 8, 4, 2 and 1 columns): the last y matches
-    the oracle with one step per tick, three (passes of 2 and 1), five and
-    eight; 1..40 steps per request leave partial groups of every size, and
-    the last step lands in every column position."""
+    """A request's steps run several to a tick, as the columns of
+    multi-vector passes (blocks of 8 columns, each one pass of 8 or passes of
+    4, 2 and 1): the last y matches the oracle with 1, 3, 5, 8, 13 (a full
+    block and a partial one) and 64 steps per tick; 1..40 steps per request
+    leave partial groups of every size, and the last step lands in every
+    column position and block.  From 8 steps per tick up, every tick but a
+    request's last runs whole blocks of 8, so the results are bit-identical
+    for 8, 13 and 64 (and whatever the load made each tick's cap)."""
     pool = _pool()
     trace = synth.serving_trace(20, rate=5e4, pool=len(pool), seed=9, k_lo=1, k_hi=40)
     outs = {}
-    for spt in (1, 3, 5, 8):
+    for spt in (1, 3, 5, 8, 13, 64):
         res, st = serving.serve(pool, trace, budget_bytes=2 << 30, vtype=vt, seed=SEED,
                                 keep_y=True, steps_per_tick=spt)
         assert st["n_done"] == len(trace) and st["n_failed"] == 0
         _check_last_y(pool, trace, res, vt)
-        outs[spt] = st
-    assert outs[8]["ticks"] < outs[3]["ticks"] < outs[1]["ticks"]
+        outs[spt] = (res, st)
+    ticks = {spt: st["ticks"] for spt, (_, st) in outs.items()}
+    assert ticks[64] <= ticks[13] <= ticks[8] < ticks[3] < ticks[1]
+    for spt in (13, 64):
+        for q, a, b in zip(trace, outs[8][0], outs[spt][0]):
+            assert np.array_equal(a.y, b.y), (spt, q.rid)
 
 
 def test_incremental_server_register():

@@ -19,14 +19,16 @@ def _pool(count=6, m_hi=20_000):
     return [A for A, _ in synth.batched_set(count, seed=3, m_lo=500, m_hi=m_hi)]
 
 
-SPT = 8  # the library's default steps per tick: a request's X and Y have min(steps, SPT) columns
+SPT = 64  # the library's default steps per tick: a request's X and Y have min(steps, SPT) columns
 
 
 def _bytes(A, np_, xb=8, steps=1):
     r = lambda b: (b + 255) // 256 * 256
     c = max(1, min(steps, SPT))
+    ld = min(8, c)
+    cb = ld * (-(-c // ld))  # whole blocks of ld columns
     mat = r(4 * (A.m + 1)) + r(4 * A.nnz) + r(xb * A.nnz)
-    req = (r(c * xb * A.n) + r(c * xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) +
+    req = (r(cb * xb * A.n) + r(cb * xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) +
            r(16 * np_ * c))
     return mat, req
 
@@ -135,3 +137,37 @@ def test_x_generator_matches_published_definition():
     assert np.array_equal(np.array(xs), synth.serving_x(16, 11, 7, 3))
     # known SplitMix64 output for key 0 (first output of a generator seeded 0)
     assert int(synth.splitmix64(np.array([0], np.uint64))[0]) == 0xE220A8397B1DCDAF
+
+
+def test_tick_cap_follows_load():
+    """How many steps of a request a tick runs follows the load: a lone
+    request runs all its steps in one tick; 240 requests at once, whose
+    64-step ticks would hold far more (partition, pass) items than the GPU
+    has resident wavefronts, run 8 steps each per tick."""
+    pool = _pool()
+    nps = [64] * len(pool)
+    lone, st = serving.serve(pool, [synth.Request(0, 0.0, 0, 40)], budget_bytes=1 << 34,
+                             simulate=True, nps=nps)
+    assert lone[0].status == 0 and st["ticks"] == 1
+    burst = [synth.Request(i, 0.0, i % len(pool), 64) for i in range(240)]
+    res, st = serving.serve(pool, burst, budget_bytes=1 << 36, max_slots=240, simulate=True,
+                            nps=nps)
+    assert all(r.status == 0 for r in res)
+    assert st["ticks"] >= 8  # 8 steps of each request per tick, once all are in
+
+
+def test_large_requests_reserve_eight_columns():
+    """A request reserves min(steps, steps_per_tick) columns of X and Y,
+    except when those would take more than a sixteenth of the arena: then 8
+    (what a tick under load runs), so that a small arena holds more
+    requests."""
+    pool = _pool()
+    A = pool[0]
+    mat, full = _bytes(A, _np(A), steps=40)
+    _, eight = _bytes(A, _np(A), steps=8)
+    assert eight < full
+    for budget, want in ((16 * full + (1 << 20), full), (16 * full - 256, eight)):
+        res, st = serving.serve(pool, [synth.Request(0, 0.0, 0, 40)], budget_bytes=budget,
+                                simulate=True)
+        assert res[0].status == 0
+        assert st["peak_bytes"] == mat + want, (budget, st["peak_bytes"], mat + want)
