@@ -130,6 +130,10 @@ struct TickColSrc : TickSrc {
   }
 };
 
+// a tick's descriptor and the merge's alpha and beta fit the 4 KB of
+// kernel arguments
+static_assert(sizeof(TickColSrc) + 2 * sizeof(double) <= 4096, "tick arguments above 4 KB");
+
 // The tick's products: resident wavefronts, those of one XCD sweeping its
 // group of (request, partition, pass) items together (a partition's passes
 // are neighbours, so they read its slice of A through one L2).  Pass b of a
