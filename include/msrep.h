@@ -217,6 +217,8 @@ size_t msrep_convert_ws_bytes(const msrep_mat *src, int32_t dst_fmt);
  * its entries are sorted stably by the target's major index, ties by its
  * minor index, so equal (row, column) pairs keep their storage order; it is
  * not a target (MSREP_ERR_UNSUPPORTED; msrep_spmv takes it as it is).
+ * dst's arrays must not overlap src's: between the passes of its sort a
+ * transposing conversion keeps entries in dst's index and value arrays.
  * ws_d: msrep_convert_ws_bytes bytes of device memory.
  */
 msrep_status msrep_convert(const msrep_mat *src, msrep_mat *dst, void *ws_d,

@@ -195,3 +195,29 @@ def test_convert_from_any_order_rmat20_round_trip():
     M = pk.Mat(pk.COO_ANY, pk.F64, A.m, A.n, idx=r, idx2=c, val=v)
     ptr, idx, _, val = _host(pk.msrep_convert(M, pk.CSR))
     assert np.array_equal(ptr, A.ptr) and np.array_equal(idx, A.col) and np.array_equal(val, A.val)
+
+
+def _tridiagonal(m, seed):
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(m), 3) + np.tile([-1, 0, 1], m)
+    cols = np.repeat(np.arange(m), 3)
+    keep = (rows >= 0) & (rows < m)
+    r, c = cols[keep], rows[keep]  # row-major: row i holds i-1, i, i+1
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(r, minlength=m))]).astype(np.int32)
+    return synth.Csr(m, m, ptr, c.astype(np.int32), rng.uniform(-1, 1, len(c)),
+                     name="tridiagonal%d" % m)
+
+
+@pytest.mark.parametrize("src,dst", [("csr", "csc"), ("csc", "csr"), ("coo", "coo_col"),
+                                     ("coo_col", "csr")])
+@pytest.mark.parametrize("vt", [0, 1, 2])
+def test_transpose_both_strategies(src, dst, vt):
+    """A transposing conversion sorts (key, position) pairs and gathers the
+    entries when the matrix is banded (9 in 10 sampled entries with row and
+    column within max(m, n)/64), and moves whole entries through the sort
+    otherwise: banded matrices (a 64^3 stencil, a tridiagonal one) take the
+    first, uniform random ones the second; all bit-exact."""
+    mats = [synth.stencil7_csr(g=64, seed=5)[0], _tridiagonal(5000, 6),
+            synth.uniform_csr(5000, 5000, 9, seed=7)[0], synth.uniform_csr(64, 300, 5, seed=8)[0]]
+    for A in mats:
+        _check(A, src, dst, vt)
