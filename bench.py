@@ -219,9 +219,11 @@ def trace_summary(trace_dir, out_name, command, bench_json=None):
             grid = r.get("Grid_Size_X", r.get("Grid_Size", "?"))
             d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
             by.setdefault((name.split("(")[0][:60], grid), []).append(d)
-        lines += ["", "# per launch grid (msrep kernels): calls, average and median us",
+        top = sorted(by.items(), key=lambda kv: -sum(kv[1]))
+        lines += ["", "# per launch grid (msrep kernels, the %d of %d with the most time): calls,"
+                  " average and median us" % (min(40, len(top)), len(top)),
                   "%-60s %10s %8s %12s %12s" % ("kernel", "grid", "calls", "avg_us", "median_us")]
-        for (name, grid), ds in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        for (name, grid), ds in top[:40]:
             lines.append("%-60s %10s %8d %12.2f %12.2f" % (name, grid, len(ds), sum(ds) / len(ds),
                                                          float(np.median(ds))))
     if bench_json:
