@@ -228,12 +228,16 @@ def trace_summary(trace_dir, out_name, command, bench_json=None):
                                                          float(np.median(ds))))
     if bench_json:
         rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
-        rf = rec.get("roofline", {})
-        lines += ["", "# the traced run's bench line: roofline kernel %s, %.2f us per launch by"
-                  " HIP events, %.1f GB/s algorithmic (%.4f of %g)" % (
-                      rf.get("kernel"), rf.get("kernel_avg_us", float("nan")),
-                      rf.get("achieved", float("nan")), rf.get("frac", float("nan")),
-                      rf.get("peak", float("nan")))]
+        rf = rec.get("roofline") or {}
+        if rf:
+            lines += ["", "# the traced run's bench line: roofline kernel %s, %.2f us per launch by"
+                      " HIP events, %.1f GB/s algorithmic (%.4f of %g)" % (
+                          rf.get("kernel"), rf.get("kernel_avg_us", float("nan")),
+                          rf.get("achieved", float("nan")), rf.get("frac", float("nan")),
+                          rf.get("peak", float("nan")))]
+        else:
+            lines += ["", "# the traced run's bench line: %s %s %s, %s ms per step" % (
+                rec.get("metric"), rec.get("value"), rec.get("unit"), rec.get("ms_per_step"))]
         for f, v in rec.get("per_format", {}).items():
             lines.append("#   %s: %s" % (f, json.dumps(v.get("kernels_us", {}))))
     path = os.path.join(ROOT, "profiles", out_name)
