@@ -441,7 +441,8 @@ msrep_status msrep_plan_destroy(msrep_plan plan);
  * share a tick are the columns of a multi-vector product Y = A*X, run as
  * passes of up to 8 columns side by side, so the matrix is read once per 8
  * steps rather than once per step.  A request reserves c = min(steps,
- * steps_per_tick) columns of X and Y (in blocks of 8, each block row-major).
+ * steps_per_tick) columns of X and Y (in blocks of 8, each block row-major;
+ * 8 columns when c would take more than a sixteenth of the budget).
  * How many of them a tick runs follows the load: all that are left while
  * the tick is small against the GPU, else 8 per request.  Every tick but a
  * request's last runs a multiple of 8 of its steps, so its passes, and its
