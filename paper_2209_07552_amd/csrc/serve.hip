@@ -10,18 +10,22 @@
 //    merge buffers fit in the free arena; one that can never fit fails with
 //    MSREP_ERR_BUDGET.  At most max_slots requests are admitted at once.
 //  * Continuous batching: every tick runs the next steps of every ready
-//    request (up to steps_per_tick of each) in one persistent launch over
-//    all their equal-nnz partitions, so requests that arrive while others
-//    run join the next tick.  A request's steps are independent SpMVs: those
-//    of one tick are the columns of a multi-vector product (X and Y of
-//    steps_per_tick columns), so its matrix is read once per tick, not once
-//    per step.  A request's device descriptor is written once, when it is
-//    admitted; a tick passes only its entries (slot, first step, steps), in
-//    the kernel arguments, so a tick costs three launches and one event
-//    record.
+//    request in one persistent launch over all their equal-nnz partitions,
+//    so requests that arrive while others run join the next tick.  A
+//    request's steps are independent SpMVs: those of one tick are the
+//    columns of a multi-vector product, run as passes of up to 8 columns
+//    side by side, so its matrix is read once per 8 steps, not once per
+//    step.  How many steps of each request a tick runs follows the load: as
+//    many as steps_per_tick allows while the tick's items fit the resident
+//    wavefronts, else 8.  A request's device descriptor is written once, when
+//    it is admitted; a tick passes only its entries (slot, first step,
+//    steps), in the kernel arguments, so a tick costs three launches and one
+//    event record.
 //    Uploads and partition builds run on a copy stream, overlapping compute.
-//  * Each request's arithmetic depends only on its matrix, its partitions and
-//    its x: its results are the same alone and in any mix.
+//  * Each request's arithmetic depends only on its matrix, its partitions,
+//    its x and its passes, and every tick but a request's last runs whole
+//    blocks of 8 of its steps, so its passes do not depend on the load: its
+//    results are the same alone and in any mix.
 // One scheduler serves three drivers: msrep_serve replays a trace known in
 // advance on the GPU; msrep_server_* runs the scheduler on a thread of its
 // own and takes requests as they come (submit / poll); msrep_serve_simulate
