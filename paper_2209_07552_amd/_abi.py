@@ -99,6 +99,15 @@ def load_library():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise MsrepError(-4, "libmsrep.so is not built (python -m paper_2209_07552_amd.build)")
+    # torch brings a HIP runtime of its own into the process; it sets up the
+    # device before the library's first HIP call (loaded first, the library's
+    # runtime has found no device on some hosts)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = ctypes.CDLL(_LIB_PATH)
     P = ctypes.POINTER
     sig = {

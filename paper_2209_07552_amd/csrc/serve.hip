@@ -566,8 +566,13 @@ struct HipExec {
       std::this_thread::yield();
       return;
     }
-    const double s = std::min(wait / cfg.time_scale, 2e-4);
-    std::this_thread::sleep_for(std::chrono::duration<double>(s));
+    // a sleep overshoots by up to the timer slack (tens of microseconds):
+    // sleep until shortly before the next arrival and spin the rest
+    const double s = std::min(wait / cfg.time_scale, 2e-4) - 8e-5;
+    if (s > 0)
+      std::this_thread::sleep_for(std::chrono::duration<double>(s));
+    else
+      std::this_thread::yield();
   }
   void release_all(std::vector<Resident> &res) {
     for (auto &r : res) give_event(&r.ev);
@@ -683,7 +688,15 @@ class Scheduler {
     waiting_.push_back(q.get());
     owned_.push_back(std::move(q));
   }
-  bool device_busy() const { return !inflight_.empty(); }
+  // Device work the host must watch: ticks in flight, or requests whose
+  // uploads and partitions are being prepared (the host launches their
+  // first tick as soon as those are done).
+  bool device_busy() const {
+    if (!inflight_.empty()) return true;
+    for (const Req *q : admitted_)
+      if (q->st == kLoading) return true;
+    return false;
+  }
   bool empty() const { return waiting_.empty() && admitted_.empty() && inflight_.empty(); }
   size_t waiting() const { return waiting_.size(); }
   // The earliest time something in flight can change (simulated executor).
