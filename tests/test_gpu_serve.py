@@ -136,6 +136,26 @@ def test_small_budget_queues():
     _check_last_y(pool, [q for q, o in zip(trace, ok) if o], [r for r, o in zip(res, ok) if o], 0)
 
 
+def test_small_arena_reserves_eight_columns_same_results():
+    """With an arena too small for a request's full set of columns (more
+    than a sixteenth of it), requests reserve 8 columns and run 8 steps a
+    tick; since every tick but a request's last runs whole blocks of 8, the
+    last y is bit-identical to a roomy arena's (all steps in one or two
+    ticks), and matches the oracle."""
+    # 15,000-20,000 rows: 17 or more steps reserve at least 24 columns, over
+    # 5 MB of vectors, beyond a sixteenth of the small arena
+    pool = [A for A, _ in synth.batched_set(3, seed=8, m_lo=15_000, m_hi=20_000)]
+    trace = synth.serving_trace(8, rate=2e3, pool=len(pool), seed=12, k_lo=17, k_hi=40)
+    big, st_big = serving.serve(pool, trace, budget_bytes=2 << 30, seed=SEED, keep_y=True)
+    small, st_small = serving.serve(pool, trace, budget_bytes=48 << 20, seed=SEED, keep_y=True)
+    assert all(r.status == 0 for r in big) and all(r.status == 0 for r in small)
+    assert st_small["peak_bytes"] <= 48 << 20
+    assert st_small["ticks"] > st_big["ticks"]  # 8 steps a tick against up to 64
+    for q, a, b in zip(trace, big, small):
+        assert np.array_equal(a.y, b.y), q.rid
+    _check_last_y(pool, trace, small, 0)
+
+
 @pytest.mark.parametrize("vt", [0, 1])
 def test_fill_x_matches_published_generator(vt):
     """The device x generator (msrep_serve_fill_x, also the server's) equals
