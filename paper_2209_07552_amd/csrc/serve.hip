@@ -519,8 +519,10 @@ struct HipExec {
     static_cast<TickSrc &>(msrc) = src;
     const int grid = (src.n_waves + kSpmmWaves - 1) / kSpmmWaves;
     const int gm = static_cast<int>((items + kMergeBlock - 1) / kMergeBlock);
-    const dim3 gf(static_cast<unsigned>(std::min(64, (max_n + 255) / 256)),
-                  static_cast<unsigned>(src.count));
+    // x fill: a thread per row of X up to about 8192 blocks in all, so that a
+    // lone request's fill spreads over the chip
+    const int fill_x = std::min((max_n + 255) / 256, std::max(64, 8192 / src.count));
+    const dim3 gf(static_cast<unsigned>(fill_x), static_cast<unsigned>(src.count));
     const dim3 gmc(static_cast<unsigned>(gm > 0 ? gm : 1), static_cast<unsigned>(kmax));
     if (vtype == MSREP_F64) {
       hipLaunchKernelGGL(fill_x_tick<double>, gf, dim3(256), 0, comp, src, cfg.seed);
