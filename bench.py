@@ -601,7 +601,8 @@ def main():
     ap.add_argument("--rhs", type=int, default=0,
                     help="k > 0: time msrep_spmm with k right-hand sides (CSR) instead")
     ap.add_argument("--count", type=int, default=512, help="batched / serving pool size")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
+    ap.add_argument("--requests", type=int, default=10000,
+                    help="serving: requests per load point (the plain path serves a quarter)")
     ap.add_argument("--rates", default="0.1,0.5,0.9,1.2", help="serving: fractions of capacity")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--steps-per-tick", type=int, default=0,
