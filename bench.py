@@ -1093,8 +1093,9 @@ def bench_serve(args, vt):
     # steady state rather than first uploads and a draining tail
     probe = synth.serving_trace(max(64, 4 * args.count), rate=1e9, pool=len(pool), seed=99)
     spt = args.steps_per_tick
+    npw = args.nnz_per_wave or 1024  # the server's partition size (nonzeros per wavefront)
     _, st = serving.serve(pool, probe, budget_bytes=budget, vtype=vt, max_slots=256,
-                          steps_per_tick=spt)
+                          nnz_per_wave=npw, steps_per_tick=spt)
     cap_req = st["spmv_per_s"] / mean_steps
     log("saturated mix: %.0f SpMV/s -> capacity ~%.1f req/s" % (st["spmv_per_s"], cap_req))
     points = []
@@ -1102,7 +1103,7 @@ def bench_serve(args, vt):
     for f in [float(v) for v in args.rates.split(",")]:
         trace = synth.serving_trace(args.requests, rate=max(f * cap_req, 1e-3), pool=len(pool), seed=1)
         _, st = serving.serve(pool, trace, budget_bytes=budget, vtype=vt, max_slots=256,
-                              steps_per_tick=spt)
+                              nnz_per_wave=npw, steps_per_tick=spt)
         pt = {"load": f, "rate_req_s": round(f * cap_req, 2),
               "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
               "req_per_s": round(st["req_per_s"], 2),
@@ -1120,7 +1121,7 @@ def bench_serve(args, vt):
     # and that step's x (for FP32 pools also on the stored values)
     chk = synth.serving_trace(64, rate=0.5 * cap_req, pool=len(pool), seed=2)
     res, _ = serving.serve(pool, chk, budget_bytes=budget, vtype=vt, max_slots=256,
-                           keep_y=range(0, 64, 4), steps_per_tick=spt)
+                           nnz_per_wave=npw, keep_y=range(0, 64, 4), steps_per_tick=spt)
     err = err_st = 0.0
     for i in range(0, 64, 4):
         q, A = chk[i], pool[chk[i].matrix]
@@ -1139,7 +1140,7 @@ def bench_serve(args, vt):
            "vs_baseline": None, "dtype": args.vtype, "data": "synthetic",
            "config": {"workload": "serve-pool%d" % len(pool), "budget_gb": args.budget_gb,
                       "steps_per_request": "U{10..100}",
-                      "steps_per_tick": spt or 8},
+                      "steps_per_tick": spt or "by load, up to 64", "nnz_per_wave": npw},
            "points": points,
            "plain_path": "the same trace's first %d requests, one at a time in arrival order "
                          "(queueing included), x generated on the device, one msrep_spmv per "
