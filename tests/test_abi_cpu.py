@@ -319,3 +319,19 @@ def test_server_argument_errors():
     assert L.msrep_server_poll(None, None, 0, 0) == -1
     assert L.msrep_server_destroy(None, None) == 0
     assert ctypes.sizeof(_abi._Completion) == 40
+
+
+@pytest.mark.parametrize("vt,vbytes", [(0, 8), (1, 4), (2, 2)])
+def test_transposing_conversion_workspace_holds_the_entries(vt, vbytes):
+    """A transposing conversion may move whole entries through its sort: its
+    workspace has room for every value once more (and the strategy slots);
+    conversions that keep the grouping, and COO in any order, do not."""
+    L = _lib()
+    nnz = 1 << 20
+    src = _desc(vtype=vt, m=1000, n=1000, nnz=nnz)
+    same = L.msrep_convert_ws_bytes(ctypes.byref(src), 2)      # CSR -> COO
+    trans = L.msrep_convert_ws_bytes(ctypes.byref(src), 1)     # CSR -> CSC
+    assert trans - same >= vbytes * nnz + 8
+    coo = _desc(fmt=2, vtype=vt, m=1000, n=1000, nnz=nnz, idx2=0x2800)
+    assert L.msrep_convert_ws_bytes(ctypes.byref(coo), 4) == trans  # COO -> COO_COL transposes
+    assert L.msrep_convert_ws_bytes(ctypes.byref(coo), 0) == same   # COO -> CSR does not
