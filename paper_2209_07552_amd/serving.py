@@ -180,7 +180,9 @@ def serve(pool: Sequence, trace: Sequence, budget_bytes: int, max_slots: int = 2
     ptr, col, val); trace: list of synth.Request.  keep_y: True to return
     every request's last y, or a collection of trace indices to return only
     theirs.  steps_per_tick: most steps of one request per tick (0: the
-    library's default).  Returns (results, stats)."""
+    library's default, 64; a tick runs fewer, in blocks of 8, when the GPU is
+    busy, with the same results).  nps: partitions per pool matrix (default:
+    nnz_per_wave nonzeros each).  Returns (results, stats)."""
     L = load_library()
     _bind(L)
     keep = []
