@@ -286,9 +286,10 @@ class Arena {
 // ------------------------------------------------------ scheduler state
 enum State { kWaiting, kLoading, kReady, kDraining, kDone };
 
-struct Resident {  // a pool matrix in the arena
+struct Resident {  // a pool matrix in the arena, with its partitions
   bool present = false;
   size_t off = 0, bytes = 0;
+  int32_t np = 1;         // partitions, shared by every request on the matrix
   int refs = 0;
   int64_t last_use = 0;
   double ready_at = 0;   // simulated executor
@@ -306,8 +307,8 @@ struct Req {
   // columns per block of X and Y, and blocks
   int32_t ld() const { return copies < kSpmmMaxCols ? copies : kSpmmMaxCols; }
   int32_t blocks() const { return (copies + ld() - 1) / ld(); }
-  size_t off = 0, bytes = 0;  // X, Y, parts, lptr, carries
-  size_t x_off = 0, y_off = 0, parts_off = 0, lptr_off = 0, carry_off = 0;
+  size_t off = 0, bytes = 0;  // X, Y, carries
+  size_t x_off = 0, y_off = 0, carry_off = 0;
   int32_t enq = 0;            // steps enqueued
   int64_t last_tick = -1;
   double t_arrive = 0, t_admit = 0, t_done = 0, ready_at = 0;
@@ -321,10 +322,18 @@ struct Completion {
   int32_t matrix, steps;
 };
 
-size_t mat_bytes(const msrep_mat &A) {
+// A resident matrix's region: its arrays (ptr, idx, val; what is uploaded),
+// then its partitions and local pointers (built on the device after the
+// upload, once for every request on the matrix).
+size_t mat_array_bytes(const msrep_mat &A) {
   return align_up(4 * (static_cast<size_t>(A.m) + 1), 256) +
          align_up(4 * static_cast<size_t>(A.nnz), 256) +
          align_up(static_cast<size_t>(value_bytes(A.vtype)) * A.nnz, 256);
+}
+size_t part_bytes(int32_t np) { return align_up(sizeof(msrep_part) * static_cast<size_t>(np), 256); }
+size_t mat_bytes(const msrep_mat &A, int32_t np) {
+  return mat_array_bytes(A) + part_bytes(np) +
+         align_up(4 * static_cast<size_t>(msrep_lptr_bound(A.m, np)), 256);
 }
 
 void layout_req(Req &q, const msrep_mat &A) {
@@ -339,8 +348,6 @@ void layout_req(Req &q, const msrep_mat &A) {
   const size_t cb = static_cast<size_t>(q.ld()) * q.blocks();  // whole blocks
   q.x_off = take(xb * static_cast<size_t>(A.n) * cb);
   q.y_off = take(xb * static_cast<size_t>(A.m) * cb);
-  q.parts_off = take(sizeof(msrep_part) * q.np);
-  q.lptr_off = take(4 * static_cast<size_t>(msrep_lptr_bound(A.m, q.np)));
   q.carry_off = take(16 * static_cast<size_t>(q.np) * c);
   q.bytes = o;
 }
@@ -448,6 +455,14 @@ struct HipExec {
     A.idx2 = nullptr;
     return A;
   }
+  msrep_part *res_parts(int32_t k, const Resident &R) const {
+    return reinterpret_cast<msrep_part *>(arena + R.off + mat_array_bytes(pool[k].A));
+  }
+  int32_t *res_lptr(int32_t k, const Resident &R) const {
+    return reinterpret_cast<int32_t *>(arena + R.off + mat_array_bytes(pool[k].A) +
+                                       part_bytes(R.np));
+  }
+  // The matrix's arrays, then its partitions, on the copy stream.
   msrep_status upload(int32_t k, Resident &R) {
     const msrep_mat &H = pool[k].A;
     const msrep_mat D = device_mat(k, R);
@@ -460,24 +475,22 @@ struct HipExec {
                                static_cast<size_t>(value_bytes(H.vtype)) * H.nnz,
                                hipMemcpyHostToDevice, copy));
     }
+    if (msrep_status st = msrep_build_partition(&D, R.np, res_parts(k, R), res_lptr(k, R),
+                                                msrep_lptr_bound(D.m, R.np), nullptr, copy))
+      return st;
     if (msrep_status st = take_event(&R.ev)) return st;
     MSREP_HIP(hipEventRecord(R.ev, copy));
     return MSREP_OK;
   }
   void evicted(Resident &R) { give_event(&R.ev); }
-  // Partitions of the request's matrix and its slot descriptor, on the copy
-  // stream after the matrix upload.
+  // The request's slot descriptor (its matrix's partitions, its own vectors
+  // and carries), on the copy stream after the matrix upload.
   msrep_status prepare(Req &q, const Resident &R) {
     const msrep_mat D = device_mat(q.r.matrix, R);
     char *b = arena + q.off;
-    if (msrep_status st = msrep_build_partition(
-            &D, q.np, reinterpret_cast<msrep_part *>(b + q.parts_off),
-            reinterpret_cast<int32_t *>(b + q.lptr_off), msrep_lptr_bound(D.m, q.np), nullptr, copy))
-      return st;
     ServeSlot &S = slots_h[q.slot];
-    S.M = BatchMat{D.idx, D.val, reinterpret_cast<const msrep_part *>(b + q.parts_off),
-                   reinterpret_cast<const int32_t *>(b + q.lptr_off), D.m, D.n, q.np, 0,
-                   reinterpret_cast<double *>(b + q.carry_off)};
+    S.M = BatchMat{D.idx, D.val, res_parts(q.r.matrix, R), res_lptr(q.r.matrix, R), D.m, D.n,
+                   R.np, 0, reinterpret_cast<double *>(b + q.carry_off)};
     S.xy = BatchXY{b + q.x_off, b + q.y_off};
     S.rid = q.r.rid;
     S.ld = q.ld();
@@ -597,7 +610,7 @@ struct SimExec {
   void shutdown() {}
   double now() const { return clock; }
   msrep_status upload(int32_t k, Resident &R) {
-    copy_free = std::max(copy_free, clock) + static_cast<double>(mat_bytes(pool[k].A)) / upload_bw;
+    copy_free = std::max(copy_free, clock) + static_cast<double>(mat_array_bytes(pool[k].A)) / upload_bw;
     R.ready_at = copy_free;
     return MSREP_OK;
   }
@@ -834,7 +847,7 @@ class Scheduler {
     while (!waiting_.empty() && !free_slots_.empty()) {
       Req &q = *waiting_.front();
       Resident &R = res_[q.r.matrix];
-      const size_t mb = mat_bytes(pool_[q.r.matrix].A);
+      const size_t mb = mat_bytes(pool_[q.r.matrix].A, q.np);
       const size_t table = std::min(arena_.cap(), ex_.reserved_bytes());
       if (q.bytes + mb + 512 > arena_.cap() - table) {  // can never fit
         waiting_.pop_front();
@@ -855,6 +868,7 @@ class Scheduler {
             R.present = true;
             R.off = mo;
             R.bytes = mb;
+            R.np = q.np;
             if (msrep_status st = ex_.upload(q.r.matrix, R)) {
               err = st;
               return progressed;

@@ -27,9 +27,10 @@ def _bytes(A, np_, xb=8, steps=1):
     c = max(1, min(steps, SPT))
     ld = min(8, c)
     cb = ld * (-(-c // ld))  # whole blocks of ld columns
-    mat = r(4 * (A.m + 1)) + r(4 * A.nnz) + r(xb * A.nnz)
-    req = (r(cb * xb * A.n) + r(cb * xb * A.m) + r(40 * np_) + r(4 * (A.m + 2 * np_)) +
-           r(16 * np_ * c))
+    # a resident matrix holds its arrays and its partitions (shared by every
+    # request on it); a request holds its vectors and carries
+    mat = r(4 * (A.m + 1)) + r(4 * A.nnz) + r(xb * A.nnz) + r(40 * np_) + r(4 * (A.m + 2 * np_))
+    req = r(cb * xb * A.n) + r(cb * xb * A.m) + r(16 * np_ * c)
     return mat, req
 
 
