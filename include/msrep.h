@@ -434,7 +434,9 @@ msrep_status msrep_plan_destroy(msrep_plan plan);
  * a matrix of a host pool plus `steps` SpMVs y_j = A*x_j against fresh x_j.
  * Matrices are uploaded into the caller's arena when the request is admitted
  * (admission is by bytes: matrix + partitions + vectors must fit in what the
- * arena has free) and stay resident while the request runs.  Every tick
+ * arena has free) and stay resident while the request runs; a resident
+ * matrix's partitions are built once, with its upload, and shared by every
+ * request on it.  Every tick
  * executes the next steps of every active request (240 requests per tick at
  * most) in one batched launch, so requests that arrive while others run
  * join the next tick.  A request's steps are independent SpMVs: those that
