@@ -172,3 +172,16 @@ def test_large_requests_reserve_eight_columns():
                                 simulate=True)
         assert res[0].status == 0
         assert st["peak_bytes"] == mat + want, (budget, st["peak_bytes"], mat + want)
+
+
+def test_requests_on_one_matrix_share_its_partitions():
+    """A resident matrix holds its partitions once: two requests on it,
+    admitted together, take the matrix's bytes (arrays and partitions) once
+    and their own vectors and carries each."""
+    pool = _pool()
+    A = pool[2]
+    mat, req = _bytes(A, _np(A), steps=5)
+    trace = [synth.Request(0, 0.0, 2, 5), synth.Request(1, 0.0, 2, 5)]
+    res, st = serving.serve(pool, trace, budget_bytes=1 << 34, simulate=True)
+    assert all(r.status == 0 for r in res)
+    assert st["peak_bytes"] == mat + 2 * req
